@@ -1,0 +1,112 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module draws and lays out input data only: collocation points in the
+mapped coordinate s in [0, 1), quadrature nodes and weights for integrals over
+s in (0, 1), validation grids, loss weights and Glorot-initialised parameter
+vectors.  It holds none of the method's arithmetic (no coordinate map, no
+network, no residual): both the oracle and the GPU library receive these
+arrays and do their own computation from them.
+
+The paper trains on point groups and loss weights defined in its (unpublished)
+supplementary material; these seeded sets stand in for them with the shapes
+listed in WORKLOADS.
+
+Parameter layout (shared convention of both sides): for each affine layer l,
+W^l row-major (w_l x w_{l-1}) followed by b^l.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Blow-up scaling of the CCF first unstable profile (paper, main text, CCF
+# paragraph): lambda_1 ~= 0.6057.
+LAM_CCF1 = 0.6057
+
+WORKLOADS = {
+    # CCF profile, small network, uniform points.
+    "ccf_small": dict(equation="ccf1d", widths=[1, 32, 32, 1], lam=LAM_CCF1,
+                      n=1024, points="uniform", m_quad=1024, seed=1,
+                      mu=1e-3, steps=10, c_norm=1.0, c_target=1.0),
+    # CCF profile, medium network, Chebyshev-clustered points.
+    "ccf_medium": dict(equation="ccf1d", widths=[1, 64, 64, 64, 1], lam=LAM_CCF1,
+                       n=8192, points="chebyshev", m_quad=1024, seed=2,
+                       mu=1e-3, steps=50, c_norm=1.0, c_target=1.0),
+}
+
+
+def num_params(widths) -> int:
+    return int(sum(b * (a + 1) for a, b in zip(widths[:-1], widths[1:])))
+
+
+def glorot_theta(widths, seed: int) -> np.ndarray:
+    """Glorot-uniform weights U(+-sqrt(6/(fan_in+fan_out))), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for a, b in zip(widths[:-1], widths[1:]):
+        lim = np.sqrt(6.0 / (a + b))
+        parts.append(rng.uniform(-lim, lim, size=(b, a)).ravel())
+        parts.append(np.zeros(b))
+    return np.concatenate(parts).astype(np.float64)
+
+
+def points_uniform(n: int) -> np.ndarray:
+    """s_i = i/n, i = 0..n-1 (s = 0 is the origin)."""
+    return np.arange(n, dtype=np.float64) / n
+
+
+def points_chebyshev(n: int) -> np.ndarray:
+    """Chebyshev-clustered s_i = (1 - cos(pi (i + 1/2) / n)) / 2."""
+    i = np.arange(n, dtype=np.float64)
+    return (1.0 - np.cos(np.pi * (i + 0.5) / n)) / 2.0
+
+
+def quadrature_s(m: int):
+    """Nodes and weights for integrals over s in (0, 1).
+
+    Gauss-Legendre in tau on (0, 1) with s = tau^2, so that ds = 2 tau dtau;
+    the returned weights already include that factor.  Integrands that behave
+    like 1/sqrt(s) near s = 0 become smooth in tau.
+    """
+    x, w = np.polynomial.legendre.leggauss(m)
+    tau = (x + 1.0) / 2.0
+    wt = w / 2.0
+    return tau * tau, 2.0 * tau * wt
+
+
+def validation_grid(n: int) -> np.ndarray:
+    """Dense validation grid: the origin plus 4n cell midpoints in s."""
+    k = np.arange(4 * n, dtype=np.float64)
+    return np.concatenate([[0.0], (k + 0.5) / (4 * n)])
+
+
+def perturbation(p: int, seed: int) -> np.ndarray:
+    """Unit-norm random direction in parameter space."""
+    v = np.random.default_rng(seed).standard_normal(p)
+    return v / np.linalg.norm(v)
+
+
+def make_inputs(name: str, n: int | None = None, m_quad: int | None = None,
+                widths=None) -> dict:
+    """All arrays for one named workload (sizes may be overridden for tests)."""
+    cfg = dict(WORKLOADS[name])
+    if n is not None:
+        cfg["n"] = n
+    if m_quad is not None:
+        cfg["m_quad"] = m_quad
+    if widths is not None:
+        cfg["widths"] = list(widths)
+    n = cfg["n"]
+    s = points_uniform(n) if cfg["points"] == "uniform" else points_chebyshev(n)
+    sq, wq = quadrature_s(cfg["m_quad"])
+    out = dict(cfg)
+    out.update(
+        s=s,
+        rho=np.ones(n),
+        f=np.zeros(n),
+        sq=sq,
+        wq=wq,
+        sval=validation_grid(n),
+        theta0=glorot_theta(cfg["widths"], cfg["seed"]),
+        P=num_params(cfg["widths"]),
+    )
+    return out
