@@ -1,0 +1,187 @@
+/*
+ * gn.h -- C ABI of the MI355X (gfx950) damped Gauss-Newton library for
+ * physics-informed networks fitted to self-similar blow-up profiles.
+ *
+ * Paper: "Discovery of Unstable Singularities" (arXiv 2509.14185), Methods.
+ *   - "Self-similar Solutions" and "Solution Modeling and Equation
+ *     Factorisation": profile equations in the self-similar variable y, the
+ *     compactified coordinate q = (1+|y|^2)^{-1/(2(1+lambda))} fed to a tanh
+ *     MLP, envelopes that fix symmetry and far-field behaviour.
+ *   - "Training Loss": d0 residual rows weighted by rho/(N N_E) and a
+ *     normalisation (data) row.
+ *   - "Second-order Optimizer": theta <- theta - (G + gamma I)^{-1} grad h
+ *     with the full Gauss-Newton matrix G = J^T J.
+ *   - "Validation Metrics for Solutions": max |R| over a validation grid.
+ *
+ * Conventions
+ *   - Pointers named d_* are DEVICE memory owned by the caller; h_* are host
+ *     memory.  The library owns only the workspace it allocates in
+ *     gn_create/gn_set_points; no other entry point allocates.
+ *   - Every call is asynchronous on the handle's stream unless it says it
+ *     synchronises.  No C++ exception crosses the ABI; errors are returned
+ *     as gn_status and the text of the last error is kept per handle
+ *     (gn_last_error).
+ *   - theta layout: for each affine layer l = 1..L, W^l row-major
+ *     (w_l x w_{l-1}) followed by b^l.  P = sum_l w_l (w_{l-1} + 1).
+ *   - Row order of r and J: the N collocation rows in point order, then the
+ *     normalisation row (m = N + 1 rows).
+ *   - Matrices are row-major: element (i, j) of X with leading dimension ld
+ *     is X[i*ld + j].  Only the lower triangle (j <= i) of a Gram matrix or
+ *     Cholesky factor is read or written; the strict upper triangle is left
+ *     untouched.
+ *   - Device pointers must be 8-byte aligned; leading dimensions are in
+ *     elements.
+ */
+#ifndef GN_H
+#define GN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gn_context *gn_handle;
+
+typedef enum {
+    GN_OK = 0,
+    GN_ENOTPD = 1,       /* Cholesky pivot not positive: G + mu I is not numerically PD */
+    GN_EINVAL = -1,      /* bad argument (null pointer, size, leading dimension, widths) */
+    GN_ENOMEM = -2,      /* workspace allocation failed */
+    GN_EDEVICE = -3,     /* HIP runtime error */
+    GN_ENONFINITE = -4,  /* NaN or Inf in r, g or the update */
+    GN_ESTATE = -5       /* call out of order (e.g. no points set) */
+} gn_status;
+
+/* Profile equation.  CCF: R = -lam Theta + ((1+lam) y + H Theta) Theta_y with
+ * the half-line Hilbert transform of the even field Theta (the Cordoba-
+ * Cordoba-Fontelos model under the self-similar ansatz).  BURGERS1D: the
+ * local analogue with H Theta replaced by Theta (odd field). */
+typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1 } gn_equation;
+
+/* Arithmetic of the Jacobian/Gram bulk.  GN_FP64: FP64 throughout.
+ * GN_SPLIT32: reserved for the split (hi/lo FP32) Jacobian and Gram. */
+typedef enum { GN_FP64 = 0, GN_SPLIT32 = 1 } gn_precision;
+
+#define GN_MAX_LAYERS 8   /* affine layers */
+#define GN_MAX_WIDTH 64   /* hidden width limit of the 1D kernels */
+
+typedef struct {
+    int32_t equation;        /* gn_equation */
+    int32_t precision;       /* gn_precision */
+    int32_t n_layers;        /* L, number of affine layers (1..GN_MAX_LAYERS) */
+    const int32_t *widths;   /* host, L+1 entries: [1, w_1, ..., w_{L-1}, 1] */
+    double lam;              /* self-similar scaling lambda (> 0) */
+    double c_norm;           /* weight of the normalisation row (>= 0) */
+    double c_target;         /* target value of NN at q = 1 (the origin) */
+} gn_problem;
+
+typedef struct {
+    double half_sq_norm;     /* |r|^2 / 2 at the input theta */
+    double max_abs_R;        /* max |R_i| over collocation points (raw, unscaled) */
+    double max_abs_R_val;    /* max |R| over the validation grid (0 if none set) */
+    double grad_dot_delta;   /* g^T delta (negative for a descent step) */
+    double model_sq_norm;    /* |r + J delta|^2 + mu |delta|^2 (predicted) */
+    int64_t chol_info;       /* 0, or 1-based index of the first bad pivot */
+    int32_t status;          /* gn_status of the step */
+    int32_t updated;         /* 1 if theta was updated */
+} gn_stats;
+
+/* Text for a status code (static storage). */
+const char *gn_status_string(int32_t status);
+/* Text of the last error on this handle (valid until the next call). */
+const char *gn_last_error(gn_handle h);
+
+/* Create a handle for one problem on the current HIP device.  Copies *prob
+ * (including widths).  Errors: GN_EINVAL for bad widths (first/last != 1,
+ * hidden width > GN_MAX_WIDTH, L out of range), lam <= 0, c_norm < 0. */
+gn_status gn_create(const gn_problem *prob, gn_handle *out);
+gn_status gn_destroy(gn_handle h);
+
+/* Bind a HIP stream (hipStream_t passed as void*; NULL = default stream). */
+gn_status gn_set_stream(gn_handle h, void *stream);
+
+/*
+ * Set the point sets (paper: collocation batch Y_0 of pairs (y, rho); points
+ * are kept fixed for many steps, so geometry is computed once here).
+ *   d_s   [n]      collocation points in the mapped coordinate s = 1 - q,
+ *                  0 <= s < 1 (y = sqrt(q^{-2(1+lam)} - 1)).
+ *   d_rho [n]      loss weights rho_i (NULL: all 1).
+ *   d_f   [n]      source term subtracted from R_i (NULL: zero).
+ *   d_sq, d_wq [m_quad]  nodes 0 < s_j < 1 and weights of a quadrature for
+ *                  integrals over s in (0,1); used by the Hilbert term of
+ *                  GN_EQ_CCF1D (ignored, may be NULL with m_quad = 0, for
+ *                  GN_EQ_BURGERS1D).
+ *   d_sval [n_val] validation grid in s (NULL with n_val = 0: none).
+ * The library copies what it needs; caller buffers may be freed afterwards.
+ * Allocates the per-step workspace (Jacobian, Gram, factor).  Synchronises.
+ * Errors: GN_EINVAL (n < 1, m_quad < 1 for CCF, null pointers), GN_ENOMEM.
+ */
+gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double *d_rho,
+                        const double *d_f, int64_t m_quad, const double *d_sq,
+                        const double *d_wq, int64_t n_val, const double *d_sval);
+
+int64_t gn_num_params(gn_handle h);  /* P */
+int64_t gn_num_rows(gn_handle h);    /* m = N + 1, or -1 before gn_set_points */
+
+/* Residual rows r (length m): r_i = sqrt(rho_i/N) (R_i - f_i), i < N;
+ * r_N = sqrt(c_norm) (NN(q=1) - c_target).  Paper: "Training Loss". */
+gn_status gn_residual(gn_handle h, const double *d_theta, double *d_r);
+
+/* Jacobian J = dr/dtheta, m x P, row-major, ldJ >= P.  If d_r is not NULL
+ * the residual rows are written too.  Paper: "Second-order Optimizer"
+ * (Jacobian of the residual functions). */
+gn_status gn_jacobian(gn_handle h, const double *d_theta, double *d_J, int64_t ldJ, double *d_r);
+
+/* Lower triangle of G = J^T J (p x p, ldG >= p) and g = J^T r (p), for any
+ * m x p row-major J (ldJ >= p).  d_r may be NULL (then g is not written). */
+gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t ldJ,
+                  const double *d_r, double *d_G, int64_t ldG, double *d_g);
+
+/* Damped solve (G + mu I) delta = -g.  In: lower triangle of G (p x p,
+ * ldG >= p); out: its lower Cholesky factor L in place, delta (p).
+ * Synchronises to fill *h_info (0, or the 1-based first non-positive pivot).
+ * Returns GN_ENOTPD (delta not written) or GN_ENONFINITE. */
+gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu,
+                   const double *d_g, double *d_delta, int64_t *h_info);
+
+/* One damped GN step in place: theta <- theta - (J^T J + mu I)^{-1} J^T r.
+ * theta is left unchanged when the factorisation fails (GN_ENOTPD) or the
+ * update is not finite (GN_ENONFINITE).  Synchronises once to fill *h_stats
+ * (may be NULL: then it does not synchronise and returns GN_OK after
+ * enqueueing; failures still leave theta unchanged). */
+gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats);
+
+/* Residual statistics at theta (half_sq_norm, max_abs_R, max_abs_R_val).
+ * Synchronises. */
+gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats);
+
+/* out = J^T v (P) without forming J; activations are recomputed.  The
+ * adjoint of gn_residual (backward of a differentiable residual). */
+gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *d_out);
+
+/* Phase timing of gn_step with HIP events recorded on the handle's stream
+ * (tracing support; not part of the paper's method).  Phases: */
+typedef enum {
+    GN_PHASE_FORWARD = 0,   /* weight transpose, forward jets, residual rows, validation grid */
+    GN_PHASE_JLOCAL = 1,    /* per-row reverse sweeps writing the local Jacobian rows */
+    GN_PHASE_COUPLING = 2,  /* Hilbert coupling GEMM J[:N] += diag(sc Theta_y) Q B */
+    GN_PHASE_GRAM = 3,      /* Gram of [J | r] (lower triangle, FP64 MFMA) and |r|^2 */
+    GN_PHASE_CHOLESKY = 4,  /* blocked Cholesky of the bordered matrix */
+    GN_PHASE_SOLVE = 5,     /* back substitution, finiteness check, update of theta */
+    GN_PHASE_COUNT = 6
+} gn_phase;
+
+/* enable = 1: record the phases of the next max_steps calls of gn_step
+ * (creates the events here, outside the step path); enable = 0: stop and
+ * release them.  Re-enabling restarts the count. */
+gn_status gn_profile_enable(gn_handle h, int32_t enable, int32_t max_steps);
+/* Synchronises; h_ms[k] = summed duration (ms) of phase k over the recorded
+ * steps (n_phases <= GN_PHASE_COUNT entries written); *n_steps = steps
+ * recorded. */
+gn_status gn_profile_read(gn_handle h, double *h_ms, int32_t n_phases, int32_t *n_steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GN_H */

@@ -1,0 +1,572 @@
+// C ABI of the gfx950 damped Gauss-Newton library (declared in include/gn.h).
+// Argument checking, workspace ownership and the order of kernel launches for
+// each entry point.  Every arithmetic step runs in the HIP kernels of
+// k_profile1d.hip, k_dgemm.hip and k_solve.hip.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "gn_internal.h"
+
+using namespace gn;
+
+
+struct gn_context {
+    int equation = 0, precision = 0;
+    double lam = 0, c_norm = 0, c_target = 0;
+    MlpDesc md{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    std::vector<void *> allocs;       // problem-lifetime allocations
+    std::vector<void *> pt_allocs;    // point-set allocations
+    // P-dependent workspace (gn_create)
+    int64_t cap = 0;                  // largest p accepted by gn_gram/gn_solve work buffers (P + 1)
+    double *thetaT = nullptr, *linv = nullptr, *ybuf = nullptr, *zbuf = nullptr, *delta = nullptr;
+    double *gemv_work = nullptr, *red_work = nullptr, *one_x = nullptr, *nn_one = nullptr, *seed_one = nullptr;
+    DevStatus *status = nullptr;
+    // point-set data (gn_set_points)
+    int64_t n = 0, m = 0, nv = 0;
+    Geo1D pts{}, nodes{}, val{};
+    double *rho = nullptr, *f = nullptr;
+    double *Q = nullptr;
+    int64_t ldQ = 0;
+    double *nn_pts = nullptr, *nn_nodes = nullptr, *nn_val = nullptr;
+    double *R = nullptr, *seed0 = nullptr, *seed1 = nullptr, *cscale = nullptr, *r_tmp = nullptr;
+    double *vseed0 = nullptr, *vseed1 = nullptr, *useed = nullptr, *hadj_work = nullptr;
+    double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
+    int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
+    // phase timing
+    std::vector<hipEvent_t> events;   // max_steps x (GN_PHASE_COUNT + 1)
+    int32_t prof_max = 0, prof_count = 0;
+};
+
+namespace {
+
+const char *kStatusText[] = {"ok", "invalid argument", "out of device memory", "HIP runtime error",
+                             "non-finite value", "call out of order"};
+
+gn_status fail(gn_handle h, gn_status s, const char *fmt, const char *detail = "") {
+    if (h) {
+        char buf[512];
+        snprintf(buf, sizeof buf, fmt, detail);
+        h->err = buf;
+    }
+    return s;
+}
+
+#define GN_HIP(h, expr)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail((h), GN_EDEVICE, "HIP: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+template <class T>
+gn_status dev_alloc(gn_handle h, std::vector<void *> &list, T **out, int64_t count) {
+    *out = nullptr;
+    if (count <= 0) count = 1;
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, GN_ENOMEM, "hipMalloc of %s failed", std::to_string(sizeof(T) * count).c_str());
+    }
+    list.push_back(p);
+    *out = (T *)p;
+    return GN_OK;
+}
+
+void free_list(std::vector<void *> &list) {
+    for (void *p : list) (void)hipFree(p);
+    list.clear();
+}
+
+#define GN_TRY(expr)                  \
+    do {                              \
+        gn_status s_ = (expr);        \
+        if (s_ != GN_OK) return s_;   \
+    } while (0)
+
+bool points_ready(gn_handle h) { return h->n > 0; }
+
+// Forward jets at the nodes (CCF), the collocation points and q = 1.
+gn_status forward_all(gn_handle h, const double *theta) {
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_transpose_weights(st, h->md, theta, h->thetaT));
+    if (h->equation == GN_EQ_CCF1D) {
+        SweepBatch b{};
+        b.x = h->nodes.q; b.n = h->m; b.nn = h->nn_nodes;
+        GN_HIP(h, launch_mlp_forward(st, h->md, theta, h->thetaT, b));
+    }
+    SweepBatch b{};
+    b.x = h->pts.q; b.n = h->n; b.nn = h->nn_pts;
+    GN_HIP(h, launch_mlp_forward(st, h->md, theta, h->thetaT, b));
+    SweepBatch o{};
+    o.x = h->one_x; o.n = 1; o.nn = h->nn_one;
+    GN_HIP(h, launch_mlp_forward(st, h->md, theta, h->thetaT, o));
+    return GN_OK;
+}
+
+// Residual rows into r (stride r_stride); seeds/cscale when `seeds`.
+gn_status residual_rows(gn_handle h, double *r, int64_t r_stride, bool seeds) {
+    ResidualArgs a{};
+    a.equation = h->equation; a.lam = h->lam; a.n = h->n; a.m = h->m;
+    a.pts = h->pts; a.nodes = h->nodes;
+    a.nn = h->nn_pts; a.nn_nodes = h->nn_nodes;
+    a.rho = h->rho; a.f = h->f; a.inv_n = 1.0 / (double)h->n;
+    a.R = h->R; a.r = r; a.r_stride = r_stride;
+    a.seed0 = seeds ? h->seed0 : nullptr; a.seed1 = seeds ? h->seed1 : nullptr;
+    a.cscale = seeds ? h->cscale : nullptr;
+    a.max_out = &h->status->max_R;
+    GN_HIP(h, launch_residual(h->stream, a));
+    GN_HIP(h, launch_norm_row(h->stream, h->nn_one, sqrt(h->c_norm), h->c_target, r + h->n * r_stride));
+    return GN_OK;
+}
+
+// max |R| on the validation grid (theta's weights already transposed).
+gn_status validation(gn_handle h, const double *theta) {
+    if (h->nv <= 0) return GN_OK;
+    SweepBatch b{};
+    b.x = h->val.q; b.n = h->nv; b.nn = h->nn_val;
+    GN_HIP(h, launch_mlp_forward(h->stream, h->md, theta, h->thetaT, b));
+    ResidualArgs a{};
+    a.equation = h->equation; a.lam = h->lam; a.n = h->nv; a.m = h->m;
+    a.pts = h->val; a.nodes = h->nodes;
+    a.nn = h->nn_val; a.nn_nodes = h->nn_nodes;
+    a.inv_n = 1.0;
+    a.max_out = &h->status->max_R_val;
+    GN_HIP(h, launch_residual(h->stream, a));
+    return GN_OK;
+}
+
+// J (and r when r != null, with stride r_stride) for the current theta.
+gn_status jacobian_into(gn_handle h, const double *theta, double *J, int64_t ldJ, double *r, int64_t r_stride) {
+    GN_TRY(forward_all(h, theta));
+    GN_TRY(residual_rows(h, r ? r : h->r_tmp, r ? r_stride : 1, true));
+    hipStream_t st = h->stream;
+    SweepBatch b{};
+    b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
+    GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, b));
+    SweepBatch o{};
+    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + h->n * ldJ; o.ld = ldJ;
+    GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, o));
+    if (h->equation == GN_EQ_CCF1D) {
+        // B_j = dTheta(t_j)/dtheta = E_j dNN(t_j)/dtheta, then J[:N] += diag(sc Theta_y) Q B
+        SweepBatch nb{};
+        nb.x = h->nodes.q; nb.s0 = h->nodes.E; nb.s1c = 0.0; nb.n = h->m; nb.rows = h->Bm; nb.ld = h->ldJ;
+        GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, nb));
+        GemmDesc g{};
+        g.M = h->n; g.N = h->md.P; g.K = h->m;
+        g.A = h->Q; g.lda = h->ldQ; g.la = 0;
+        g.B = h->Bm; g.ldb = h->ldJ; g.lb = 0;
+        g.C = J; g.ldc = ldJ;
+        g.alpha = 1.0; g.beta = 1.0; g.rowscale = h->cscale;
+        GN_HIP(h, launch_dgemm(st, g));
+    }
+    return GN_OK;
+}
+
+gn_status read_status(gn_handle h, DevStatus *out) {
+    GN_HIP(h, hipMemcpyAsync(out, h->status, sizeof(DevStatus), hipMemcpyDeviceToHost, h->stream));
+    GN_HIP(h, hipStreamSynchronize(h->stream));
+    return GN_OK;
+}
+
+// Records the boundary event `k` of the current profiled step (no-op when
+// profiling is off or the step budget is used up).
+void mark(gn_handle h, int k) {
+    if (h->prof_count >= h->prof_max) return;
+    (void)hipEventRecord(h->events[(size_t)h->prof_count * (GN_PHASE_COUNT + 1) + k], h->stream);
+}
+
+double bits_to_double(unsigned long long b) {
+    double d;
+    memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gn_status_string(int32_t s) {
+    if (s == GN_ENOTPD) return "matrix not positive definite";
+    if (s <= 0 && s >= -5) return kStatusText[-s];
+    return "unknown status";
+}
+
+const char *gn_last_error(gn_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+gn_status gn_create(const gn_problem *prob, gn_handle *out) {
+    if (!prob || !out || !prob->widths) return GN_EINVAL;
+    *out = nullptr;
+    const int L = prob->n_layers;
+    if (L < 1 || L > GN_MAX_LAYERS) return GN_EINVAL;
+    if (prob->equation != GN_EQ_CCF1D && prob->equation != GN_EQ_BURGERS1D) return GN_EINVAL;
+    if (prob->precision != GN_FP64) return GN_EINVAL;
+    if (!(prob->lam > 0.0) || !(prob->c_norm >= 0.0)) return GN_EINVAL;
+    if (prob->widths[0] != 1 || prob->widths[L] != 1) return GN_EINVAL;
+    for (int l = 1; l < L; ++l)
+        if (prob->widths[l] < 1 || prob->widths[l] > GN_MAX_WIDTH) return GN_EINVAL;
+    gn_handle h = new (std::nothrow) gn_context();
+    if (!h) return GN_ENOMEM;
+    h->equation = prob->equation;
+    h->precision = prob->precision;
+    h->lam = prob->lam;
+    h->c_norm = prob->c_norm;
+    h->c_target = prob->c_target;
+    MlpDesc &d = h->md;
+    d.L = L;
+    int o = 0;
+    for (int l = 0; l <= L; ++l) d.w[l] = prob->widths[l];
+    for (int l = 0; l < L; ++l) {
+        d.off[l] = o;
+        o += d.w[l + 1] * (d.w[l] + 1);
+    }
+    d.P = o;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return GN_EDEVICE;
+    }
+    const int64_t P = d.P;
+    h->cap = P + 1;
+    gn_status s = GN_OK;
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->thetaT, P);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->linv, chol_linv_size(h->cap));
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->ybuf, h->cap);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->zbuf, h->cap);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->delta, h->cap);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gemv_work, gemv_t_work_size(0, h->cap));
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->red_work, 1024);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->one_x, 1);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->nn_one, 2);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->seed_one, 1);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->status, 1);
+    if (s != GN_OK) {
+        free_list(h->allocs);
+        delete h;
+        return s;
+    }
+    const double one = 1.0;
+    if (hipMemcpy(h->one_x, &one, sizeof one, hipMemcpyHostToDevice) != hipSuccess) {
+        free_list(h->allocs);
+        delete h;
+        return GN_EDEVICE;
+    }
+    *out = h;
+    return GN_OK;
+}
+
+gn_status gn_destroy(gn_handle h) {
+    if (!h) return GN_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    free_list(h->pt_allocs);
+    free_list(h->allocs);
+    delete h;
+    return GN_OK;
+}
+
+gn_status gn_set_stream(gn_handle h, void *stream) {
+    if (!h) return GN_EINVAL;
+    h->stream = (hipStream_t)stream;
+    return GN_OK;
+}
+
+int64_t gn_num_params(gn_handle h) { return h ? h->md.P : -1; }
+int64_t gn_num_rows(gn_handle h) { return (h && h->n > 0) ? h->n + 1 : -1; }
+
+gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double *d_rho, const double *d_f,
+                        int64_t m_quad, const double *d_sq, const double *d_wq, int64_t n_val,
+                        const double *d_sval) {
+    if (!h) return GN_EINVAL;
+    if (n < 1 || !d_s) return fail(h, GN_EINVAL, "need n >= 1 collocation points%s");
+    if (h->equation == GN_EQ_CCF1D && (m_quad < 1 || !d_sq || !d_wq))
+        return fail(h, GN_EINVAL, "the CCF Hilbert term needs m_quad >= 1 nodes and weights%s");
+    if (n_val < 0 || (n_val > 0 && !d_sval)) return fail(h, GN_EINVAL, "bad validation grid%s");
+    if (h->equation != GN_EQ_CCF1D) m_quad = 0;
+    GN_HIP(h, hipStreamSynchronize(h->stream));
+    free_list(h->pt_allocs);
+    h->n = h->m = h->nv = 0;
+    auto &A = h->pt_allocs;
+    const int64_t P = h->md.P;
+    const int64_t m_rows = n + 1;
+    h->ldJ = round_up(P + 1, 32);
+    h->ldG = round_up(P + 1, 32);
+    h->ldQ = m_quad;
+    const int64_t nparts = mlp_vjp_partials(h->md, n) + mlp_vjp_partials(h->md, 1) + mlp_vjp_partials(h->md, m_quad);
+    auto geo = [&](Geo1D &g, int64_t cnt, bool with_w) -> gn_status {
+        GN_TRY(dev_alloc(h, A, &g.y, cnt));
+        GN_TRY(dev_alloc(h, A, &g.q, cnt));
+        GN_TRY(dev_alloc(h, A, &g.E, cnt));
+        GN_TRY(dev_alloc(h, A, &g.Ey, cnt));
+        GN_TRY(dev_alloc(h, A, &g.qy, cnt));
+        g.wh = nullptr;
+        if (with_w) GN_TRY(dev_alloc(h, A, &g.wh, cnt));
+        return GN_OK;
+    };
+    gn_status s = GN_OK;
+    s = geo(h->pts, n, false);
+    if (s == GN_OK) s = geo(h->nodes, m_quad, true);
+    if (s == GN_OK) s = geo(h->val, n_val, false);
+    if (s == GN_OK && d_rho) s = dev_alloc(h, A, &h->rho, n);
+    if (s == GN_OK && !d_rho) h->rho = nullptr;
+    if (s == GN_OK && d_f) s = dev_alloc(h, A, &h->f, n);
+    if (s == GN_OK && !d_f) h->f = nullptr;
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Q, n * m_quad);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->nn_pts, 2 * n);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->nn_nodes, 2 * m_quad);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->nn_val, 2 * n_val);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->R, n);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->seed0, n);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->seed1, n);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->cscale, n);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->r_tmp, m_rows);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->vseed0, n);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->vseed1, n);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->useed, m_quad);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->hadj_work, hilbert_adjoint_work_size(m_quad));
+    if (s == GN_OK) s = dev_alloc(h, A, &h->J, m_rows * h->ldJ);
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Bm, m_quad * h->ldJ);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->G, (P + 1) * h->ldG);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->partial, nparts * P);
+    if (s != GN_OK) {
+        free_list(A);
+        return s;
+    }
+    h->n_partial_cap = nparts;
+    hipStream_t st = h->stream;
+    if (d_rho) GN_HIP(h, hipMemcpyAsync(h->rho, d_rho, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    if (d_f) GN_HIP(h, hipMemcpyAsync(h->f, d_f, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    GN_HIP(h, launch_geometry(st, h->equation, h->lam, n, d_s, nullptr, h->pts));
+    if (m_quad > 0) {
+        GN_HIP(h, launch_geometry(st, h->equation, h->lam, m_quad, d_sq, d_wq, h->nodes));
+        GN_HIP(h, launch_hilbert_matrix(st, n, m_quad, h->pts.y, h->nodes.y, h->nodes.wh, h->Q, h->ldQ));
+    }
+    if (n_val > 0) GN_HIP(h, launch_geometry(st, h->equation, h->lam, n_val, d_sval, nullptr, h->val));
+    GN_HIP(h, hipStreamSynchronize(st));
+    h->n = n;
+    h->m = m_quad;
+    h->nv = n_val;
+    return GN_OK;
+}
+
+gn_status gn_residual(gn_handle h, const double *d_theta, double *d_r) {
+    if (!h || !d_theta || !d_r) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    GN_HIP(h, launch_reset_status(h->stream, h->status));
+    GN_TRY(forward_all(h, d_theta));
+    return residual_rows(h, d_r, 1, false);
+}
+
+gn_status gn_jacobian(gn_handle h, const double *d_theta, double *d_J, int64_t ldJ, double *d_r) {
+    if (!h || !d_theta || !d_J) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (ldJ < h->md.P) return fail(h, GN_EINVAL, "ldJ < P%s");
+    GN_HIP(h, launch_reset_status(h->stream, h->status));
+    return jacobian_into(h, d_theta, d_J, ldJ, d_r, 1);
+}
+
+gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t ldJ, const double *d_r,
+                  double *d_G, int64_t ldG, double *d_g) {
+    if (!h || !d_J || !d_G || m < 0 || p < 1) return GN_EINVAL;
+    if (ldJ < p || ldG < p) return fail(h, GN_EINVAL, "leading dimension smaller than p%s");
+    if (d_r && !d_g) return fail(h, GN_EINVAL, "d_g is required when d_r is given%s");
+    if (d_r && p > h->cap) return fail(h, GN_EINVAL, "p exceeds the gradient workspace (P + 1)%s");
+    GemmDesc g{};
+    g.M = p; g.N = p; g.K = m;
+    g.A = d_J; g.lda = ldJ; g.la = 1;
+    g.B = d_J; g.ldb = ldJ; g.lb = 0;
+    g.C = d_G; g.ldc = ldG;
+    g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
+    GN_HIP(h, launch_dgemm(h->stream, g));
+    if (d_r) GN_HIP(h, launch_gemv_t(h->stream, d_J, m, p, ldJ, d_r, d_g, h->gemv_work));
+    return GN_OK;
+}
+
+gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, const double *d_g,
+                   double *d_delta, int64_t *h_info) {
+    if (!h || !d_G || !d_g || !d_delta || p < 1) return GN_EINVAL;
+    if (ldG < p) return fail(h, GN_EINVAL, "ldG < p%s");
+    if (p > h->cap) return fail(h, GN_EINVAL, "p exceeds the solver workspace (P + 1)%s");
+    if (!(mu >= 0.0)) return fail(h, GN_EINVAL, "mu must be >= 0%s");
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_reset_status(st, h->status));
+    GN_HIP(h, launch_cholesky(st, d_G, p, ldG, mu, 0, h->linv, h->status));
+    GN_HIP(h, launch_copy_strided(st, d_g, p, 1, h->ybuf, 1, -1.0));
+    GN_HIP(h, launch_solve_lower(st, d_G, p, ldG, h->linv, h->ybuf, h->zbuf, h->status));
+    GN_HIP(h, launch_solve_upper(st, d_G, p, ldG, h->linv, h->zbuf, d_delta, h->status));
+    GN_HIP(h, launch_check_finite(st, d_delta, p, h->status));
+    DevStatus ds;
+    GN_TRY(read_status(h, &ds));
+    if (h_info) *h_info = ds.chol_info;
+    if (ds.flag) return fail(h, GN_ENOTPD, "Cholesky pivot %s is not positive", std::to_string(ds.chol_info).c_str());
+    if (ds.nonfinite) return fail(h, GN_ENONFINITE, "non-finite update%s");
+    return GN_OK;
+}
+
+gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
+    if (!h || !d_theta) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (!(mu >= 0.0)) return fail(h, GN_EINVAL, "mu must be >= 0%s");
+    hipStream_t st = h->stream;
+    const int64_t P = h->md.P, m_rows = h->n + 1;
+    double *J = h->J;
+    const int64_t ldJ = h->ldJ;
+    mark(h, 0);
+    GN_HIP(h, launch_reset_status(st, h->status));
+    // residual rows go to column P of J: the Gram of [J | r] then carries
+    // g = J^T r in its last row and r^T r in its corner
+    GN_TRY(forward_all(h, d_theta));
+    GN_TRY(residual_rows(h, J + P, ldJ, true));
+    GN_TRY(validation(h, d_theta));
+    mark(h, 1);
+    SweepBatch b{};
+    b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
+    GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, b));
+    SweepBatch o{};
+    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + h->n * ldJ; o.ld = ldJ;
+    GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, o));
+    if (h->equation == GN_EQ_CCF1D) {
+        SweepBatch nb{};
+        nb.x = h->nodes.q; nb.s0 = h->nodes.E; nb.s1c = 0.0; nb.n = h->m; nb.rows = h->Bm; nb.ld = ldJ;
+        GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, nb));
+    }
+    mark(h, 2);
+    if (h->equation == GN_EQ_CCF1D) {
+        GemmDesc c{};
+        c.M = h->n; c.N = P; c.K = h->m;
+        c.A = h->Q; c.lda = h->ldQ; c.la = 0;
+        c.B = h->Bm; c.ldb = ldJ; c.lb = 0;
+        c.C = J; c.ldc = ldJ;
+        c.alpha = 1.0; c.beta = 1.0; c.rowscale = h->cscale;
+        GN_HIP(h, launch_dgemm(st, c));
+    }
+    mark(h, 3);
+    GemmDesc g{};
+    g.M = P + 1; g.N = P + 1; g.K = m_rows;
+    g.A = J; g.lda = ldJ; g.la = 1;
+    g.B = J; g.ldb = ldJ; g.lb = 0;
+    g.C = h->G; g.ldc = h->ldG;
+    g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
+    GN_HIP(h, launch_dgemm(st, g));
+    GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
+    mark(h, 4);
+    // Cholesky of [[G + mu I, g], [g^T, r^T r]]: last row = (L^{-1} g)^T, Schur complement
+    GN_HIP(h, launch_cholesky(st, h->G, P + 1, h->ldG, mu, 1, h->linv, h->status));
+    mark(h, 5);
+    double *w = h->G + P * h->ldG;
+    GN_HIP(h, launch_sumsq(st, w, P, 1, &h->status->grad_dot_delta, h->red_work));
+    GN_HIP(h, launch_copy_strided(st, w + P, 1, 1, &h->status->model_sq_norm, 1, 1.0));
+    GN_HIP(h, launch_copy_strided(st, w, P, 1, h->ybuf, 1, -1.0));
+    GN_HIP(h, launch_solve_upper(st, h->G, P, h->ldG, h->linv, h->ybuf, h->delta, h->status));
+    GN_HIP(h, launch_finalize_step(st, d_theta, h->delta, nullptr, P, 1, h->status));
+    mark(h, 6);
+    if (h->prof_count < h->prof_max) ++h->prof_count;
+    if (!h_stats) return GN_OK;
+    DevStatus ds;
+    GN_TRY(read_status(h, &ds));
+    memset(h_stats, 0, sizeof *h_stats);
+    h_stats->half_sq_norm = 0.5 * ds.half_sq_norm;
+    h_stats->max_abs_R = bits_to_double(ds.max_R);
+    h_stats->max_abs_R_val = bits_to_double(ds.max_R_val);
+    h_stats->grad_dot_delta = -ds.grad_dot_delta;
+    h_stats->model_sq_norm = ds.model_sq_norm;
+    h_stats->chol_info = ds.chol_info;
+    h_stats->updated = ds.updated;
+    gn_status s = GN_OK;
+    const bool r_finite = (ds.half_sq_norm - ds.half_sq_norm == 0.0);
+    if (!r_finite) s = GN_ENONFINITE;       // a non-finite residual is the root cause
+    else if (ds.flag) s = GN_ENOTPD;
+    else if (ds.nonfinite) s = GN_ENONFINITE;
+    h_stats->status = s;
+    if (s == GN_ENOTPD) return fail(h, s, "Cholesky pivot %s is not positive", std::to_string(ds.chol_info).c_str());
+    if (s == GN_ENONFINITE) return fail(h, s, "non-finite residual or update%s");
+    return GN_OK;
+}
+
+gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats) {
+    if (!h || !d_theta || !h_stats) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_reset_status(st, h->status));
+    GN_TRY(forward_all(h, d_theta));
+    GN_TRY(residual_rows(h, h->r_tmp, 1, false));
+    GN_HIP(h, launch_sumsq(st, h->r_tmp, h->n + 1, 1, &h->status->half_sq_norm, h->red_work));
+    GN_TRY(validation(h, d_theta));
+    DevStatus ds;
+    GN_TRY(read_status(h, &ds));
+    memset(h_stats, 0, sizeof *h_stats);
+    h_stats->half_sq_norm = 0.5 * ds.half_sq_norm;
+    h_stats->max_abs_R = bits_to_double(ds.max_R);
+    h_stats->max_abs_R_val = bits_to_double(ds.max_R_val);
+    return GN_OK;
+}
+
+gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *d_out) {
+    if (!h || !d_theta || !d_v || !d_out) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    hipStream_t st = h->stream;
+    const int64_t P = h->md.P;
+    GN_HIP(h, launch_reset_status(st, h->status));
+    GN_TRY(forward_all(h, d_theta));
+    GN_TRY(residual_rows(h, h->r_tmp, 1, true));
+    // collocation rows: seeds scaled by v_i
+    GN_HIP(h, launch_mul(st, d_v, h->seed0, h->vseed0, h->n, 1.0));
+    GN_HIP(h, launch_mul(st, d_v, h->seed1, h->vseed1, h->n, 1.0));
+    int64_t c0 = 0, c1 = 0, c2 = 0;
+    SweepBatch b{};
+    b.x = h->pts.q; b.s0 = h->vseed0; b.s1 = h->vseed1; b.n = h->n;
+    GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, b, h->partial, &c0));
+    // normalisation row: seed v_N sqrt(c_norm)
+    GN_HIP(h, launch_copy_strided(st, d_v + h->n, 1, 1, h->seed_one, 1, sqrt(h->c_norm)));
+    SweepBatch o{};
+    o.x = h->one_x; o.s0 = h->seed_one; o.s1c = 0.0; o.n = 1;
+    GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, o, h->partial + c0 * P, &c1));
+    if (h->equation == GN_EQ_CCF1D) {
+        // Hilbert coupling adjoint: node seeds E_j sum_i Q_ij v_i sc_i Theta_y,i
+        GN_HIP(h, launch_hilbert_adjoint(st, h->n, h->m, h->Q, h->ldQ, d_v, h->cscale, h->nodes.E, h->useed,
+                                         h->hadj_work));
+        SweepBatch nb{};
+        nb.x = h->nodes.q; nb.s0 = h->useed; nb.s1c = 0.0; nb.n = h->m;
+        GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, nb, h->partial + (c0 + c1) * P, &c2));
+    }
+    GN_HIP(h, launch_reduce_partials(st, h->partial, c0 + c1 + c2, P, d_out, 0));
+    return GN_OK;
+}
+
+gn_status gn_profile_enable(gn_handle h, int32_t enable, int32_t max_steps) {
+    if (!h) return GN_EINVAL;
+    GN_HIP(h, hipStreamSynchronize(h->stream));
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+    h->prof_max = h->prof_count = 0;
+    if (!enable) return GN_OK;
+    if (max_steps < 1) return fail(h, GN_EINVAL, "max_steps must be >= 1%s");
+    h->events.resize((size_t)max_steps * (GN_PHASE_COUNT + 1));
+    for (auto &e : h->events) GN_HIP(h, hipEventCreate(&e));
+    h->prof_max = max_steps;
+    return GN_OK;
+}
+
+gn_status gn_profile_read(gn_handle h, double *h_ms, int32_t n_phases, int32_t *n_steps) {
+    if (!h || !h_ms || n_phases < 0 || n_phases > GN_PHASE_COUNT) return GN_EINVAL;
+    GN_HIP(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < n_phases; ++k) h_ms[k] = 0.0;
+    for (int32_t s = 0; s < h->prof_count; ++s) {
+        hipEvent_t *ev = &h->events[(size_t)s * (GN_PHASE_COUNT + 1)];
+        for (int k = 0; k < n_phases; ++k) {
+            float ms = 0.f;
+            GN_HIP(h, hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            h_ms[k] += ms;
+        }
+    }
+    if (n_steps) *n_steps = h->prof_count;
+    return GN_OK;
+}
+
+}  // extern "C"

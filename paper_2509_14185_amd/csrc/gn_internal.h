@@ -1,0 +1,167 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer of the
+// gfx950 damped Gauss-Newton library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gn.h"
+
+namespace gn {
+
+// Network shape passed by value to kernels.  theta layout per affine layer
+// l: W^l row-major (w[l+1] x w[l]) then b^l; off[l] is the offset of W^l.
+struct MlpDesc {
+    int L;                       // affine layers
+    int w[GN_MAX_LAYERS + 1];    // widths, w[0] = input dim, w[L] = outputs
+    int off[GN_MAX_LAYERS];      // offset of W^l in theta
+    int P;                       // number of parameters
+};
+
+// Geometry of one point set (structure of arrays, length n each).
+struct Geo1D {
+    double *y;    // self-similar coordinate y >= 0
+    double *q;    // network input q = 1 - s
+    double *E;    // envelope E(y)
+    double *Ey;   // dE/dy
+    double *qy;   // dq/dy
+    double *wh;   // Hilbert node weight (quadrature nodes only), else null
+};
+
+// One batch of points swept through the network.
+//   x: network inputs; s0/s1: seeds on NN and NN_x (null -> constants
+//   s0c/s1c); rows: output (row i at rows + i*ld) in the row mode;
+//   partial: per-workgroup gradient partials (P each) in the VJP mode.
+struct SweepBatch {
+    const double *x;
+    const double *s0;
+    const double *s1;
+    double s0c, s1c;
+    int64_t n;
+    double *rows;
+    int64_t ld;
+    double *nn;    // forward outputs (2n: NN then NN_x), forward mode only
+};
+
+// Device-side status shared by the kernels of one step.
+struct DevStatus {
+    unsigned long long max_R;      // bit pattern of max |R| (collocation); non-negative doubles order as integers
+    unsigned long long max_R_val;  // same, validation grid
+    int64_t chol_info;             // 0 or 1-based first bad pivot
+    int32_t flag;                  // nonzero: stop (factorisation failed)
+    int32_t nonfinite;             // nonzero: non-finite update found
+    int32_t updated;
+    int32_t pad;
+    double half_sq_norm;
+    double grad_dot_delta;
+    double model_sq_norm;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return hipGetLastError().
+
+// Geometry of points s (mapped coordinate); nodes additionally get the
+// Hilbert weights from quadrature weights ws.
+hipError_t launch_geometry(hipStream_t st, int equation, double lam, int64_t n, const double *s,
+                           const double *ws, Geo1D g);
+// Q[i][j] (n x m, ld) of the half-line Hilbert quadrature.
+hipError_t launch_hilbert_matrix(hipStream_t st, int64_t n, int64_t m, const double *y,
+                                 const double *t, const double *wh, double *Q, int64_t ld);
+
+// Network sweeps.  thetaT holds the per-layer transposed weights written by
+// launch_transpose_weights for the same theta (P doubles).
+hipError_t launch_transpose_weights(hipStream_t st, const MlpDesc &d, const double *theta, double *thetaT);
+size_t mlp_sweep_lds_bytes(const MlpDesc &d);
+hipError_t launch_mlp_forward(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                              SweepBatch b);
+hipError_t launch_mlp_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                           SweepBatch b);
+// VJP: writes ceil(n / tile) partial gradients (P each) to `partial`;
+// returns the number of partials via *n_partials.
+hipError_t launch_mlp_vjp(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                          SweepBatch b, double *partial, int64_t *n_partials);
+int64_t mlp_vjp_partials(const MlpDesc &d, int64_t n);
+
+// Residual of the collocation points (train=1: writes r, seeds, Theta_y
+// scale; train=0: R only and the validation max).
+struct ResidualArgs {
+    int equation;
+    double lam;
+    int64_t n, m;            // points, Hilbert nodes
+    Geo1D pts;
+    Geo1D nodes;
+    const double *nn;        // NN then NN_x at the points (2n)
+    const double *nn_nodes;  // NN at the nodes (first m entries of 2m)
+    const double *rho, *f;   // may be null
+    double inv_n;            // 1/N (row scale uses rho/N)
+    double *R;               // raw residual (n), may be null
+    double *r;               // scaled residual rows (n), may be null
+    int64_t r_stride;        // stride of r (1, or ldJ when written into a J column)
+    double *seed0, *seed1;   // Jacobian seeds on NN, NN_x (scaled), may be null
+    double *cscale;          // sc_i * Theta_y,i (row scale of the Hilbert coupling), may be null
+    unsigned long long *max_out;  // max |R| (bit pattern)
+};
+hipError_t launch_residual(hipStream_t st, const ResidualArgs &a);
+// Normalisation row: r = sqrt(c) (NN(1) - target), written to r_out.
+hipError_t launch_norm_row(hipStream_t st, const double *nn1, double sqrt_c, double target,
+                           double *r_out);
+// Node seeds for the coupling adjoint: out_j = E_j * (Q^T w)_j, w_i = v_i cscale_i.
+// work holds hilbert_adjoint_work_size(m) doubles.
+int64_t hilbert_adjoint_work_size(int64_t m);
+hipError_t launch_hilbert_adjoint(hipStream_t st, int64_t n, int64_t m, const double *Q, int64_t ldq,
+                                  const double *v, const double *cscale, const double *E_nodes,
+                                  double *out, double *work);
+
+// Generic FP64 MFMA GEMM: C = beta C + alpha diag(rowscale) op(A) op(B).
+// la: 0 = A(m,k) at A[m*lda+k], 1 = A(m,k) at A[k*lda+m].
+// lb: 0 = B(k,n) at B[k*ldb+n], 1 = B(k,n) at B[n*ldb+k].
+// lower: only C entries with n <= m are written (tiles above skipped).
+struct GemmDesc {
+    int64_t M, N, K;
+    const double *A; int64_t lda; int la;
+    const double *B; int64_t ldb; int lb;
+    double *C; int64_t ldc;
+    double alpha, beta;
+    const double *rowscale;
+    int lower;
+    const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
+};
+hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
+
+// g = J^T r (J m x p row-major) via deterministic two-pass reduction;
+// work must hold gemv_t_work_size(m, p) doubles.
+int64_t gemv_t_work_size(int64_t m, int64_t p);
+hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj,
+                         const double *r, double *g, double *work);
+
+// Blocked Cholesky of the lower triangle of A (n x n) after adding mu to the
+// first n - border diagonal entries.  border = 1: the last row is a border
+// row whose final diagonal entry receives the Schur complement (no sqrt).
+// linv receives the inverses of the 64x64 diagonal blocks.
+int64_t chol_linv_size(int64_t n);
+hipError_t launch_cholesky(hipStream_t st, double *A, int64_t n, int64_t lda, double mu, int border,
+                           double *linv, DevStatus *status);
+// L z = b (forward), then L^T x = z (back), using the factor and the
+// diagonal-block inverses from launch_cholesky.  b is overwritten.
+hipError_t launch_solve_lower(hipStream_t st, const double *L, int64_t n, int64_t ldl,
+                              const double *linv, double *b, double *z, DevStatus *status);
+hipError_t launch_solve_upper(hipStream_t st, const double *L, int64_t n, int64_t ldl,
+                              const double *linv, double *y, double *x, DevStatus *status);
+
+// Small kernels.
+hipError_t launch_sumsq(hipStream_t st, const double *x, int64_t n, int64_t stride, double *out,
+                        double *work);
+hipError_t launch_finalize_step(hipStream_t st, double *theta, const double *delta,
+                                const double *grad, int64_t p, int apply, DevStatus *status);
+hipError_t launch_check_finite(hipStream_t st, const double *x, int64_t n, DevStatus *status);
+hipError_t launch_reduce_partials(hipStream_t st, const double *partial, int64_t count, int64_t p,
+                                  double *out, int accumulate);
+hipError_t launch_copy_strided(hipStream_t st, const double *src, int64_t n, int64_t src_stride,
+                               double *dst, int64_t dst_stride, double scale);
+
+}  // namespace gn
+
+namespace gn {
+hipError_t launch_reset_status(hipStream_t st, DevStatus *s);
+hipError_t launch_mul(hipStream_t st, const double *a, const double *b, double *out, int64_t n, double scale);
+}  // namespace gn

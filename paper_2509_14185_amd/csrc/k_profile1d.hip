@@ -1,0 +1,487 @@
+// 1D self-similar profile kernels for gfx950: geometry of the compactified
+// coordinate, the half-line Hilbert quadrature, tanh-MLP sweeps (forward
+// jets, Jacobian rows, vector-Jacobian product) and the residual rows.
+//
+// Paper (arXiv 2509.14185), Methods:
+//  - "Solution Modeling and Equation Factorisation": q = (1+|y|^2)^{-1/(2(1+l))}
+//    as network input; the field is an envelope times the network output;
+//    tanh MLP.
+//  - "Self-similar Solutions": static profile equation in y.
+//  - "Training Loss": rows weighted by sqrt(rho/(N N_E)).
+//
+// Equation (CCF under the self-similar ansatz):
+//   R = -lam Theta + ((1+lam) y + U) Theta_y,  U = H Theta,
+//   Theta = E(y) NN(q),  Theta_y = E_y NN + E q_y NN_q.
+// In terms of q = 1 - s (1 + y^2 = q^{-2(1+lam)}):
+//   y^2 = expm1(-2(1+lam) log1p(-s)),  q_y = -y q^{3+2 lam}/(1+lam),
+//   CCF envelope E = y^2/(1+y^2) q^{-lam} = y^2 q^{2+lam},
+//       E_y = y/(1+lam) (lam q^{2+lam} + (2+lam) q^{4+3 lam}),
+//   local (Burgers) envelope E = y/sqrt(1+y^2) q^{-lam} = y q,
+//       E_y = q + y q_y.
+// Hilbert term on the half line for an even field:
+//   U_i = sum_j Q_ij (Theta(t_j) - Theta(y_i)),
+//   Q_ij = wh_j 2 y_i / ((y_i - t_j)(y_i + t_j)),  wh_j = ws_j (dt/ds)_j / pi,
+//   dt/ds = (1+lam)(1+t^2)/(q t).
+#include "gn_internal.h"
+
+namespace gn {
+
+static constexpr int SWEEP_THREADS = 256;
+static constexpr int SWEEP_TILE = 8;  // points per workgroup
+
+__device__ __forceinline__ double hilbert_q(double yi, double tj, double whj) {
+    return whj * (2.0 * yi) / ((yi - tj) * (yi + tj));
+}
+
+// ------------------------------------------------------------------ geometry
+__global__ void geometry_kernel(int equation, double lam, int64_t n, const double *__restrict__ s,
+                                const double *__restrict__ ws, Geo1D g) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double si = s[i];
+    const double q = 1.0 - si;
+    const double y2 = expm1(-2.0 * (1.0 + lam) * log1p(-si));
+    const double y = sqrt(y2);
+    const double qy = -y * pow(q, 3.0 + 2.0 * lam) / (1.0 + lam);
+    double E, Ey;
+    if (equation == GN_EQ_CCF1D) {
+        const double a = pow(q, 2.0 + lam);
+        E = y2 * a;
+        Ey = y / (1.0 + lam) * (lam * a + (2.0 + lam) * pow(q, 4.0 + 3.0 * lam));
+    } else {
+        E = y * q;
+        Ey = q + y * qy;
+    }
+    g.y[i] = y;
+    g.q[i] = q;
+    g.E[i] = E;
+    g.Ey[i] = Ey;
+    g.qy[i] = qy;
+    if (ws != nullptr && g.wh != nullptr) {
+        const double dtds = (1.0 + lam) * (1.0 + y2) / (q * y);
+        g.wh[i] = ws[i] * dtds / M_PI;
+    }
+}
+
+hipError_t launch_geometry(hipStream_t st, int equation, double lam, int64_t n, const double *s,
+                           const double *ws, Geo1D g) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)blocks), dim3(256), 0, st, equation, lam, n, s,
+                       ws, g);
+    return hipGetLastError();
+}
+
+__global__ void hilbert_matrix_kernel(int64_t n, int64_t m, const double *__restrict__ y,
+                                      const double *__restrict__ t, const double *__restrict__ wh,
+                                      double *__restrict__ Q, int64_t ld) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    Q[i * ld + j] = hilbert_q(y[i], t[j], wh[j]);
+}
+
+hipError_t launch_hilbert_matrix(hipStream_t st, int64_t n, int64_t m, const double *y, const double *t,
+                                 const double *wh, double *Q, int64_t ld) {
+    if (n <= 0 || m <= 0) return hipSuccess;
+    dim3 grid((unsigned)((m + 255) / 256), (unsigned)n);
+    hipLaunchKernelGGL(hilbert_matrix_kernel, grid, dim3(256), 0, st, n, m, y, t, wh, Q, ld);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ network sweeps
+// LDS layout per workgroup (T = SWEEP_TILE points):
+//   act: for each hidden layer input l = 1..L-1: Tl[T][w_l] (tanh values)
+//        then ZXl[T][w_l] (input-derivative pre-activations);
+//   cur: h/hx of the layer being computed in the forward pass (aliases act);
+//   zb0/zbx0, zb1/zbx1: adjoint buffers, T x maxw each.
+// Weights are read from global memory: row-major W for the adjoint (lanes
+// over the input index are contiguous) and the transposed copy Wt for the
+// forward pass (lanes over the output index are contiguous).
+enum SweepMode { SWEEP_FORWARD = 0, SWEEP_ROWS = 1, SWEEP_VJP = 2 };
+
+struct SweepLds {
+    int act_off[GN_MAX_LAYERS + 1];  // offset of T^l (l >= 1); ZX^l follows at + T*w_l
+    int zb_off;                       // start of the adjoint buffers
+    int maxw;
+    int total;                        // doubles
+};
+
+static SweepLds sweep_lds_layout(const MlpDesc &d) {
+    SweepLds s{};
+    int o = 0, maxw = 1;
+    for (int l = 1; l < d.L; ++l) {
+        s.act_off[l] = o;
+        o += 2 * SWEEP_TILE * d.w[l];
+        if (d.w[l] > maxw) maxw = d.w[l];
+    }
+    s.zb_off = o;
+    s.maxw = maxw;
+    s.total = o + 4 * SWEEP_TILE * maxw;
+    return s;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(SWEEP_THREADS) void mlp_sweep_kernel(MlpDesc d, SweepLds lay,
+                                                                  const double *__restrict__ theta,
+                                                                  const double *__restrict__ thetaT,
+                                                                  SweepBatch b, double *__restrict__ partial) {
+    extern __shared__ double sm[];
+    const int tid = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * SWEEP_TILE;
+    const int np = (int)((b.n - p0) < SWEEP_TILE ? (b.n - p0) : SWEEP_TILE);
+    if (np <= 0) return;
+    const int L = d.L;
+    double *zbA = sm + lay.zb_off;
+    double *zbxA = zbA + SWEEP_TILE * lay.maxw;
+    double *zbB = zbxA + SWEEP_TILE * lay.maxw;
+    double *zbxB = zbB + SWEEP_TILE * lay.maxw;
+
+    // ---------------- forward: hidden layers l = 0..L-2 produce T^{l+1}, ZX^{l+1}
+    for (int l = 0; l < L - 1; ++l) {
+        const int win = d.w[l], wout = d.w[l + 1];
+        const double *Wt = thetaT + d.off[l];     // Wt[j][k] = W[k][j], win x wout
+        const double *bias = theta + d.off[l] + win * wout;
+        double *Tn = sm + lay.act_off[l + 1];
+        double *ZXn = Tn + SWEEP_TILE * wout;
+        for (int idx = tid; idx < np * wout; idx += SWEEP_THREADS) {
+            const int pt = idx / wout, k = idx - pt * wout;
+            double z = bias[k], zx = 0.0;
+            if (l == 0) {
+                const double x = b.x[p0 + pt];
+                z = fma(Wt[k], x, z);
+                zx = Wt[k];
+            } else {
+                const double *Tp = sm + lay.act_off[l] + pt * win;
+                const double *ZXp = Tp + SWEEP_TILE * win;
+                for (int j = 0; j < win; ++j) {
+                    const double tj = Tp[j];
+                    const double hxj = (1.0 - tj * tj) * ZXp[j];
+                    const double w = Wt[j * wout + k];
+                    z = fma(w, tj, z);
+                    zx = fma(w, hxj, zx);
+                }
+            }
+            Tn[pt * wout + k] = tanh(z);
+            ZXn[pt * wout + k] = zx;
+        }
+        __syncthreads();
+    }
+
+    // ---------------- output layer (width 1): NN, NN_x
+    {
+        const int l = L - 1;
+        const int win = d.w[l];
+        const double *W = theta + d.off[l];  // 1 x win
+        const double bias = theta[d.off[l] + win];
+        // one wave per point: lanes over j, fixed-order butterfly reduction
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int pt = wave; pt < np; pt += SWEEP_THREADS / 64) {
+            double z = 0.0, zx = 0.0;
+            if (l == 0) {
+                if (lane == 0) {
+                    z = W[0] * b.x[p0 + pt];
+                    zx = W[0];
+                }
+            } else {
+                const double *Tp = sm + lay.act_off[l] + pt * win;
+                const double *ZXp = Tp + SWEEP_TILE * win;
+                for (int j = lane; j < win; j += 64) {
+                    const double tj = Tp[j];
+                    z = fma(W[j], tj, z);
+                    zx = fma(W[j], (1.0 - tj * tj) * ZXp[j], zx);
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                z += __shfl_xor(z, o, 64);
+                zx += __shfl_xor(zx, o, 64);
+            }
+            if (lane == 0) {
+                if (MODE == SWEEP_FORWARD) {
+                    b.nn[p0 + pt] = z + bias;
+                    b.nn[b.n + p0 + pt] = zx;
+                }
+                zbA[pt * lay.maxw] = b.s0 ? b.s0[p0 + pt] : b.s0c;
+                zbxA[pt * lay.maxw] = b.s1 ? b.s1[p0 + pt] : b.s1c;
+            }
+        }
+    }
+    if (MODE == SWEEP_FORWARD) return;
+    __syncthreads();
+
+    // ---------------- adjoint sweep, layer l = L-1 .. 0
+    double *zb = zbA, *zbx = zbxA, *zbn = zbB, *zbxn = zbxB;
+    const int ldz = lay.maxw;
+    for (int l = L - 1; l >= 0; --l) {
+        const int win = d.w[l], wout = d.w[l + 1];
+        const int nseg = wout * (win + 1);  // W^l then b^l
+        const double *Tp = (l > 0) ? sm + lay.act_off[l] : nullptr;
+        const double *ZXp = (l > 0) ? Tp + SWEEP_TILE * win : nullptr;
+        if (MODE == SWEEP_ROWS) {
+            for (int pt = 0; pt < np; ++pt) {
+                double *row = b.rows + (p0 + pt) * b.ld + d.off[l];
+                const double *zr = zb + pt * ldz;
+                const double *zxr = zbx + pt * ldz;
+                const double xin = (l == 0) ? b.x[p0 + pt] : 0.0;
+                for (int idx = tid; idx < nseg; idx += SWEEP_THREADS) {
+                    double v;
+                    if (idx < wout * win) {
+                        const int k = idx / win, j = idx - k * win;
+                        double h, hx;
+                        if (l == 0) {
+                            h = xin;
+                            hx = 1.0;
+                        } else {
+                            h = Tp[pt * win + j];
+                            hx = (1.0 - h * h) * ZXp[pt * win + j];
+                        }
+                        v = fma(zr[k], h, zxr[k] * hx);
+                    } else {
+                        v = zr[idx - wout * win];
+                    }
+                    row[idx] = v;
+                }
+            }
+        } else {  // SWEEP_VJP: sum over the points of this workgroup
+            double *out = partial + (int64_t)blockIdx.x * d.P + d.off[l];
+            for (int idx = tid; idx < nseg; idx += SWEEP_THREADS) {
+                double acc = 0.0;
+                if (idx < wout * win) {
+                    const int k = idx / win, j = idx - k * win;
+                    for (int pt = 0; pt < np; ++pt) {
+                        double h, hx;
+                        if (l == 0) {
+                            h = b.x[p0 + pt];
+                            hx = 1.0;
+                        } else {
+                            h = Tp[pt * win + j];
+                            hx = (1.0 - h * h) * ZXp[pt * win + j];
+                        }
+                        acc += fma(zb[pt * ldz + k], h, zbx[pt * ldz + k] * hx);
+                    }
+                } else {
+                    const int k = idx - wout * win;
+                    for (int pt = 0; pt < np; ++pt) acc += zb[pt * ldz + k];
+                }
+                out[idx] = acc;
+            }
+        }
+        if (l == 0) break;
+        // hbar = W^T zbar, hbar_x = W^T zbar_x; then through h = tanh(z),
+        // h_x = (1 - t^2) z_x:
+        //   zbar_x' = hbar_x (1 - t^2),  zbar' = hbar (1 - t^2) - 2 t (1 - t^2) z_x hbar_x.
+        const double *W = theta + d.off[l];  // wout x win
+        for (int idx = tid; idx < np * win; idx += SWEEP_THREADS) {
+            const int pt = idx / win, j = idx - pt * win;
+            double hb = 0.0, hbx = 0.0;
+            for (int k = 0; k < wout; ++k) {
+                const double w = W[k * win + j];
+                hb = fma(w, zb[pt * ldz + k], hb);
+                hbx = fma(w, zbx[pt * ldz + k], hbx);
+            }
+            const double t = Tp[pt * win + j];
+            const double dd = 1.0 - t * t;
+            const double zxv = ZXp[pt * win + j];
+            zbxn[pt * ldz + j] = hbx * dd;
+            zbn[pt * ldz + j] = hb * dd - 2.0 * t * dd * zxv * hbx;
+        }
+        __syncthreads();
+        double *tmp = zb;
+        zb = zbn;
+        zbn = tmp;
+        tmp = zbx;
+        zbx = zbxn;
+        zbxn = tmp;
+    }
+}
+
+// W^T per layer (same offsets as theta; biases copied).
+__global__ void transpose_weights_kernel(MlpDesc d, const double *__restrict__ theta, double *__restrict__ out) {
+    for (int l = 0; l < d.L; ++l) {
+        const int win = d.w[l], wout = d.w[l + 1];
+        const int nseg = wout * (win + 1);
+        for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nseg; idx += gridDim.x * blockDim.x) {
+            if (idx < wout * win) {
+                const int j = idx / wout, k = idx - j * wout;  // out[j][k] = W[k][j]
+                out[d.off[l] + idx] = theta[d.off[l] + k * win + j];
+            } else {
+                out[d.off[l] + idx] = theta[d.off[l] + idx];
+            }
+        }
+    }
+}
+
+template <int MODE>
+static hipError_t launch_sweep_mode(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                                    SweepBatch b, double *partial) {
+    SweepLds lay = sweep_lds_layout(d);
+    const size_t shm = sizeof(double) * (size_t)lay.total;
+    static bool attr_set = false;
+    if (!attr_set) {
+        // allow up to the full 160 KB of LDS of a gfx950 workgroup
+        hipFuncSetAttribute((const void *)mlp_sweep_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr_set = true;
+    }
+    const int64_t blocks = (b.n + SWEEP_TILE - 1) / SWEEP_TILE;
+    hipLaunchKernelGGL(mlp_sweep_kernel<MODE>, dim3((unsigned)blocks), dim3(SWEEP_THREADS), shm, st, d, lay, theta,
+                       thetaT, b, partial);
+    return hipGetLastError();
+}
+
+size_t mlp_sweep_lds_bytes(const MlpDesc &d) { return sizeof(double) * (size_t)sweep_lds_layout(d).total; }
+
+hipError_t launch_transpose_weights(hipStream_t st, const MlpDesc &d, const double *theta, double *thetaT) {
+    hipLaunchKernelGGL(transpose_weights_kernel, dim3(8), dim3(256), 0, st, d, theta, thetaT);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                              SweepBatch b) {
+    if (b.n <= 0) return hipSuccess;
+    return launch_sweep_mode<SWEEP_FORWARD>(st, d, theta, thetaT, b, nullptr);
+}
+hipError_t launch_mlp_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                           SweepBatch b) {
+    if (b.n <= 0) return hipSuccess;
+    return launch_sweep_mode<SWEEP_ROWS>(st, d, theta, thetaT, b, nullptr);
+}
+int64_t mlp_vjp_partials(const MlpDesc &, int64_t n) { return (n + SWEEP_TILE - 1) / SWEEP_TILE; }
+hipError_t launch_mlp_vjp(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                          SweepBatch b, double *partial, int64_t *n_partials) {
+    *n_partials = mlp_vjp_partials(d, b.n);
+    if (b.n <= 0) return hipSuccess;
+    return launch_sweep_mode<SWEEP_VJP>(st, d, theta, thetaT, b, partial);
+}
+
+// ------------------------------------------------------------------ residual
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double v) {
+    if (p == nullptr) return;
+    if (!(v == v)) v = __builtin_inf();  // NaN counts as +inf so it is visible
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+// One wave per point.  Lanes accumulate a fixed strided subset of the nodes
+// in order, then a fixed butterfly combines them: deterministic.
+__global__ __launch_bounds__(256) void ccf_residual_kernel(ResidualArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= a.n) return;
+    const double yi = a.pts.y[i];
+    const double Ei = a.pts.E[i];
+    const double NNi = a.nn[i];
+    const double Thi = Ei * NNi;
+    double U = 0.0, c = 0.0;
+    for (int64_t j = lane; j < a.m; j += 64) {
+        const double qij = hilbert_q(yi, a.nodes.y[j], a.nodes.wh[j]);
+        const double Thj = a.nodes.E[j] * a.nn_nodes[j];
+        U = fma(qij, Thj - Thi, U);
+        c += qij;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        U += __shfl_xor(U, o, 64);
+        c += __shfl_xor(c, o, 64);
+    }
+    if (lane != 0) return;
+    const double lam = a.lam;
+    const double NNq = a.nn[a.n + i];
+    const double Eyi = a.pts.Ey[i], qyi = a.pts.qy[i];
+    const double Thy = Eyi * NNi + Ei * qyi * NNq;
+    const double V = (1.0 + lam) * yi + U;
+    const double R = -lam * Thi + V * Thy;
+    if (a.R) a.R[i] = R;
+    atomic_max_nonneg(a.max_out, fabs(R));
+    if (a.r) {
+        const double sc = sqrt((a.rho ? a.rho[i] : 1.0) * a.inv_n);
+        a.r[i * a.r_stride] = sc * (R - (a.f ? a.f[i] : 0.0));
+        if (a.seed0) {
+            // dR/dNN_i (including U's dependence on Theta_i via -c_i E_i) and dR/dNN_q,i
+            a.seed0[i] = sc * (-lam * Ei + V * Eyi - Thy * c * Ei);
+            a.seed1[i] = sc * (V * Ei * qyi);
+        }
+        if (a.cscale) a.cscale[i] = sc * Thy;
+    }
+}
+
+// Local variant: R = -lam U + ((1+lam) y + U) U_y with U = Theta.
+__global__ void burgers_residual_kernel(ResidualArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double lam = a.lam;
+    const double yi = a.pts.y[i], Ei = a.pts.E[i], Eyi = a.pts.Ey[i], qyi = a.pts.qy[i];
+    const double NNi = a.nn[i], NNq = a.nn[a.n + i];
+    const double Th = Ei * NNi;
+    const double Thy = Eyi * NNi + Ei * qyi * NNq;
+    const double V = (1.0 + lam) * yi + Th;
+    const double R = -lam * Th + V * Thy;
+    if (a.R) a.R[i] = R;
+    atomic_max_nonneg(a.max_out, fabs(R));
+    if (a.r) {
+        const double sc = sqrt((a.rho ? a.rho[i] : 1.0) * a.inv_n);
+        a.r[i * a.r_stride] = sc * (R - (a.f ? a.f[i] : 0.0));
+        if (a.seed0) {
+            a.seed0[i] = sc * ((Thy - lam) * Ei + V * Eyi);
+            a.seed1[i] = sc * (V * Ei * qyi);
+        }
+        if (a.cscale) a.cscale[i] = 0.0;
+    }
+}
+
+hipError_t launch_residual(hipStream_t st, const ResidualArgs &a) {
+    if (a.n <= 0) return hipSuccess;
+    if (a.equation == GN_EQ_CCF1D) {
+        hipLaunchKernelGGL(ccf_residual_kernel, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(burgers_residual_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+__global__ void norm_row_kernel(const double *nn1, double sqrt_c, double target, double *r_out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) r_out[0] = sqrt_c * (nn1[0] - target);
+}
+
+hipError_t launch_norm_row(hipStream_t st, const double *nn1, double sqrt_c, double target, double *r_out) {
+    hipLaunchKernelGGL(norm_row_kernel, dim3(1), dim3(64), 0, st, nn1, sqrt_c, target, r_out);
+    return hipGetLastError();
+}
+
+// out_j = E_j sum_i Q_ij v_i cscale_i, two passes over row chunks.
+static constexpr int HADJ_CHUNKS = 64;
+
+__global__ void hilbert_adjoint_partial(int64_t n, int64_t m, const double *__restrict__ Q, int64_t ldq,
+                                        const double *__restrict__ v, const double *__restrict__ cs,
+                                        double *__restrict__ part) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int64_t per = (n + HADJ_CHUNKS - 1) / HADJ_CHUNKS;
+    const int64_t i0 = blockIdx.y * per;
+    const int64_t i1 = (i0 + per < n) ? i0 + per : n;
+    double acc = 0.0;
+    for (int64_t i = i0; i < i1; ++i) acc = fma(Q[i * ldq + j], v[i] * cs[i], acc);
+    part[blockIdx.y * m + j] = acc;
+}
+
+__global__ void hilbert_adjoint_final(int64_t m, const double *__restrict__ part, const double *__restrict__ E,
+                                      double *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double acc = 0.0;
+    for (int c = 0; c < HADJ_CHUNKS; ++c) acc += part[c * m + j];
+    out[j] = E[j] * acc;
+}
+
+int64_t hilbert_adjoint_work_size(int64_t m) { return (int64_t)HADJ_CHUNKS * m; }
+
+hipError_t launch_hilbert_adjoint(hipStream_t st, int64_t n, int64_t m, const double *Q, int64_t ldq,
+                                  const double *v, const double *cscale, const double *E_nodes, double *out,
+                                  double *part) {
+    if (m <= 0) return hipSuccess;
+    dim3 g1((unsigned)((m + 255) / 256), HADJ_CHUNKS);
+    hipLaunchKernelGGL(hilbert_adjoint_partial, g1, dim3(256), 0, st, n, m, Q, ldq, v, cscale, part);
+    hipLaunchKernelGGL(hilbert_adjoint_final, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, part,
+                       E_nodes, out);
+    return hipGetLastError();
+}
+
+}  // namespace gn

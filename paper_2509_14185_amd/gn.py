@@ -1,0 +1,264 @@
+"""Python binding of the gfx950 Gauss-Newton library (include/gn.h).
+
+Argument marshalling only: device buffers are torch tensors (PyTorch
+provides memory and streams); every arithmetic step runs in the HIP kernels
+of libgn.so.  There is no CPU fallback: if the library is not built, or no
+GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgn.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "gn.h")
+
+GN_OK, GN_ENOTPD, GN_EINVAL, GN_ENOMEM, GN_EDEVICE, GN_ENONFINITE, GN_ESTATE = 0, 1, -1, -2, -3, -4, -5
+EQUATIONS = {"ccf1d": 0, "burgers1d": 1}
+PRECISIONS = {"fp64": 0, "split32": 1}
+
+
+class GNError(RuntimeError):
+    def __init__(self, status: int, message: str, info: int = 0):
+        super().__init__(message)
+        self.status = status
+        self.info = info
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("equation", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_layers", ctypes.c_int32),
+                ("widths", ctypes.POINTER(ctypes.c_int32)), ("lam", ctypes.c_double),
+                ("c_norm", ctypes.c_double), ("c_target", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("half_sq_norm", ctypes.c_double), ("max_abs_R", ctypes.c_double),
+                ("max_abs_R_val", ctypes.c_double), ("grad_dot_delta", ctypes.c_double),
+                ("model_sq_norm", ctypes.c_double), ("chol_info", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("updated", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+
+def exported_names():
+    """Function names declared in include/gn.h."""
+    return re.findall(r"^\w[\w\s\*]*?\b(gn_\w+)\s*\(", open(HEADER).read(), flags=re.M)
+
+
+def load():
+    """Load libgn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2509_14185_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "gn_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+        "gn_last_error": (ctypes.c_char_p, [_VP]),
+        "gn_create": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_VP)]),
+        "gn_destroy": (ctypes.c_int, [_VP]),
+        "gn_set_stream": (ctypes.c_int, [_VP, _VP]),
+        "gn_set_points": (ctypes.c_int, [_VP, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _I64, _VP]),
+        "gn_num_params": (_I64, [_VP]),
+        "gn_num_rows": (_I64, [_VP]),
+        "gn_residual": (ctypes.c_int, [_VP, _VP, _VP]),
+        "gn_jacobian": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP]),
+        "gn_gram": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I64, _VP, _VP, _I64, _VP]),
+        "gn_solve": (ctypes.c_int, [_VP, _VP, _I64, _I64, _D, _VP, _VP, ctypes.POINTER(_I64)]),
+        "gn_step": (ctypes.c_int, [_VP, _VP, _D, ctypes.POINTER(_Stats)]),
+        "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
+        "gn_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+        "gn_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+        "gn_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(x, device):
+    """FP64 contiguous device tensor (copies numpy / host tensors)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+    return x.to(device=device, dtype=torch.float64).contiguous()
+
+
+class Problem:
+    """One profile problem bound to a gn handle on the current CUDA (HIP) device."""
+
+    def __init__(self, equation: str, widths, lam: float, c_norm: float = 1.0, c_target: float = 1.0,
+                 precision: str = "fp64", device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the gn library runs only on the GPU")
+        self.lib = load()
+        self.device = torch.device(device)
+        self.widths = [int(w) for w in widths]
+        self._w = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        prob = _Problem(EQUATIONS[equation], PRECISIONS[precision], len(self.widths) - 1, self._w,
+                        float(lam), float(c_norm), float(c_target))
+        h = _VP()
+        with torch.cuda.device(self.device):
+            st = self.lib.gn_create(ctypes.byref(prob), ctypes.byref(h))
+        if st != GN_OK:
+            raise GNError(st, f"gn_create failed: {self.lib.gn_status_string(st).decode()}")
+        self.h = h
+        self.P = int(self.lib.gn_num_params(h))
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def _bind(self):
+        self.lib.gn_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _check(self, st, what, info=0):
+        if st != GN_OK:
+            msg = self.lib.gn_last_error(self.h).decode()
+            raise GNError(st, f"{what}: {self.lib.gn_status_string(st).decode()} ({msg})", info)
+
+    @property
+    def m(self) -> int:
+        return int(self.lib.gn_num_rows(self.h))
+
+    # ------------------------------------------------------------ ABI calls
+    def set_points(self, s, rho=None, f=None, sq=None, wq=None, sval=None):
+        self._bind()
+        s, rho, f, sq, wq, sval = (_dev(x, self.device) for x in (s, rho, f, sq, wq, sval))
+        n = s.numel()
+        mq = 0 if sq is None else sq.numel()
+        nv = 0 if sval is None else sval.numel()
+        st = self.lib.gn_set_points(self.h, n, _ptr(s), _ptr(rho), _ptr(f), mq, _ptr(sq), _ptr(wq), nv, _ptr(sval))
+        self._check(st, "gn_set_points")
+        self.n = n
+
+    def residual(self, theta, out=None):
+        self._bind()
+        r = out if out is not None else torch.empty(self.m, dtype=torch.float64, device=self.device)
+        self._check(self.lib.gn_residual(self.h, _ptr(theta), _ptr(r)), "gn_residual")
+        return r
+
+    def jacobian(self, theta, ld=None, with_r=True):
+        self._bind()
+        ld = self.P if ld is None else ld
+        J = torch.empty((self.m, ld), dtype=torch.float64, device=self.device)
+        r = torch.empty(self.m, dtype=torch.float64, device=self.device) if with_r else None
+        self._check(self.lib.gn_jacobian(self.h, _ptr(theta), _ptr(J), ld, _ptr(r)), "gn_jacobian")
+        return J[:, :self.P], r
+
+    def gram(self, J, r=None, ldG=None):
+        """Lower triangle of J^T J (upper triangle left zero) and J^T r."""
+        self._bind()
+        m, p = J.shape
+        ldJ = J.stride(0)
+        assert J.stride(1) == 1 and J.dtype == torch.float64
+        ldG = p if ldG is None else ldG
+        G = torch.zeros((p, ldG), dtype=torch.float64, device=self.device)
+        g = torch.empty(p, dtype=torch.float64, device=self.device) if r is not None else None
+        st = self.lib.gn_gram(self.h, _ptr(J), m, p, ldJ, _ptr(r), _ptr(G), ldG, _ptr(g))
+        self._check(st, "gn_gram")
+        return G[:, :p], g
+
+    def solve(self, G, mu, g):
+        """(G + mu I) delta = -g; G (lower triangle used) is overwritten by L."""
+        self._bind()
+        p = G.shape[0]
+        assert G.stride(1) == 1
+        delta = torch.empty(p, dtype=torch.float64, device=self.device)
+        info = _I64(0)
+        st = self.lib.gn_solve(self.h, _ptr(G), p, G.stride(0), float(mu), _ptr(g), _ptr(delta), ctypes.byref(info))
+        self._check(st, "gn_solve", info.value)
+        return delta, int(info.value)
+
+    def step(self, theta, mu, stats=True):
+        self._bind()
+        s = _Stats()
+        st = self.lib.gn_step(self.h, _ptr(theta), float(mu), ctypes.byref(s) if stats else None)
+        if stats:
+            d = s.as_dict()
+            d["rc"] = st
+            return d
+        self._check(st, "gn_step")
+        return None
+
+    def eval(self, theta):
+        self._bind()
+        s = _Stats()
+        self._check(self.lib.gn_eval(self.h, _ptr(theta), ctypes.byref(s)), "gn_eval")
+        return s.as_dict()
+
+    def vjp(self, theta, v):
+        self._bind()
+        out = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        self._check(self.lib.gn_vjp(self.h, _ptr(theta), _ptr(v.contiguous()), _ptr(out)), "gn_vjp")
+        return out
+
+
+PHASES = ["forward", "jacobian_local", "coupling", "gram", "cholesky", "solve"]
+
+
+def _profile_methods():
+    def profile_enable(self, enable=True, max_steps=1024):
+        self._bind()
+        self._check(self.lib.gn_profile_enable(self.h, int(bool(enable)), int(max_steps)), "gn_profile_enable")
+
+    def profile_read(self):
+        ms = (ctypes.c_double * len(PHASES))()
+        n = ctypes.c_int32(0)
+        self._check(self.lib.gn_profile_read(self.h, ms, len(PHASES), ctypes.byref(n)), "gn_profile_read")
+        return {k: ms[i] for i, k in enumerate(PHASES)}, int(n.value)
+
+    return profile_enable, profile_read
+
+
+Problem.profile_enable, Problem.profile_read = _profile_methods()
+
+
+class ResidualFunction(torch.autograd.Function):
+    """r(theta) with backward J^T grad_r; activations are recomputed in backward."""
+
+    @staticmethod
+    def forward(ctx, theta, problem):
+        ctx.problem = problem
+        ctx.save_for_backward(theta)
+        return problem.residual(theta.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_r):
+        (theta,) = ctx.saved_tensors
+        return ctx.problem.vjp(theta.detach().contiguous(), grad_r.to(torch.float64)), None
+
+
+def residual(theta, problem):
+    return ResidualFunction.apply(theta, problem)
