@@ -89,7 +89,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ccf_medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU row sharding of the "
                                    "Gram is designed but not built (see DESIGN.md)", "n_gpus": args.gpus}))
@@ -163,7 +176,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gram (dgemm_mfma_kernel<128,128,16,1,0>)",
+            "kernel": "gram (dgemm_mfma_kernel<128,128,32,1,0>)",
             "achieved": gram_tf,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",

@@ -26,7 +26,7 @@ struct gn_context {
     // P-dependent workspace (gn_create)
     int64_t cap = 0;                  // largest p accepted by gn_gram/gn_solve work buffers (P + 1)
     double *thetaT = nullptr, *linv = nullptr, *ybuf = nullptr, *zbuf = nullptr, *delta = nullptr;
-    double *gemv_work = nullptr, *red_work = nullptr, *one_x = nullptr, *nn_one = nullptr, *seed_one = nullptr;
+    double *gemv_work = nullptr, *red_work = nullptr, *chol_tmp = nullptr, *one_x = nullptr, *nn_one = nullptr, *seed_one = nullptr;
     DevStatus *status = nullptr;
     // point-set data (gn_set_points)
     int64_t n = 0, m = 0, nv = 0;
@@ -242,6 +242,7 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->delta, h->cap);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gemv_work, gemv_t_work_size(0, h->cap));
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->red_work, 1024);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->chol_tmp, chol_tmp_size());
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->one_x, 1);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->nn_one, 2);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->seed_one, 1);
@@ -396,7 +397,7 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, 
     if (!(mu >= 0.0)) return fail(h, GN_EINVAL, "mu must be >= 0%s");
     hipStream_t st = h->stream;
     GN_HIP(h, launch_reset_status(st, h->status));
-    GN_HIP(h, launch_cholesky(st, d_G, p, ldG, mu, 0, h->linv, h->status));
+    GN_HIP(h, launch_cholesky(st, d_G, p, ldG, mu, 0, h->linv, h->chol_tmp, h->status));
     GN_HIP(h, launch_copy_strided(st, d_g, p, 1, h->ybuf, 1, -1.0));
     GN_HIP(h, launch_solve_lower(st, d_G, p, ldG, h->linv, h->ybuf, h->zbuf, h->status));
     GN_HIP(h, launch_solve_upper(st, d_G, p, ldG, h->linv, h->zbuf, d_delta, h->status));
@@ -457,7 +458,7 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
     GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     mark(h, 4);
     // Cholesky of [[G + mu I, g], [g^T, r^T r]]: last row = (L^{-1} g)^T, Schur complement
-    GN_HIP(h, launch_cholesky(st, h->G, P + 1, h->ldG, mu, 1, h->linv, h->status));
+    GN_HIP(h, launch_cholesky(st, h->G, P + 1, h->ldG, mu, 1, h->linv, h->chol_tmp, h->status));
     mark(h, 5);
     double *w = h->G + P * h->ldG;
     GN_HIP(h, launch_sumsq(st, w, P, 1, &h->status->grad_dot_delta, h->red_work));

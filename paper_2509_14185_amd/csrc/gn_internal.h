@@ -137,10 +137,12 @@ hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, 
 // Blocked Cholesky of the lower triangle of A (n x n) after adding mu to the
 // first n - border diagonal entries.  border = 1: the last row is a border
 // row whose final diagonal entry receives the Schur complement (no sqrt).
-// linv receives the inverses of the 64x64 diagonal blocks.
+// linv receives the inverses of the 128x128 diagonal blocks; tmp holds
+// chol_tmp_size() doubles of scratch.
 int64_t chol_linv_size(int64_t n);
+int64_t chol_tmp_size();
 hipError_t launch_cholesky(hipStream_t st, double *A, int64_t n, int64_t lda, double mu, int border,
-                           double *linv, DevStatus *status);
+                           double *linv, double *tmp, DevStatus *status);
 // L z = b (forward), then L^T x = z (back), using the factor and the
 // diagonal-block inverses from launch_cholesky.  b is overwritten.
 hipError_t launch_solve_lower(hipStream_t st, const double *L, int64_t n, int64_t ldl,

@@ -7,13 +7,15 @@
 //
 // C[m][n] = beta C[m][n] + alpha * rowscale[m] * sum_k A(m,k) B(k,n)
 //
-// Tiling: a 256-thread workgroup (4 waves, 2 x 2) owns a BM x BN tile of C;
-// each wave owns (BM/2) x (BN/2) as 16x16 MFMA blocks held in registers.
-// K is consumed in chunks of BK staged through double-buffered LDS in a
+// Tiling: a 512-thread workgroup (8 waves, 2 x 4, two per SIMD so one wave's
+// memory waits overlap the other's MFMAs) owns a BM x BN tile of C; each wave
+// owns (BM/2) x (BN/4) as 16x16 MFMA blocks held in registers.
+// K is consumed in chunks of BK = 32 staged through double-buffered LDS in a
 // k-major layout ([k][m], [k][n]) so that an MFMA fragment (16 consecutive m
 // or n for each of 4 k) is one contiguous LDS row segment.  Global loads for
-// chunk c+1 are issued before the MFMAs of chunk c.  Both operand layouts
-// (contiguous in m/n or contiguous in k) are read with unit-stride runs.
+// chunk c+1 (16-byte pairs along the operand's contiguous direction, no
+// bounds checks for interior tiles) are issued before the MFMAs of chunk c.
+// Tiles are grouped in 4 x 8 super-tiles, one per XCD at a time (L2 reuse).
 //
 // Fragment layout of v_mfma_f64_16x16x4_f64 (wave64):
 //   A (16x4):  lane l holds A[l%16][l/16]
@@ -26,39 +28,139 @@ namespace gn {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-static constexpr int GEMM_THREADS = 256;
+static constexpr int GEMM_THREADS = 512;  // 8 waves: two per SIMD
+static constexpr int SUP_M = 4, SUP_N = 8;   // tiles per super-tile (one XCD round)
+static constexpr int SUP = SUP_M * SUP_N;
+static constexpr int NXCD = 8;
+
+// Tile order.  Workgroups are dispatched round-robin over the 8 XCDs and each
+// XCD runs its share in order, 32 at a time (one per CU).  Block b is sent to
+// super-tile s = (pos / 32) * 8 + xcd (pos = b / 8, xcd = b % 8), tile
+// i = pos % 32 of it, so each XCD works on one compact 4 x 8 block of tiles at
+// a time and its L2 serves 12 operand panels instead of up to 33.
+// Lower-triangular GEMMs enumerate only super-tiles that touch the lower
+// triangle (row a of super-tiles holds b = 0 .. (4a+3)/8).
+__host__ __device__ inline int64_t lower_super_count(int64_t tiles) {
+    const int64_t nsr = (tiles + SUP_M - 1) / SUP_M, nsc = (tiles + SUP_N - 1) / SUP_N;
+    int64_t n = 0;
+    for (int64_t a = 0; a < nsr; ++a) {
+        int64_t c = (SUP_M * a + SUP_M - 1) / SUP_N + 1;
+        n += c < nsc ? c : nsc;
+    }
+    return n;
+}
+
+// Returns false for padding blocks and tiles outside the (lower) tile set.
+__device__ __forceinline__ bool tile_of_block(int64_t b, int lower, int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int64_t x = b % NXCD, pos = b / NXCD;
+    const int64_t sidx = (pos / SUP) * NXCD + x;
+    const int i = (int)(pos % SUP);
+    int64_t sm, sn;
+    if (lower) {
+        const int64_t nsr = (tiles_m + SUP_M - 1) / SUP_M, nsc = (tiles_m + SUP_N - 1) / SUP_N;
+        int64_t rem = sidx, a = 0;
+        for (; a < nsr; ++a) {
+            int64_t c = (SUP_M * a + SUP_M - 1) / SUP_N + 1;
+            if (c > nsc) c = nsc;
+            if (rem < c) break;
+            rem -= c;
+        }
+        if (a >= nsr) return false;
+        sm = a;
+        sn = rem;
+    } else {
+        const int64_t nsm = (tiles_m + SUP_M - 1) / SUP_M, nsn = (tiles_n + SUP_N - 1) / SUP_N;
+        if (sidx >= nsm * nsn) return false;
+        sm = sidx % nsm;
+        sn = sidx / nsm;
+    }
+    tm = (int)(sm * SUP_M + i % SUP_M);
+    tn = (int)(sn * SUP_N + i / SUP_M);
+    if (tm >= tiles_m || tn >= tiles_n) return false;
+    if (lower && tn > tm) return false;
+    return true;
+}
+
+// One operand tile (rows x cols of the tile in (m or n, k) space) is loaded
+// as 16-byte pairs along the operand's contiguous direction.
+//   CONTIG_MN: element (r, k) at base[k*ld + r] (pairs along r)
+//   else:      element (r, k) at base[r*ld + k] (pairs along k)
+template <int R, int BK, bool CONTIG_MN>
+struct TileLoader {
+    static constexpr int PAIRS = R * BK / 2;
+    static constexpr int PER = PAIRS / GEMM_THREADS;
+    static_assert(PER * GEMM_THREADS == PAIRS, "tile split");
+    double2 v[PER];
+
+    __device__ __forceinline__ static void coords(int e, int &r, int &k) {
+        const int idx = threadIdx.x + e * GEMM_THREADS;
+        if (CONTIG_MN) { r = 2 * (idx % (R / 2)); k = idx / (R / 2); }
+        else           { k = 2 * (idx % (BK / 2)); r = idx / (BK / 2); }
+    }
+    // full: the whole tile lies inside [0,rmax) x [0,kmax) and pairs are aligned
+    __device__ __forceinline__ void load(const double *base, int64_t ld, int64_t r0, int64_t k0, int64_t rmax,
+                                         int64_t kmax, bool full) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int r, k;
+            coords(e, r, k);
+            const int64_t gr = r0 + r, gk = k0 + k;
+            if (full) {
+                const double *p = CONTIG_MN ? base + gk * ld + gr : base + gr * ld + gk;
+                v[e] = *reinterpret_cast<const double2 *>(p);
+            } else {
+                double a = 0.0, b = 0.0;
+                if (CONTIG_MN) {
+                    if (gk < kmax) {
+                        if (gr < rmax) a = base[gk * ld + gr];
+                        if (gr + 1 < rmax) b = base[gk * ld + gr + 1];
+                    }
+                } else {
+                    if (gr < rmax) {
+                        if (gk < kmax) a = base[gr * ld + gk];
+                        if (gk + 1 < kmax) b = base[gr * ld + gk + 1];
+                    }
+                }
+                v[e] = make_double2(a, b);
+            }
+        }
+    }
+    // store into LDS laid out [k][r] with row stride LDR
+    template <int LDR>
+    __device__ __forceinline__ void store(double *lds) const {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int r, k;
+            coords(e, r, k);
+            if (CONTIG_MN) {
+                *reinterpret_cast<double2 *>(lds + k * LDR + r) = v[e];
+            } else {
+                lds[k * LDR + r] = v[e].x;
+                lds[(k + 1) * LDR + r] = v[e].y;
+            }
+        }
+    }
+};
 
 template <int BM, int BN, int BK, int LA, int LB>
 __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, int tiles_m, int tiles_n) {
     if (g.stop_flag != nullptr && *g.stop_flag != 0) return;
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int WAVES_M = 2, WAVES_N = 4;
+    constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
     constexpr int FM = WM / 16, FN = WN / 16;
-    constexpr int A_PER = BM * BK / GEMM_THREADS;
-    constexpr int B_PER = BN * BK / GEMM_THREADS;
-    static_assert(A_PER * GEMM_THREADS == BM * BK, "A tile split");
-    static_assert(B_PER * GEMM_THREADS == BN * BK, "B tile split");
+    static_assert(FM >= 1 && FN >= 1, "wave tile");
+    constexpr int LDA_S = BM, LDB_S = BN;
+    extern __shared__ double smem[];
+    double *As = smem;                       // [2][BK][BM]
+    double *Bs = smem + 2 * BK * LDA_S;      // [2][BK][BN]
 
-    __shared__ double As[2][BK][BM];
-    __shared__ double Bs[2][BK][BN];
-
-    // tile coordinates (lower: enumerate tiles with tn <= tm, BM == BN)
     int tm, tn;
-    if (g.lower) {
-        const int64_t bid = blockIdx.x;
-        int r = (int)((sqrt(8.0 * (double)bid + 1.0) - 1.0) * 0.5);
-        while ((int64_t)(r + 1) * (r + 2) / 2 <= bid) ++r;
-        while ((int64_t)r * (r + 1) / 2 > bid) --r;
-        tm = r;
-        tn = (int)(bid - (int64_t)r * (r + 1) / 2);
-    } else {
-        tm = blockIdx.x % tiles_m;
-        tn = blockIdx.x / tiles_m;
-    }
+    if (!tile_of_block(blockIdx.x, g.lower, tiles_m, tiles_n, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
 
     double4_t acc[FM][FN];
 #pragma unroll
@@ -66,52 +168,23 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-    double ra[A_PER], rb[B_PER];
-
-    auto load_chunk = [&](int64_t k0) {
-#pragma unroll
-        for (int e = 0; e < A_PER; ++e) {
-            const int idx = tid + e * GEMM_THREADS;
-            int mm, kk;
-            if (LA == 1) { mm = idx % BM; kk = idx / BM; }   // contiguous in m
-            else         { kk = idx % BK; mm = idx / BK; }   // contiguous in k
-            const int64_t gm = m0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < g.M && gk < g.K) v = (LA == 1) ? g.A[gk * g.lda + gm] : g.A[gm * g.lda + gk];
-            ra[e] = v;
-        }
-#pragma unroll
-        for (int e = 0; e < B_PER; ++e) {
-            const int idx = tid + e * GEMM_THREADS;
-            int nn, kk;
-            if (LB == 0) { nn = idx % BN; kk = idx / BN; }   // contiguous in n
-            else         { kk = idx % BK; nn = idx / BK; }   // contiguous in k
-            const int64_t gn_ = n0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gn_ < g.N && gk < g.K) v = (LB == 0) ? g.B[gk * g.ldb + gn_] : g.B[gn_ * g.ldb + gk];
-            rb[e] = v;
-        }
-    };
-    auto store_chunk = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < A_PER; ++e) {
-            const int idx = tid + e * GEMM_THREADS;
-            int mm, kk;
-            if (LA == 1) { mm = idx % BM; kk = idx / BM; }
-            else         { kk = idx % BK; mm = idx / BK; }
-            As[buf][kk][mm] = ra[e];
-        }
-#pragma unroll
-        for (int e = 0; e < B_PER; ++e) {
-            const int idx = tid + e * GEMM_THREADS;
-            int nn, kk;
-            if (LB == 0) { nn = idx % BN; kk = idx / BN; }
-            else         { kk = idx % BK; nn = idx / BK; }
-            Bs[buf][kk][nn] = rb[e];
-        }
-    };
+    TileLoader<BM, BK, LA == 1> la;
+    TileLoader<BN, BK, LB == 0> lb;
+    const bool a_aligned = ((g.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.A) & 15) == 0);
+    const bool b_aligned = ((g.ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0);
+    const bool a_rows_in = m0 + BM <= g.M, b_rows_in = n0 + BN <= g.N;
 
     const int64_t nk = (g.K + BK - 1) / BK;
+    auto load_chunk = [&](int64_t k0) {
+        const bool kin = k0 + BK <= g.K;
+        la.load(g.A, g.lda, m0, k0, g.M, g.K, kin && a_rows_in && a_aligned);
+        lb.load(g.B, g.ldb, n0, k0, g.N, g.K, kin && b_rows_in && b_aligned);
+    };
+    auto store_chunk = [&](int buf) {
+        la.template store<LDA_S>(As + buf * BK * LDA_S);
+        lb.template store<LDB_S>(Bs + buf * BK * LDB_S);
+    };
+
     if (nk > 0) {
         load_chunk(0);
         store_chunk(0);
@@ -121,13 +194,15 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
         if (kt + 1 < nk) load_chunk((kt + 1) * BK);
+        const double *as = As + cur * BK * LDA_S + wm * WM + fr;
+        const double *bs = Bs + cur * BK * LDB_S + wn * WN + fr;
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             double a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = As[cur][ks + fk][wm * WM + i * 16 + fr];
+            for (int i = 0; i < FM; ++i) a[i] = as[(ks + fk) * LDA_S + i * 16];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = Bs[cur][ks + fk][wn * WN + j * 16 + fr];
+            for (int j = 0; j < FN; ++j) b[j] = bs[(ks + fk) * LDB_S + j * 16];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -138,7 +213,29 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
         __syncthreads();
     }
 
-    // epilogue
+    // epilogue: lane l, register r holds row fk + 4 r, column fr of each
+    // 16x16 block.  All loads of C and the row scales are issued before any
+    // store so they overlap.
+    double cold[FM][FN][4], rs[FM][4];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
+            rs[i][r] = (g.rowscale && gm < g.M) ? g.rowscale[gm] : 1.0;
+        }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int64_t gn_ = n0 + wn * WN + j * 16 + fr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
+                const bool ok = gm < g.M && gn_ < g.N && !(g.lower && gn_ > gm);
+                cold[i][j][r] = (ok && g.beta != 0.0) ? g.C[gm * g.ldc + gn_] : 0.0;
+            }
+        }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
@@ -149,43 +246,51 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
                 const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
                 if (gm >= g.M || gn_ >= g.N) continue;
                 if (g.lower && gn_ > gm) continue;
-                double v = g.alpha * acc[i][j][r];
-                if (g.rowscale) v *= g.rowscale[gm];
-                double *c = g.C + gm * g.ldc + gn_;
-                *c = (g.beta == 0.0) ? v : fma(g.beta, *c, v);
+                const double v = g.alpha * acc[i][j][r] * rs[i][r];
+                g.C[gm * g.ldc + gn_] = (g.beta == 0.0) ? v : fma(g.beta, cold[i][j][r], v);
             }
         }
     }
+}
+
+template <int BM, int BN, int BK, int LA, int LB>
+static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int tiles_n, int64_t blocks) {
+    constexpr size_t shm = sizeof(double) * 2 * BK * (BM + BN);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        attr = true;
+    }
+    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB>), dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st,
+                       g, tiles_m, tiles_n);
+    return hipGetLastError();
 }
 
 template <int BM, int BN, int BK>
 static hipError_t launch_tiles(hipStream_t st, const GemmDesc &g) {
     const int tiles_m = (int)((g.M + BM - 1) / BM);
     const int tiles_n = (int)((g.N + BN - 1) / BN);
-    int64_t blocks;
+    int64_t supers;
     if (g.lower) {
-        blocks = (int64_t)tiles_m * (tiles_m + 1) / 2;  // requires M == N and BM == BN
+        supers = lower_super_count(tiles_m);
     } else {
-        blocks = (int64_t)tiles_m * tiles_n;
+        supers = (int64_t)((tiles_m + SUP_M - 1) / SUP_M) * ((tiles_n + SUP_N - 1) / SUP_N);
     }
-    if (blocks <= 0) return hipSuccess;
-    dim3 grid((unsigned)blocks), block(GEMM_THREADS);
-    if (g.la == 0 && g.lb == 0)
-        hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, 0, 0>), grid, block, 0, st, g, tiles_m, tiles_n);
-    else if (g.la == 0 && g.lb == 1)
-        hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, 0, 1>), grid, block, 0, st, g, tiles_m, tiles_n);
-    else if (g.la == 1 && g.lb == 0)
-        hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, 1, 0>), grid, block, 0, st, g, tiles_m, tiles_n);
-    else
-        hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, 1, 1>), grid, block, 0, st, g, tiles_m, tiles_n);
-    return hipGetLastError();
+    if (supers <= 0) return hipSuccess;
+    const int64_t blocks = (supers + NXCD - 1) / NXCD * NXCD * SUP;
+    if (g.la == 0 && g.lb == 0) return launch_one<BM, BN, BK, 0, 0>(st, g, tiles_m, tiles_n, blocks);
+    if (g.la == 0 && g.lb == 1) return launch_one<BM, BN, BK, 0, 1>(st, g, tiles_m, tiles_n, blocks);
+    if (g.la == 1 && g.lb == 0) return launch_one<BM, BN, BK, 1, 0>(st, g, tiles_m, tiles_n, blocks);
+    return launch_one<BM, BN, BK, 1, 1>(st, g, tiles_m, tiles_n, blocks);
 }
 
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.lower && g.M != g.N) return hipErrorInvalidValue;
-    if (!g.lower && g.N <= 64) return launch_tiles<128, 64, 16>(st, g);  // BN must equal BM when lower
-    return launch_tiles<128, 128, 16>(st, g);
+    // BN must equal BM when lower; in-place uses (C aliasing A) need BN >= N
+    if (!g.lower && g.N <= 64) return launch_tiles<128, 64, 32>(st, g);
+    return launch_tiles<128, 128, 32>(st, g);
 }
 
 // ---------------------------------------------------------------- g = J^T r

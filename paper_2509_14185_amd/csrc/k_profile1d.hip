@@ -319,7 +319,7 @@ static hipError_t launch_sweep_mode(hipStream_t st, const MlpDesc &d, const doub
     static bool attr_set = false;
     if (!attr_set) {
         // allow up to the full 160 KB of LDS of a gfx950 workgroup
-        hipFuncSetAttribute((const void *)mlp_sweep_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void *)mlp_sweep_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
         attr_set = true;
     }

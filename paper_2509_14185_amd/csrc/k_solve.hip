@@ -1,9 +1,10 @@
 // Damped solve of the Gauss-Newton system on gfx950 (paper, Methods,
 // "Second-order Optimizer": theta <- theta - (G + gamma I)^{-1} grad h).
 //
-// Right-looking blocked Cholesky with 64-wide panels:
-//   1. diagonal block: one wave factors it in LDS and forms the inverse of
-//      its triangular factor (forward substitution on the identity);
+// Right-looking blocked Cholesky with 128-wide panels:
+//   1. diagonal block: one workgroup factors it in LDS (two 64x64 register
+//      factorisations by one wave, 64x64 products by all four waves) and
+//      forms the inverse of its triangular factor;
 //   2. panel below: L21 = A21 L11^{-T} as an MFMA GEMM with the inverse;
 //   3. trailing update: A22 -= L21 L21^T (lower) as an MFMA GEMM.
 // A failed pivot records its 1-based global index and raises a device flag;
@@ -15,91 +16,311 @@
 // that row as w = L^{-1} g, so the forward substitution comes for free.
 //
 // Triangular solves use the stored diagonal-block inverses: one launch per
-// 64-row block computes the block's unknowns and applies them to the
-// remaining right-hand side, row-parallel across workgroups.
+// 128-row block applies the known block to the rest of the right-hand side,
+// one workgroup per remaining block, and the workgroup of the next block
+// then forms that block's unknowns.
 #include "gn_internal.h"
 
 namespace gn {
 
-static constexpr int NB = 64;
+static constexpr int CB = 128;         // panel width of the blocked Cholesky
+static constexpr int LDS_LD = CB + 1;  // padded LDS row stride (doubles)
 
-int64_t chol_linv_size(int64_t n) { return ((n + NB - 1) / NB) * NB * NB; }
+int64_t chol_linv_size(int64_t n) { return ((n + CB - 1) / CB) * CB * CB; }
+int64_t chol_tmp_size() { return 64 * 64; }
 
 __global__ void add_diag_kernel(double *A, int64_t n, int64_t lda, double mu) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) A[i * lda + i] += mu;
 }
 
-// One wave.  at[c][r] holds A[k0+r][k0+c] so that "lane r owns row r" is a
-// contiguous LDS access and column reads are broadcasts.
-__global__ __launch_bounds__(64) void potrf_block_kernel(double *A, int64_t lda, int64_t k0, int kb, int kf,
-                                                         double *linv, DevStatus *status) {
+// ---- diagonal-block factorisation -------------------------------------
+// The CB x CB block lives in LDS: L in the lower triangle (s[i*LDS_LD + c],
+// c <= i) and X = L^{-1} stored transposed in the strict upper triangle plus
+// the padding column (X(i,c) at s[c*LDS_LD + i + 1], i >= c), so both fit in
+// one 128 x 129 tile.  Rows >= kb are identity padding.  Work is blocked by
+// IB = 32: a one-wave register factorisation of each 32x32 diagonal block
+// (one non-inlined copy, small enough to stay in the instruction cache),
+// then loops over the panel and trailing part with all 256 threads.
+static constexpr int IB = 32;
+#define LL(i, c) s[(i) * LDS_LD + (c)]
+#define XX(i, c) s[(c) * LDS_LD + (i) + 1]
+
+// 1/sqrt(d) for d > 0: hardware estimate refined by two Newton steps
+// (y <- y (3 - d y^2) / 2), accurate to a few ulp; a short dependent chain
+// where the IEEE sqrt plus division would take about thirty operations.
+__device__ __forceinline__ double rsqrt_refined(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+    double h = 0.5 * d;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// One wave, lanes 0..31: lane i holds row o+i of the 32x32 diagonal block.
+// Step j publishes column j in colbuf; each lane reads the pivot and the
+// entries below it as broadcasts and updates with one FMA per entry using
+// a_ij / d as multiplier.  Entries right of the diagonal are never read, so
+// they are updated without masking.  Row bi (local, or -1) is a border row
+// (updated, diagonal not square-rooted, excluded from X).  Writes L back and
+// X_oo = L_oo^{-1} (lane c owns column c).  Returns -1 or the failing local
+// pivot (uniform).
+__device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *colbuf) {
+    const int lane = threadIdx.x & 63;
+    const bool act = lane < IB;
+    double row[IB];
+#pragma unroll
+    for (int c = 0; c < IB; ++c) row[c] = (act && c <= lane) ? LL(o + lane, o + c) : 0.0;
+    double rinv[IB];  // 1 / l_jj, uniform
+    int fail = -1;
+#pragma unroll
+    for (int j = 0; j < IB; ++j) {
+        rinv[j] = 0.0;
+        if (fail < 0 && j != bi) {
+            double *col = colbuf + (j & 1) * IB;
+            if (act) col[lane] = row[j];
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+            __builtin_amdgcn_wave_barrier();
+            const double d = col[j];
+            if (!(d > 0.0)) {
+                fail = j;
+            } else {
+                const double r = rsqrt_refined(d);
+                rinv[j] = r;
+                const double f = row[j] * (r * r);
+                row[j] = (lane == j) ? d * r : row[j] * r;
+#pragma unroll
+                for (int c = j + 1; c < IB; ++c) row[c] = fma(-f, col[c], row[c]);
+            }
+        }
+    }
+    if (fail >= 0) return fail;
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < IB; ++c)
+            if (c <= lane) LL(o + lane, o + c) = row[c];
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    // X = L^{-1}: lane c owns column c, X[i][c] = (delta_ic - sum_{k<i} L[i][k] X[k][c]) / L[i][i]
+    double xc[IB];
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+        if (i == bi) {
+            xc[i] = 0.0;
+        } else {
+            double a0 = (i == lane) ? 1.0 : 0.0, a1 = 0.0;
+#pragma unroll
+            for (int k = 0; k + 1 < i; k += 2) {
+                a0 = fma(-LL(o + i, o + k), xc[k], a0);
+                a1 = fma(-LL(o + i, o + k + 1), xc[k + 1], a1);
+            }
+            if (i & 1) a0 = fma(-LL(o + i, o + i - 1), xc[i - 1], a0);
+            xc[i] = (a0 + a1) * rinv[i];
+        }
+    }
+    if (act && lane != bi) {
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+            if (i >= lane) XX(o + i, o + lane) = xc[i];
+    }
+    return -1;
+}
+
+// Factor one CB x CB diagonal block (rows/cols k0 .. k0+kb) of A and form X =
+// L^{-1} of the block (row-major CB x CB, zero outside the factor and on the
+// border row/column).  Products inside the block use 4 x 4 (or 2 x 2)
+// register blocks with independent accumulators.
+__global__ __launch_bounds__(256) void potrf_block_kernel(double *A, int64_t lda, int64_t k0, int kb, int border_here,
+                                                         double *X, double *T, DevStatus *status) {
     if (status->flag) return;
-    __shared__ double at[NB][NB];
-    __shared__ double x[NB][NB];
-    const int lane = threadIdx.x;
-    for (int r = 0; r < NB; ++r) {
-        double v = 0.0;
-        if (r < kb && lane <= r) v = A[(k0 + r) * lda + k0 + lane];
-        at[lane][r] = v;
+    extern __shared__ double s[];
+    __shared__ int fail_sh;
+    __shared__ double colbuf[2 * IB];
+    __shared__ double W[IB * (IB + 1)];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int bi = border_here ? kb - 1 : -1;
+    {
+        // all 64 loads of a thread are issued before any LDS store
+        double v[CB * CB / 256];
+#pragma unroll
+        for (int e = 0; e < CB * CB / 256; ++e) {
+            const int idx = tid + e * 256, r = idx / CB, c = idx % CB;
+            v[e] = (r < kb && c <= r) ? A[(k0 + r) * lda + k0 + c] : ((r >= kb && r == c) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int e = 0; e < CB * CB / 256; ++e) {
+            const int idx = tid + e * 256, r = idx / CB, c = idx % CB;
+            s[r * LDS_LD + c] = v[e];
+        }
+        if (tid < CB) s[tid * LDS_LD + CB] = 0.0;
     }
     __syncthreads();
-    for (int j = 0; j < kf; ++j) {
-        const double d = at[j][j];
-        if (!(d > 0.0)) {  // uniform across the wave
-            if (lane == 0) {
-                status->chol_info = k0 + j + 1;
+    // ---- blocked right-looking factorisation, inner blocks of IB
+#pragma nounroll
+    for (int sb = 0; sb < CB / IB; ++sb) {
+        const int o = sb * IB;
+        if (wave == 0) {
+            const int lb = (bi >= o && bi < o + IB) ? bi - o : -1;
+            const int f = potrf32_wave(s, o, lb, colbuf);
+            if (lane == 0) fail_sh = f < 0 ? -1 : o + f;
+        }
+        __syncthreads();
+        if (fail_sh >= 0) {
+            if (tid == 0) {
+                status->chol_info = k0 + fail_sh + 1;
                 status->flag = 1;
             }
             return;
         }
-        const double ljj = sqrt(d);
+        const int r0 = o + IB, nr = CB - r0;
+        if (nr <= 0) break;
+        // panel: L[r][o+j] = sum_{k<=j} A[r][o+k] X[o+j][o+k], one row x 4 columns per item
+        {
+            constexpr int QMAX = (CB - IB) * (IB / 4) / 256;  // 3
+            double out[QMAX][4];
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                const int e = tid + 256 * q;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) out[q][v] = 0.0;
+                if (e < nr * (IB / 4)) {
+                    const int r = r0 + e / (IB / 4), j0 = 4 * (e % (IB / 4));
+                    for (int k = 0; k < j0 + 4; ++k) {
+                        const double a = LL(r, o + k);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            out[q][v] = fma(a, (k <= j0 + v) ? XX(o + j0 + v, o + k) : 0.0, out[q][v]);
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                const int e = tid + 256 * q;
+                if (e < nr * (IB / 4)) {
+                    const int r = r0 + e / (IB / 4), j0 = 4 * (e % (IB / 4));
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) LL(r, o + j0 + v) = out[q][v];
+                }
+            }
+        }
         __syncthreads();
-        if (lane == j) at[j][j] = ljj;
-        if (lane > j && lane < kb) at[j][lane] /= ljj;
-        __syncthreads();
-        if (lane > j && lane < kb) {
-            const double lij = at[j][lane];
-            for (int c = j + 1; c <= lane; ++c) at[c][lane] -= lij * at[j][c];
+        // trailing update (lower), 4x4 blocks: A[r][c] -= sum_k L[r][o+k] L[c][o+k]
+        {
+            const int nb = nr / 4;
+            for (int e = tid; e < nb * nb; e += 256) {
+                const int br = e / nb, bc = e % nb;
+                if (bc > br) continue;
+                const int r = r0 + 4 * br, c = r0 + 4 * bc;
+                double acc[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+                for (int k = 0; k < IB; ++k) {
+                    double a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] = LL(r + u, o + k);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) b[v] = LL(c + v, o + k);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (c + v <= r + u) LL(r + u, c + v) -= acc[u][v];
+            }
         }
         __syncthreads();
     }
-    // write the factor (lower triangle of the block)
-    for (int r = 0; r < kb; ++r)
-        if (lane <= r) A[(k0 + r) * lda + k0 + lane] = at[lane][r];
-    // inverse of the leading kf x kf factor, row by row: lane c owns column c,
-    // X[i][c] = (delta_ic - sum_{k<i} L[i][k] X[k][c]) / L[i][i]
-    for (int i = 0; i < NB; ++i) {
-        double v = 0.0;
-        if (i < kf && lane <= i) {
-            double s = (lane == i) ? 1.0 : 0.0;
-            for (int k = lane; k < i; ++k) s -= at[k][i] * x[k][lane];
-            v = s / at[i][i];
+    // ---- off-diagonal blocks of X by distance d = r - s, 2x2 items:
+    //      W = sum_{k=s}^{r-1} L_rk X_ks,  X_rs = -X_rr W
+#pragma nounroll
+    for (int d = 1; d < CB / IB; ++d) {
+#pragma nounroll
+        for (int sb = 0; sb + d < CB / IB; ++sb) {
+            const int ro = (sb + d) * IB, so = sb * IB;
+            {
+                const int i0 = 2 * (tid / (IB / 2)), j0 = 2 * (tid % (IB / 2));  // 256 items of 2x2
+                double w00 = 0.0, w01 = 0.0, w10 = 0.0, w11 = 0.0;
+                for (int k = so + j0; k < ro; ++k) {
+                    const double a0 = LL(ro + i0, k), a1 = LL(ro + i0 + 1, k);
+                    const double b0 = XX(k, so + j0), b1 = (k >= so + j0 + 1) ? XX(k, so + j0 + 1) : 0.0;
+                    w00 = fma(a0, b0, w00);
+                    w01 = fma(a0, b1, w01);
+                    w10 = fma(a1, b0, w10);
+                    w11 = fma(a1, b1, w11);
+                }
+                W[i0 * (IB + 1) + j0] = w00;
+                W[i0 * (IB + 1) + j0 + 1] = w01;
+                W[(i0 + 1) * (IB + 1) + j0] = w10;
+                W[(i0 + 1) * (IB + 1) + j0 + 1] = w11;
+            }
+            __syncthreads();
+            {
+                const int i0 = 2 * (tid / (IB / 2)), j0 = 2 * (tid % (IB / 2));
+                double x00 = 0.0, x01 = 0.0, x10 = 0.0, x11 = 0.0;
+                for (int k = 0; k <= i0 + 1; ++k) {
+                    const double a0 = (k <= i0) ? XX(ro + i0, ro + k) : 0.0, a1 = XX(ro + i0 + 1, ro + k);
+                    const double b0 = W[k * (IB + 1) + j0], b1 = W[k * (IB + 1) + j0 + 1];
+                    x00 = fma(a0, b0, x00);
+                    x01 = fma(a0, b1, x01);
+                    x10 = fma(a1, b0, x10);
+                    x11 = fma(a1, b1, x11);
+                }
+                XX(ro + i0, so + j0) = -x00;
+                XX(ro + i0, so + j0 + 1) = -x01;
+                XX(ro + i0 + 1, so + j0) = -x10;
+                XX(ro + i0 + 1, so + j0 + 1) = -x11;
+            }
+            __syncthreads();
         }
-        x[i][lane] = v;
-        __syncthreads();
     }
-    double *out = linv + (k0 / NB) * NB * NB;
-    for (int r = 0; r < NB; ++r) out[r * NB + lane] = x[r][lane];
+    // ---- write L (rows < kb) and X (zero outside the factor) to global memory
+#pragma unroll 8
+    for (int e = 0; e < CB * CB / 256; ++e) {
+        const int idx = tid + e * 256, r = idx / CB, c = idx % CB;
+        if (r < kb && c <= r) A[(k0 + r) * lda + k0 + c] = LL(r, c);
+        const bool valid = c <= r && r < kb && r != bi && c != bi;
+        X[idx] = valid ? XX(r, c) : 0.0;
+    }
 }
 
+#undef LL
+#undef XX
+
 hipError_t launch_cholesky(hipStream_t st, double *A, int64_t n, int64_t lda, double mu, int border, double *linv,
-                           DevStatus *status) {
+                           double *tmp, DevStatus *status) {
     if (n <= 0) return hipSuccess;
+    static bool attr = false;
+    const size_t shm = sizeof(double) * CB * LDS_LD;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)potrf_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+        attr = true;
+    }
     const int64_t nd = n - border;
     if (mu != 0.0 && nd > 0)
         hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, A, nd, lda, mu);
-    for (int64_t k0 = 0; k0 < n; k0 += NB) {
-        const int kb = (int)((n - k0) < NB ? (n - k0) : NB);
-        const int kf = (border && k0 + kb == n) ? kb - 1 : kb;
-        hipLaunchKernelGGL(potrf_block_kernel, dim3(1), dim3(64), 0, st, A, lda, k0, kb, kf, linv, status);
+    for (int64_t k0 = 0; k0 < n; k0 += CB) {
+        const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
+        const int bh = (border && k0 + kb == n) ? 1 : 0;
+        double *Xb = linv + (k0 / CB) * CB * CB;
+        hipLaunchKernelGGL(potrf_block_kernel, dim3(1), dim3(256), shm, st, A, lda, k0, kb, bh, Xb, tmp, status);
         const int64_t rest = n - k0 - kb;
         if (rest <= 0) break;
         double *a21 = A + (k0 + kb) * lda + k0;
+        // L21 = A21 X^T in place: each output tile owns its rows over all kb columns
         GemmDesc t{};
         t.M = rest; t.N = kb; t.K = kb;
         t.A = a21; t.lda = lda; t.la = 0;
-        t.B = linv + (k0 / NB) * NB * NB; t.ldb = NB; t.lb = 1;
+        t.B = Xb; t.ldb = CB; t.lb = 1;
         t.C = a21; t.ldc = lda;
         t.alpha = 1.0; t.beta = 0.0;
         t.stop_flag = &status->flag;
@@ -120,79 +341,149 @@ hipError_t launch_cholesky(hipStream_t st, double *A, int64_t n, int64_t lda, do
 }
 
 // ------------------------------------------------------- triangular solves
-static constexpr int SOLVE_ROWS = 64;  // rows per workgroup in the forward update
+// Blocks of CB rows; X_I is the inverse of the I-th diagonal block.
+// Forward L z = b: z_0 = X_0 b_0; launch I updates b_w -= L_wI z_I for every
+// block w > I (one workgroup per block) and the workgroup of block I+1 then
+// forms z_{I+1} = X_{I+1} b_{I+1}.  Back L^T x = y mirrors it column-wise.
 
-__global__ __launch_bounds__(256) void fwd_step_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
-                                                       const double *__restrict__ linv, double *b, double *z,
-                                                       int64_t r0, int kb, const DevStatus *status) {
-    if (status->flag) return;
-    __shared__ double zi[NB];
-    const int tid = threadIdx.x;
-    const double *li = linv + (r0 / NB) * NB * NB;
-    if (tid < NB) {
-        double s = 0.0;
-        if (tid < kb)
-            for (int c = 0; c <= tid; ++c) s = fma(li[tid * NB + c], b[r0 + c], s);
-        zi[tid] = s;
-        if (blockIdx.x == 0 && tid < kb) z[r0 + tid] = s;
-    }
-    __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6;
-    const int64_t base = r0 + kb + (int64_t)blockIdx.x * SOLVE_ROWS;
-    for (int rr = wave; rr < SOLVE_ROWS; rr += 4) {
-        const int64_t row = base + rr;
-        if (row >= n) break;
-        double v = (lane < kb) ? L[row * ldl + r0 + lane] * zi[lane] : 0.0;
+__device__ void block_lower_apply(const double *__restrict__ Xb, const double *bs, double *out, int kb) {
+    // out[t] = sum_{c <= t} X[t][c] bs[c]; a wave per output row, lanes over c
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = wave; t < kb; t += 4) {
+        double v = 0.0;
+        for (int c = lane; c <= t; c += 64) v = fma(Xb[t * CB + c], bs[c], v);
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) b[row] -= v;
+        if (lane == 0) out[t] = v;
     }
 }
 
-__global__ __launch_bounds__(256) void back_step_kernel(const double *__restrict__ L, int64_t ldl,
-                                                        const double *__restrict__ linv, double *y, double *x,
-                                                        int64_t r0, int kb, const DevStatus *status) {
-    if (status->flag) return;
-    __shared__ double xi[NB];
-    const int tid = threadIdx.x;
-    const double *li = linv + (r0 / NB) * NB * NB;
-    if (tid < NB) {
-        double s = 0.0;
-        if (tid < kb)
-            for (int c = tid; c < kb; ++c) s = fma(li[c * NB + tid], y[r0 + c], s);
-        xi[tid] = s;
-        if (blockIdx.x == 0 && tid < kb) x[r0 + tid] = s;
+__device__ void block_upper_apply(const double *__restrict__ Xb, const double *ys, double *out, int kb) {
+    // out[t] = sum_{c >= t} X[c][t] ys[c]; thread pairs per t (CB x 2 = 256 threads)
+    __shared__ double part[256];
+    const int tid = threadIdx.x, t = tid & (CB - 1), h = tid >> 7;
+    double v0 = 0.0, v1 = 0.0;
+    if (t < kb) {
+        int c = t + h;
+#pragma unroll 8
+        for (; c + 2 < kb; c += 4) {
+            v0 = fma(Xb[c * CB + t], ys[c], v0);
+            v1 = fma(Xb[(c + 2) * CB + t], ys[c + 2], v1);
+        }
+        for (; c < kb; c += 2) v0 = fma(Xb[c * CB + t], ys[c], v0);
     }
+    part[tid] = v0 + v1;
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * 256 + tid;
-    if (c >= r0) return;
-    double acc = 0.0;
-    for (int i = 0; i < kb; ++i) acc = fma(L[(r0 + i) * ldl + c], xi[i], acc);
-    y[c] -= acc;
+    if (h == 0 && t < kb) out[t] = part[t] + part[t + CB];
+}
+
+__global__ __launch_bounds__(256) void fwd_init_kernel(const double *linv, const double *b, double *z, int kb,
+                                                       const DevStatus *status) {
+    if (status->flag) return;
+    __shared__ double bs[CB];
+    if (threadIdx.x < kb) bs[threadIdx.x] = b[threadIdx.x];
+    __syncthreads();
+    block_lower_apply(linv, bs, z, kb);
+}
+
+__global__ __launch_bounds__(256) void fwd_update_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
+                                                         const double *__restrict__ linv, double *b, double *z,
+                                                         int64_t I, const DevStatus *status) {
+    if (status->flag) return;
+    __shared__ double zs[CB];
+    __shared__ double bs[CB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = I * CB;
+    const int kbI = (int)((n - r0) < CB ? (n - r0) : CB);
+    const int64_t w = I + 1 + blockIdx.x;
+    const int64_t w0 = w * CB;
+    const int kbw = (int)((n - w0) < CB ? (n - w0) : CB);
+    if (tid < kbI) zs[tid] = z[r0 + tid];
+    __syncthreads();
+    for (int rr = wave; rr < kbw; rr += 4) {
+        const int64_t row = w0 + rr;
+        double v = 0.0;
+        for (int k = lane; k < kbI; k += 64) v = fma(L[row * ldl + r0 + k], zs[k], v);
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) {
+            const double nb = b[row] - v;
+            b[row] = nb;
+            bs[rr] = nb;
+        }
+    }
+    if (w != I + 1) return;
+    __syncthreads();
+    block_lower_apply(linv + w * CB * CB, bs, z + w0, kbw);
+}
+
+__global__ __launch_bounds__(256) void back_init_kernel(const double *linv, const double *y, double *x, int kb,
+                                                        const DevStatus *status) {
+    if (status->flag) return;
+    __shared__ double ys[CB];
+    if (threadIdx.x < kb) ys[threadIdx.x] = y[threadIdx.x];
+    __syncthreads();
+    block_upper_apply(linv, ys, x, kb);
+}
+
+__global__ __launch_bounds__(256) void back_update_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
+                                                          const double *__restrict__ linv, double *y, double *x,
+                                                          int64_t I, const DevStatus *status) {
+    if (status->flag) return;
+    __shared__ double xs[CB];
+    __shared__ double part[256];
+    __shared__ double ys[CB];
+    const int tid = threadIdx.x, c = tid & (CB - 1), h = tid >> 7;
+    const int64_t r0 = I * CB;
+    const int kbI = (int)((n - r0) < CB ? (n - r0) : CB);
+    const int64_t w = blockIdx.x;  // column block w < I (full CB columns)
+    const int64_t col = w * CB + c;
+    if (tid < kbI) xs[tid] = x[r0 + tid];
+    __syncthreads();
+    double v0 = 0.0, v1 = 0.0;
+    if (kbI == CB) {
+        // 64 independent loads per thread, issued together
+        double lv[CB / 2];
+#pragma unroll
+        for (int e = 0; e < CB / 2; ++e) lv[e] = L[(r0 + 2 * e + h) * ldl + col];
+#pragma unroll
+        for (int e = 0; e < CB / 2; e += 2) {
+            v0 = fma(lv[e], xs[2 * e + h], v0);
+            v1 = fma(lv[e + 1], xs[2 * e + 2 + h], v1);
+        }
+    } else {
+        for (int i = h; i < kbI; i += 2) v0 = fma(L[(r0 + i) * ldl + col], xs[i], v0);
+    }
+    part[tid] = v0 + v1;
+    __syncthreads();
+    if (h == 0) {
+        const double ny = y[col] - (part[c] + part[c + CB]);
+        y[col] = ny;
+        ys[c] = ny;
+    }
+    if (w != I - 1) return;
+    __syncthreads();
+    block_upper_apply(linv + w * CB * CB, ys, x + w * CB, CB);
 }
 
 hipError_t launch_solve_lower(hipStream_t st, const double *L, int64_t n, int64_t ldl, const double *linv,
                               double *b, double *z, DevStatus *status) {
-    for (int64_t r0 = 0; r0 < n; r0 += NB) {
-        const int kb = (int)((n - r0) < NB ? (n - r0) : NB);
-        const int64_t rest = n - r0 - kb;
-        const int64_t blocks = rest > 0 ? (rest + SOLVE_ROWS - 1) / SOLVE_ROWS : 1;
-        hipLaunchKernelGGL(fwd_step_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, n, ldl, linv, b, z, r0, kb,
-                           status);
-    }
+    if (n <= 0) return hipSuccess;
+    const int64_t nblk = (n + CB - 1) / CB;
+    hipLaunchKernelGGL(fwd_init_kernel, dim3(1), dim3(256), 0, st, linv, b, z, (int)(n < CB ? n : CB), status);
+    for (int64_t I = 0; I + 1 < nblk; ++I)
+        hipLaunchKernelGGL(fwd_update_kernel, dim3((unsigned)(nblk - 1 - I)), dim3(256), 0, st, L, n, ldl, linv, b, z,
+                           I, status);
     return hipGetLastError();
 }
 
 hipError_t launch_solve_upper(hipStream_t st, const double *L, int64_t n, int64_t ldl, const double *linv,
                               double *y, double *x, DevStatus *status) {
     if (n <= 0) return hipSuccess;
-    const int64_t nblk = (n + NB - 1) / NB;
-    for (int64_t bI = nblk - 1; bI >= 0; --bI) {
-        const int64_t r0 = bI * NB;
-        const int kb = (int)((n - r0) < NB ? (n - r0) : NB);
-        const int64_t blocks = r0 > 0 ? (r0 + 255) / 256 : 1;
-        hipLaunchKernelGGL(back_step_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, ldl, linv, y, x, r0, kb,
-                           status);
-    }
+    const int64_t nblk = (n + CB - 1) / CB;
+    const int64_t rl = (nblk - 1) * CB;
+    hipLaunchKernelGGL(back_init_kernel, dim3(1), dim3(256), 0, st, linv + (nblk - 1) * CB * CB, y + rl, x + rl,
+                       (int)(n - rl), status);
+    for (int64_t I = nblk - 1; I >= 1; --I)
+        hipLaunchKernelGGL(back_update_kernel, dim3((unsigned)I), dim3(256), 0, st, L, n, ldl, linv, y, x, I, status);
     return hipGetLastError();
 }
 
