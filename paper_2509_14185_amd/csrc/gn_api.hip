@@ -19,6 +19,8 @@ struct gn_context {
     double lam = 0, c_norm = 0, c_target = 0;
     MlpDesc md{};
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;           // look-ahead stream of the Cholesky (default priority)
+    hipEvent_t ev_panel = nullptr, ev_trail = nullptr;
     int device = 0;
     std::string err;
     std::vector<void *> allocs;       // problem-lifetime allocations
@@ -253,7 +255,10 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
         return s;
     }
     const double one = 1.0;
-    if (hipMemcpy(h->one_x, &one, sizeof one, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_trail, hipEventDisableTiming) != hipSuccess ||
+        hipMemcpy(h->one_x, &one, sizeof one, hipMemcpyHostToDevice) != hipSuccess) {
         free_list(h->allocs);
         delete h;
         return GN_EDEVICE;
@@ -266,6 +271,12 @@ gn_status gn_destroy(gn_handle h) {
     if (!h) return GN_EINVAL;
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
+    if (h->ev_trail) (void)hipEventDestroy(h->ev_trail);
     free_list(h->pt_allocs);
     free_list(h->allocs);
     delete h;
@@ -397,7 +408,7 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, 
     if (!(mu >= 0.0)) return fail(h, GN_EINVAL, "mu must be >= 0%s");
     hipStream_t st = h->stream;
     GN_HIP(h, launch_reset_status(st, h->status));
-    GN_HIP(h, launch_cholesky(st, d_G, p, ldG, mu, 0, h->linv, h->chol_tmp, h->status));
+    GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, d_G, p, ldG, mu, 0, h->linv, h->chol_tmp, h->status));
     GN_HIP(h, launch_copy_strided(st, d_g, p, 1, h->ybuf, 1, -1.0));
     GN_HIP(h, launch_solve_lower(st, d_G, p, ldG, h->linv, h->ybuf, h->zbuf, h->status));
     GN_HIP(h, launch_solve_upper(st, d_G, p, ldG, h->linv, h->zbuf, d_delta, h->status));
@@ -458,7 +469,7 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
     GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     mark(h, 4);
     // Cholesky of [[G + mu I, g], [g^T, r^T r]]: last row = (L^{-1} g)^T, Schur complement
-    GN_HIP(h, launch_cholesky(st, h->G, P + 1, h->ldG, mu, 1, h->linv, h->chol_tmp, h->status));
+    GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, h->G, P + 1, h->ldG, mu, 1, h->linv, h->chol_tmp, h->status));
     mark(h, 5);
     double *w = h->G + P * h->ldG;
     GN_HIP(h, launch_sumsq(st, w, P, 1, &h->status->grad_dot_delta, h->red_work));

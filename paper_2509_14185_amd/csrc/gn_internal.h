@@ -123,7 +123,8 @@ struct GemmDesc {
     double *C; int64_t ldc;
     double alpha, beta;
     const double *rowscale;
-    int lower;
+    int lower;                 // square lower-triangular tile set (M == N)
+    int mask_lower;            // rectangular tile set, write only n <= m
     const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
@@ -141,8 +142,13 @@ hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, 
 // chol_tmp_size() doubles of scratch.
 int64_t chol_linv_size(int64_t n);
 int64_t chol_tmp_size();
-hipError_t launch_cholesky(hipStream_t st, double *A, int64_t n, int64_t lda, double mu, int border,
-                           double *linv, double *tmp, DevStatus *status);
+// The trailing update of each panel runs on `side` (a second stream of
+// default priority) while the next diagonal block is factored on `st`
+// (look-ahead); ev_panel / ev_trail order the two streams.  On return all
+// work is ordered before later work on `st`.
+hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail, double *A,
+                           int64_t n, int64_t lda, double mu, int border, double *linv, double *tmp,
+                           DevStatus *status);
 // L z = b (forward), then L^T x = z (back), using the factor and the
 // diagonal-block inverses from launch_cholesky.  b is overwritten.
 hipError_t launch_solve_lower(hipStream_t st, const double *L, int64_t n, int64_t ldl,

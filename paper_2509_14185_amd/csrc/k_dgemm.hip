@@ -157,6 +157,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
     int tm, tn;
     if (!tile_of_block(blockIdx.x, g.lower, tiles_m, tiles_n, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const bool lower_mask = g.lower || g.mask_lower;
+    if (lower_mask && n0 > m0 + BM - 1) return;  // tile entirely above the diagonal
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
-                const bool ok = gm < g.M && gn_ < g.N && !(g.lower && gn_ > gm);
+                const bool ok = gm < g.M && gn_ < g.N && !(lower_mask && gn_ > gm);
                 cold[i][j][r] = (ok && g.beta != 0.0) ? g.C[gm * g.ldc + gn_] : 0.0;
             }
         }
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
             for (int r = 0; r < 4; ++r) {
                 const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
                 if (gm >= g.M || gn_ >= g.N) continue;
-                if (g.lower && gn_ > gm) continue;
+                if (lower_mask && gn_ > gm) continue;
                 const double v = g.alpha * acc[i][j][r] * rs[i][r];
                 g.C[gm * g.ldc + gn_] = (g.beta == 0.0) ? v : fma(g.beta, cold[i][j][r], v);
             }

@@ -1,12 +1,15 @@
 // Damped solve of the Gauss-Newton system on gfx950 (paper, Methods,
 // "Second-order Optimizer": theta <- theta - (G + gamma I)^{-1} grad h).
 //
-// Right-looking blocked Cholesky with 128-wide panels:
+// Right-looking blocked Cholesky with 128-wide panels and look-ahead:
 //   1. diagonal block: one workgroup factors it in LDS (two 64x64 register
 //      factorisations by one wave, 64x64 products by all four waves) and
 //      forms the inverse of its triangular factor;
 //   2. panel below: L21 = A21 L11^{-T} as an MFMA GEMM with the inverse;
-//   3. trailing update: A22 -= L21 L21^T (lower) as an MFMA GEMM.
+//   3. trailing update: A22 -= L21 L21^T (lower) as MFMA GEMMs, split into
+//      the block column of the next panel (on the main stream) and the rest
+//      (on a second stream), so the next diagonal block and panel are
+//      factored while the bulk of the update runs.
 // A failed pivot records its 1-based global index and raises a device flag;
 // every later kernel of the factorisation and solve sees the flag and exits.
 //
@@ -57,15 +60,22 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
     return y;
 }
 
-// One wave, lanes 0..31: lane i holds row o+i of the 32x32 diagonal block.
-// Step j publishes column j in colbuf; each lane reads the pivot and the
-// entries below it as broadcasts and updates with one FMA per entry using
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// One wave, lanes 0..31: lane i holds row o+i of the 32x32 diagonal block in
+// registers.  Step j reads the pivot and the column below it lane-to-lane
+// (readlane into scalar registers) and updates with one FMA per entry using
 // a_ij / d as multiplier.  Entries right of the diagonal are never read, so
 // they are updated without masking.  Row bi (local, or -1) is a border row
 // (updated, diagonal not square-rooted, excluded from X).  Writes L back and
-// X_oo = L_oo^{-1} (lane c owns column c).  Returns -1 or the failing local
-// pivot (uniform).
-__device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *colbuf) {
+// X_oo = L_oo^{-1} (lane c owns column c, L rows read lane-to-lane).
+// The unrolled body is small enough to stay in the instruction cache.
+// Returns -1 or the failing local pivot (uniform).
+__device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *) {
     const int lane = threadIdx.x & 63;
     const bool act = lane < IB;
     double row[IB];
@@ -77,20 +87,16 @@ __device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *colbu
     for (int j = 0; j < IB; ++j) {
         rinv[j] = 0.0;
         if (fail < 0 && j != bi) {
-            double *col = colbuf + (j & 1) * IB;
-            if (act) col[lane] = row[j];
-            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-            __builtin_amdgcn_wave_barrier();
-            const double d = col[j];
+            const double d = readlane_d(row[j], j);
             if (!(d > 0.0)) {
                 fail = j;
             } else {
                 const double r = rsqrt_refined(d);
                 rinv[j] = r;
                 const double f = row[j] * (r * r);
-                row[j] = (lane == j) ? d * r : row[j] * r;
 #pragma unroll
-                for (int c = j + 1; c < IB; ++c) row[c] = fma(-f, col[c], row[c]);
+                for (int c = j + 1; c < IB; ++c) row[c] = fma(-f, readlane_d(row[j], c), row[c]);
+                row[j] = (lane == j) ? d * r : row[j] * r;
             }
         }
     }
@@ -100,8 +106,6 @@ __device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *colbu
         for (int c = 0; c < IB; ++c)
             if (c <= lane) LL(o + lane, o + c) = row[c];
     }
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
     // X = L^{-1}: lane c owns column c, X[i][c] = (delta_ic - sum_{k<i} L[i][k] X[k][c]) / L[i][i]
     double xc[IB];
 #pragma unroll
@@ -112,10 +116,10 @@ __device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *colbu
             double a0 = (i == lane) ? 1.0 : 0.0, a1 = 0.0;
 #pragma unroll
             for (int k = 0; k + 1 < i; k += 2) {
-                a0 = fma(-LL(o + i, o + k), xc[k], a0);
-                a1 = fma(-LL(o + i, o + k + 1), xc[k + 1], a1);
+                a0 = fma(-readlane_d(row[k], i), xc[k], a0);
+                a1 = fma(-readlane_d(row[k + 1], i), xc[k + 1], a1);
             }
-            if (i & 1) a0 = fma(-LL(o + i, o + i - 1), xc[i - 1], a0);
+            if (i & 1) a0 = fma(-readlane_d(row[i - 1], i), xc[i - 1], a0);
             xc[i] = (a0 + a1) * rinv[i];
         }
     }
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(double *A, int64_t lda
     extern __shared__ double s[];
     __shared__ int fail_sh;
     __shared__ double colbuf[2 * IB];
-    __shared__ double W[IB * (IB + 1)];
+    __shared__ double W[(CB / IB - 1) * IB * (IB + 1)];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int bi = border_here ? kb - 1 : -1;
     {
@@ -239,45 +243,63 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(double *A, int64_t lda
         }
         __syncthreads();
     }
-    // ---- off-diagonal blocks of X by distance d = r - s, 2x2 items:
+    // ---- off-diagonal blocks of X by distance d = r - s (all blocks of one
+    //      distance together), 4x4 items (64 per block):
     //      W = sum_{k=s}^{r-1} L_rk X_ks,  X_rs = -X_rr W
+    {
 #pragma nounroll
-    for (int d = 1; d < CB / IB; ++d) {
-#pragma nounroll
-        for (int sb = 0; sb + d < CB / IB; ++sb) {
-            const int ro = (sb + d) * IB, so = sb * IB;
-            {
-                const int i0 = 2 * (tid / (IB / 2)), j0 = 2 * (tid % (IB / 2));  // 256 items of 2x2
-                double w00 = 0.0, w01 = 0.0, w10 = 0.0, w11 = 0.0;
+        for (int d = 1; d < CB / IB; ++d) {
+            const int nblk = CB / IB - d;
+            const int q = tid >> 6, it = tid & 63;
+            const int i0 = 4 * (it >> 3), j0 = 4 * (it & 7);
+            if (q < nblk) {
+                const int ro = (q + d) * IB, so = q * IB;
+                double *Wq = W + q * IB * (IB + 1);
+                double w[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) w[u][v] = 0.0;
                 for (int k = so + j0; k < ro; ++k) {
-                    const double a0 = LL(ro + i0, k), a1 = LL(ro + i0 + 1, k);
-                    const double b0 = XX(k, so + j0), b1 = (k >= so + j0 + 1) ? XX(k, so + j0 + 1) : 0.0;
-                    w00 = fma(a0, b0, w00);
-                    w01 = fma(a0, b1, w01);
-                    w10 = fma(a1, b0, w10);
-                    w11 = fma(a1, b1, w11);
+                    double a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] = LL(ro + i0 + u, k);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) b[v] = (k >= so + j0 + v) ? XX(k, so + j0 + v) : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) w[u][v] = fma(a[u], b[v], w[u][v]);
                 }
-                W[i0 * (IB + 1) + j0] = w00;
-                W[i0 * (IB + 1) + j0 + 1] = w01;
-                W[(i0 + 1) * (IB + 1) + j0] = w10;
-                W[(i0 + 1) * (IB + 1) + j0 + 1] = w11;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Wq[(i0 + u) * (IB + 1) + j0 + v] = w[u][v];
             }
             __syncthreads();
-            {
-                const int i0 = 2 * (tid / (IB / 2)), j0 = 2 * (tid % (IB / 2));
-                double x00 = 0.0, x01 = 0.0, x10 = 0.0, x11 = 0.0;
-                for (int k = 0; k <= i0 + 1; ++k) {
-                    const double a0 = (k <= i0) ? XX(ro + i0, ro + k) : 0.0, a1 = XX(ro + i0 + 1, ro + k);
-                    const double b0 = W[k * (IB + 1) + j0], b1 = W[k * (IB + 1) + j0 + 1];
-                    x00 = fma(a0, b0, x00);
-                    x01 = fma(a0, b1, x01);
-                    x10 = fma(a1, b0, x10);
-                    x11 = fma(a1, b1, x11);
+            if (q < nblk) {
+                const int ro = (q + d) * IB, so = q * IB;
+                const double *Wq = W + q * IB * (IB + 1);
+                double x[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x[u][v] = 0.0;
+                for (int k = 0; k <= i0 + 3; ++k) {
+                    double a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] = (k <= i0 + u) ? XX(ro + i0 + u, ro + k) : 0.0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) b[v] = Wq[k * (IB + 1) + j0 + v];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) x[u][v] = fma(a[u], b[v], x[u][v]);
                 }
-                XX(ro + i0, so + j0) = -x00;
-                XX(ro + i0, so + j0 + 1) = -x01;
-                XX(ro + i0 + 1, so + j0) = -x10;
-                XX(ro + i0 + 1, so + j0 + 1) = -x11;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) XX(ro + i0 + u, so + j0 + v) = -x[u][v];
             }
             __syncthreads();
         }
@@ -295,27 +317,31 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(double *A, int64_t lda
 #undef LL
 #undef XX
 
-hipError_t launch_cholesky(hipStream_t st, double *A, int64_t n, int64_t lda, double mu, int border, double *linv,
-                           double *tmp, DevStatus *status) {
+hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail, double *A,
+                           int64_t n, int64_t lda, double mu, int border, double *linv, double *tmp,
+                           DevStatus *status) {
     if (n <= 0) return hipSuccess;
     static bool attr = false;
     const size_t shm = sizeof(double) * CB * LDS_LD;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)potrf_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)shm);
+                                  (int)shm);
         attr = true;
     }
     const int64_t nd = n - border;
     if (mu != 0.0 && nd > 0)
         hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, A, nd, lda, mu);
+    hipError_t e = hipSuccess;
+    bool trail_pending = false;  // ev_trail marks a trailing update not yet waited for on st
     for (int64_t k0 = 0; k0 < n; k0 += CB) {
         const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
         const int bh = (border && k0 + kb == n) ? 1 : 0;
         double *Xb = linv + (k0 / CB) * CB * CB;
         hipLaunchKernelGGL(potrf_block_kernel, dim3(1), dim3(256), shm, st, A, lda, k0, kb, bh, Xb, tmp, status);
-        const int64_t rest = n - k0 - kb;
+        const int64_t r1 = k0 + kb;          // first row of the next block
+        const int64_t rest = n - r1;
         if (rest <= 0) break;
-        double *a21 = A + (k0 + kb) * lda + k0;
+        double *a21 = A + r1 * lda + k0;
         // L21 = A21 X^T in place: each output tile owns its rows over all kb columns
         GemmDesc t{};
         t.M = rest; t.N = kb; t.K = kb;
@@ -324,19 +350,41 @@ hipError_t launch_cholesky(hipStream_t st, double *A, int64_t n, int64_t lda, do
         t.C = a21; t.ldc = lda;
         t.alpha = 1.0; t.beta = 0.0;
         t.stop_flag = &status->flag;
-        hipError_t e = launch_dgemm(st, t);
-        if (e != hipSuccess) return e;
-        GemmDesc s{};
-        s.M = rest; s.N = rest; s.K = kb;
-        s.A = a21; s.lda = lda; s.la = 0;
-        s.B = a21; s.ldb = lda; s.lb = 1;
-        s.C = A + (k0 + kb) * lda + (k0 + kb); s.ldc = lda;
-        s.alpha = -1.0; s.beta = 1.0;
-        s.lower = 1;
-        s.stop_flag = &status->flag;
-        e = launch_dgemm(st, s);
-        if (e != hipSuccess) return e;
+        if ((e = launch_dgemm(st, t)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
+        // block column of the next panel (rows >= r1, cols r1 .. r1+kb1), needed first
+        const int kb1 = (int)(rest < CB ? rest : CB);
+        if (trail_pending) {
+            if ((e = hipStreamWaitEvent(st, ev_trail, 0)) != hipSuccess) return e;
+            trail_pending = false;
+        }
+        GemmDesc nx{};
+        nx.M = rest; nx.N = kb1; nx.K = kb;
+        nx.A = a21; nx.lda = lda; nx.la = 0;
+        nx.B = a21; nx.ldb = lda; nx.lb = 1;
+        nx.C = A + r1 * lda + r1; nx.ldc = lda;
+        nx.alpha = -1.0; nx.beta = 1.0;
+        nx.mask_lower = 1;
+        nx.stop_flag = &status->flag;
+        if ((e = launch_dgemm(st, nx)) != hipSuccess) return e;
+        // the rest of the trailing matrix (cols >= r1 + kb1) on the side stream
+        const int64_t r2 = r1 + kb1, rest2 = n - r2;
+        if (rest2 > 0) {
+            if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
+            GemmDesc sy{};
+            sy.M = rest2; sy.N = rest2; sy.K = kb;
+            sy.A = A + r2 * lda + k0; sy.lda = lda; sy.la = 0;
+            sy.B = A + r2 * lda + k0; sy.ldb = lda; sy.lb = 1;
+            sy.C = A + r2 * lda + r2; sy.ldc = lda;
+            sy.alpha = -1.0; sy.beta = 1.0;
+            sy.lower = 1;
+            sy.stop_flag = &status->flag;
+            if ((e = launch_dgemm(side, sy)) != hipSuccess) return e;
+            if ((e = hipEventRecord(ev_trail, side)) != hipSuccess) return e;
+            trail_pending = true;
+        }
     }
+    if (trail_pending && (e = hipStreamWaitEvent(st, ev_trail, 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
