@@ -38,6 +38,23 @@ def flops(P, m, n, mq):
     }
 
 
+def gram_traffic():
+    """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (profiles/gram_ccf_medium_pmc.txt, scaled by a plain
+    copy of known size), or None if the GEMM source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "gram_ccf_medium_pmc.txt")
+    src = os.path.join(ROOT, "paper_2509_14185_amd", "csrc", "k_dgemm.hip")
+    try:
+        kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("#"))
+        if kv.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        return float(kv["gram_hbm_traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(inp, mu):
     """Oracle step time on a bounded sample of the same workload, extrapolated.
 
@@ -181,7 +198,8 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": gram_tf / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": gram_traffic(),
+            "traffic_unit": "bytes per launch",
         },
         "gram_cholesky_frac": (fl["gram"] + fl["cholesky"]) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS,
         "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
