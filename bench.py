@@ -55,6 +55,53 @@ def gram_traffic():
         return None
 
 
+def split_comparison(inp, mu, steps, target, fp64_elapsed):
+    """Split-precision form (FP32 hi/lo Gram, FP64 residual/gradient/solve)
+    from the same start: steps/s over the same number of steps and the steps
+    and time needed to reach the FP64 run's final validation max-norm
+    (within 5%), capped at three times as many steps."""
+    import torch
+
+    from paper_2509_14185_amd import gn
+
+    prob = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"],
+                      precision="split32")
+    prob.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+    theta = torch.from_numpy(inp["theta0"].copy()).cuda()
+    prob.step(theta.clone(), mu, stats=False)  # warm-up on a copy
+    torch.cuda.synchronize()
+    prob.profile_enable(True, steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.step(theta, mu, stats=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phases, nrec = prob.profile_read()
+    prob.profile_enable(False)
+    final = prob.eval(theta)["max_abs_R_val"]
+    # steps to reach the FP64 target (time = steps x measured step time)
+    theta2 = torch.from_numpy(inp["theta0"].copy()).cuda()
+    reached = None
+    for k in range(1, 3 * steps + 1):
+        st = prob.step(theta2, mu)
+        if prob.eval(theta2)["max_abs_R_val"] <= 1.05 * target:
+            reached = k
+            break
+    prob.close()
+    return {
+        "value": steps / el,
+        "unit": "steps/s",
+        "ms_per_step": 1e3 * el / steps,
+        "gram_ms": phases["gram"] / nrec,
+        "max_abs_R_val_final": final,
+        "target_max_abs_R_val": target,
+        "steps_to_target": reached,
+        "time_to_target_s": None if reached is None else reached * el / steps,
+        "fp64_steps_to_target": steps,
+        "fp64_time_to_target_s": fp64_elapsed,
+    }
+
+
 def cpu_baseline(inp, mu):
     """Oracle step time on a bounded sample of the same workload, extrapolated.
 
@@ -106,6 +153,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ccf_medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -204,6 +252,8 @@ def main():
         "gram_cholesky_frac": (fl["gram"] + fl["cholesky"]) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS,
         "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
     }
+    if not args.no_split:
+        out["split32"] = split_comparison(inp, mu, args.steps, ev1["max_abs_R_val"], elapsed)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inp, mu)

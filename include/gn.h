@@ -59,8 +59,12 @@ typedef enum {
  * local analogue with H Theta replaced by Theta (odd field). */
 typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1 } gn_equation;
 
-/* Arithmetic of the Jacobian/Gram bulk.  GN_FP64: FP64 throughout.
- * GN_SPLIT32: reserved for the split (hi/lo FP32) Jacobian and Gram. */
+/* Arithmetic of the Gram bulk.  GN_FP64: FP64 throughout.  GN_SPLIT32: the
+ * FP64 Jacobian is split into FP32 parts hi = fl32(J), lo = fl32(J - hi) and
+ * G = J^T J is formed as hi^T hi + hi^T lo + lo^T hi with FP32 matrix
+ * products, summed in FP64 every 32 rows (about 1e-7 relative error in G);
+ * the residual, g = J^T r, the Cholesky and the update stay FP64, so the
+ * step is an inexact Newton step with the same fixed point. */
 typedef enum { GN_FP64 = 0, GN_SPLIT32 = 1 } gn_precision;
 
 #define GN_MAX_LAYERS 8   /* affine layers */

@@ -40,6 +40,7 @@ struct gn_context {
     double *R = nullptr, *seed0 = nullptr, *seed1 = nullptr, *cscale = nullptr, *r_tmp = nullptr;
     double *vseed0 = nullptr, *vseed1 = nullptr, *useed = nullptr, *hadj_work = nullptr;
     double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
+    float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
     int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
     // phase timing
     std::vector<hipEvent_t> events;   // max_steps x (GN_PHASE_COUNT + 1)
@@ -209,7 +210,7 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     const int L = prob->n_layers;
     if (L < 1 || L > GN_MAX_LAYERS) return GN_EINVAL;
     if (prob->equation != GN_EQ_CCF1D && prob->equation != GN_EQ_BURGERS1D) return GN_EINVAL;
-    if (prob->precision != GN_FP64) return GN_EINVAL;
+    if (prob->precision != GN_FP64 && prob->precision != GN_SPLIT32) return GN_EINVAL;
     if (!(prob->lam > 0.0) || !(prob->c_norm >= 0.0)) return GN_EINVAL;
     if (prob->widths[0] != 1 || prob->widths[L] != 1) return GN_EINVAL;
     for (int l = 1; l < L; ++l)
@@ -345,6 +346,8 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     if (s == GN_OK) s = dev_alloc(h, A, &h->J, m_rows * h->ldJ);
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Bm, m_quad * h->ldJ);
     if (s == GN_OK) s = dev_alloc(h, A, &h->G, (P + 1) * h->ldG);
+    if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jhi, m_rows * h->ldJ);
+    if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jlo, m_rows * h->ldJ);
     if (s == GN_OK) s = dev_alloc(h, A, &h->partial, nparts * P);
     if (s != GN_OK) {
         free_list(A);
@@ -389,13 +392,20 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
     if (ldJ < p || ldG < p) return fail(h, GN_EINVAL, "leading dimension smaller than p%s");
     if (d_r && !d_g) return fail(h, GN_EINVAL, "d_g is required when d_r is given%s");
     if (d_r && p > h->cap) return fail(h, GN_EINVAL, "p exceeds the gradient workspace (P + 1)%s");
-    GemmDesc g{};
-    g.M = p; g.N = p; g.K = m;
-    g.A = d_J; g.lda = ldJ; g.la = 1;
-    g.B = d_J; g.ldb = ldJ; g.lb = 0;
-    g.C = d_G; g.ldc = ldG;
-    g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
-    GN_HIP(h, launch_dgemm(h->stream, g));
+    if (h->precision == GN_SPLIT32) {
+        if (!h->Jhi || m > h->n + 1 || ldJ > h->ldJ)
+            return fail(h, GN_EINVAL, "split-precision gram needs m <= N + 1 and ldJ <= the workspace ld%s");
+        GN_HIP(h, launch_split(h->stream, d_J, m, p, ldJ, h->Jhi, h->Jlo));
+        GN_HIP(h, launch_split_gram(h->stream, h->Jhi, h->Jlo, m, p, ldJ, d_G, ldG));
+    } else {
+        GemmDesc g{};
+        g.M = p; g.N = p; g.K = m;
+        g.A = d_J; g.lda = ldJ; g.la = 1;
+        g.B = d_J; g.ldb = ldJ; g.lb = 0;
+        g.C = d_G; g.ldc = ldG;
+        g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
+        GN_HIP(h, launch_dgemm(h->stream, g));
+    }
     if (d_r) GN_HIP(h, launch_gemv_t(h->stream, d_J, m, p, ldJ, d_r, d_g, h->gemv_work));
     return GN_OK;
 }
@@ -459,13 +469,23 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
         GN_HIP(h, launch_dgemm(st, c));
     }
     mark(h, 3);
-    GemmDesc g{};
-    g.M = P + 1; g.N = P + 1; g.K = m_rows;
-    g.A = J; g.lda = ldJ; g.la = 1;
-    g.B = J; g.ldb = ldJ; g.lb = 0;
-    g.C = h->G; g.ldc = h->ldG;
-    g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
-    GN_HIP(h, launch_dgemm(st, g));
+    if (h->precision == GN_SPLIT32) {
+        // G from FP32 hi/lo products; the border row g = J^T r and r^T r stay FP64
+        double *Grow = h->G + P * h->ldG;
+        GN_HIP(h, launch_split(st, J, m_rows, P, ldJ, h->Jhi, h->Jlo));
+        GN_HIP(h, launch_split_gram(st, h->Jhi, h->Jlo, m_rows, P, ldJ, h->G, h->ldG));
+        GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
+        GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
+        GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
+    } else {
+        GemmDesc g{};
+        g.M = P + 1; g.N = P + 1; g.K = m_rows;
+        g.A = J; g.lda = ldJ; g.la = 1;
+        g.B = J; g.ldb = ldJ; g.lb = 0;
+        g.C = h->G; g.ldc = h->ldG;
+        g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
+        GN_HIP(h, launch_dgemm(st, g));
+    }
     GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     mark(h, 4);
     // Cholesky of [[G + mu I, g], [g^T, r^T r]]: last row = (L^{-1} g)^T, Schur complement

@@ -135,6 +135,14 @@ int64_t gemv_t_work_size(int64_t m, int64_t p);
 hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj,
                          const double *r, double *g, double *work);
 
+// Split precision: hi = fl32(J), lo = fl32(J - hi) for the first p columns
+// (same leading dimension), and the lower triangle of
+// Jhi^T Jhi + Jhi^T Jlo + Jlo^T Jhi (FP32 MFMA products, FP64 accumulation
+// per 32-row chunk).
+hipError_t launch_split(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, float *hi, float *lo);
+hipError_t launch_split_gram(hipStream_t st, const float *hi, const float *lo, int64_t m, int64_t p, int64_t lda,
+                             double *C, int64_t ldc);
+
 // Blocked Cholesky of the lower triangle of A (n x n) after adding mu to the
 // first n - border diagonal entries.  border = 1: the last row is a border
 // row whose final diagonal entry receives the Schur complement (no sqrt).
