@@ -102,6 +102,62 @@ def split_comparison(inp, mu, steps, target, fp64_elapsed):
     }
 
 
+def batched_comparison(steps):
+    """Batched CCF workload (independent instances with their own lambda and
+    point count, shared widths): batched steps (gn_step_batched) against the
+    same instances stepped one after another with gn_step."""
+    import torch
+
+    import workloads
+    from paper_2509_14185_amd import gn
+
+    inps = workloads.make_batched_inputs()
+    mu = inps[0]["mu"]
+    pgs = []
+    for x in inps:
+        p = gn.Problem(x["equation"], x["widths"], x["lam"], x["c_norm"], x["c_target"])
+        p.set_points(x["s"], x["rho"], x["f"], x["sq"], x["wq"], x["sval"])
+        pgs.append(p)
+    batch = gn.Batch(pgs)
+    ts = [torch.from_numpy(x["theta0"].copy()).cuda() for x in inps]
+    init = [p.eval(t)["max_abs_R_val"] for p, t in zip(pgs, ts)]
+    batch.step(ts, mu, stats=False)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.step(ts, mu, stats=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    final = [p.eval(t)["max_abs_R_val"] for p, t in zip(pgs, ts)]
+    us = [torch.from_numpy(x["theta0"].copy()).cuda() for x in inps]
+    for p, u in zip(pgs, us):
+        p.step(u, mu, stats=False)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for p, u in zip(pgs, us):
+            p.step(u, mu, stats=False)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
+    batch.close()
+    for p in pgs:
+        p.close()
+    n = len(inps)
+    return {
+        "workload": "ccf_batched",
+        "instances": n,
+        "params": inps[0]["P"],
+        "rows_total": int(sum(x["n"] + 1 for x in inps)),
+        "steps": steps,
+        "batch_steps_per_s": steps / el,
+        "instance_steps_per_s": n * steps / el,
+        "sequential_instance_steps_per_s": n * steps / el_seq,
+        "speedup_vs_sequential": el_seq / el,
+        "max_abs_R_val_initial_median": float(sorted(init)[n // 2]),
+        "max_abs_R_val_final_median": float(sorted(final)[n // 2]),
+    }
+
+
 def cpu_baseline(inp, mu):
     """Oracle step time on a bounded sample of the same workload, extrapolated.
 
@@ -154,6 +210,7 @@ def main():
     ap.add_argument("--workload", default="ccf_medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched CCF workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -254,6 +311,9 @@ def main():
     }
     if not args.no_split:
         out["split32"] = split_comparison(inp, mu, args.steps, ev1["max_abs_R_val"], elapsed)
+    if not args.no_batched:
+        print("[bench] batched CCF workload", file=sys.stderr, flush=True)
+        out["batched"] = batched_comparison(10)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inp, mu)

@@ -164,6 +164,29 @@ gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats);
  * adjoint of gn_residual (backward of a differentiable residual). */
 gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *d_out);
 
+/* Batches of independent problems (e.g. one profile per blow-up rate lambda)
+ * that share the network widths (hence P) and use GN_FP64.  Each handle keeps
+ * its own points, lambda and workspace; the batch groups the dense stages of
+ * a step: one launch forms the Gram of every instance, each Cholesky panel is
+ * one launch over all instances (a workgroup per instance for the diagonal
+ * block, batched MFMA GEMMs for the panel and trailing update), and the back
+ * substitution and update are batched likewise.  gn_batch_create copies the
+ * handle list, reads their workspace layout (after gn_set_points) and
+ * allocates the device descriptor arrays.  It does not own the handles, which
+ * must outlive it; after gn_set_points on any of them, gn_step_batched returns
+ * GN_ESTATE.  Errors: GN_EINVAL (n < 1, NULL handle, mixed P or a GN_SPLIT32
+ * handle), GN_ESTATE (points not set), GN_ENOMEM.  All work is enqueued on
+ * `stream` (hipStream_t as void*, NULL = default stream). */
+typedef struct gn_batch_context *gn_batch;
+gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out);
+gn_status gn_batch_destroy(gn_batch b);
+/* One damped GN step of every instance: d_thetas is a host array of n device
+ * pointers (each updated in place, left unchanged on failure).  h_stats (n
+ * entries, may be NULL) receives each instance's statistics and status; the
+ * call synchronises only to fill it.  Returns GN_OK unless an argument or the
+ * runtime fails; per-instance failures are reported in h_stats[i].status. */
+gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_stats *h_stats);
+
 /* Phase timing of gn_step with HIP events recorded on the handle's stream
  * (tracing support; not part of the paper's method).  Phases: */
 typedef enum {

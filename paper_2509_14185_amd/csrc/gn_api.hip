@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gn_internal.h"
@@ -25,6 +26,7 @@ struct gn_context {
     std::string err;
     std::vector<void *> allocs;       // problem-lifetime allocations
     std::vector<void *> pt_allocs;    // point-set allocations
+    uint64_t points_gen = 0;          // bumped by every gn_set_points
     // P-dependent workspace (gn_create)
     int64_t cap = 0;                  // largest p accepted by gn_gram/gn_solve work buffers (P + 1)
     double *thetaT = nullptr, *linv = nullptr, *ybuf = nullptr, *zbuf = nullptr, *delta = nullptr;
@@ -186,13 +188,75 @@ void mark(gn_handle h, int k) {
     (void)hipEventRecord(h->events[(size_t)h->prof_count * (GN_PHASE_COUNT + 1) + k], h->stream);
 }
 
+// Phase 1 of a step: forward jets, residual rows into column P of the
+// workspace J (the Gram of [J | r] then carries g and r^T r), validation
+// max-norm, Jacobian rows and the Hilbert coupling.  Marks phase boundaries.
+gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks) {
+    hipStream_t st = h->stream;
+    const int64_t P = h->md.P;
+    double *J = h->J;
+    const int64_t ldJ = h->ldJ;
+    GN_TRY(forward_all(h, d_theta));
+    GN_TRY(residual_rows(h, J + P, ldJ, true));
+    GN_TRY(validation(h, d_theta));
+    if (marks) mark(h, 1);
+    SweepBatch b{};
+    b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
+    GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, b));
+    SweepBatch o{};
+    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + h->n * ldJ; o.ld = ldJ;
+    GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, o));
+    if (h->equation == GN_EQ_CCF1D) {
+        SweepBatch nb{};
+        nb.x = h->nodes.q; nb.s0 = h->nodes.E; nb.s1c = 0.0; nb.n = h->m; nb.rows = h->Bm; nb.ld = ldJ;
+        GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, nb));
+    }
+    if (marks) mark(h, 2);
+    if (h->equation == GN_EQ_CCF1D) {
+        GemmDesc c{};
+        c.M = h->n; c.N = P; c.K = h->m;
+        c.A = h->Q; c.lda = h->ldQ; c.la = 0;
+        c.B = h->Bm; c.ldb = ldJ; c.lb = 0;
+        c.C = J; c.ldc = ldJ;
+        c.alpha = 1.0; c.beta = 1.0; c.rowscale = h->cscale;
+        GN_HIP(h, launch_dgemm(st, c));
+    }
+    return GN_OK;
+}
+
 double bits_to_double(unsigned long long b) {
     double d;
     memcpy(&d, &b, sizeof d);
     return d;
 }
 
+void fill_stats(const DevStatus &ds, gn_stats *o) {
+    memset(o, 0, sizeof *o);
+    o->half_sq_norm = 0.5 * ds.half_sq_norm;
+    o->max_abs_R = bits_to_double(ds.max_R);
+    o->max_abs_R_val = bits_to_double(ds.max_R_val);
+    o->grad_dot_delta = -ds.grad_dot_delta;
+    o->model_sq_norm = ds.model_sq_norm;
+    o->chol_info = ds.chol_info;
+    o->updated = ds.updated;
+    const bool r_finite = (ds.half_sq_norm - ds.half_sq_norm == 0.0);
+    o->status = !r_finite ? GN_ENONFINITE : (ds.flag ? GN_ENOTPD : (ds.nonfinite ? GN_ENONFINITE : GN_OK));
+}
+
 }  // namespace
+
+struct gn_batch_context {
+    std::vector<gn_handle> hs;
+    hipStream_t stream = nullptr;
+    int64_t P = 0;
+    std::vector<BatchChol> h_bc;
+    std::vector<GemmDesc> h_gram, h_chol;
+    BatchChol *d_bc = nullptr;
+    GemmDesc *d_gram = nullptr, *d_chol = nullptr;
+    std::vector<double *> uploaded_thetas;
+    std::vector<DevStatus> ds;
+    std::vector<uint64_t> gen;  // point-set generation of every handle when the batch was made
+};
 
 extern "C" {
 
@@ -304,6 +368,7 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     if (h->equation != GN_EQ_CCF1D) m_quad = 0;
     GN_HIP(h, hipStreamSynchronize(h->stream));
     free_list(h->pt_allocs);
+    ++h->points_gen;
     h->n = h->m = h->nv = 0;
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
@@ -441,33 +506,7 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
     const int64_t ldJ = h->ldJ;
     mark(h, 0);
     GN_HIP(h, launch_reset_status(st, h->status));
-    // residual rows go to column P of J: the Gram of [J | r] then carries
-    // g = J^T r in its last row and r^T r in its corner
-    GN_TRY(forward_all(h, d_theta));
-    GN_TRY(residual_rows(h, J + P, ldJ, true));
-    GN_TRY(validation(h, d_theta));
-    mark(h, 1);
-    SweepBatch b{};
-    b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
-    GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, b));
-    SweepBatch o{};
-    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + h->n * ldJ; o.ld = ldJ;
-    GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, o));
-    if (h->equation == GN_EQ_CCF1D) {
-        SweepBatch nb{};
-        nb.x = h->nodes.q; nb.s0 = h->nodes.E; nb.s1c = 0.0; nb.n = h->m; nb.rows = h->Bm; nb.ld = ldJ;
-        GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, nb));
-    }
-    mark(h, 2);
-    if (h->equation == GN_EQ_CCF1D) {
-        GemmDesc c{};
-        c.M = h->n; c.N = P; c.K = h->m;
-        c.A = h->Q; c.lda = h->ldQ; c.la = 0;
-        c.B = h->Bm; c.ldb = ldJ; c.lb = 0;
-        c.C = J; c.ldc = ldJ;
-        c.alpha = 1.0; c.beta = 1.0; c.rowscale = h->cscale;
-        GN_HIP(h, launch_dgemm(st, c));
-    }
+    GN_TRY(build_step_jacobian(h, d_theta, true));
     mark(h, 3);
     if (h->precision == GN_SPLIT32) {
         // G from FP32 hi/lo products; the border row g = J^T r and r^T r stay FP64
@@ -502,20 +541,8 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
     if (!h_stats) return GN_OK;
     DevStatus ds;
     GN_TRY(read_status(h, &ds));
-    memset(h_stats, 0, sizeof *h_stats);
-    h_stats->half_sq_norm = 0.5 * ds.half_sq_norm;
-    h_stats->max_abs_R = bits_to_double(ds.max_R);
-    h_stats->max_abs_R_val = bits_to_double(ds.max_R_val);
-    h_stats->grad_dot_delta = -ds.grad_dot_delta;
-    h_stats->model_sq_norm = ds.model_sq_norm;
-    h_stats->chol_info = ds.chol_info;
-    h_stats->updated = ds.updated;
-    gn_status s = GN_OK;
-    const bool r_finite = (ds.half_sq_norm - ds.half_sq_norm == 0.0);
-    if (!r_finite) s = GN_ENONFINITE;       // a non-finite residual is the root cause
-    else if (ds.flag) s = GN_ENOTPD;
-    else if (ds.nonfinite) s = GN_ENONFINITE;
-    h_stats->status = s;
+    fill_stats(ds, h_stats);
+    const gn_status s = (gn_status)h_stats->status;
     if (s == GN_ENOTPD) return fail(h, s, "Cholesky pivot %s is not positive", std::to_string(ds.chol_info).c_str());
     if (s == GN_ENONFINITE) return fail(h, s, "non-finite residual or update%s");
     return GN_OK;
@@ -568,6 +595,109 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
         GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, nb, h->partial + (c0 + c1) * P, &c2));
     }
     GN_HIP(h, launch_reduce_partials(st, h->partial, c0 + c1 + c2, P, d_out, 0));
+    return GN_OK;
+}
+
+gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out) {
+    if (!hs || n < 1 || !out) return GN_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || hs[i]->n <= 0) return GN_ESTATE;
+        if (hs[i]->md.P != hs[0]->md.P || hs[i]->precision != GN_FP64) return GN_EINVAL;
+    }
+    gn_batch b = new (std::nothrow) gn_batch_context();
+    if (!b) return GN_ENOMEM;
+    b->hs.assign(hs, hs + n);
+    b->stream = (hipStream_t)stream;
+    b->P = hs[0]->md.P;
+    const int64_t P = b->P;
+    for (int i = 0; i < n; ++i) {
+        gn_handle h = hs[i];
+        GemmDesc g{};
+        g.M = P + 1; g.N = P + 1; g.K = h->n + 1;
+        g.A = h->J; g.lda = h->ldJ; g.la = 1;
+        g.B = h->J; g.ldb = h->ldJ; g.lb = 0;
+        g.C = h->G; g.ldc = h->ldG;
+        g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
+        b->h_gram.push_back(g);
+        BatchChol c{};
+        c.A = h->G; c.lda = h->ldG; c.linv = h->linv; c.y = h->ybuf; c.x = h->delta; c.theta = nullptr;
+        c.status = h->status;
+        b->h_bc.push_back(c);
+    }
+    cholesky_batched_descs(b->h_bc.data(), n, P + 1, b->h_chol);
+    auto up = [&](auto **dst, const auto &v) -> bool {
+        using T = typename std::remove_reference<decltype(v)>::type::value_type;
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(T) * (v.size() ? v.size() : 1)) != hipSuccess) return false;
+        *dst = (std::remove_reference_t<decltype(*dst)>)p;
+        return v.empty() || hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(&b->d_bc, b->h_bc) || !up(&b->d_gram, b->h_gram) || !up(&b->d_chol, b->h_chol)) {
+        (void)hipFree(b->d_bc);
+        (void)hipFree(b->d_gram);
+        (void)hipFree(b->d_chol);
+        delete b;
+        return GN_ENOMEM;
+    }
+    b->uploaded_thetas.assign(n, nullptr);
+    b->ds.resize(n);
+    for (int i = 0; i < n; ++i) b->gen.push_back(hs[i]->points_gen);
+    *out = b;
+    return GN_OK;
+}
+
+gn_status gn_batch_destroy(gn_batch b) {
+    if (!b) return GN_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(b->d_bc);
+    (void)hipFree(b->d_gram);
+    (void)hipFree(b->d_chol);
+    delete b;
+    return GN_OK;
+}
+
+gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_stats *h_stats) {
+    if (!b || !d_thetas || !(mu >= 0.0)) return GN_EINVAL;
+    const int n = (int)b->hs.size();
+    const int64_t P = b->P;
+    hipStream_t st = b->stream;
+    gn_handle h0 = b->hs[0];
+    for (int i = 0; i < n; ++i) {
+        if (!d_thetas[i]) return GN_EINVAL;
+        if (b->hs[i]->points_gen != b->gen[i]) return GN_ESTATE;
+    }
+    // parameter pointers live in the device descriptors; re-upload when they change
+    bool changed = false;
+    for (int i = 0; i < n; ++i) changed |= (b->uploaded_thetas[i] != d_thetas[i]);
+    if (changed) {
+        GN_HIP(h0, hipStreamSynchronize(st));
+        for (int i = 0; i < n; ++i) b->h_bc[i].theta = d_thetas[i];
+        GN_HIP(h0, hipMemcpy(b->d_bc, b->h_bc.data(), sizeof(BatchChol) * n, hipMemcpyHostToDevice));
+        b->uploaded_thetas.assign(d_thetas, d_thetas + n);
+    }
+    // phase 1 per instance: residual, validation, Jacobian with r in column P
+    for (int i = 0; i < n; ++i) {
+        gn_handle h = b->hs[i];
+        hipStream_t own = h->stream;
+        h->stream = st;
+        gn_status e = GN_OK;
+        if (launch_reset_status(st, h->status) != hipSuccess) e = GN_EDEVICE;
+        if (e == GN_OK) e = build_step_jacobian(h, d_thetas[i], false);
+        if (e == GN_OK && launch_sumsq(st, h->J + P, h->n + 1, h->ldJ, &h->status->half_sq_norm, h->red_work) != hipSuccess)
+            e = GN_EDEVICE;
+        h->stream = own;
+        if (e != GN_OK) return e;
+    }
+    // batched Gram, bordered Cholesky, back substitution and update
+    GN_HIP(h0, launch_dgemm_batched(st, b->h_gram.data(), b->d_gram, n));
+    GN_HIP(h0, launch_cholesky_batched(st, b->h_bc.data(), b->d_bc, b->h_chol.data(), b->d_chol, n, P + 1, mu, 1));
+    GN_HIP(h0, launch_solve_upper_batched(st, b->d_bc, n, P));
+    if (!h_stats) return GN_OK;
+    for (int i = 0; i < n; ++i)
+        GN_HIP(h0, hipMemcpyAsync(&b->ds[i], b->hs[i]->status, sizeof(DevStatus), hipMemcpyDeviceToHost, st));
+    GN_HIP(h0, hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) fill_stats(b->ds[i], &h_stats[i]);
     return GN_OK;
 }
 

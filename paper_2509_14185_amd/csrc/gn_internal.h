@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "gn.h"
 
 namespace gn {
@@ -128,6 +130,10 @@ struct GemmDesc {
     const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
+// n independent GEMMs in one launch (problem = blockIdx.y): h_descs is the
+// host copy (grid sizing), d_descs the same descriptors in device memory.
+// Layouts and the lower flag must agree across the batch.
+hipError_t launch_dgemm_batched(hipStream_t st, const GemmDesc *h_descs, const GemmDesc *d_descs, int n);
 
 // g = J^T r (J m x p row-major) via deterministic two-pass reduction;
 // work must hold gemv_t_work_size(m, p) doubles.
@@ -157,6 +163,26 @@ int64_t chol_tmp_size();
 hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail, double *A,
                            int64_t n, int64_t lda, double mu, int border, double *linv, double *tmp,
                            DevStatus *status);
+// Batched bordered Cholesky and back substitution over instances that share
+// the order n (one instance = one problem of a batch).
+struct BatchChol {
+    double *A;          // bordered Gram, (n+1) x lda, factored in place
+    int64_t lda;
+    double *linv;       // diagonal-block inverses
+    double *y, *x;      // right-hand side workspace, solution (delta)
+    double *theta;      // parameters updated in place
+    DevStatus *status;
+};
+hipError_t launch_cholesky_batched(hipStream_t st, const BatchChol *h_bc, const BatchChol *d_bc,
+                                   const GemmDesc *h_gd, const GemmDesc *d_gd, int nb, int64_t n, double mu,
+                                   int border);
+// Descriptors of the per-panel TRSM and trailing SYRK of every instance
+// ([panel][pass][instance]) for launch_cholesky_batched.
+void cholesky_batched_descs(const BatchChol *bc, int nb, int64_t n, std::vector<GemmDesc> &out);
+// y = -(border row), |w|^2 and the Schur complement into status, L^T x = y,
+// then theta += x when finite and the factorisation succeeded.
+hipError_t launch_solve_upper_batched(hipStream_t st, const BatchChol *d_bc, int nb, int64_t n);
+
 // L z = b (forward), then L^T x = z (back), using the factor and the
 // diagonal-block inverses from launch_cholesky.  b is overwritten.
 hipError_t launch_solve_lower(hipStream_t st, const double *L, int64_t n, int64_t ldl,

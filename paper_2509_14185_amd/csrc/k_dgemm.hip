@@ -142,8 +142,14 @@ struct TileLoader {
     }
 };
 
-template <int BM, int BN, int BK, int LA, int LB>
-__global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, int tiles_m, int tiles_n) {
+template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
+__global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0,
+                                                                 const GemmDesc *__restrict__ batch) {
+    // batched launches take problem blockIdx.y from a device array of descriptors
+    const GemmDesc g = BATCH ? batch[blockIdx.y] : g0;
+    const int tiles_m = BATCH ? (int)((g.M + BM - 1) / BM) : tiles_m0;
+    const int tiles_n = BATCH ? (int)((g.N + BN - 1) / BN) : tiles_n0;
+    if (g.M <= 0 || g.N <= 0) return;
     if (g.stop_flag != nullptr && *g.stop_flag != 0) return;
     constexpr int WAVES_M = 2, WAVES_N = 4;
     constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
@@ -255,44 +261,71 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g, in
     }
 }
 
-template <int BM, int BN, int BK, int LA, int LB>
-static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int tiles_n, int64_t blocks) {
+template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
+static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int tiles_n, int64_t blocks,
+                             const GemmDesc *batch, int nbatch) {
     constexpr size_t shm = sizeof(double) * 2 * BK * (BM + BN);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB>,
+        (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         attr = true;
     }
-    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB>), dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st,
-                       g, tiles_m, tiles_n);
+    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)blocks, (unsigned)nbatch),
+                       dim3(GEMM_THREADS), shm, st, g, tiles_m, tiles_n, batch);
     return hipGetLastError();
 }
 
 template <int BM, int BN, int BK>
-static hipError_t launch_tiles(hipStream_t st, const GemmDesc &g) {
-    const int tiles_m = (int)((g.M + BM - 1) / BM);
-    const int tiles_n = (int)((g.N + BN - 1) / BN);
-    int64_t supers;
-    if (g.lower) {
-        supers = lower_super_count(tiles_m);
-    } else {
-        supers = (int64_t)((tiles_m + SUP_M - 1) / SUP_M) * ((tiles_n + SUP_N - 1) / SUP_N);
-    }
-    if (supers <= 0) return hipSuccess;
-    const int64_t blocks = (supers + NXCD - 1) / NXCD * NXCD * SUP;
-    if (g.la == 0 && g.lb == 0) return launch_one<BM, BN, BK, 0, 0>(st, g, tiles_m, tiles_n, blocks);
-    if (g.la == 0 && g.lb == 1) return launch_one<BM, BN, BK, 0, 1>(st, g, tiles_m, tiles_n, blocks);
-    if (g.la == 1 && g.lb == 0) return launch_one<BM, BN, BK, 1, 0>(st, g, tiles_m, tiles_n, blocks);
-    return launch_one<BM, BN, BK, 1, 1>(st, g, tiles_m, tiles_n, blocks);
+static int64_t blocks_for(const GemmDesc &g, int &tiles_m, int &tiles_n) {
+    tiles_m = (int)((g.M + BM - 1) / BM);
+    tiles_n = (int)((g.N + BN - 1) / BN);
+    if (g.M <= 0 || g.N <= 0) return 0;
+    const int64_t supers = g.lower ? lower_super_count(tiles_m)
+                                   : (int64_t)((tiles_m + SUP_M - 1) / SUP_M) * ((tiles_n + SUP_N - 1) / SUP_N);
+    return (supers + NXCD - 1) / NXCD * NXCD * SUP;
+}
+
+template <int BM, int BN, int BK, bool BATCH>
+static hipError_t launch_tiles(hipStream_t st, const GemmDesc &g, int64_t blocks, int tiles_m, int tiles_n,
+                               const GemmDesc *batch, int nbatch) {
+    if (blocks <= 0) return hipSuccess;
+    if (g.la == 0 && g.lb == 0) return launch_one<BM, BN, BK, 0, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
+    if (g.la == 0 && g.lb == 1) return launch_one<BM, BN, BK, 0, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
+    if (g.la == 1 && g.lb == 0) return launch_one<BM, BN, BK, 1, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
+    return launch_one<BM, BN, BK, 1, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
 }
 
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.lower && g.M != g.N) return hipErrorInvalidValue;
+    int tm, tn;
     // BN must equal BM when lower; in-place uses (C aliasing A) need BN >= N
-    if (!g.lower && g.N <= 64) return launch_tiles<128, 64, 32>(st, g);
-    return launch_tiles<128, 128, 32>(st, g);
+    if (!g.lower && g.N <= 64) {
+        const int64_t b = blocks_for<128, 64, 32>(g, tm, tn);
+        return launch_tiles<128, 64, 32, false>(st, g, b, tm, tn, nullptr, 1);
+    }
+    const int64_t b = blocks_for<128, 128, 32>(g, tm, tn);
+    return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, 1);
+}
+
+hipError_t launch_dgemm_batched(hipStream_t st, const GemmDesc *h_descs, const GemmDesc *d_descs, int n) {
+    if (n <= 0) return hipSuccess;
+    // the tile configuration and layouts must agree across the batch
+    const GemmDesc &f = h_descs[0];
+    const bool small_n = !f.lower && f.N <= 64;
+    int64_t blocks = 0;
+    for (int i = 0; i < n; ++i) {
+        const GemmDesc &g = h_descs[i];
+        if (g.la != f.la || g.lb != f.lb || g.lower != f.lower || (!g.lower && g.N <= 64) != small_n)
+            return hipErrorInvalidValue;
+        if (g.lower && g.M != g.N) return hipErrorInvalidValue;
+        int tm, tn;
+        const int64_t b = small_n ? blocks_for<128, 64, 32>(g, tm, tn) : blocks_for<128, 128, 32>(g, tm, tn);
+        if (b > blocks) blocks = b;
+    }
+    if (small_n) return launch_tiles<128, 64, 32, true>(st, f, blocks, 0, 0, d_descs, n);
+    return launch_tiles<128, 128, 32, true>(st, f, blocks, 0, 0, d_descs, n);
 }
 
 // ---------------------------------------------------------------- g = J^T r

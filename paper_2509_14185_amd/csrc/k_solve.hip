@@ -22,6 +22,8 @@
 // 128-row block applies the known block to the rest of the right-hand side,
 // one workgroup per remaining block, and the workgroup of the next block
 // then forms that block's unknowns.
+#include <vector>
+
 #include "gn_internal.h"
 
 namespace gn {
@@ -135,8 +137,8 @@ __device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *) {
 // L^{-1} of the block (row-major CB x CB, zero outside the factor and on the
 // border row/column).  Products inside the block use 4 x 4 (or 2 x 2)
 // register blocks with independent accumulators.
-__global__ __launch_bounds__(256) void potrf_block_kernel(double *A, int64_t lda, int64_t k0, int kb, int border_here,
-                                                         double *X, double *T, DevStatus *status) {
+__device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t k0, int kb, int border_here, double *X,
+                                                 DevStatus *status) {
     if (status->flag) return;
     extern __shared__ double s[];
     __shared__ int fail_sh;
@@ -314,6 +316,18 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(double *A, int64_t lda
     }
 }
 
+__global__ __launch_bounds__(256) void potrf_block_kernel(double *A, int64_t lda, int64_t k0, int kb, int border_here,
+                                                         double *X, double *, DevStatus *status) {
+    potrf_block_body(A, lda, k0, kb, border_here, X, status);
+}
+
+// One diagonal block per instance of a batch (blockIdx.x = instance).
+__global__ __launch_bounds__(256) void potrf_block_batched_kernel(const BatchChol *__restrict__ bc, int64_t k0, int kb,
+                                                                 int border_here) {
+    const BatchChol c = bc[blockIdx.x];
+    potrf_block_body(c.A, c.lda, k0, kb, border_here, c.linv + (k0 / CB) * CB * CB, c.status);
+}
+
 #undef LL
 #undef XX
 
@@ -472,9 +486,9 @@ __global__ __launch_bounds__(256) void back_init_kernel(const double *linv, cons
     block_upper_apply(linv, ys, x, kb);
 }
 
-__global__ __launch_bounds__(256) void back_update_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
-                                                          const double *__restrict__ linv, double *y, double *x,
-                                                          int64_t I, const DevStatus *status) {
+__device__ __forceinline__ void back_update_body(const double *__restrict__ L, int64_t n, int64_t ldl,
+                                                 const double *__restrict__ linv, double *y, double *x, int64_t I,
+                                                 const DevStatus *status) {
     if (status->flag) return;
     __shared__ double xs[CB];
     __shared__ double part[256];
@@ -510,6 +524,149 @@ __global__ __launch_bounds__(256) void back_update_kernel(const double *__restri
     if (w != I - 1) return;
     __syncthreads();
     block_upper_apply(linv + w * CB * CB, ys, x + w * CB, CB);
+}
+
+__global__ __launch_bounds__(256) void back_update_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
+                                                          const double *__restrict__ linv, double *y, double *x,
+                                                          int64_t I, const DevStatus *status) {
+    back_update_body(L, n, ldl, linv, y, x, I, status);
+}
+
+// blockIdx.y = instance
+__global__ __launch_bounds__(256) void back_init_batched_kernel(const BatchChol *__restrict__ bc, int64_t n) {
+    const BatchChol c = bc[blockIdx.y];
+    if (c.status->flag) return;
+    const int64_t nblk = (n + CB - 1) / CB, rl = (nblk - 1) * CB;
+    const int kb = (int)(n - rl);
+    __shared__ double ys[CB];
+    if (threadIdx.x < kb) ys[threadIdx.x] = c.y[rl + threadIdx.x];
+    __syncthreads();
+    block_upper_apply(c.linv + (nblk - 1) * CB * CB, ys, c.x + rl, kb);
+}
+
+__global__ __launch_bounds__(256) void back_update_batched_kernel(const BatchChol *__restrict__ bc, int64_t n, int64_t I) {
+    const BatchChol c = bc[blockIdx.y];
+    back_update_body(c.A, n, c.lda, c.linv, c.y, c.x, I, c.status);
+}
+
+// Border row of the bordered factor (row n of A): y = -w, |w|^2, corner value.
+__global__ __launch_bounds__(256) void border_extract_batched_kernel(const BatchChol *__restrict__ bc, int64_t n) {
+    const BatchChol c = bc[blockIdx.y];
+    __shared__ double sh[256];
+    const double *w = c.A + n * c.lda;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double v = w[i];
+        c.y[i] = -v;
+        acc = fma(v, v, acc);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        c.status->grad_dot_delta = sh[0];
+        c.status->model_sq_norm = w[n];
+    }
+}
+
+// theta += delta when the residual is finite, the factorisation succeeded and
+// delta is finite (one workgroup per instance).
+__global__ __launch_bounds__(256) void update_batched_kernel(const BatchChol *__restrict__ bc, int64_t p) {
+    const BatchChol c = bc[blockIdx.y];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < p; i += 256) {
+        const double v = c.x[i];
+        if (!(v - v == 0.0)) bad = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && bad) c.status->nonfinite = 1;
+    const double h = c.status->half_sq_norm;
+    if (!(h - h == 0.0) || c.status->flag || bad) {
+        if (threadIdx.x == 0 && !(h - h == 0.0)) c.status->nonfinite = 1;
+        return;
+    }
+    for (int64_t i = threadIdx.x; i < p; i += 256) c.theta[i] += c.x[i];
+    if (threadIdx.x == 0) c.status->updated = 1;
+}
+
+hipError_t launch_cholesky_batched(hipStream_t st, const BatchChol *h_bc, const BatchChol *d_bc,
+                                   const GemmDesc *h_gd, const GemmDesc *d_gd, int nb, int64_t n, double mu,
+                                   int border) {
+    if (nb <= 0 || n <= 0) return hipSuccess;
+    static bool attr = false;
+    const size_t shm = sizeof(double) * CB * LDS_LD;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)potrf_block_batched_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        attr = true;
+    }
+    const int64_t nd = n - border;
+    if (mu != 0.0 && nd > 0)
+        for (int i = 0; i < nb; ++i)
+            hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, h_bc[i].A, nd,
+                               h_bc[i].lda, mu);
+    hipError_t e;
+    int64_t panel = 0;
+    for (int64_t k0 = 0; k0 < n; k0 += CB, ++panel) {
+        const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
+        const int bh = (border && k0 + kb == n) ? 1 : 0;
+        hipLaunchKernelGGL(potrf_block_batched_kernel, dim3((unsigned)nb), dim3(256), shm, st, d_bc, k0, kb, bh);
+        if (n - k0 - kb <= 0) break;
+        // descriptors per panel: [panel][0: TRSM, 1: trailing SYRK][instance]
+        const GemmDesc *ht = h_gd + (panel * 2 + 0) * nb, *dt = d_gd + (panel * 2 + 0) * nb;
+        const GemmDesc *hs = h_gd + (panel * 2 + 1) * nb, *ds = d_gd + (panel * 2 + 1) * nb;
+        if ((e = launch_dgemm_batched(st, ht, dt, nb)) != hipSuccess) return e;
+        if ((e = launch_dgemm_batched(st, hs, ds, nb)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+void cholesky_batched_descs(const BatchChol *bc, int nb, int64_t n, std::vector<GemmDesc> &out) {
+    out.clear();
+    for (int64_t k0 = 0; k0 < n; k0 += CB) {
+        const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
+        const int64_t r1 = k0 + kb, rest = n - r1;
+        if (rest <= 0) break;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < nb; ++i) {
+                double *A = bc[i].A;
+                const int64_t lda = bc[i].lda;
+                double *a21 = A + r1 * lda + k0;
+                GemmDesc g{};
+                if (pass == 0) {
+                    g.M = rest; g.N = kb; g.K = kb;
+                    g.A = a21; g.lda = lda; g.la = 0;
+                    g.B = bc[i].linv + (k0 / CB) * CB * CB; g.ldb = CB; g.lb = 1;
+                    g.C = a21; g.ldc = lda;
+                    g.alpha = 1.0; g.beta = 0.0;
+                } else {
+                    g.M = rest; g.N = rest; g.K = kb;
+                    g.A = a21; g.lda = lda; g.la = 0;
+                    g.B = a21; g.ldb = lda; g.lb = 1;
+                    g.C = A + r1 * lda + r1; g.ldc = lda;
+                    g.alpha = -1.0; g.beta = 1.0;
+                    g.lower = 1;
+                }
+                g.stop_flag = &bc[i].status->flag;
+                out.push_back(g);
+            }
+    }
+}
+
+hipError_t launch_solve_upper_batched(hipStream_t st, const BatchChol *d_bc, int nb, int64_t n) {
+    if (n <= 0 || nb <= 0) return hipSuccess;
+    const int64_t nblk = (n + CB - 1) / CB;
+    hipLaunchKernelGGL(border_extract_batched_kernel, dim3(1, (unsigned)nb), dim3(256), 0, st, d_bc, n);
+    hipLaunchKernelGGL(back_init_batched_kernel, dim3(1, (unsigned)nb), dim3(256), 0, st, d_bc, n);
+    for (int64_t I = nblk - 1; I >= 1; --I)
+        hipLaunchKernelGGL(back_update_batched_kernel, dim3((unsigned)I, (unsigned)nb), dim3(256), 0, st, d_bc, n, I);
+    hipLaunchKernelGGL(update_batched_kernel, dim3(1, (unsigned)nb), dim3(256), 0, st, d_bc, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_solve_lower(hipStream_t st, const double *L, int64_t n, int64_t ldl, const double *linv,

@@ -81,6 +81,9 @@ def load():
         "gn_step": (ctypes.c_int, [_VP, _VP, _D, ctypes.POINTER(_Stats)]),
         "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
         "gn_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+        "gn_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
+        "gn_batch_destroy": (ctypes.c_int, [_VP]),
+        "gn_step_batched": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), _D, ctypes.POINTER(_Stats)]),
         "gn_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
         "gn_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32)]),
@@ -243,6 +246,63 @@ def _profile_methods():
 
 
 Problem.profile_enable, Problem.profile_read = _profile_methods()
+
+
+class Batch:
+    """Independent problems with equal widths stepped together (gn_step_batched).
+
+    The problems must have their points set; calling set_points on one of
+    them afterwards makes the batch stale (GN_ESTATE)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        if not self.problems:
+            raise ValueError("empty batch")
+        self.lib = self.problems[0].lib
+        self.device = self.problems[0].device
+        hs = (_VP * len(self.problems))(*[p.h.value for p in self.problems])
+        b = _VP()
+        st = self.lib.gn_batch_create(hs, len(self.problems),
+                                      ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream),
+                                      ctypes.byref(b))
+        if st != GN_OK:
+            raise GNError(st, f"gn_batch_create: {self.lib.gn_status_string(st).decode()}")
+        self.b = b
+
+    def __len__(self):
+        return len(self.problems)
+
+    def step(self, thetas, mu, stats=True):
+        """One damped GN step of every instance; thetas updated in place.
+        Returns a list of per-instance stats dicts (rc = per-instance status)."""
+        if len(thetas) != len(self.problems):
+            raise ValueError("one parameter vector per instance")
+        for t, p in zip(thetas, self.problems):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == p.P
+        ptrs = (_VP * len(thetas))(*[t.data_ptr() for t in thetas])
+        out = (_Stats * len(thetas))() if stats else None
+        st = self.lib.gn_step_batched(self.b, ptrs, float(mu), out)
+        if st != GN_OK:
+            raise GNError(st, f"gn_step_batched: {self.lib.gn_status_string(st).decode()}")
+        if not stats:
+            return None
+        res = []
+        for s in out:
+            d = s.as_dict()
+            d["rc"] = d["status"]
+            res.append(d)
+        return res
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.gn_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class ResidualFunction(torch.autograd.Function):

@@ -1,0 +1,172 @@
+"""GPU parity of the batched step (gn_step_batched) against the CPU FP64
+oracle and against the single-instance gn_step.
+
+Instances differ in blow-up rate lambda, point count and seed (batched CCF
+workload).  Tolerances as for the single step: backward error of the solve
+<= 5e-14, forward error <= max(1e-12, 10 kappa eps), statistics relative
+1e-12; batched versus single-instance steps agree to 1e-12 (same kernels,
+summation order may differ only in the reductions)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import gn as ogn
+from oracle import profile1d as p1
+from paper_2509_14185_amd import gn
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def make_problem(inp):
+    pg = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
+    pg.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+    return pg
+
+
+def check_against_oracle(inp, theta0, theta1, st, mu):
+    po = p1.Problem.from_inputs(inp)
+    ref, ost = ogn.step(po, theta0, mu)
+    d, dref = theta1 - theta0, ref - theta0
+    G, g = ost["G"], ost["g"]
+    assert ogn.backward_error(G, mu, g, d) < 5e-14
+    kappa = np.linalg.cond(G + mu * np.eye(G.shape[0]))
+    assert rel(d, dref) < max(1e-12, 10 * kappa * EPS)
+    assert abs(st["half_sq_norm"] - ost["half_sq_norm"]) <= 1e-12 * ost["half_sq_norm"]
+    gd = float(g @ dref)
+    assert st["grad_dot_delta"] < 0 and abs(st["grad_dot_delta"] - gd) <= 1e-10 * abs(gd)
+    R, _ = p1.raw_residual(po, theta0)
+    assert abs(st["max_abs_R"] - np.max(np.abs(R))) <= 1e-12 * np.max(np.abs(R))
+    assert abs(st["max_abs_R_val"] - p1.validation_max(po, theta0)) <= 1e-12 * p1.validation_max(po, theta0)
+
+
+@pytest.fixture(scope="module")
+def small():
+    # P = 481: the bordered order 482 spans four 128-wide panels with a ragged tail
+    print("\n[gpu batch] small batch: 5 instances, widths [1,20,20,1], n in [200,900]", flush=True)
+    inps = workloads.make_batched_inputs(instances=5, n_range=(200, 900), m_quad=64, widths=[1, 20, 20, 1], seed=9)
+    pgs = [make_problem(x) for x in inps]
+    b = gn.Batch(pgs)
+    yield inps, pgs, b
+    b.close()
+    for p in pgs:
+        p.close()
+
+
+def test_batched_step_matches_oracle(small):
+    inps, pgs, b = small
+    mu = 1e-3
+    ts = [dev(x["theta0"]) for x in inps]
+    sts = b.step(ts, mu)
+    for inp, t, st in zip(inps, ts, sts):
+        assert st["rc"] == gn.GN_OK and st["updated"] == 1 and st["chol_info"] == 0
+        check_against_oracle(inp, inp["theta0"], t.cpu().numpy(), st, mu)
+
+
+def test_batched_matches_single(small):
+    inps, pgs, b = small
+    mu = 1e-3
+    ts = [dev(x["theta0"]) for x in inps]
+    for _ in range(2):  # second step: new iterate, same descriptors
+        sts = b.step(ts, mu)
+    for inp, pg, t, st in zip(inps, pgs, ts, sts):
+        u = dev(inp["theta0"])
+        pg.step(u, mu)
+        s1 = pg.step(u, mu)
+        assert rel(t.cpu().numpy(), u.cpu().numpy()) < 1e-12
+        for k in ("half_sq_norm", "max_abs_R", "max_abs_R_val", "model_sq_norm"):
+            assert abs(st[k] - s1[k]) <= 1e-12 * abs(s1[k])
+        assert abs(st["grad_dot_delta"] - s1["grad_dot_delta"]) <= 1e-12 * abs(s1["grad_dot_delta"])
+
+
+def test_batched_new_parameter_buffers_and_determinism(small):
+    inps, pgs, b = small
+    a = [dev(x["theta0"]) for x in inps]
+    c = [dev(x["theta0"]) for x in inps]
+    b.step(a, 1e-3, stats=False)
+    b.step(c, 1e-3, stats=False)
+    torch.cuda.synchronize()
+    for x, y in zip(a, c):
+        assert torch.equal(x, y)
+
+
+def test_batched_failure_is_isolated(small):
+    inps, pgs, b = small
+    good = [dev(x["theta0"]) for x in inps]
+    b.step(good, 1e-3)
+    bad_np = inps[2]["theta0"].copy()
+    bad_np[5] = np.nan
+    ts = [dev(x["theta0"]) for x in inps]
+    ts[2] = dev(bad_np)
+    sts = b.step(ts, 1e-3)
+    assert sts[2]["rc"] == gn.GN_ENONFINITE and sts[2]["updated"] == 0
+    got = ts[2].cpu().numpy()
+    keep = ~np.isnan(bad_np)
+    assert np.array_equal(got[keep], bad_np[keep])
+    for i in (0, 1, 3, 4):
+        assert sts[i]["rc"] == gn.GN_OK and sts[i]["updated"] == 1
+        assert torch.equal(ts[i], good[i])
+
+
+def test_batch_argument_checks(small):
+    inps, pgs, b = small
+    with pytest.raises(ValueError):
+        b.step([dev(inps[0]["theta0"])], 1e-3)
+    with pytest.raises(gn.GNError) as e:
+        b.step([dev(x["theta0"]) for x in inps], -1.0)
+    assert e.value.status == gn.GN_EINVAL
+    # mixed parameter counts are rejected
+    other = gn.Problem("ccf1d", [1, 8, 1], 0.5)
+    other.set_points(inps[0]["s"], None, None, inps[0]["sq"], inps[0]["wq"], None)
+    with pytest.raises(gn.GNError) as e:
+        gn.Batch([pgs[0], other])
+    assert e.value.status == gn.GN_EINVAL
+    other.close()
+
+
+def test_batch_stale_after_set_points():
+    inps = workloads.make_batched_inputs(instances=2, n_range=(100, 200), m_quad=32, widths=[1, 8, 8, 1], seed=3)
+    pgs = [make_problem(x) for x in inps]
+    b = gn.Batch(pgs)
+    ts = [dev(x["theta0"]) for x in inps]
+    assert all(s["rc"] == gn.GN_OK for s in b.step(ts, 1e-3))
+    x = inps[1]
+    pgs[1].set_points(x["s"], x["rho"], x["f"], x["sq"], x["wq"], x["sval"])
+    with pytest.raises(gn.GNError) as e:
+        b.step(ts, 1e-3)
+    assert e.value.status == gn.GN_ESTATE
+    b.close()
+    for p in pgs:
+        p.close()
+
+
+def test_full_batched_workload_sampled():
+    """64 instances at full size: every instance against its own single-
+    instance step; the smallest instance against the oracle."""
+    inps = workloads.make_batched_inputs()
+    print(f"\n[gpu batch] full batch: {len(inps)} instances, N total {sum(x['n'] for x in inps)}", flush=True)
+    pgs = [make_problem(x) for x in inps]
+    b = gn.Batch(pgs)
+    mu = inps[0]["mu"]
+    ts = [dev(x["theta0"]) for x in inps]
+    sts = b.step(ts, mu)
+    assert all(s["rc"] == gn.GN_OK and s["updated"] == 1 for s in sts)
+    for inp, pg, t in zip(inps, pgs, ts):
+        u = dev(inp["theta0"])
+        pg.step(u, mu)
+        assert rel(t.cpu().numpy(), u.cpu().numpy()) < 1e-12
+    k = int(np.argmin([x["n"] for x in inps]))
+    print(f"[gpu batch] oracle check of instance {k} (n={inps[k]['n']})", flush=True)
+    check_against_oracle(inps[k], inps[k]["theta0"], ts[k].cpu().numpy(), sts[k], mu)
+    b.close()
+    for p in pgs:
+        p.close()

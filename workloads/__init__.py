@@ -33,6 +33,13 @@ WORKLOADS = {
                        mu=1e-3, steps=50, c_norm=1.0, c_target=1.0),
 }
 
+# Batched CCF: independent instances with their own blow-up rate lambda drawn
+# uniformly in [0.3, 1.0], uneven point counts N drawn uniformly in
+# [1024, 16384], the small network with a per-instance seed.
+BATCHED = dict(name="ccf_batched", equation="ccf1d", widths=[1, 32, 32, 1], instances=64,
+               n_range=(1024, 16384), lam_range=(0.3, 1.0), points="uniform", m_quad=1024,
+               seed=4, mu=1e-3, steps=10, c_norm=1.0, c_target=1.0)
+
 
 def num_params(widths) -> int:
     return int(sum(b * (a + 1) for a, b in zip(widths[:-1], widths[1:])))
@@ -109,4 +116,32 @@ def make_inputs(name: str, n: int | None = None, m_quad: int | None = None,
         theta0=glorot_theta(cfg["widths"], cfg["seed"]),
         P=num_params(cfg["widths"]),
     )
+    return out
+
+
+def make_batched_inputs(instances: int | None = None, n_range=None, m_quad: int | None = None,
+                        widths=None, seed: int | None = None) -> list:
+    """Per-instance input dicts of the batched CCF workload (same keys as
+    make_inputs); sizes may be overridden for tests."""
+    cfg = dict(BATCHED)
+    for k, v in (("instances", instances), ("n_range", n_range), ("m_quad", m_quad),
+                 ("widths", widths), ("seed", seed)):
+        if v is not None:
+            cfg[k] = v
+    rng = np.random.default_rng(cfg["seed"])
+    lo, hi = cfg["n_range"]
+    ns = rng.integers(lo, hi + 1, size=cfg["instances"])
+    a, b = cfg["lam_range"]
+    lams = a + (b - a) * rng.random(cfg["instances"])
+    sq, wq = quadrature_s(cfg["m_quad"])
+    out = []
+    for i in range(cfg["instances"]):
+        n = int(ns[i])
+        d = dict(equation=cfg["equation"], widths=list(cfg["widths"]), lam=float(lams[i]), n=n,
+                 points=cfg["points"], m_quad=cfg["m_quad"], seed=1000 + i, mu=cfg["mu"],
+                 steps=cfg["steps"], c_norm=cfg["c_norm"], c_target=cfg["c_target"])
+        d.update(s=points_uniform(n), rho=np.ones(n), f=np.zeros(n), sq=sq, wq=wq,
+                 sval=validation_grid(n), theta0=glorot_theta(cfg["widths"], 1000 + i),
+                 P=num_params(cfg["widths"]))
+        out.append(d)
     return out
