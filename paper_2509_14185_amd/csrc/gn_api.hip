@@ -191,7 +191,28 @@ void mark(gn_handle h, int k) {
 // Phase 1 of a step: forward jets, residual rows into column P of the
 // workspace J (the Gram of [J | r] then carries g and r^T r), validation
 // max-norm, Jacobian rows and the Hilbert coupling.  Marks phase boundaries.
-gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks) {
+GemmDesc coupling_desc(gn_handle h) {
+    GemmDesc c{};
+    c.M = h->n; c.N = h->md.P; c.K = h->m;
+    c.A = h->Q; c.lda = h->ldQ; c.la = 0;
+    c.B = h->Bm; c.ldb = h->ldJ; c.lb = 0;
+    c.C = h->J; c.ldc = h->ldJ;
+    c.alpha = 1.0; c.beta = 1.0; c.rowscale = h->cscale;
+    return c;
+}
+
+GemmDesc gram_desc(gn_handle h) {
+    const int64_t P = h->md.P;
+    GemmDesc g{};
+    g.M = P + 1; g.N = P + 1; g.K = h->n + 1;
+    g.A = h->J; g.lda = h->ldJ; g.la = 1;
+    g.B = h->J; g.ldb = h->ldJ; g.lb = 0;
+    g.C = h->G; g.ldc = h->ldG;
+    g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
+    return g;
+}
+
+gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks, bool coupling = true) {
     hipStream_t st = h->stream;
     const int64_t P = h->md.P;
     double *J = h->J;
@@ -212,15 +233,7 @@ gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks) {
         GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, nb));
     }
     if (marks) mark(h, 2);
-    if (h->equation == GN_EQ_CCF1D) {
-        GemmDesc c{};
-        c.M = h->n; c.N = P; c.K = h->m;
-        c.A = h->Q; c.lda = h->ldQ; c.la = 0;
-        c.B = h->Bm; c.ldb = ldJ; c.lb = 0;
-        c.C = J; c.ldc = ldJ;
-        c.alpha = 1.0; c.beta = 1.0; c.rowscale = h->cscale;
-        GN_HIP(h, launch_dgemm(st, c));
-    }
+    if (coupling && h->equation == GN_EQ_CCF1D) GN_HIP(h, launch_dgemm(st, coupling_desc(h)));
     return GN_OK;
 }
 
@@ -250,9 +263,9 @@ struct gn_batch_context {
     hipStream_t stream = nullptr;
     int64_t P = 0;
     std::vector<BatchChol> h_bc;
-    std::vector<GemmDesc> h_gram, h_chol;
     BatchChol *d_bc = nullptr;
-    GemmDesc *d_gram = nullptr, *d_chol = nullptr;
+    BatchedGemmPlan coupling, gram;          // Hilbert coupling of the CCF instances, bordered Gram
+    std::vector<BatchedGemmPlan> chol;       // per Cholesky panel: panel solve, trailing update
     std::vector<double *> uploaded_thetas;
     std::vector<DevStatus> ds;
     std::vector<uint64_t> gen;  // point-set generation of every handle when the batch was made
@@ -517,13 +530,7 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
         GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
         GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
     } else {
-        GemmDesc g{};
-        g.M = P + 1; g.N = P + 1; g.K = m_rows;
-        g.A = J; g.lda = ldJ; g.la = 1;
-        g.B = J; g.ldb = ldJ; g.lb = 0;
-        g.C = h->G; g.ldc = h->ldG;
-        g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
-        GN_HIP(h, launch_dgemm(st, g));
+        GN_HIP(h, launch_dgemm(st, gram_desc(h)));
     }
     GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     mark(h, 4);
@@ -598,11 +605,20 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
     return GN_OK;
 }
 
+static void batch_free(gn_batch b) {
+    if (b->d_bc) (void)hipFree(b->d_bc);
+    batched_plan_free(b->coupling);
+    batched_plan_free(b->gram);
+    for (auto &p : b->chol) batched_plan_free(p);
+    delete b;
+}
+
 gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out) {
     if (!hs || n < 1 || !out) return GN_EINVAL;
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
-        if (!hs[i] || hs[i]->n <= 0) return GN_ESTATE;
+        if (!hs[i]) return GN_EINVAL;
+        if (hs[i]->n <= 0) return GN_ESTATE;
         if (hs[i]->md.P != hs[0]->md.P || hs[i]->precision != GN_FP64) return GN_EINVAL;
     }
     gn_batch b = new (std::nothrow) gn_batch_context();
@@ -613,32 +629,23 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     const int64_t P = b->P;
     for (int i = 0; i < n; ++i) {
         gn_handle h = hs[i];
-        GemmDesc g{};
-        g.M = P + 1; g.N = P + 1; g.K = h->n + 1;
-        g.A = h->J; g.lda = h->ldJ; g.la = 1;
-        g.B = h->J; g.ldb = h->ldJ; g.lb = 0;
-        g.C = h->G; g.ldc = h->ldG;
-        g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
-        b->h_gram.push_back(g);
+        if (h->equation == GN_EQ_CCF1D) b->coupling.h_descs.push_back(coupling_desc(h));
+        b->gram.h_descs.push_back(gram_desc(h));
         BatchChol c{};
         c.A = h->G; c.lda = h->ldG; c.linv = h->linv; c.y = h->ybuf; c.x = h->delta; c.theta = nullptr;
         c.status = h->status;
         b->h_bc.push_back(c);
     }
-    cholesky_batched_descs(b->h_bc.data(), n, P + 1, b->h_chol);
-    auto up = [&](auto **dst, const auto &v) -> bool {
-        using T = typename std::remove_reference<decltype(v)>::type::value_type;
-        void *p = nullptr;
-        if (hipMalloc(&p, sizeof(T) * (v.size() ? v.size() : 1)) != hipSuccess) return false;
-        *dst = (std::remove_reference_t<decltype(*dst)>)p;
-        return v.empty() || hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) == hipSuccess;
-    };
-    if (!up(&b->d_bc, b->h_bc) || !up(&b->d_gram, b->h_gram) || !up(&b->d_chol, b->h_chol)) {
-        (void)hipFree(b->d_bc);
-        (void)hipFree(b->d_gram);
-        (void)hipFree(b->d_chol);
-        delete b;
-        return GN_ENOMEM;
+    cholesky_batched_plans(b->h_bc.data(), n, P + 1, b->chol);
+    hipError_t e = hipMalloc((void **)&b->d_bc, sizeof(BatchChol) * n);
+    if (e == hipSuccess) e = hipMemcpy(b->d_bc, b->h_bc.data(), sizeof(BatchChol) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = batched_plan_upload(b->coupling);
+    if (e == hipSuccess) e = batched_plan_upload(b->gram);
+    for (auto &p : b->chol)
+        if (e == hipSuccess) e = batched_plan_upload(p);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return e == hipErrorOutOfMemory ? GN_ENOMEM : GN_EDEVICE;
     }
     b->uploaded_thetas.assign(n, nullptr);
     b->ds.resize(n);
@@ -650,10 +657,7 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
 gn_status gn_batch_destroy(gn_batch b) {
     if (!b) return GN_EINVAL;
     (void)hipStreamSynchronize(b->stream);
-    (void)hipFree(b->d_bc);
-    (void)hipFree(b->d_gram);
-    (void)hipFree(b->d_chol);
-    delete b;
+    batch_free(b);
     return GN_OK;
 }
 
@@ -676,22 +680,23 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
         GN_HIP(h0, hipMemcpy(b->d_bc, b->h_bc.data(), sizeof(BatchChol) * n, hipMemcpyHostToDevice));
         b->uploaded_thetas.assign(d_thetas, d_thetas + n);
     }
-    // phase 1 per instance: residual, validation, Jacobian with r in column P
+    // per instance: residual, validation, local Jacobian rows with r in column P
     for (int i = 0; i < n; ++i) {
         gn_handle h = b->hs[i];
         hipStream_t own = h->stream;
         h->stream = st;
         gn_status e = GN_OK;
         if (launch_reset_status(st, h->status) != hipSuccess) e = GN_EDEVICE;
-        if (e == GN_OK) e = build_step_jacobian(h, d_thetas[i], false);
+        if (e == GN_OK) e = build_step_jacobian(h, d_thetas[i], false, false);
         if (e == GN_OK && launch_sumsq(st, h->J + P, h->n + 1, h->ldJ, &h->status->half_sq_norm, h->red_work) != hipSuccess)
             e = GN_EDEVICE;
         h->stream = own;
         if (e != GN_OK) return e;
     }
-    // batched Gram, bordered Cholesky, back substitution and update
-    GN_HIP(h0, launch_dgemm_batched(st, b->h_gram.data(), b->d_gram, n));
-    GN_HIP(h0, launch_cholesky_batched(st, b->h_bc.data(), b->d_bc, b->h_chol.data(), b->d_chol, n, P + 1, mu, 1));
+    // batched Hilbert coupling, Gram, bordered Cholesky, back substitution and update
+    GN_HIP(h0, launch_batched_plan(st, b->coupling));
+    GN_HIP(h0, launch_batched_plan(st, b->gram));
+    GN_HIP(h0, launch_cholesky_batched(st, b->h_bc.data(), b->d_bc, b->chol, n, P + 1, mu, 1));
     GN_HIP(h0, launch_solve_upper_batched(st, b->d_bc, n, P));
     if (!h_stats) return GN_OK;
     for (int i = 0; i < n; ++i)

@@ -130,10 +130,30 @@ struct GemmDesc {
     const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
-// n independent GEMMs in one launch (problem = blockIdx.y): h_descs is the
-// host copy (grid sizing), d_descs the same descriptors in device memory.
-// Layouts and the lower flag must agree across the batch.
-hipError_t launch_dgemm_batched(hipStream_t st, const GemmDesc *h_descs, const GemmDesc *d_descs, int n);
+// n independent GEMMs in one launch.  plan_dgemm_batched builds, once per
+// set of shapes, the work table: one int4 (problem, tile row, tile column, 0)
+// per workgroup in dispatch order, entry b running on XCD b % 8, padding
+// entries with problem -1.  Tiles are grouped by 4 x 8 super-tiles of one
+// problem and the groups are spread over XCDs by longest-processing-time on
+// their K extent.  Layouts, the lower flag and the tile configuration must
+// agree across the batch (else it returns -1); otherwise the table length.
+// h_descs is the host copy, d_descs and d_work the device copies.
+int64_t plan_dgemm_batched(const GemmDesc *descs, int n, std::vector<int4> &table);
+hipError_t launch_dgemm_batched(hipStream_t st, const GemmDesc *h_descs, const GemmDesc *d_descs, int n,
+                                const int4 *d_work, int64_t nwork);
+
+// One batched GEMM launch with its descriptors and work table (host copies
+// filled by the caller, device copies by batched_plan_upload).
+struct BatchedGemmPlan {
+    std::vector<GemmDesc> h_descs;
+    std::vector<int4> h_work;
+    GemmDesc *d_descs = nullptr;
+    int4 *d_work = nullptr;
+};
+// Plans the work table from h_descs and copies both to the device.
+hipError_t batched_plan_upload(BatchedGemmPlan &p);
+void batched_plan_free(BatchedGemmPlan &p);
+hipError_t launch_batched_plan(hipStream_t st, const BatchedGemmPlan &p);
 
 // g = J^T r (J m x p row-major) via deterministic two-pass reduction;
 // work must hold gemv_t_work_size(m, p) doubles.
@@ -173,12 +193,13 @@ struct BatchChol {
     double *theta;      // parameters updated in place
     DevStatus *status;
 };
+// plans[2 * panel + pass]: pass 0 the panel solve L21 = A21 X^T, pass 1 the
+// trailing update, over all instances (from cholesky_batched_plans, uploaded).
 hipError_t launch_cholesky_batched(hipStream_t st, const BatchChol *h_bc, const BatchChol *d_bc,
-                                   const GemmDesc *h_gd, const GemmDesc *d_gd, int nb, int64_t n, double mu,
+                                   const std::vector<BatchedGemmPlan> &plans, int nb, int64_t n, double mu,
                                    int border);
-// Descriptors of the per-panel TRSM and trailing SYRK of every instance
-// ([panel][pass][instance]) for launch_cholesky_batched.
-void cholesky_batched_descs(const BatchChol *bc, int nb, int64_t n, std::vector<GemmDesc> &out);
+// Host descriptors of those GEMMs (work tables and device copies not yet made).
+void cholesky_batched_plans(const BatchChol *bc, int nb, int64_t n, std::vector<BatchedGemmPlan> &out);
 // y = -(border row), |w|^2 and the Schur complement into status, L^T x = y,
 // then theta += x when finite and the factorisation succeeded.
 hipError_t launch_solve_upper_batched(hipStream_t st, const BatchChol *d_bc, int nb, int64_t n);

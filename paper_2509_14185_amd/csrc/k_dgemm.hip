@@ -24,6 +24,8 @@
 //              register group, unlike the 4-row groups of the f32 variant)
 #include "gn_internal.h"
 
+#include <algorithm>
+
 namespace gn {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -144,11 +146,16 @@ struct TileLoader {
 
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
 __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0,
-                                                                 const GemmDesc *__restrict__ batch) {
-    // batched launches take problem blockIdx.y from a device array of descriptors
-    const GemmDesc g = BATCH ? batch[blockIdx.y] : g0;
-    const int tiles_m = BATCH ? (int)((g.M + BM - 1) / BM) : tiles_m0;
-    const int tiles_n = BATCH ? (int)((g.N + BN - 1) / BN) : tiles_n0;
+                                                                 const GemmDesc *__restrict__ batch,
+                                                                 const int4 *__restrict__ work) {
+    // batched launches read (problem, tile row, tile column) from a work table
+    // laid out in dispatch order (entry b runs on XCD b % 8)
+    int4 wi = make_int4(0, 0, 0, 0);
+    if (BATCH) {
+        wi = work[blockIdx.x];
+        if (wi.x < 0) return;
+    }
+    const GemmDesc g = BATCH ? batch[wi.x] : g0;
     if (g.M <= 0 || g.N <= 0) return;
     if (g.stop_flag != nullptr && *g.stop_flag != 0) return;
     constexpr int WAVES_M = 2, WAVES_N = 4;
@@ -160,8 +167,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
     double *As = smem;                       // [2][BK][BM]
     double *Bs = smem + 2 * BK * LDA_S;      // [2][BK][BN]
 
-    int tm, tn;
-    if (!tile_of_block(blockIdx.x, g.lower, tiles_m, tiles_n, tm, tn)) return;
+    int tm = wi.y, tn = wi.z;
+    if (!BATCH && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const bool lower_mask = g.lower || g.mask_lower;
     if (lower_mask && n0 > m0 + BM - 1) return;  // tile entirely above the diagonal
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
 
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
 static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int tiles_n, int64_t blocks,
-                             const GemmDesc *batch, int nbatch) {
+                             const GemmDesc *batch, const int4 *work) {
     constexpr size_t shm = sizeof(double) * 2 * BK * (BM + BN);
     static bool attr = false;
     if (!attr) {
@@ -271,8 +278,8 @@ static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         attr = true;
     }
-    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)blocks, (unsigned)nbatch),
-                       dim3(GEMM_THREADS), shm, st, g, tiles_m, tiles_n, batch);
+    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)blocks), dim3(GEMM_THREADS),
+                       shm, st, g, tiles_m, tiles_n, batch, work);
     return hipGetLastError();
 }
 
@@ -288,12 +295,12 @@ static int64_t blocks_for(const GemmDesc &g, int &tiles_m, int &tiles_n) {
 
 template <int BM, int BN, int BK, bool BATCH>
 static hipError_t launch_tiles(hipStream_t st, const GemmDesc &g, int64_t blocks, int tiles_m, int tiles_n,
-                               const GemmDesc *batch, int nbatch) {
+                               const GemmDesc *batch, const int4 *work) {
     if (blocks <= 0) return hipSuccess;
-    if (g.la == 0 && g.lb == 0) return launch_one<BM, BN, BK, 0, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
-    if (g.la == 0 && g.lb == 1) return launch_one<BM, BN, BK, 0, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
-    if (g.la == 1 && g.lb == 0) return launch_one<BM, BN, BK, 1, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
-    return launch_one<BM, BN, BK, 1, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, nbatch);
+    if (g.la == 0 && g.lb == 0) return launch_one<BM, BN, BK, 0, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
+    if (g.la == 0 && g.lb == 1) return launch_one<BM, BN, BK, 0, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
+    if (g.la == 1 && g.lb == 0) return launch_one<BM, BN, BK, 1, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
+    return launch_one<BM, BN, BK, 1, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
 }
 
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
@@ -303,29 +310,110 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     // BN must equal BM when lower; in-place uses (C aliasing A) need BN >= N
     if (!g.lower && g.N <= 64) {
         const int64_t b = blocks_for<128, 64, 32>(g, tm, tn);
-        return launch_tiles<128, 64, 32, false>(st, g, b, tm, tn, nullptr, 1);
+        return launch_tiles<128, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
     }
     const int64_t b = blocks_for<128, 128, 32>(g, tm, tn);
-    return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, 1);
+    return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
 }
 
-hipError_t launch_dgemm_batched(hipStream_t st, const GemmDesc *h_descs, const GemmDesc *d_descs, int n) {
-    if (n <= 0) return hipSuccess;
-    // the tile configuration and layouts must agree across the batch
-    const GemmDesc &f = h_descs[0];
-    const bool small_n = !f.lower && f.N <= 64;
-    int64_t blocks = 0;
+// Batched tile configuration: 128 x 64 tiles for narrow rectangular products
+// (in-place triangular solves need one tile column), else 128 x 128.
+static bool batched_small_n(const GemmDesc &f) { return !f.lower && f.N <= 64; }
+
+int64_t plan_dgemm_batched(const GemmDesc *descs, int n, std::vector<int4> &table) {
+    table.clear();
+    if (n <= 0) return 0;
+    const GemmDesc &f = descs[0];
+    const bool small_n = batched_small_n(f);
+    const int BM = 128, BN = small_n ? 64 : 128;
     for (int i = 0; i < n; ++i) {
-        const GemmDesc &g = h_descs[i];
-        if (g.la != f.la || g.lb != f.lb || g.lower != f.lower || (!g.lower && g.N <= 64) != small_n)
-            return hipErrorInvalidValue;
-        if (g.lower && g.M != g.N) return hipErrorInvalidValue;
-        int tm, tn;
-        const int64_t b = small_n ? blocks_for<128, 64, 32>(g, tm, tn) : blocks_for<128, 128, 32>(g, tm, tn);
-        if (b > blocks) blocks = b;
+        const GemmDesc &g = descs[i];
+        if (g.la != f.la || g.lb != f.lb || g.lower != f.lower || batched_small_n(g) != small_n) return -1;
+        if (g.lower && g.M != g.N) return -1;
     }
-    if (small_n) return launch_tiles<128, 64, 32, true>(st, f, blocks, 0, 0, d_descs, n);
-    return launch_tiles<128, 128, 32, true>(st, f, blocks, 0, 0, d_descs, n);
+    // chunks: a block of tiles of one problem that share operand panels, 4 x 8
+    // tiles, or smaller when that leaves fewer than 8 chunks per XCD
+    struct Chunk { double cost; int inst; std::vector<int4> tiles; };
+    std::vector<Chunk> chunks;
+    static const int shapes[3][2] = {{SUP_M, SUP_N}, {2, 4}, {1, 1}};
+    for (const auto &sh : shapes) {
+        const int cm = sh[0], cn = sh[1];
+        chunks.clear();
+        for (int i = 0; i < n; ++i) {
+            const GemmDesc &g = descs[i];
+            if (g.M <= 0 || g.N <= 0) continue;
+            const int tm_n = (int)((g.M + BM - 1) / BM), tn_n = (int)((g.N + BN - 1) / BN);
+            const double per_tile = (double)(g.K > 0 ? g.K : 0) + 64.0;  // K loop plus epilogue
+            for (int sm = 0; sm * cm < tm_n; ++sm)
+                for (int sn = 0; sn * cn < tn_n; ++sn) {
+                    Chunk c{0.0, i, {}};
+                    for (int t = 0; t < cm * cn; ++t) {
+                        const int tm = sm * cm + t % cm, tn = sn * cn + t / cm;
+                        if (tm >= tm_n || tn >= tn_n) continue;
+                        if ((g.lower || g.mask_lower) && (int64_t)tn * BN > (int64_t)tm * BM + BM - 1) continue;
+                        c.tiles.push_back(make_int4(i, tm, tn, 0));
+                    }
+                    if (c.tiles.empty()) continue;
+                    c.cost = per_tile * (double)c.tiles.size();
+                    chunks.push_back(std::move(c));
+                }
+        }
+        if (chunks.size() >= 8 * NXCD) break;
+    }
+    // longest-processing-time assignment of chunks to XCDs; inside an XCD the
+    // hardware hands tiles to free CUs in table order, costliest chunks first
+    std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &b) { return a.cost > b.cost; });
+    std::vector<std::vector<int4>> per(NXCD);
+    double load[NXCD] = {0};
+    for (const Chunk &c : chunks) {
+        int x = 0;
+        for (int k = 1; k < NXCD; ++k)
+            if (load[k] < load[x]) x = k;
+        load[x] += c.cost;
+        per[x].insert(per[x].end(), c.tiles.begin(), c.tiles.end());
+    }
+    size_t len = 0;
+    for (auto &v : per) len = v.size() > len ? v.size() : len;
+    table.assign(len * NXCD, make_int4(-1, 0, 0, 0));
+    for (int x = 0; x < NXCD; ++x)
+        for (size_t p = 0; p < per[x].size(); ++p) table[p * NXCD + x] = per[x][p];
+    return (int64_t)table.size();
+}
+
+hipError_t launch_dgemm_batched(hipStream_t st, const GemmDesc *h_descs, const GemmDesc *d_descs, int n,
+                                const int4 *d_work, int64_t nwork) {
+    if (n <= 0 || nwork <= 0) return hipSuccess;
+    const GemmDesc &f = h_descs[0];
+    if (batched_small_n(f)) return launch_tiles<128, 64, 32, true>(st, f, nwork, 0, 0, d_descs, d_work);
+    return launch_tiles<128, 128, 32, true>(st, f, nwork, 0, 0, d_descs, d_work);
+}
+
+hipError_t batched_plan_upload(BatchedGemmPlan &p) {
+    batched_plan_free(p);
+    const int n = (int)p.h_descs.size();
+    if (plan_dgemm_batched(p.h_descs.data(), n, p.h_work) < 0) return hipErrorInvalidValue;
+    if (n == 0 || p.h_work.empty()) return hipSuccess;
+    hipError_t e = hipMalloc((void **)&p.d_descs, sizeof(GemmDesc) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&p.d_work, sizeof(int4) * p.h_work.size());
+    if (e == hipSuccess) e = hipMemcpy(p.d_descs, p.h_descs.data(), sizeof(GemmDesc) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p.d_work, p.h_work.data(), sizeof(int4) * p.h_work.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) batched_plan_free(p);
+    return e;
+}
+
+void batched_plan_free(BatchedGemmPlan &p) {
+    if (p.d_descs) (void)hipFree(p.d_descs);
+    if (p.d_work) (void)hipFree(p.d_work);
+    p.d_descs = nullptr;
+    p.d_work = nullptr;
+}
+
+hipError_t launch_batched_plan(hipStream_t st, const BatchedGemmPlan &p) {
+    if (p.h_descs.empty() || p.h_work.empty()) return hipSuccess;
+    if (!p.d_descs || !p.d_work) return hipErrorInvalidValue;
+    return launch_dgemm_batched(st, p.h_descs.data(), p.d_descs, (int)p.h_descs.size(), p.d_work,
+                                (int64_t)p.h_work.size());
 }
 
 // ---------------------------------------------------------------- g = J^T r

@@ -595,7 +595,7 @@ __global__ __launch_bounds__(256) void update_batched_kernel(const BatchChol *__
 }
 
 hipError_t launch_cholesky_batched(hipStream_t st, const BatchChol *h_bc, const BatchChol *d_bc,
-                                   const GemmDesc *h_gd, const GemmDesc *d_gd, int nb, int64_t n, double mu,
+                                   const std::vector<BatchedGemmPlan> &plans, int nb, int64_t n, double mu,
                                    int border) {
     if (nb <= 0 || n <= 0) return hipSuccess;
     static bool attr = false;
@@ -611,28 +611,27 @@ hipError_t launch_cholesky_batched(hipStream_t st, const BatchChol *h_bc, const 
             hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, h_bc[i].A, nd,
                                h_bc[i].lda, mu);
     hipError_t e;
-    int64_t panel = 0;
+    size_t panel = 0;
     for (int64_t k0 = 0; k0 < n; k0 += CB, ++panel) {
         const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
         const int bh = (border && k0 + kb == n) ? 1 : 0;
         hipLaunchKernelGGL(potrf_block_batched_kernel, dim3((unsigned)nb), dim3(256), shm, st, d_bc, k0, kb, bh);
         if (n - k0 - kb <= 0) break;
-        // descriptors per panel: [panel][0: TRSM, 1: trailing SYRK][instance]
-        const GemmDesc *ht = h_gd + (panel * 2 + 0) * nb, *dt = d_gd + (panel * 2 + 0) * nb;
-        const GemmDesc *hs = h_gd + (panel * 2 + 1) * nb, *ds = d_gd + (panel * 2 + 1) * nb;
-        if ((e = launch_dgemm_batched(st, ht, dt, nb)) != hipSuccess) return e;
-        if ((e = launch_dgemm_batched(st, hs, ds, nb)) != hipSuccess) return e;
+        if (2 * panel + 1 >= plans.size()) return hipErrorInvalidValue;
+        if ((e = launch_batched_plan(st, plans[2 * panel])) != hipSuccess) return e;
+        if ((e = launch_batched_plan(st, plans[2 * panel + 1])) != hipSuccess) return e;
     }
     return hipGetLastError();
 }
 
-void cholesky_batched_descs(const BatchChol *bc, int nb, int64_t n, std::vector<GemmDesc> &out) {
+void cholesky_batched_plans(const BatchChol *bc, int nb, int64_t n, std::vector<BatchedGemmPlan> &out) {
     out.clear();
     for (int64_t k0 = 0; k0 < n; k0 += CB) {
         const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
         const int64_t r1 = k0 + kb, rest = n - r1;
         if (rest <= 0) break;
-        for (int pass = 0; pass < 2; ++pass)
+        for (int pass = 0; pass < 2; ++pass) {
+            BatchedGemmPlan p;
             for (int i = 0; i < nb; ++i) {
                 double *A = bc[i].A;
                 const int64_t lda = bc[i].lda;
@@ -653,8 +652,10 @@ void cholesky_batched_descs(const BatchChol *bc, int nb, int64_t n, std::vector<
                     g.lower = 1;
                 }
                 g.stop_flag = &bc[i].status->flag;
-                out.push_back(g);
+                p.h_descs.push_back(g);
             }
+            out.push_back(std::move(p));
+        }
     }
 }
 

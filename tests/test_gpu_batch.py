@@ -133,6 +133,33 @@ def test_batch_argument_checks(small):
     other.close()
 
 
+def test_batch_mixed_equations():
+    """A Burgers instance (no Hilbert coupling) beside CCF instances."""
+    inps = workloads.make_batched_inputs(instances=3, n_range=(150, 400), m_quad=48, widths=[1, 12, 12, 1], seed=5)
+    inps[1]["equation"] = "burgers1d"
+    inps[1]["c_target"] = -1.0
+    pgs = []
+    for x in inps:
+        ccf = x["equation"] == "ccf1d"
+        p = gn.Problem(x["equation"], x["widths"], x["lam"], x["c_norm"], x["c_target"])
+        p.set_points(x["s"], x["rho"], x["f"], x["sq"] if ccf else None, x["wq"] if ccf else None, x["sval"])
+        pgs.append(p)
+    b = gn.Batch(pgs)
+    ts = [dev(x["theta0"]) for x in inps]
+    sts = b.step(ts, 1e-3)
+    for x, t, st in zip(inps, ts, sts):
+        assert st["rc"] == gn.GN_OK
+        po = p1.Problem.from_inputs(x, equation=x["equation"])
+        ref, ost = ogn.step(po, x["theta0"], 1e-3)
+        d, dref = t.cpu().numpy() - x["theta0"], ref - x["theta0"]
+        assert ogn.backward_error(ost["G"], 1e-3, ost["g"], d) < 5e-14
+        kappa = np.linalg.cond(ost["G"] + 1e-3 * np.eye(ost["G"].shape[0]))
+        assert rel(d, dref) < max(1e-12, 10 * kappa * EPS)
+    b.close()
+    for p in pgs:
+        p.close()
+
+
 def test_batch_stale_after_set_points():
     inps = workloads.make_batched_inputs(instances=2, n_range=(100, 200), m_quad=32, widths=[1, 8, 8, 1], seed=3)
     pgs = [make_problem(x) for x in inps]
