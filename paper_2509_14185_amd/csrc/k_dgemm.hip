@@ -10,11 +10,13 @@
 // Tiling: a 512-thread workgroup (8 waves, 2 x 4, two per SIMD so one wave's
 // memory waits overlap the other's MFMAs) owns a BM x BN tile of C; each wave
 // owns (BM/2) x (BN/4) as 16x16 MFMA blocks held in registers.
-// K is consumed in chunks of BK = 32 staged through double-buffered LDS in a
-// k-major layout ([k][m], [k][n]) so that an MFMA fragment (16 consecutive m
-// or n for each of 4 k) is one contiguous LDS row segment.  Global loads for
-// chunk c+1 (16-byte pairs along the operand's contiguous direction, no
-// bounds checks for interior tiles) are issued before the MFMAs of chunk c.
+// K is consumed in chunks of BK = 32 staged through double-buffered LDS.
+// Each operand keeps its global orientation in LDS ([k][m] when contiguous
+// along m, else [m][k] with a padded row), so staging is a straight 16-byte
+// copy without bank conflicts and an MFMA fragment read (16 consecutive m or
+// n for each of 4 k) touches distinct banks.  Global loads for chunk c+1
+// (16-byte pairs along the operand's contiguous direction, no bounds checks
+// for interior tiles) are issued before the MFMAs of chunk c.
 // Tiles are grouped in 4 x 8 super-tiles, one per XCD at a time (L2 reuse).
 //
 // Fragment layout of v_mfma_f64_16x16x4_f64 (wave64):
@@ -127,26 +129,26 @@ struct TileLoader {
             }
         }
     }
-    // store into LDS laid out [k][r] with row stride LDR
-    template <int LDR>
+    // LDS keeps the operand's global orientation, so every store is a plain
+    // 16-byte copy: [k][r] (stride R) when contiguous along r, else [r][k]
+    // with stride LDK = BK + 2 (even, so pairs stay 16-byte aligned; the pad
+    // spreads the 16 rows of an MFMA fragment read over distinct banks).
+    static constexpr int LDK = BK + 2;
+    static constexpr int SIZE = CONTIG_MN ? BK * R : R * LDK;  // doubles per buffer
+    __device__ __forceinline__ static int at(int r, int k) { return CONTIG_MN ? k * R + r : r * LDK + k; }
     __device__ __forceinline__ void store(double *lds) const {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             int r, k;
             coords(e, r, k);
-            if (CONTIG_MN) {
-                *reinterpret_cast<double2 *>(lds + k * LDR + r) = v[e];
-            } else {
-                lds[k * LDR + r] = v[e].x;
-                lds[(k + 1) * LDR + r] = v[e].y;
-            }
+            *reinterpret_cast<double2 *>(lds + at(r, k)) = v[e];
         }
     }
 };
 
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
 __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0,
-                                                                 const GemmDesc *__restrict__ batch,
+                                                                 int64_t nvirt, const GemmDesc *__restrict__ batch,
                                                                  const int4 *__restrict__ work) {
     // batched launches read (problem, tile row, tile column) from a work table
     // laid out in dispatch order (entry b runs on XCD b % 8)
@@ -162,16 +164,24 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
     constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
     constexpr int FM = WM / 16, FN = WN / 16;
     static_assert(FM >= 1 && FN >= 1, "wave tile");
-    constexpr int LDA_S = BM, LDB_S = BN;
+    using LoaderA = TileLoader<BM, BK, LA == 1>;
+    using LoaderB = TileLoader<BN, BK, LB == 0>;
     extern __shared__ double smem[];
-    double *As = smem;                       // [2][BK][BM]
-    double *Bs = smem + 2 * BK * LDA_S;      // [2][BK][BN]
+    double *As = smem;                       // two buffers of LoaderA::SIZE
+    double *Bs = smem + 2 * LoaderA::SIZE;   // two buffers of LoaderB::SIZE
 
-    int tm = wi.y, tn = wi.z;
-    if (!BATCH && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, tm, tn)) return;
-    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    // A capped grid (fewer workgroups than virtual blocks) walks the virtual
+    // blocks with stride gridDim.x, a multiple of 8, so each workgroup keeps
+    // its XCD's share of the tile order.
     const bool lower_mask = g.lower || g.mask_lower;
-    if (lower_mask && n0 > m0 + BM - 1) return;  // tile entirely above the diagonal
+    for (int64_t vb = blockIdx.x; BATCH || vb < nvirt; vb += gridDim.x) {
+    int tm = wi.y, tn = wi.z;
+    if (!BATCH && !tile_of_block(vb, g.lower, tiles_m0, tiles_n0, tm, tn)) continue;
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    if (lower_mask && n0 > m0 + BM - 1) {  // tile entirely above the diagonal
+        if (BATCH) break;
+        continue;
+    }
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -183,8 +193,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-    TileLoader<BM, BK, LA == 1> la;
-    TileLoader<BN, BK, LB == 0> lb;
+    LoaderA la;
+    LoaderB lb;
     const bool a_aligned = ((g.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.A) & 15) == 0);
     const bool b_aligned = ((g.ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0);
     const bool a_rows_in = m0 + BM <= g.M, b_rows_in = n0 + BN <= g.N;
@@ -196,8 +206,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
         lb.load(g.B, g.ldb, n0, k0, g.N, g.K, kin && b_rows_in && b_aligned);
     };
     auto store_chunk = [&](int buf) {
-        la.template store<LDA_S>(As + buf * BK * LDA_S);
-        lb.template store<LDB_S>(Bs + buf * BK * LDB_S);
+        la.store(As + buf * LoaderA::SIZE);
+        lb.store(Bs + buf * LoaderB::SIZE);
     };
 
     if (nk > 0) {
@@ -209,15 +219,15 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
         if (kt + 1 < nk) load_chunk((kt + 1) * BK);
-        const double *as = As + cur * BK * LDA_S + wm * WM + fr;
-        const double *bs = Bs + cur * BK * LDB_S + wn * WN + fr;
+        const double *as = As + cur * LoaderA::SIZE;
+        const double *bs = Bs + cur * LoaderB::SIZE;
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             double a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = as[(ks + fk) * LDA_S + i * 16];
+            for (int i = 0; i < FM; ++i) a[i] = as[LoaderA::at(wm * WM + i * 16 + fr, ks + fk)];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = bs[(ks + fk) * LDB_S + j * 16];
+            for (int j = 0; j < FN; ++j) b[j] = bs[LoaderB::at(wn * WN + j * 16 + fr, ks + fk)];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -266,20 +276,26 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
             }
         }
     }
+    if (BATCH) break;
+    }
 }
 
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
 static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int tiles_n, int64_t blocks,
                              const GemmDesc *batch, const int4 *work) {
-    constexpr size_t shm = sizeof(double) * 2 * BK * (BM + BN);
+    constexpr size_t shm = sizeof(double) * 2 * (TileLoader<BM, BK, LA == 1>::SIZE + TileLoader<BN, BK, LB == 0>::SIZE);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         attr = true;
     }
-    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)blocks), dim3(GEMM_THREADS),
-                       shm, st, g, tiles_m, tiles_n, batch, work);
+    // a non-batched launch may cap its grid (GemmDesc::max_blocks, rounded to
+    // whole rounds of 8 XCDs); the workgroups then stride over the blocks
+    int64_t grid = blocks;
+    if (!BATCH && g.max_blocks > 0 && g.max_blocks < blocks) grid = (g.max_blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)grid), dim3(GEMM_THREADS),
+                       shm, st, g, tiles_m, tiles_n, blocks, batch, work);
     return hipGetLastError();
 }
 
@@ -303,17 +319,49 @@ static hipError_t launch_tiles(hipStream_t st, const GemmDesc &g, int64_t blocks
     return launch_one<BM, BN, BK, 1, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
 }
 
+// Tile configuration.  128 x 128 tiles when there are enough of them to
+// fill the chip twice; otherwise smaller tiles (64 x 64, or 64 x 128 for an
+// in-place product) so that short, latency-bound products (the panel solves
+// and updates of the Cholesky) spread over more CUs.  A lower product needs
+// square tiles; an in-place product (C aliasing A, the panel solve
+// L21 = A21 X^T) needs one tile column spanning all of N.
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.lower && g.M != g.N) return hipErrorInvalidValue;
+    const bool inplace = g.C == g.A;
+    if (inplace && (g.lower || g.N > 128)) return hipErrorInvalidValue;
+    constexpr int64_t FILL = 2 * 256;
+    auto ntiles = [&](int bm, int bn) {
+        const int64_t a = (g.M + bm - 1) / bm, b = (g.N + bn - 1) / bn;
+        return g.lower ? a * (a + 1) / 2 : a * b;
+    };
     int tm, tn;
-    // BN must equal BM when lower; in-place uses (C aliasing A) need BN >= N
-    if (!g.lower && g.N <= 64) {
-        const int64_t b = blocks_for<128, 64, 32>(g, tm, tn);
-        return launch_tiles<128, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+    if (g.lower) {
+        if (ntiles(128, 128) >= FILL) {
+            const int64_t b = blocks_for<128, 128, 32>(g, tm, tn);
+            return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+        }
+        const int64_t b = blocks_for<64, 64, 32>(g, tm, tn);
+        return launch_tiles<64, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
     }
-    const int64_t b = blocks_for<128, 128, 32>(g, tm, tn);
-    return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+    if (g.N <= 64) {
+        if (ntiles(128, 64) >= FILL) {
+            const int64_t b = blocks_for<128, 64, 32>(g, tm, tn);
+            return launch_tiles<128, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+        }
+        const int64_t b = blocks_for<64, 64, 32>(g, tm, tn);
+        return launch_tiles<64, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+    }
+    if (ntiles(128, 128) >= FILL) {
+        const int64_t b = blocks_for<128, 128, 32>(g, tm, tn);
+        return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+    }
+    if (inplace) {
+        const int64_t b = blocks_for<64, 128, 32>(g, tm, tn);
+        return launch_tiles<64, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+    }
+    const int64_t b = blocks_for<64, 64, 32>(g, tm, tn);
+    return launch_tiles<64, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
 }
 
 // Batched tile configuration: 128 x 64 tiles for narrow rectangular products

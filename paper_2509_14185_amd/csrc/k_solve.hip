@@ -1,15 +1,18 @@
 // Damped solve of the Gauss-Newton system on gfx950 (paper, Methods,
 // "Second-order Optimizer": theta <- theta - (G + gamma I)^{-1} grad h).
 //
-// Right-looking blocked Cholesky with 128-wide panels and look-ahead:
-//   1. diagonal block: one workgroup factors it in LDS (two 64x64 register
-//      factorisations by one wave, 64x64 products by all four waves) and
-//      forms the inverse of its triangular factor;
+// Right-looking blocked Cholesky, two levels (128-wide diagonal blocks inside
+// 512-wide outer panels) with look-ahead:
+//   1. diagonal block: one workgroup factors it in LDS (one-wave 32x32
+//      register factorisations, the rest by all four waves) and forms the
+//      inverse of its triangular factor;
 //   2. panel below: L21 = A21 L11^{-T} as an MFMA GEMM with the inverse;
-//   3. trailing update: A22 -= L21 L21^T (lower) as MFMA GEMMs, split into
-//      the block column of the next panel (on the main stream) and the rest
-//      (on a second stream), so the next diagonal block and panel are
-//      factored while the bulk of the update runs.
+//   3. the remaining columns of the outer panel are updated (K = 128);
+//   4. after an outer panel, the trailing matrix is updated once with
+//      K = 512 (lower), split into the next outer panel's columns (main
+//      stream) and the rest (a second stream), so the next panel is factored
+//      while the bulk of the update runs.  K = 512 keeps the update's C tiles
+//      (read and written once per update) from dominating its HBM traffic.
 // A failed pivot records its 1-based global index and raises a device flag;
 // every later kernel of the factorisation and solve sees the flag and exits.
 //
@@ -28,7 +31,9 @@
 
 namespace gn {
 
-static constexpr int CB = 128;         // panel width of the blocked Cholesky
+static constexpr int CB = 128;         // diagonal block width of the blocked Cholesky
+static constexpr int NB = 4 * CB;      // outer panel width (K of the trailing update)
+static constexpr int SIDE_BLOCKS = 192;  // workgroups of the look-ahead trailing update
 static constexpr int LDS_LD = CB + 1;  // padded LDS row stride (doubles)
 
 int64_t chol_linv_size(int64_t n) { return ((n + CB - 1) / CB) * CB * CB; }
@@ -68,37 +73,71 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
     return __hiloint2double(hi, lo);
 }
 
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// One 16x16 tile of an in-LDS product, acc += A(16 x K) B(K x 16) over
+// k in [kbeg, kend) (multiples of 4), fragments read through accessors
+// a_at(m, k), b_at(k, n).  FP64 MFMA layout: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; register r of the result is row l/16 + 4r, column l%16.
+template <class FA, class FB>
+__device__ __forceinline__ double4_t lds_mfma(double4_t acc, FA a_at, FB b_at, int kbeg, int kend) {
+    const int lane = threadIdx.x & 63, fr = lane & 15, fk = lane >> 4;
+#pragma unroll 4
+    for (int k = kbeg; k < kend; k += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a_at(fr, k + fk), b_at(k + fk, fr), acc, 0, 0, 0);
+    return acc;
+}
+
 // One wave, lanes 0..31: lane i holds row o+i of the 32x32 diagonal block in
-// registers.  Step j reads the pivot and the column below it lane-to-lane
-// (readlane into scalar registers) and updates with one FMA per entry using
-// a_ij / d as multiplier.  Entries right of the diagonal are never read, so
+// registers.  Pivot j: the pivot is read from lane j, every lane scales its
+// entry of column j and stores it to an LDS column buffer (two buffers by
+// parity of j), and every lane reads the column back as broadcasts for its
+// rank-1 update of row i (LDS operations of one wave complete in order, so
+// no barrier is involved).  Entries right of the diagonal are never read, so
 // they are updated without masking.  Row bi (local, or -1) is a border row
-// (updated, diagonal not square-rooted, excluded from X).  Writes L back and
-// X_oo = L_oo^{-1} (lane c owns column c, L rows read lane-to-lane).
-// The unrolled body is small enough to stay in the instruction cache.
+// (updated, diagonal not square-rooted, excluded from X).
+// Then X_oo = L_oo^{-1}: the two 16x16 diagonal blocks are inverted at once
+// (lane c owns column c, rows of L read as LDS broadcasts; a 16-step chain
+// instead of 32) and the off-diagonal block follows from two MFMA products,
+// X21 = -X22 (L21 X11), with t (16 x 17 doubles of LDS) holding L21 X11.
 // Returns -1 or the failing local pivot (uniform).
-__device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *) {
+__device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *cb, double *t) {
     const int lane = threadIdx.x & 63;
     const bool act = lane < IB;
     double row[IB];
 #pragma unroll
     for (int c = 0; c < IB; ++c) row[c] = (act && c <= lane) ? LL(o + lane, o + c) : 0.0;
-    double rinv[IB];  // 1 / l_jj, uniform
+    // rl[i]: 1 / l_ii of this lane's group of the inverse below (row g0 + i)
+    constexpr int H = IB / 2;
+    const int g0 = (lane & H);  // 0 or 16
+    double rl[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) rl[i] = 0.0;
     int fail = -1;
 #pragma unroll
     for (int j = 0; j < IB; ++j) {
-        rinv[j] = 0.0;
         if (fail < 0 && j != bi) {
             const double d = readlane_d(row[j], j);
             if (!(d > 0.0)) {
                 fail = j;
             } else {
                 const double r = rsqrt_refined(d);
-                rinv[j] = r;
-                const double f = row[j] * (r * r);
+                if (g0 == (j & H)) rl[j & (H - 1)] = r;
+                const double l = row[j] * r;
+                double *col = cb + (j & 1) * IB;
+                if (act && lane > j) col[lane] = l;
+                // the whole column in flight at once, then the updates
+                const int c0 = (j + 1) & ~1;
+                double2 cv[IB / 2];
 #pragma unroll
-                for (int c = j + 1; c < IB; ++c) row[c] = fma(-f, readlane_d(row[j], c), row[c]);
-                row[j] = (lane == j) ? d * r : row[j] * r;
+                for (int q = 0; q < (IB - c0) / 2; ++q) cv[q] = reinterpret_cast<const double2 *>(col + c0)[q];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = j + 1; c < IB; ++c) {
+                    const double2 w = cv[(c - c0) / 2];
+                    row[c] = fma(-l, ((c - c0) & 1) ? w.y : w.x, row[c]);
+                }
+                row[j] = (lane == j) ? d * r : l;
             }
         }
     }
@@ -108,43 +147,67 @@ __device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *) {
         for (int c = 0; c < IB; ++c)
             if (c <= lane) LL(o + lane, o + c) = row[c];
     }
-    // X = L^{-1}: lane c owns column c, X[i][c] = (delta_ic - sum_{k<i} L[i][k] X[k][c]) / L[i][i]
-    double xc[IB];
+    // diagonal 16x16 blocks of X: lane c (group g = c / 16) forms column c of
+    // X_gg, X[16g+i][c] = (delta - sum_{k<i} L[16g+i][16g+k] X[16g+k][c]) / L[16g+i][16g+i]
+    const int cl = lane & (H - 1);
+    double xc[H];
 #pragma unroll
-    for (int i = 0; i < IB; ++i) {
-        if (i == bi) {
+    for (int i = 0; i < H; ++i) {
+        if (i + g0 == bi) {
             xc[i] = 0.0;
         } else {
-            double a0 = (i == lane) ? 1.0 : 0.0, a1 = 0.0;
+            double lr[H];
+#pragma unroll
+            for (int k = 0; k < i; ++k) lr[k] = LL(o + g0 + i, o + g0 + k);
+            __builtin_amdgcn_sched_barrier(0);
+            double a0 = (i == cl) ? 1.0 : 0.0, a1 = 0.0;
 #pragma unroll
             for (int k = 0; k + 1 < i; k += 2) {
-                a0 = fma(-readlane_d(row[k], i), xc[k], a0);
-                a1 = fma(-readlane_d(row[k + 1], i), xc[k + 1], a1);
+                a0 = fma(-lr[k], xc[k], a0);
+                a1 = fma(-lr[k + 1], xc[k + 1], a1);
             }
-            if (i & 1) a0 = fma(-readlane_d(row[i - 1], i), xc[i - 1], a0);
-            xc[i] = (a0 + a1) * rinv[i];
+            if (i & 1) a0 = fma(-lr[i - 1], xc[i - 1], a0);
+            xc[i] = (a0 + a1) * rl[i];
         }
     }
     if (act && lane != bi) {
 #pragma unroll
-        for (int i = 0; i < IB; ++i)
-            if (i >= lane) XX(o + i, o + lane) = xc[i];
+        for (int i = 0; i < H; ++i)
+            if (i >= cl) XX(o + g0 + i, o + lane) = xc[i];
     }
+    // X21 = -X22 (L21 X11)
+    const int fr = lane & 15, fk = lane >> 4;
+    double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+    acc = lds_mfma(
+        acc, [&](int m, int k) { return LL(o + H + m, o + k); },
+        [&](int k, int n) { return (k >= n) ? XX(o + k, o + n) : 0.0; }, 0, H);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[(fk + 4 * r) * (H + 1) + fr] = acc[r];
+    acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+    acc = lds_mfma(
+        acc, [&](int m, int k) { return (k <= m) ? XX(o + H + m, o + H + k) : 0.0; },
+        [&](int k, int n) { return t[k * (H + 1) + n]; }, 0, H);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) XX(o + H + fk + 4 * r, o + fr) = -acc[r];
     return -1;
 }
 
 // Factor one CB x CB diagonal block (rows/cols k0 .. k0+kb) of A and form X =
 // L^{-1} of the block (row-major CB x CB, zero outside the factor and on the
-// border row/column).  Products inside the block use 4 x 4 (or 2 x 2)
-// register blocks with independent accumulators.
+// border row/column).  Right-looking over four 32-wide sub-blocks: a one-wave
+// leaf factorisation, then the sub-panel solve and the trailing update as
+// 16x16 FP64 MFMA tiles spread over the four waves; finally the off-diagonal
+// blocks of X by distance, X_rs = -X_rr sum_{k=s}^{r-1} L_rk X_ks, as MFMA
+// tiles as well.
 __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t k0, int kb, int border_here, double *X,
                                                  DevStatus *status) {
     if (status->flag) return;
     extern __shared__ double s[];
     __shared__ int fail_sh;
-    __shared__ double colbuf[2 * IB];
+    __shared__ __align__(16) double colbuf[2 * IB];
     __shared__ double W[(CB / IB - 1) * IB * (IB + 1)];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int fr = lane & 15, fk = lane >> 4;
     const int bi = border_here ? kb - 1 : -1;
     {
         // all 64 loads of a thread are issued before any LDS store
@@ -168,7 +231,7 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
         const int o = sb * IB;
         if (wave == 0) {
             const int lb = (bi >= o && bi < o + IB) ? bi - o : -1;
-            const int f = potrf32_wave(s, o, lb, colbuf);
+            const int f = potrf32_wave(s, o, lb, colbuf, W);
             if (lane == 0) fail_sh = f < 0 ? -1 : o + f;
         }
         __syncthreads();
@@ -181,130 +244,85 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
         }
         const int r0 = o + IB, nr = CB - r0;
         if (nr <= 0) break;
-        // panel: L[r][o+j] = sum_{k<=j} A[r][o+k] X[o+j][o+k], one row x 4 columns per item
+        // sub-panel: L[r][o+j] = sum_{k<=j} A[r][o+k] X[o+j][o+k]; (nr/16) x 2 tiles, at most 3 per wave
         {
-            constexpr int QMAX = (CB - IB) * (IB / 4) / 256;  // 3
-            double out[QMAX][4];
+            double4_t acc[3];
+            const int ntile = (nr / 16) * 2;
 #pragma unroll
-            for (int q = 0; q < QMAX; ++q) {
-                const int e = tid + 256 * q;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) out[q][v] = 0.0;
-                if (e < nr * (IB / 4)) {
-                    const int r = r0 + e / (IB / 4), j0 = 4 * (e % (IB / 4));
-                    for (int k = 0; k < j0 + 4; ++k) {
-                        const double a = LL(r, o + k);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            out[q][v] = fma(a, (k <= j0 + v) ? XX(o + j0 + v, o + k) : 0.0, out[q][v]);
-                    }
+            for (int q = 0; q < 3; ++q) {
+                acc[q] = (double4_t){0.0, 0.0, 0.0, 0.0};
+                const int t = wave + 4 * q;
+                if (t < ntile) {
+                    const int rm = r0 + 16 * (t >> 1), cn = o + 16 * (t & 1);
+                    acc[q] = lds_mfma(
+                        acc[q], [&](int m, int k) { return LL(rm + m, o + k); },
+                        [&](int k, int n) { return (o + k <= cn + n) ? XX(cn + n, o + k) : 0.0; }, 0, IB);
                 }
             }
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < QMAX; ++q) {
-                const int e = tid + 256 * q;
-                if (e < nr * (IB / 4)) {
-                    const int r = r0 + e / (IB / 4), j0 = 4 * (e % (IB / 4));
+            for (int q = 0; q < 3; ++q) {
+                const int t = wave + 4 * q;
+                if (t < ntile) {
+                    const int rm = r0 + 16 * (t >> 1), cn = o + 16 * (t & 1);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) LL(r, o + j0 + v) = out[q][v];
+                    for (int r = 0; r < 4; ++r) LL(rm + fk + 4 * r, cn + fr) = acc[q][r];
                 }
             }
         }
         __syncthreads();
-        // trailing update (lower), 4x4 blocks: A[r][c] -= sum_k L[r][o+k] L[c][o+k]
+        // trailing update (lower tiles): A[r][c] -= sum_k L[r][o+k] L[c][o+k]
         {
-            const int nb = nr / 4;
-            for (int e = tid; e < nb * nb; e += 256) {
-                const int br = e / nb, bc = e % nb;
-                if (bc > br) continue;
-                const int r = r0 + 4 * br, c = r0 + 4 * bc;
-                double acc[4][4];
+            const int nt = nr / 16, nlow = nt * (nt + 1) / 2;
+            for (int t = wave; t < nlow; t += 4) {
+                int ti = 0;
+                while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+                const int tj = t - ti * (ti + 1) / 2;
+                const int rm = r0 + 16 * ti, cn = r0 + 16 * tj;
+                double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+                acc = lds_mfma(
+                    acc, [&](int m, int k) { return LL(rm + m, o + k); },
+                    [&](int k, int n) { return LL(cn + n, o + k); }, 0, IB);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-                for (int k = 0; k < IB; ++k) {
-                    double a[4], b[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) a[u] = LL(r + u, o + k);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) b[v] = LL(c + v, o + k);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rm + fk + 4 * r, col = cn + fr;
+                    if (col <= row) LL(row, col) -= acc[r];
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (c + v <= r + u) LL(r + u, c + v) -= acc[u][v];
             }
         }
         __syncthreads();
     }
     // ---- off-diagonal blocks of X by distance d = r - s (all blocks of one
-    //      distance together), 4x4 items (64 per block):
+    //      distance together), 16x16 tiles:
     //      W = sum_{k=s}^{r-1} L_rk X_ks,  X_rs = -X_rr W
-    {
 #pragma nounroll
-        for (int d = 1; d < CB / IB; ++d) {
-            const int nblk = CB / IB - d;
-            const int q = tid >> 6, it = tid & 63;
-            const int i0 = 4 * (it >> 3), j0 = 4 * (it & 7);
-            if (q < nblk) {
-                const int ro = (q + d) * IB, so = q * IB;
-                double *Wq = W + q * IB * (IB + 1);
-                double w[4][4];
+    for (int d = 1; d < CB / IB; ++d) {
+        const int nblk = CB / IB - d, ntile = nblk * 4;
+        for (int t = wave; t < ntile; t += 4) {
+            const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
+            const int ro = (q + d) * IB, so = q * IB;
+            const int rm = ro + 16 * ti, cn = so + 16 * tj;
+            double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+            acc = lds_mfma(
+                acc, [&](int m, int k) { return LL(rm + m, k); },
+                [&](int k, int n) { return (k >= cn + n) ? XX(k, cn + n) : 0.0; }, so, ro);
+            double *Wq = W + q * IB * (IB + 1);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) w[u][v] = 0.0;
-                for (int k = so + j0; k < ro; ++k) {
-                    double a[4], b[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) a[u] = LL(ro + i0 + u, k);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) b[v] = (k >= so + j0 + v) ? XX(k, so + j0 + v) : 0.0;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) w[u][v] = fma(a[u], b[v], w[u][v]);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) Wq[(i0 + u) * (IB + 1) + j0 + v] = w[u][v];
-            }
-            __syncthreads();
-            if (q < nblk) {
-                const int ro = (q + d) * IB, so = q * IB;
-                const double *Wq = W + q * IB * (IB + 1);
-                double x[4][4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) x[u][v] = 0.0;
-                for (int k = 0; k <= i0 + 3; ++k) {
-                    double a[4], b[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) a[u] = (k <= i0 + u) ? XX(ro + i0 + u, ro + k) : 0.0;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) b[v] = Wq[k * (IB + 1) + j0 + v];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) x[u][v] = fma(a[u], b[v], x[u][v]);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) XX(ro + i0 + u, so + j0 + v) = -x[u][v];
-            }
-            __syncthreads();
+            for (int r = 0; r < 4; ++r) Wq[(16 * ti + fk + 4 * r) * (IB + 1) + 16 * tj + fr] = acc[r];
         }
+        __syncthreads();
+        for (int t = wave; t < ntile; t += 4) {
+            const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
+            const int ro = (q + d) * IB, so = q * IB;
+            const double *Wq = W + q * IB * (IB + 1);
+            double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+            acc = lds_mfma(
+                acc, [&](int m, int k) { return (k <= 16 * ti + m) ? XX(ro + 16 * ti + m, ro + k) : 0.0; },
+                [&](int k, int n) { return Wq[k * (IB + 1) + 16 * tj + n]; }, 0, 16 * ti + 16);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) XX(ro + 16 * ti + fk + 4 * r, so + 16 * tj + fr) = -acc[r];
+        }
+        __syncthreads();
     }
     // ---- write L (rows < kb) and X (zero outside the factor) to global memory
 #pragma unroll 8
@@ -347,53 +365,62 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
         hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, A, nd, lda, mu);
     hipError_t e = hipSuccess;
     bool trail_pending = false;  // ev_trail marks a trailing update not yet waited for on st
-    for (int64_t k0 = 0; k0 < n; k0 += CB) {
-        const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
-        const int bh = (border && k0 + kb == n) ? 1 : 0;
-        double *Xb = linv + (k0 / CB) * CB * CB;
-        hipLaunchKernelGGL(potrf_block_kernel, dim3(1), dim3(256), shm, st, A, lda, k0, kb, bh, Xb, tmp, status);
-        const int64_t r1 = k0 + kb;          // first row of the next block
-        const int64_t rest = n - r1;
-        if (rest <= 0) break;
-        double *a21 = A + r1 * lda + k0;
-        // L21 = A21 X^T in place: each output tile owns its rows over all kb columns
-        GemmDesc t{};
-        t.M = rest; t.N = kb; t.K = kb;
-        t.A = a21; t.lda = lda; t.la = 0;
-        t.B = Xb; t.ldb = CB; t.lb = 1;
-        t.C = a21; t.ldc = lda;
-        t.alpha = 1.0; t.beta = 0.0;
-        t.stop_flag = &status->flag;
-        if ((e = launch_dgemm(st, t)) != hipSuccess) return e;
+    auto gemm = [&](hipStream_t s_, int64_t M, int64_t N, int64_t K, const double *a, const double *b, const double *bx,
+                    double *c, double alpha, double beta, int lower, int mask, int64_t max_blocks = 0) {
+        GemmDesc g{};
+        g.M = M; g.N = N; g.K = K;
+        g.A = a; g.lda = lda; g.la = 0;
+        g.B = b; g.ldb = bx ? CB : lda; g.lb = 1;
+        if (bx) g.B = bx;
+        g.C = c; g.ldc = lda;
+        g.alpha = alpha; g.beta = beta;
+        g.lower = lower; g.mask_lower = mask;
+        g.stop_flag = &status->flag;
+        g.max_blocks = max_blocks;
+        return launch_dgemm(s_, g);
+    };
+    // Two-level right-looking blocking: outer panels of NB columns, factored
+    // in CB-wide blocks (diagonal block, panel solve, update of the rest of the
+    // outer panel); the trailing matrix is then updated once per outer panel
+    // with K = NB, so each C tile is read and written once per NB columns.
+    for (int64_t K0 = 0; K0 < n; K0 += NB) {
+        const int64_t pe = (n - K0) < NB ? n : K0 + NB;  // end of the outer panel
+        for (int64_t k0 = K0; k0 < pe; k0 += CB) {
+            const int kb = (int)((n - k0) < CB ? (n - k0) : CB);
+            const int bh = (border && k0 + kb == n) ? 1 : 0;
+            double *Xb = linv + (k0 / CB) * CB * CB;
+            hipLaunchKernelGGL(potrf_block_kernel, dim3(1), dim3(256), shm, st, A, lda, k0, kb, bh, Xb, tmp, status);
+            const int64_t r1 = k0 + kb, rest = n - r1;
+            if (rest <= 0) break;
+            double *a21 = A + r1 * lda + k0;
+            // L21 = A21 X^T in place: each output tile owns its rows over all kb columns
+            if ((e = gemm(st, rest, kb, kb, a21, nullptr, Xb, a21, 1.0, 0.0, 0, 0)) != hipSuccess) return e;
+            // remaining columns of this outer panel
+            if (r1 < pe && (e = gemm(st, rest, pe - r1, kb, a21, a21, nullptr, A + r1 * lda + r1, -1.0, 1.0, 0, 1)) !=
+                               hipSuccess)
+                return e;
+        }
+        if (pe >= n) break;
+        const int64_t rest = n - pe, kw = pe - K0;
+        const double *lp = A + pe * lda + K0;  // L rows pe.. of the outer panel
         if ((e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
-        // block column of the next panel (rows >= r1, cols r1 .. r1+kb1), needed first
-        const int kb1 = (int)(rest < CB ? rest : CB);
+        // the next outer panel's columns first (main stream) ...
+        const int64_t nb1 = rest < NB ? rest : NB;
         if (trail_pending) {
             if ((e = hipStreamWaitEvent(st, ev_trail, 0)) != hipSuccess) return e;
             trail_pending = false;
         }
-        GemmDesc nx{};
-        nx.M = rest; nx.N = kb1; nx.K = kb;
-        nx.A = a21; nx.lda = lda; nx.la = 0;
-        nx.B = a21; nx.ldb = lda; nx.lb = 1;
-        nx.C = A + r1 * lda + r1; nx.ldc = lda;
-        nx.alpha = -1.0; nx.beta = 1.0;
-        nx.mask_lower = 1;
-        nx.stop_flag = &status->flag;
-        if ((e = launch_dgemm(st, nx)) != hipSuccess) return e;
-        // the rest of the trailing matrix (cols >= r1 + kb1) on the side stream
-        const int64_t r2 = r1 + kb1, rest2 = n - r2;
+        if ((e = gemm(st, rest, nb1, kw, lp, lp, nullptr, A + pe * lda + pe, -1.0, 1.0, 0, 1)) != hipSuccess) return e;
+        // ... the rest of the trailing matrix on the side stream (look-ahead)
+        const int64_t r2 = pe + nb1, rest2 = n - r2;
         if (rest2 > 0) {
             if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
-            GemmDesc sy{};
-            sy.M = rest2; sy.N = rest2; sy.K = kb;
-            sy.A = A + r2 * lda + k0; sy.lda = lda; sy.la = 0;
-            sy.B = A + r2 * lda + k0; sy.ldb = lda; sy.lb = 1;
-            sy.C = A + r2 * lda + r2; sy.ldc = lda;
-            sy.alpha = -1.0; sy.beta = 1.0;
-            sy.lower = 1;
-            sy.stop_flag = &status->flag;
-            if ((e = launch_dgemm(side, sy)) != hipSuccess) return e;
+            const double *l2 = A + r2 * lda + K0;
+            // capped so that a quarter of the CUs stay free for the next
+            // panel's diagonal blocks and solves on the main stream
+            if ((e = gemm(side, rest2, rest2, kw, l2, l2, nullptr, A + r2 * lda + r2, -1.0, 1.0, 1, 0, SIDE_BLOCKS)) !=
+                hipSuccess)
+                return e;
             if ((e = hipEventRecord(ev_trail, side)) != hipSuccess) return e;
             trail_pending = true;
         }
