@@ -75,18 +75,27 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-// One 16x16 tile of an in-LDS product, acc += A(16 x K) B(K x 16) over
-// k in [kbeg, kend) (multiples of 4), fragments read through accessors
-// a_at(m, k), b_at(k, n).  FP64 MFMA layout: lane l supplies A[l%16][l/16]
-// and B[l/16][l%16]; register r of the result is row l/16 + 4r, column l%16.
-template <class FA, class FB>
-__device__ __forceinline__ double4_t lds_mfma(double4_t acc, FA a_at, FB b_at, int kbeg, int kend) {
+// One 16x16 tile of an in-LDS product, acc += A(16 x KN) B(KN x 16) over
+// k in [kbeg, kbeg + KN) (KN a multiple of 4, fully unrolled so that the
+// fragment loads run ahead of the MFMAs), fragments read through accessors
+// a_at(m, k), b_at(k, n) (unconditional LDS loads; masks are selects).
+// FP64 MFMA layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// register r of the result is row l/16 + 4r, column l%16.
+template <int KN, class FA, class FB>
+__device__ __forceinline__ double4_t lds_mfma(double4_t acc, FA a_at, FB b_at, int kbeg) {
     const int lane = threadIdx.x & 63, fr = lane & 15, fk = lane >> 4;
-#pragma unroll 4
-    for (int k = kbeg; k < kend; k += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a_at(fr, k + fk), b_at(k + fk, fr), acc, 0, 0, 0);
+    double a[KN / 4], b[KN / 4];
+#pragma unroll
+    for (int q = 0; q < KN / 4; ++q) {
+        a[q] = a_at(fr, kbeg + 4 * q + fk);
+        b[q] = b_at(kbeg + 4 * q + fk, fr);
+    }
+#pragma unroll
+    for (int q = 0; q < KN / 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
     return acc;
 }
+
+__device__ __forceinline__ double sel(bool keep, double v) { return keep ? v : 0.0; }
 
 // One wave, lanes 0..31: lane i holds row o+i of the 32x32 diagonal block in
 // registers.  Pivot j: the pivot is read from lane j, every lane scales its
@@ -178,18 +187,53 @@ __device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *cb, d
     // X21 = -X22 (L21 X11)
     const int fr = lane & 15, fk = lane >> 4;
     double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-    acc = lds_mfma(
+    acc = lds_mfma<H>(
         acc, [&](int m, int k) { return LL(o + H + m, o + k); },
-        [&](int k, int n) { return (k >= n) ? XX(o + k, o + n) : 0.0; }, 0, H);
+        [&](int k, int n) { return sel(k >= n, XX(o + k, o + n)); }, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) t[(fk + 4 * r) * (H + 1) + fr] = acc[r];
     acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-    acc = lds_mfma(
-        acc, [&](int m, int k) { return (k <= m) ? XX(o + H + m, o + H + k) : 0.0; },
-        [&](int k, int n) { return t[k * (H + 1) + n]; }, 0, H);
+    acc = lds_mfma<H>(
+        acc, [&](int m, int k) { return sel(k <= m, XX(o + H + m, o + H + k)); },
+        [&](int k, int n) { return t[k * (H + 1) + n]; }, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) XX(o + H + fk + 4 * r, o + fr) = -acc[r];
     return -1;
+}
+
+// Off-diagonal blocks X_rs of the inverse of the block's factor at distance
+// D = r - s (in 32-blocks), from the blocks at smaller distances:
+// W = sum_{k=s}^{r-1} L_rk X_ks, then X_rs = -X_rr W.  16x16 MFMA tiles
+// spread over the four waves; W (three 32x33 buffers) holds the sums.
+template <int D>
+__device__ __forceinline__ void x_blocks_at_distance(double *s, double *W, int wave) {
+    const int lane = threadIdx.x & 63, fr = lane & 15, fk = lane >> 4;
+    constexpr int NBLK = CB / IB - D, NTILE = NBLK * 4;
+    for (int t = wave; t < NTILE; t += 4) {
+        const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
+        const int ro = (q + D) * IB, so = q * IB;
+        const int rm = ro + 16 * ti, cn = so + 16 * tj;
+        double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+        acc = lds_mfma<IB * D>(
+            acc, [&](int m, int k) { return LL(rm + m, k); },
+            [&](int k, int n) { return sel(k >= cn + n, XX(k, cn + n)); }, so);
+        double *Wq = W + q * IB * (IB + 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wq[(16 * ti + fk + 4 * r) * (IB + 1) + 16 * tj + fr] = acc[r];
+    }
+    __syncthreads();
+    for (int t = wave; t < NTILE; t += 4) {
+        const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
+        const int ro = (q + D) * IB, so = q * IB;
+        const double *Wq = W + q * IB * (IB + 1);
+        double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+        acc = lds_mfma<IB>(
+            acc, [&](int m, int k) { return sel(k <= 16 * ti + m, XX(ro + 16 * ti + m, ro + k)); },
+            [&](int k, int n) { return Wq[k * (IB + 1) + 16 * tj + n]; }, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) XX(ro + 16 * ti + fk + 4 * r, so + 16 * tj + fr) = -acc[r];
+    }
+    __syncthreads();
 }
 
 // Factor one CB x CB diagonal block (rows/cols k0 .. k0+kb) of A and form X =
@@ -206,7 +250,8 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
     __shared__ int fail_sh;
     __shared__ __align__(16) double colbuf[2 * IB];
     __shared__ double W[(CB / IB - 1) * IB * (IB + 1)];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over tiles stay scalar
     const int fr = lane & 15, fk = lane >> 4;
     const int bi = border_here ? kb - 1 : -1;
     {
@@ -254,9 +299,9 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
                 const int t = wave + 4 * q;
                 if (t < ntile) {
                     const int rm = r0 + 16 * (t >> 1), cn = o + 16 * (t & 1);
-                    acc[q] = lds_mfma(
+                    acc[q] = lds_mfma<IB>(
                         acc[q], [&](int m, int k) { return LL(rm + m, o + k); },
-                        [&](int k, int n) { return (o + k <= cn + n) ? XX(cn + n, o + k) : 0.0; }, 0, IB);
+                        [&](int k, int n) { return sel(o + k <= cn + n, XX(cn + n, o + k)); }, 0);
                 }
             }
             __syncthreads();
@@ -280,9 +325,9 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
                 const int tj = t - ti * (ti + 1) / 2;
                 const int rm = r0 + 16 * ti, cn = r0 + 16 * tj;
                 double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-                acc = lds_mfma(
+                acc = lds_mfma<IB>(
                     acc, [&](int m, int k) { return LL(rm + m, o + k); },
-                    [&](int k, int n) { return LL(cn + n, o + k); }, 0, IB);
+                    [&](int k, int n) { return LL(cn + n, o + k); }, 0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = rm + fk + 4 * r, col = cn + fr;
@@ -295,35 +340,9 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
     // ---- off-diagonal blocks of X by distance d = r - s (all blocks of one
     //      distance together), 16x16 tiles:
     //      W = sum_{k=s}^{r-1} L_rk X_ks,  X_rs = -X_rr W
-#pragma nounroll
-    for (int d = 1; d < CB / IB; ++d) {
-        const int nblk = CB / IB - d, ntile = nblk * 4;
-        for (int t = wave; t < ntile; t += 4) {
-            const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
-            const int ro = (q + d) * IB, so = q * IB;
-            const int rm = ro + 16 * ti, cn = so + 16 * tj;
-            double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-            acc = lds_mfma(
-                acc, [&](int m, int k) { return LL(rm + m, k); },
-                [&](int k, int n) { return (k >= cn + n) ? XX(k, cn + n) : 0.0; }, so, ro);
-            double *Wq = W + q * IB * (IB + 1);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Wq[(16 * ti + fk + 4 * r) * (IB + 1) + 16 * tj + fr] = acc[r];
-        }
-        __syncthreads();
-        for (int t = wave; t < ntile; t += 4) {
-            const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
-            const int ro = (q + d) * IB, so = q * IB;
-            const double *Wq = W + q * IB * (IB + 1);
-            double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-            acc = lds_mfma(
-                acc, [&](int m, int k) { return (k <= 16 * ti + m) ? XX(ro + 16 * ti + m, ro + k) : 0.0; },
-                [&](int k, int n) { return Wq[k * (IB + 1) + 16 * tj + n]; }, 0, 16 * ti + 16);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) XX(ro + 16 * ti + fk + 4 * r, so + 16 * tj + fr) = -acc[r];
-        }
-        __syncthreads();
-    }
+    x_blocks_at_distance<1>(s, W, wave);
+    x_blocks_at_distance<2>(s, W, wave);
+    x_blocks_at_distance<3>(s, W, wave);
     // ---- write L (rows < kb) and X (zero outside the factor) to global memory
 #pragma unroll 8
     for (int e = 0; e < CB * CB / 256; ++e) {
