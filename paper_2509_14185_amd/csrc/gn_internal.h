@@ -128,7 +128,6 @@ struct GemmDesc {
     int lower;                 // square lower-triangular tile set (M == N)
     int mask_lower;            // rectangular tile set, write only n <= m
     const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
-    int64_t max_blocks;        // > 0: at most this many workgroups (rest of the chip left to other streams)
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
 // n independent GEMMs in one launch.  plan_dgemm_batched builds, once per

@@ -136,6 +136,25 @@ struct TileLoader {
     static constexpr int LDK = BK + 2;
     static constexpr int SIZE = CONTIG_MN ? BK * R : R * LDK;  // doubles per buffer
     __device__ __forceinline__ static int at(int r, int k) { return CONTIG_MN ? k * R + r : r * LDK + k; }
+    // Direct global -> LDS copy of one chunk (operands contiguous along r,
+    // whole chunk in bounds, 16-byte aligned): each wave instruction moves 64
+    // x 16 bytes = 128 doubles, i.e. 128 / R consecutive k-rows of the tile,
+    // which are also consecutive in the [k][r] LDS layout.  No registers are
+    // involved; completion is waited for with vmcnt before the barrier.
+    __device__ __forceinline__ static void direct(const double *base, int64_t ld, int64_t r0, int64_t k0, double *lds,
+                                                  int wave) {
+        static_assert(CONTIG_MN, "direct copies need the [k][r] layout");
+        constexpr int ROWS = 128 / R;                          // k-rows per wave instruction
+        constexpr int PERW = BK / ROWS / (GEMM_THREADS / 64);  // instructions per wave
+        static_assert(PERW * ROWS * (GEMM_THREADS / 64) == BK, "chunk split");
+        const int lane = threadIdx.x & 63;
+        const int kin = (2 * lane) / R, r = (2 * lane) % R;
+#pragma unroll
+        for (int q = 0; q < PERW; ++q) {
+            const int kk = (wave * PERW + q) * ROWS;
+            __builtin_amdgcn_global_load_lds(base + (k0 + kk + kin) * ld + r0 + r, lds + kk * R, 16, 0, 0);
+        }
+    }
     __device__ __forceinline__ void store(double *lds) const {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
@@ -148,7 +167,7 @@ struct TileLoader {
 
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
 __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0,
-                                                                 int64_t nvirt, const GemmDesc *__restrict__ batch,
+                                                                 const GemmDesc *__restrict__ batch,
                                                                  const int4 *__restrict__ work) {
     // batched launches read (problem, tile row, tile column) from a work table
     // laid out in dispatch order (entry b runs on XCD b % 8)
@@ -170,21 +189,14 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
     double *As = smem;                       // two buffers of LoaderA::SIZE
     double *Bs = smem + 2 * LoaderA::SIZE;   // two buffers of LoaderB::SIZE
 
-    // A capped grid (fewer workgroups than virtual blocks) walks the virtual
-    // blocks with stride gridDim.x, a multiple of 8, so each workgroup keeps
-    // its XCD's share of the tile order.
-    const bool lower_mask = g.lower || g.mask_lower;
-    for (int64_t vb = blockIdx.x; BATCH || vb < nvirt; vb += gridDim.x) {
     int tm = wi.y, tn = wi.z;
-    if (!BATCH && !tile_of_block(vb, g.lower, tiles_m0, tiles_n0, tm, tn)) continue;
+    if (!BATCH && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-    if (lower_mask && n0 > m0 + BM - 1) {  // tile entirely above the diagonal
-        if (BATCH) break;
-        continue;
-    }
+    const bool lower_mask = g.lower || g.mask_lower;
+    if (lower_mask && n0 > m0 + BM - 1) return;  // tile entirely above the diagonal
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
 
     double4_t acc[FM][FN];
@@ -209,35 +221,73 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
         la.store(As + buf * LoaderA::SIZE);
         lb.store(Bs + buf * LoaderB::SIZE);
     };
-
-    if (nk > 0) {
-        load_chunk(0);
-        store_chunk(0);
-        __syncthreads();
-    }
     const int fr = lane & 15, fk = lane >> 4;
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int cur = (int)(kt & 1);
-        if (kt + 1 < nk) load_chunk((kt + 1) * BK);
-        const double *as = As + cur * LoaderA::SIZE;
-        const double *bs = Bs + cur * LoaderB::SIZE;
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            double a[FM], b[FN];
-#pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = as[LoaderA::at(wm * WM + i * 16 + fr, ks + fk)];
-#pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = bs[LoaderB::at(wn * WN + j * 16 + fr, ks + fk)];
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    // MFMAs of one staged chunk (a macro so the accumulators stay registers)
+#define GEMM_COMPUTE(buf)                                                                          \
+    do {                                                                                           \
+        const double *as_ = As + (buf) * LoaderA::SIZE;                                            \
+        const double *bs_ = Bs + (buf) * LoaderB::SIZE;                                            \
+        _Pragma("unroll") for (int ks = 0; ks < BK; ks += 4) {                                     \
+            double a_[FM], b_[FN];                                                                 \
+            _Pragma("unroll") for (int i = 0; i < FM; ++i) a_[i] =                                 \
+                as_[LoaderA::at(wm * WM + i * 16 + fr, ks + fk)];                                  \
+            _Pragma("unroll") for (int j = 0; j < FN; ++j) b_[j] =                                 \
+                bs_[LoaderB::at(wn * WN + j * 16 + fr, ks + fk)];                                  \
+            _Pragma("unroll") for (int i = 0; i < FM; ++i)                                         \
+                _Pragma("unroll") for (int j = 0; j < FN; ++j) acc[i][j] =                         \
+                    __builtin_amdgcn_mfma_f64_16x16x4f64(a_[i], b_[j], acc[i][j], 0, 0, 0);        \
+        }                                                                                          \
+    } while (0)
+
+    bool direct_done = false;
+    if constexpr (LA == 1 && LB == 0) {
+        // both operands contiguous: interior tiles copy full chunks global ->
+        // LDS directly (no staging registers); a ragged last chunk of K is
+        // staged through registers on its own after the loop
+        if (a_rows_in && b_rows_in && a_aligned && b_aligned) {
+            direct_done = true;
+            const int64_t nkf = g.K / BK;
+            if (nkf > 0) {
+                LoaderA::direct(g.A, g.lda, m0, 0, As, wave);
+                LoaderB::direct(g.B, g.ldb, n0, 0, Bs, wave);
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+            }
+            for (int64_t kt = 0; kt < nkf; ++kt) {
+                const int cur = (int)(kt & 1);
+                if (kt + 1 < nkf) {
+                    LoaderA::direct(g.A, g.lda, m0, (kt + 1) * BK, As + (cur ^ 1) * LoaderA::SIZE, wave);
+                    LoaderB::direct(g.B, g.ldb, n0, (kt + 1) * BK, Bs + (cur ^ 1) * LoaderB::SIZE, wave);
+                }
+                GEMM_COMPUTE(cur);
+                __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of the next chunk have landed
+                __syncthreads();
+            }
+            if (nkf < nk) {
+                const int buf = (int)(nkf & 1);
+                load_chunk(nkf * BK);
+                store_chunk(buf);
+                __syncthreads();
+                GEMM_COMPUTE(buf);
+            }
         }
-        if (kt + 1 < nk) store_chunk(cur ^ 1);
-        __syncthreads();
+    }
+    if (!direct_done) {
+        if (nk > 0) {
+            load_chunk(0);
+            store_chunk(0);
+            __syncthreads();
+        }
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int cur = (int)(kt & 1);
+            if (kt + 1 < nk) load_chunk((kt + 1) * BK);
+            GEMM_COMPUTE(cur);
+            if (kt + 1 < nk) store_chunk(cur ^ 1);
+            __syncthreads();
+        }
     }
 
+#undef GEMM_COMPUTE
     // epilogue: lane l, register r holds row fk + 4 r, column fr of each
     // 16x16 block.  All loads of C and the row scales are issued before any
     // store so they overlap.
@@ -276,8 +326,6 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
             }
         }
     }
-    if (BATCH) break;
-    }
 }
 
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
@@ -290,12 +338,8 @@ static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         attr = true;
     }
-    // a non-batched launch may cap its grid (GemmDesc::max_blocks, rounded to
-    // whole rounds of 8 XCDs); the workgroups then stride over the blocks
-    int64_t grid = blocks;
-    if (!BATCH && g.max_blocks > 0 && g.max_blocks < blocks) grid = (g.max_blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)grid), dim3(GEMM_THREADS),
-                       shm, st, g, tiles_m, tiles_n, blocks, batch, work);
+    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)blocks), dim3(GEMM_THREADS),
+                       shm, st, g, tiles_m, tiles_n, batch, work);
     return hipGetLastError();
 }
 

@@ -33,7 +33,6 @@ namespace gn {
 
 static constexpr int CB = 128;         // diagonal block width of the blocked Cholesky
 static constexpr int NB = 4 * CB;      // outer panel width (K of the trailing update)
-static constexpr int SIDE_BLOCKS = 192;  // workgroups of the look-ahead trailing update
 static constexpr int LDS_LD = CB + 1;  // padded LDS row stride (doubles)
 
 int64_t chol_linv_size(int64_t n) { return ((n + CB - 1) / CB) * CB * CB; }
@@ -385,7 +384,7 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
     hipError_t e = hipSuccess;
     bool trail_pending = false;  // ev_trail marks a trailing update not yet waited for on st
     auto gemm = [&](hipStream_t s_, int64_t M, int64_t N, int64_t K, const double *a, const double *b, const double *bx,
-                    double *c, double alpha, double beta, int lower, int mask, int64_t max_blocks = 0) {
+                    double *c, double alpha, double beta, int lower, int mask) {
         GemmDesc g{};
         g.M = M; g.N = N; g.K = K;
         g.A = a; g.lda = lda; g.la = 0;
@@ -395,7 +394,6 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
         g.alpha = alpha; g.beta = beta;
         g.lower = lower; g.mask_lower = mask;
         g.stop_flag = &status->flag;
-        g.max_blocks = max_blocks;
         return launch_dgemm(s_, g);
     };
     // Two-level right-looking blocking: outer panels of NB columns, factored
@@ -435,10 +433,7 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
         if (rest2 > 0) {
             if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
             const double *l2 = A + r2 * lda + K0;
-            // capped so that a quarter of the CUs stay free for the next
-            // panel's diagonal blocks and solves on the main stream
-            if ((e = gemm(side, rest2, rest2, kw, l2, l2, nullptr, A + r2 * lda + r2, -1.0, 1.0, 1, 0, SIDE_BLOCKS)) !=
-                hipSuccess)
+            if ((e = gemm(side, rest2, rest2, kw, l2, l2, nullptr, A + r2 * lda + r2, -1.0, 1.0, 1, 0)) != hipSuccess)
                 return e;
             if ((e = hipEventRecord(ev_trail, side)) != hipSuccess) return e;
             trail_pending = true;
