@@ -36,11 +36,11 @@ struct gn_context {
     int64_t n = 0, m = 0, nv = 0;
     Geo1D pts{}, nodes{}, val{};
     double *rho = nullptr, *f = nullptr;
-    double *Q = nullptr;
+    double *Q = nullptr;              // Q^T of the Hilbert quadrature (m rows, stride ldQ)
     int64_t ldQ = 0;
     double *nn_pts = nullptr, *nn_nodes = nullptr, *nn_val = nullptr;
     double *R = nullptr, *seed0 = nullptr, *seed1 = nullptr, *cscale = nullptr, *r_tmp = nullptr;
-    double *vseed0 = nullptr, *vseed1 = nullptr, *useed = nullptr, *hadj_work = nullptr;
+    double *vseed0 = nullptr, *vseed1 = nullptr, *useed = nullptr;
     double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
     float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
     int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
@@ -166,7 +166,7 @@ gn_status jacobian_into(gn_handle h, const double *theta, double *J, int64_t ldJ
         GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, nb));
         GemmDesc g{};
         g.M = h->n; g.N = h->md.P; g.K = h->m;
-        g.A = h->Q; g.lda = h->ldQ; g.la = 0;
+        g.A = h->Q; g.lda = h->ldQ; g.la = 1;
         g.B = h->Bm; g.ldb = h->ldJ; g.lb = 0;
         g.C = J; g.ldc = ldJ;
         g.alpha = 1.0; g.beta = 1.0; g.rowscale = h->cscale;
@@ -194,7 +194,7 @@ void mark(gn_handle h, int k) {
 GemmDesc coupling_desc(gn_handle h) {
     GemmDesc c{};
     c.M = h->n; c.N = h->md.P; c.K = h->m;
-    c.A = h->Q; c.lda = h->ldQ; c.la = 0;
+    c.A = h->Q; c.lda = h->ldQ; c.la = 1;
     c.B = h->Bm; c.ldb = h->ldJ; c.lb = 0;
     c.C = h->J; c.ldc = h->ldJ;
     c.alpha = 1.0; c.beta = 1.0; c.rowscale = h->cscale;
@@ -388,7 +388,7 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     const int64_t m_rows = n + 1;
     h->ldJ = round_up(P + 1, 32);
     h->ldG = round_up(P + 1, 32);
-    h->ldQ = m_quad;
+    h->ldQ = round_up(n, 2);  // Q^T: m_quad rows of n points (even stride: 16-byte aligned rows)
     const int64_t nparts = mlp_vjp_partials(h->md, n) + mlp_vjp_partials(h->md, 1) + mlp_vjp_partials(h->md, m_quad);
     auto geo = [&](Geo1D &g, int64_t cnt, bool with_w) -> gn_status {
         GN_TRY(dev_alloc(h, A, &g.y, cnt));
@@ -408,7 +408,7 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     if (s == GN_OK && !d_rho) h->rho = nullptr;
     if (s == GN_OK && d_f) s = dev_alloc(h, A, &h->f, n);
     if (s == GN_OK && !d_f) h->f = nullptr;
-    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Q, n * m_quad);
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Q, m_quad * h->ldQ);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_pts, 2 * n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_nodes, 2 * m_quad);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_val, 2 * n_val);
@@ -420,7 +420,6 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     if (s == GN_OK) s = dev_alloc(h, A, &h->vseed0, n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->vseed1, n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->useed, m_quad);
-    if (s == GN_OK) s = dev_alloc(h, A, &h->hadj_work, hilbert_adjoint_work_size(m_quad));
     if (s == GN_OK) s = dev_alloc(h, A, &h->J, m_rows * h->ldJ);
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Bm, m_quad * h->ldJ);
     if (s == GN_OK) s = dev_alloc(h, A, &h->G, (P + 1) * h->ldG);
@@ -596,7 +595,7 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
     if (h->equation == GN_EQ_CCF1D) {
         // Hilbert coupling adjoint: node seeds E_j sum_i Q_ij v_i sc_i Theta_y,i
         GN_HIP(h, launch_hilbert_adjoint(st, h->n, h->m, h->Q, h->ldQ, d_v, h->cscale, h->nodes.E, h->useed,
-                                         h->hadj_work));
+                                         nullptr));
         SweepBatch nb{};
         nb.x = h->nodes.q; nb.s0 = h->useed; nb.s1c = 0.0; nb.n = h->m;
         GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, nb, h->partial + (c0 + c1) * P, &c2));

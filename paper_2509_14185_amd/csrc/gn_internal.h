@@ -67,8 +67,9 @@ struct DevStatus {
 hipError_t launch_geometry(hipStream_t st, int equation, double lam, int64_t n, const double *s,
                            const double *ws, Geo1D g);
 // Q[i][j] (n x m, ld) of the half-line Hilbert quadrature.
+// Q^T of the half-line Hilbert quadrature: QT[j*ld + i] = Q_ij (m rows of n).
 hipError_t launch_hilbert_matrix(hipStream_t st, int64_t n, int64_t m, const double *y,
-                                 const double *t, const double *wh, double *Q, int64_t ld);
+                                 const double *t, const double *wh, double *QT, int64_t ld);
 
 // Network sweeps.  thetaT holds the per-layer transposed weights written by
 // launch_transpose_weights for the same theta (P doubles).
@@ -107,10 +108,10 @@ hipError_t launch_residual(hipStream_t st, const ResidualArgs &a);
 // Normalisation row: r = sqrt(c) (NN(1) - target), written to r_out.
 hipError_t launch_norm_row(hipStream_t st, const double *nn1, double sqrt_c, double target,
                            double *r_out);
-// Node seeds for the coupling adjoint: out_j = E_j * (Q^T w)_j, w_i = v_i cscale_i.
-// work holds hilbert_adjoint_work_size(m) doubles.
+// Node seeds for the coupling adjoint: out_j = E_j * (Q^T w)_j, w_i = v_i cscale_i
+// (QT as from launch_hilbert_matrix; work is unused, kept for the interface).
 int64_t hilbert_adjoint_work_size(int64_t m);
-hipError_t launch_hilbert_adjoint(hipStream_t st, int64_t n, int64_t m, const double *Q, int64_t ldq,
+hipError_t launch_hilbert_adjoint(hipStream_t st, int64_t n, int64_t m, const double *QT, int64_t ld,
                                   const double *v, const double *cscale, const double *E_nodes,
                                   double *out, double *work);
 

@@ -72,20 +72,22 @@ hipError_t launch_geometry(hipStream_t st, int equation, double lam, int64_t n, 
     return hipGetLastError();
 }
 
+// Q^T: row j (node), column i (point), so the coupling product reads it
+// contiguously along i (the output rows) and the adjoint along i as well.
 __global__ void hilbert_matrix_kernel(int64_t n, int64_t m, const double *__restrict__ y,
                                       const double *__restrict__ t, const double *__restrict__ wh,
-                                      double *__restrict__ Q, int64_t ld) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    Q[i * ld + j] = hilbert_q(y[i], t[j], wh[j]);
+                                      double *__restrict__ QT, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (i >= n || j >= m) return;
+    QT[j * ld + i] = hilbert_q(y[i], t[j], wh[j]);
 }
 
 hipError_t launch_hilbert_matrix(hipStream_t st, int64_t n, int64_t m, const double *y, const double *t,
-                                 const double *wh, double *Q, int64_t ld) {
+                                 const double *wh, double *QT, int64_t ld) {
     if (n <= 0 || m <= 0) return hipSuccess;
-    dim3 grid((unsigned)((m + 255) / 256), (unsigned)n);
-    hipLaunchKernelGGL(hilbert_matrix_kernel, grid, dim3(256), 0, st, n, m, y, t, wh, Q, ld);
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)m);
+    hipLaunchKernelGGL(hilbert_matrix_kernel, grid, dim3(256), 0, st, n, m, y, t, wh, QT, ld);
     return hipGetLastError();
 }
 
@@ -446,41 +448,30 @@ hipError_t launch_norm_row(hipStream_t st, const double *nn1, double sqrt_c, dou
     return hipGetLastError();
 }
 
-// out_j = E_j sum_i Q_ij v_i cscale_i, two passes over row chunks.
-static constexpr int HADJ_CHUNKS = 64;
-
-__global__ void hilbert_adjoint_partial(int64_t n, int64_t m, const double *__restrict__ Q, int64_t ldq,
-                                        const double *__restrict__ v, const double *__restrict__ cs,
-                                        double *__restrict__ part) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// out_j = E_j sum_i Q_ij v_i cscale_i: one wave per node j, lanes stride over
+// the points of row j of Q^T in order, then a fixed butterfly (deterministic).
+__global__ __launch_bounds__(256) void hilbert_adjoint_kernel(int64_t n, int64_t m, const double *__restrict__ QT,
+                                                              int64_t ld, const double *__restrict__ v,
+                                                              const double *__restrict__ cs,
+                                                              const double *__restrict__ E, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= m) return;
-    const int64_t per = (n + HADJ_CHUNKS - 1) / HADJ_CHUNKS;
-    const int64_t i0 = blockIdx.y * per;
-    const int64_t i1 = (i0 + per < n) ? i0 + per : n;
+    const double *row = QT + j * ld;
     double acc = 0.0;
-    for (int64_t i = i0; i < i1; ++i) acc = fma(Q[i * ldq + j], v[i] * cs[i], acc);
-    part[blockIdx.y * m + j] = acc;
+    for (int64_t i = lane; i < n; i += 64) acc = fma(row[i], v[i] * cs[i], acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) out[j] = E[j] * acc;
 }
 
-__global__ void hilbert_adjoint_final(int64_t m, const double *__restrict__ part, const double *__restrict__ E,
-                                      double *__restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    double acc = 0.0;
-    for (int c = 0; c < HADJ_CHUNKS; ++c) acc += part[c * m + j];
-    out[j] = E[j] * acc;
-}
+int64_t hilbert_adjoint_work_size(int64_t) { return 0; }
 
-int64_t hilbert_adjoint_work_size(int64_t m) { return (int64_t)HADJ_CHUNKS * m; }
-
-hipError_t launch_hilbert_adjoint(hipStream_t st, int64_t n, int64_t m, const double *Q, int64_t ldq,
+hipError_t launch_hilbert_adjoint(hipStream_t st, int64_t n, int64_t m, const double *QT, int64_t ld,
                                   const double *v, const double *cscale, const double *E_nodes, double *out,
-                                  double *part) {
+                                  double *) {
     if (m <= 0) return hipSuccess;
-    dim3 g1((unsigned)((m + 255) / 256), HADJ_CHUNKS);
-    hipLaunchKernelGGL(hilbert_adjoint_partial, g1, dim3(256), 0, st, n, m, Q, ldq, v, cscale, part);
-    hipLaunchKernelGGL(hilbert_adjoint_final, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, part,
-                       E_nodes, out);
+    hipLaunchKernelGGL(hilbert_adjoint_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, n, m, QT, ld, v,
+                       cscale, E_nodes, out);
     return hipGetLastError();
 }
 
