@@ -8,6 +8,9 @@ Only the seeded input generators (package `workloads`) feed both sides.
 Contents:
 - profile1d: geometry, tanh-MLP jets, envelope, Hilbert term, CCF / local
   Burgers residual rows, parameter Jacobian by a reverse sweep (numpy).
+- profile2d: 2D coordinates, second-order network jets in y (Taylor mode),
+  IPM-style and Boussinesq-type residual rows, parameter Jacobian by the
+  complex-step derivative (numpy).
 - dense (dense.c): compensated Gram and gradient, textbook Cholesky, forward
   and back substitution (plain C, built with gcc).
 - gn: the damped Gauss-Newton step composed from the two.

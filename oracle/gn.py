@@ -36,10 +36,16 @@ def damped_solve(G, g, mu):
     return dense.solve_lower_t(L, z), 0
 
 
-def step(prob: p1.Problem, theta, mu):
-    """One damped GN step.  Returns (theta_next, info dict)."""
-    r = p1.residual_rows(prob, theta)
-    J = p1.jacobian(prob, theta)
+def step(prob, theta, mu):
+    """One damped GN step.  Returns (theta_next, info dict).  prob is a 1D
+    profile problem (profile1d.Problem) or any problem with residual_rows and
+    jacobian methods (profile2d.Problem)."""
+    if hasattr(prob, "residual_rows"):
+        r = prob.residual_rows(theta)
+        J = prob.jacobian(theta)
+    else:
+        r = p1.residual_rows(prob, theta)
+        J = p1.jacobian(prob, theta)
     G, g = gram_and_gradient(J, r)
     delta, info = damped_solve(G, g, mu)
     stats = dict(half_sq_norm=0.5 * float(r @ r), r=r, J=J, G=G, g=g, delta=delta, chol_info=info)

@@ -33,6 +33,21 @@ WORKLOADS = {
                        mu=1e-3, steps=50, c_norm=1.0, c_target=1.0),
 }
 
+# 2D stand-ins (the paper's IPM and Boussinesq residuals are in its missing
+# supplementary material): blow-up rates of the first unstable profiles
+# (paper, main text, table of lambda_n fits, n = 1).
+LAM_IPM1 = 0.4721
+LAM_BOUSS1 = 1.3992
+
+WORKLOADS_2D = {
+    # IPM-style: one field, second-order jets, d1 rows, symmetry rows.
+    "ipm2d": dict(equation="ipm2d", widths=[2, 64, 64, 64, 64, 1], lam=LAM_IPM1, n=65536, n1=16384, ne=256,
+                  seed=3, mu=1e-3, steps=10, c_norm=1.0, c_target=1.0),
+    # Boussinesq-type: three fields from one network, streamed row chunks.
+    "bouss2d": dict(equation="bouss2d", widths=[2, 128, 128, 128, 128, 3], lam=LAM_BOUSS1, n=262144, n1=0,
+                    ne=256, seed=5, mu=1e-3, steps=20, c_norm=1.0, c_target=1.0, row_chunk=32768),
+}
+
 # Batched CCF: independent instances with their own blow-up rate lambda drawn
 # uniformly in [0.3, 1.0], uneven point counts N drawn uniformly in
 # [1024, 16384], the small network with a per-instance seed.
@@ -144,4 +159,57 @@ def make_batched_inputs(instances: int | None = None, n_range=None, m_quad: int 
                  sval=validation_grid(n), theta0=glorot_theta(cfg["widths"], 1000 + i),
                  P=num_params(cfg["widths"]))
         out.append(d)
+    return out
+
+
+def sobol_points(n: int, n1: int, seed: int):
+    """Scrambled Sobol points on [0,1)^2: the first n (a power of two uses the
+    balanced base-2 block) and the next n1 of the same sequence."""
+    from scipy.stats import qmc
+
+    eng = qmc.Sobol(d=2, scramble=True, seed=seed)
+    k = int(n).bit_length() - 1
+    if n > 0 and (1 << k) == n:
+        s = eng.random_base2(k)
+    else:
+        s = eng.random(n)
+    s1 = eng.random(n1) if n1 > 0 else np.zeros((0, 2))
+    return np.ascontiguousarray(s, dtype=np.float64), np.ascontiguousarray(s1, dtype=np.float64)
+
+
+def validation_grid_2d(n: int) -> np.ndarray:
+    """Midpoint grid of (2 sqrt(n))^2 = 4n points in s-space (the 2D analogue
+    of the 1D 4n-midpoint grid), row-major, shape (nv, 2)."""
+    k = max(2, int(round(2.0 * np.sqrt(n))))
+    g = (np.arange(k, dtype=np.float64) + 0.5) / k
+    a, b = np.meshgrid(g, g, indexing="ij")
+    return np.ascontiguousarray(np.stack([a.ravel(), b.ravel()], axis=1))
+
+
+def edge_points(ne: int) -> np.ndarray:
+    """s-coordinates of the symmetry/boundary rows on y2 = 0: midpoints in s1."""
+    return (np.arange(ne, dtype=np.float64) + 0.5) / ne
+
+
+def make_inputs_2d(name: str, n: int | None = None, n1: int | None = None, ne: int | None = None,
+                   widths=None, nval: int | None = None) -> dict:
+    """All arrays for one 2D workload (sizes may be overridden for tests).
+    s (n,2), s1 (n1,2), se (ne,), sval (nv,2) are s-coordinates; the map to
+    y and to the network inputs is computed by each side."""
+    cfg = dict(WORKLOADS_2D[name])
+    for k, v in (("n", n), ("n1", n1), ("ne", ne)):
+        if v is not None:
+            cfg[k] = v
+    if widths is not None:
+        cfg["widths"] = list(widths)
+    s, s1 = sobol_points(cfg["n"], cfg["n1"], cfg["seed"])
+    out = dict(cfg)
+    out.update(
+        s=s,
+        s1=s1,
+        se=edge_points(cfg["ne"]),
+        sval=validation_grid_2d(cfg["n"] if nval is None else nval),
+        theta0=glorot_theta(cfg["widths"], cfg["seed"]),
+        P=num_params(cfg["widths"]),
+    )
     return out
