@@ -56,8 +56,21 @@ typedef enum {
 /* Profile equation.  CCF: R = -lam Theta + ((1+lam) y + H Theta) Theta_y with
  * the half-line Hilbert transform of the even field Theta (the Cordoba-
  * Cordoba-Fontelos model under the self-similar ansatz).  BURGERS1D: the
- * local analogue with H Theta replaced by Theta (odd field). */
-typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1 } gn_equation;
+ * local analogue with H Theta replaced by Theta (odd field).
+ * 2D stand-ins (paper, Methods, "Solution Modeling and Equation
+ * Factorisation": network inputs q = (1+|y|^2)^{-1/(2(1+lam))},
+ * beta = y2/sqrt(1+|y|^2), field = symmetry prefactor x NN x decay; the
+ * actual IPM and Boussinesq residuals are in unpublished supplementary
+ * material).  Points y in the quadrant, y_k = s_k / (1 - s_k):
+ *   IPM2D (one output): Phi = (y1/rho) NN q, rho = sqrt(1+|y|^2),
+ *     R = Phi + ((1+lam) y + (Phi, 0)) . grad Phi; d1 rows dR/dy1, dR/dy2;
+ *     boundary rows dPhi/dy2 = 0 on y2 = 0.
+ *   BOUSS2D (three outputs): Omega = (y1/rho) NN_0 q, Theta = NN_1 q,
+ *     Psi = (y1/rho) NN_2 q rho^2, U = (-Psi_2, Psi_1),
+ *     R_Omega = Omega + ((1+lam) y + U) . grad Omega - Theta_1,
+ *     R_Theta = (1-lam) Theta + ((1+lam) y + U) . grad Theta,
+ *     R_Psi = Psi_11 + Psi_22 - Omega; boundary rows Psi = 0 on y2 = 0. */
+typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1, GN_EQ_IPM2D = 3, GN_EQ_BOUSS2D = 4 } gn_equation;
 
 /* Arithmetic of the Gram bulk.  GN_FP64: FP64 throughout.  GN_SPLIT32: the
  * FP64 Jacobian is split into FP32 parts hi = fl32(J), lo = fl32(J - hi) and
@@ -69,15 +82,19 @@ typedef enum { GN_FP64 = 0, GN_SPLIT32 = 1 } gn_precision;
 
 #define GN_MAX_LAYERS 8   /* affine layers */
 #define GN_MAX_WIDTH 64   /* hidden width limit of the 1D kernels */
+#define GN_MAX_WIDTH_2D 256  /* hidden width limit of the 2D kernels */
 
 typedef struct {
     int32_t equation;        /* gn_equation */
     int32_t precision;       /* gn_precision */
     int32_t n_layers;        /* L, number of affine layers (1..GN_MAX_LAYERS) */
-    const int32_t *widths;   /* host, L+1 entries: [1, w_1, ..., w_{L-1}, 1] */
+    const int32_t *widths;   /* host, L+1 entries: [1, w_1, ..., 1] (1D);
+                                [2, w_1, ..., n_out] (2D, n_out = 1 IPM2D, 3 BOUSS2D) */
     double lam;              /* self-similar scaling lambda (> 0) */
     double c_norm;           /* weight of the normalisation row (>= 0) */
-    double c_target;         /* target value of NN at q = 1 (the origin) */
+    double c_target;         /* target value of NN (output 0) at q = 1, beta = 0 (the origin) */
+    int64_t row_chunk;       /* 2D: rows of J formed at a time in gn_step (0: all); the
+                                Gram is accumulated over the chunks (streamed J) */
 } gn_problem;
 
 typedef struct {
@@ -125,8 +142,25 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
                         const double *d_f, int64_t m_quad, const double *d_sq,
                         const double *d_wq, int64_t n_val, const double *d_sval);
 
+/*
+ * Point sets of a 2D problem (GN_EQ_IPM2D, GN_EQ_BOUSS2D), s-coordinates in
+ * [0,1) mapped per axis to y = s / (1 - s):
+ *   d_s    [n x 2]   collocation points (equation rows), n >= 1;
+ *   d_s1   [n1 x 2]  points of the d1 rows (IPM2D only; NULL with n1 = 0);
+ *   d_se   [ne]      y1-coordinates (as s) of the y2 = 0 boundary rows;
+ *   d_sval [n_val x 2] validation grid (NULL with n_val = 0).
+ * Row order: n x n_eq equation rows (equations interleaved per point),
+ * 2 n1 d1 rows, ne boundary rows, the normalisation row; scales
+ * sqrt(1/(n n_eq)), sqrt(1/(2 n1)), sqrt(1/ne), sqrt(c_norm).
+ * Allocates the workspace (Jacobian of row_chunk rows, Gram, factor).
+ * Synchronises.  Errors: GN_EINVAL (1D handle, n < 1, n1 > 0 for BOUSS2D,
+ * null pointers), GN_ENOMEM.
+ */
+gn_status gn_set_points_2d(gn_handle h, int64_t n, const double *d_s, int64_t n1, const double *d_s1,
+                           int64_t ne, const double *d_se, int64_t n_val, const double *d_sval);
+
 int64_t gn_num_params(gn_handle h);  /* P */
-int64_t gn_num_rows(gn_handle h);    /* m = N + 1, or -1 before gn_set_points */
+int64_t gn_num_rows(gn_handle h);    /* m (1D: N + 1), or -1 before the points are set */
 
 /* Residual rows r (length m): r_i = sqrt(rho_i/N) (R_i - f_i), i < N;
  * r_N = sqrt(c_norm) (NN(q=1) - c_target).  Paper: "Training Loss". */

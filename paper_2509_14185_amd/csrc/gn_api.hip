@@ -44,6 +44,14 @@ struct gn_context {
     double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
     float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
     int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
+    // 2D problems (gn_set_points_2d)
+    int dim = 1, nout = 1, n_eq = 1;
+    int64_t row_chunk = 0;            // rows of J per chunk in gn_step (0: all)
+    RowMap2D map2{};
+    Pts2D pts2{}, val2{};
+    double *origin_s = nullptr;       // (0, 0): the normalisation point
+    double *nn2 = nullptr, *nn2v = nullptr, *seeds2 = nullptr, *r2 = nullptr;
+    int64_t ldn2 = 0, ldnv2 = 0, rows_ws = 0;
     // phase timing
     std::vector<hipEvent_t> events;   // max_steps x (GN_PHASE_COUNT + 1)
     int32_t prof_max = 0, prof_count = 0;
@@ -97,6 +105,8 @@ void free_list(std::vector<void *> &list) {
     } while (0)
 
 bool points_ready(gn_handle h) { return h->n > 0; }
+
+int64_t total_rows(gn_handle h) { return h->dim == 2 ? h->map2.rows() : h->n + 1; }
 
 // Forward jets at the nodes (CCF), the collocation points and q = 1.
 gn_status forward_all(gn_handle h, const double *theta) {
@@ -237,6 +247,122 @@ gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks, bo
     return GN_OK;
 }
 
+
+// ---------------------------------------------------------------- 2D helpers
+Sweep2DArgs sweep2d_args(gn_handle h) {
+    Sweep2DArgs b{};
+    b.map = h->map2;
+    b.pts = h->pts2;
+    b.seeds = h->seeds2;
+    b.lds = total_rows(h);
+    return b;
+}
+
+// network output jets at every point of the table
+gn_status forward2d(gn_handle h, const double *theta) {
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_transpose_weights(st, h->md, theta, h->thetaT));
+    Sweep2DArgs b = sweep2d_args(h);
+    b.nrows = h->map2.n + h->map2.n1 + h->map2.ne + 1;
+    b.nn = h->nn2;
+    b.ldn = h->ldn2;
+    GN_HIP(h, launch_jets2d_forward(st, h->md, theta, h->thetaT, b));
+    return GN_OK;
+}
+
+Res2DArgs res2d_args(gn_handle h) {
+    Res2DArgs a{};
+    a.equation = h->equation;
+    a.lam = h->lam;
+    a.map = h->map2;
+    a.nout = h->nout;
+    a.c_norm = h->c_norm;
+    a.c_target = h->c_target;
+    a.scale_eq = sqrt(1.0 / (double)(h->map2.n * h->map2.n_eq));
+    a.scale_d1 = h->map2.n1 > 0 ? sqrt(1.0 / (2.0 * (double)h->map2.n1)) : 0.0;
+    a.scale_edge = h->map2.ne > 0 ? sqrt(1.0 / (double)h->map2.ne) : 0.0;
+    return a;
+}
+
+// scaled rows into r (stride), seeds into seeds2 when `seeds`; max |R| on the collocation points
+gn_status residual2d_rows(gn_handle h, double *r, int64_t r_stride, bool seeds) {
+    Res2DArgs a = res2d_args(h);
+    a.pts = h->pts2;
+    a.nn = h->nn2;
+    a.ldn = h->ldn2;
+    a.r = r;
+    a.r_stride = r_stride;
+    a.seeds = seeds ? h->seeds2 : nullptr;
+    a.lds = total_rows(h);
+    a.max_out = &h->status->max_R;
+    GN_HIP(h, launch_residual2d(h->stream, a));
+    return GN_OK;
+}
+
+// max |R| over the equations at the validation points (weights already transposed)
+gn_status validation2d(gn_handle h, const double *theta) {
+    if (h->nv <= 0) return GN_OK;
+    Sweep2DArgs b{};
+    b.pts = h->val2;
+    b.nrows = h->nv;
+    b.nn = h->nn2v;
+    b.ldn = h->ldnv2;
+    GN_HIP(h, launch_jets2d_forward(h->stream, h->md, theta, h->thetaT, b));
+    Res2DArgs a = res2d_args(h);
+    a.map = RowMap2D{h->nv, 0, 0, h->n_eq};
+    a.pts = h->val2;
+    a.nn = h->nn2v;
+    a.ldn = h->ldnv2;
+    a.validation = 1;
+    a.max_out = &h->status->max_R_val;
+    GN_HIP(h, launch_residual2d(h->stream, a));
+    return GN_OK;
+}
+
+// rows [row0, row0 + nrows) of J (seeds2 current) into J (row row0 at J)
+gn_status jac_rows2d(gn_handle h, const double *theta, int64_t row0, int64_t nrows, double *J, int64_t ldJ) {
+    Sweep2DArgs b = sweep2d_args(h);
+    b.row0 = row0;
+    b.nrows = nrows;
+    b.J = J;
+    b.ldJ = ldJ;
+    GN_HIP(h, launch_jets2d_rows(h->stream, h->md, theta, h->thetaT, b));
+    return GN_OK;
+}
+
+GemmDesc gram_desc_rows(gn_handle h, int64_t rows, double beta) {
+    const int64_t P = h->md.P;
+    GemmDesc g{};
+    g.M = P + 1; g.N = P + 1; g.K = rows;
+    g.A = h->J; g.lda = h->ldJ; g.la = 1;
+    g.B = h->J; g.ldb = h->ldJ; g.lb = 0;
+    g.C = h->G; g.ldc = h->ldG;
+    g.alpha = 1.0; g.beta = beta; g.lower = 1;
+    return g;
+}
+
+// Bordered Gram of [J | r] over all rows of a 2D problem, row chunk by row
+// chunk (J of the chunk formed, then accumulated into G); r^T r from r2.
+gn_status gram2d(gn_handle h, const double *theta) {
+    hipStream_t st = h->stream;
+    const int64_t P = h->md.P, m = total_rows(h);
+    double *Grow = h->G + P * h->ldG;
+    for (int64_t r0 = 0, c = 0; r0 < m; r0 += h->rows_ws, ++c) {
+        const int64_t nr = (m - r0) < h->rows_ws ? (m - r0) : h->rows_ws;
+        GN_TRY(jac_rows2d(h, theta, r0, nr, h->J, h->ldJ));
+        if (h->precision == GN_SPLIT32) {
+            GN_HIP(h, launch_split(st, h->J, nr, P, h->ldJ, h->Jhi, h->Jlo));
+            GN_HIP(h, launch_split_gram(st, h->Jhi, h->Jlo, nr, P, h->ldJ, h->G, h->ldG, c > 0));
+            GN_HIP(h, launch_gemv_t(st, h->J, nr, P, h->ldJ, h->r2 + r0, Grow, h->gemv_work, c > 0));
+        } else {
+            GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
+            GN_HIP(h, launch_dgemm(st, gram_desc_rows(h, nr, c > 0 ? 1.0 : 0.0)));
+        }
+    }
+    if (h->precision == GN_SPLIT32) GN_HIP(h, launch_sumsq(st, h->r2, m, 1, Grow + P, h->red_work));
+    return GN_OK;
+}
+
 double bits_to_double(unsigned long long b) {
     double d;
     memcpy(&d, &b, sizeof d);
@@ -286,12 +412,20 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     *out = nullptr;
     const int L = prob->n_layers;
     if (L < 1 || L > GN_MAX_LAYERS) return GN_EINVAL;
-    if (prob->equation != GN_EQ_CCF1D && prob->equation != GN_EQ_BURGERS1D) return GN_EINVAL;
+    const bool two_d = prob->equation == GN_EQ_IPM2D || prob->equation == GN_EQ_BOUSS2D;
+    if (!two_d && prob->equation != GN_EQ_CCF1D && prob->equation != GN_EQ_BURGERS1D) return GN_EINVAL;
     if (prob->precision != GN_FP64 && prob->precision != GN_SPLIT32) return GN_EINVAL;
-    if (!(prob->lam > 0.0) || !(prob->c_norm >= 0.0)) return GN_EINVAL;
-    if (prob->widths[0] != 1 || prob->widths[L] != 1) return GN_EINVAL;
-    for (int l = 1; l < L; ++l)
-        if (prob->widths[l] < 1 || prob->widths[l] > GN_MAX_WIDTH) return GN_EINVAL;
+    if (!(prob->lam > 0.0) || !(prob->c_norm >= 0.0) || prob->row_chunk < 0) return GN_EINVAL;
+    if (two_d) {
+        const int nout = prob->equation == GN_EQ_IPM2D ? 1 : 3;
+        if (prob->widths[0] != 2 || prob->widths[L] != nout) return GN_EINVAL;
+        for (int l = 1; l < L; ++l)
+            if (prob->widths[l] < 1 || prob->widths[l] > GN_MAX_WIDTH_2D) return GN_EINVAL;
+    } else {
+        if (prob->widths[0] != 1 || prob->widths[L] != 1) return GN_EINVAL;
+        for (int l = 1; l < L; ++l)
+            if (prob->widths[l] < 1 || prob->widths[l] > GN_MAX_WIDTH) return GN_EINVAL;
+    }
     gn_handle h = new (std::nothrow) gn_context();
     if (!h) return GN_ENOMEM;
     h->equation = prob->equation;
@@ -299,6 +433,10 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     h->lam = prob->lam;
     h->c_norm = prob->c_norm;
     h->c_target = prob->c_target;
+    h->dim = two_d ? 2 : 1;
+    h->nout = prob->widths[L];
+    h->n_eq = prob->equation == GN_EQ_BOUSS2D ? 3 : 1;
+    h->row_chunk = prob->row_chunk;
     MlpDesc &d = h->md;
     d.L = L;
     int o = 0;
@@ -368,12 +506,13 @@ gn_status gn_set_stream(gn_handle h, void *stream) {
 }
 
 int64_t gn_num_params(gn_handle h) { return h ? h->md.P : -1; }
-int64_t gn_num_rows(gn_handle h) { return (h && h->n > 0) ? h->n + 1 : -1; }
+int64_t gn_num_rows(gn_handle h) { return (h && h->n > 0) ? total_rows(h) : -1; }
 
 gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double *d_rho, const double *d_f,
                         int64_t m_quad, const double *d_sq, const double *d_wq, int64_t n_val,
                         const double *d_sval) {
     if (!h) return GN_EINVAL;
+    if (h->dim != 1) return fail(h, GN_EINVAL, "2D problems take gn_set_points_2d%s");
     if (n < 1 || !d_s) return fail(h, GN_EINVAL, "need n >= 1 collocation points%s");
     if (h->equation == GN_EQ_CCF1D && (m_quad < 1 || !d_sq || !d_wq))
         return fail(h, GN_EINVAL, "the CCF Hilbert term needs m_quad >= 1 nodes and weights%s");
@@ -447,10 +586,78 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     return GN_OK;
 }
 
+gn_status gn_set_points_2d(gn_handle h, int64_t n, const double *d_s, int64_t n1, const double *d_s1, int64_t ne,
+                           const double *d_se, int64_t n_val, const double *d_sval) {
+    if (!h) return GN_EINVAL;
+    if (h->dim != 2) return fail(h, GN_EINVAL, "1D problems take gn_set_points%s");
+    if (n < 1 || !d_s) return fail(h, GN_EINVAL, "need n >= 1 collocation points%s");
+    if (n1 < 0 || (n1 > 0 && !d_s1)) return fail(h, GN_EINVAL, "bad d1 point set%s");
+    if (n1 > 0 && h->equation != GN_EQ_IPM2D) return fail(h, GN_EINVAL, "d1 rows are defined for GN_EQ_IPM2D%s");
+    if (ne < 0 || (ne > 0 && !d_se)) return fail(h, GN_EINVAL, "bad boundary point set%s");
+    if (n_val < 0 || (n_val > 0 && !d_sval)) return fail(h, GN_EINVAL, "bad validation grid%s");
+    GN_HIP(h, hipStreamSynchronize(h->stream));
+    free_list(h->pt_allocs);
+    ++h->points_gen;
+    h->n = h->m = h->nv = 0;
+    auto &A = h->pt_allocs;
+    const int64_t P = h->md.P;
+    h->map2 = RowMap2D{n, n1, ne, h->n_eq};
+    const int64_t m = h->map2.rows(), npt = n + n1 + ne + 1;
+    h->rows_ws = (h->row_chunk > 0 && h->row_chunk < m) ? h->row_chunk : m;
+    h->ldJ = round_up(P + 1, 32);
+    h->ldG = round_up(P + 1, 32);
+    const int64_t nparts = jets2d_vjp_partials(h->md, m);
+    const int nc = 6 * h->nout;
+    gn_status s = GN_OK;
+    auto table = [&](Pts2D &p, int64_t cnt) -> gn_status {
+        GN_TRY(dev_alloc(h, A, &p.y1, cnt));
+        GN_TRY(dev_alloc(h, A, &p.y2, cnt));
+        GN_TRY(dev_alloc(h, A, &p.xin, 12 * cnt));
+        p.ld = cnt;
+        return GN_OK;
+    };
+    s = table(h->pts2, npt);
+    if (s == GN_OK) s = table(h->val2, n_val);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->origin_s, 2);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->nn2, nc * npt);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->nn2v, nc * n_val);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->seeds2, nc * m);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->r2, m);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->J, h->rows_ws * h->ldJ);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->G, (P + 1) * h->ldG);
+    if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jhi, h->rows_ws * h->ldJ);
+    if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jlo, h->rows_ws * h->ldJ);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->partial, nparts * P);
+    if (s != GN_OK) {
+        free_list(A);
+        return s;
+    }
+    h->ldn2 = npt;
+    h->ldnv2 = n_val;
+    h->r_tmp = h->r2;
+    h->n_partial_cap = nparts;
+    hipStream_t st = h->stream;
+    const double zero2[2] = {0.0, 0.0};
+    GN_HIP(h, hipMemcpy(h->origin_s, zero2, sizeof zero2, hipMemcpyHostToDevice));
+    GN_HIP(h, launch_geometry2d(st, n, d_s, 0, h->lam, h->pts2, 0));
+    GN_HIP(h, launch_geometry2d(st, n1, d_s1, 0, h->lam, h->pts2, n));
+    GN_HIP(h, launch_geometry2d(st, ne, d_se, 1, h->lam, h->pts2, n + n1));
+    GN_HIP(h, launch_geometry2d(st, 1, h->origin_s, 0, h->lam, h->pts2, n + n1 + ne));
+    GN_HIP(h, launch_geometry2d(st, n_val, d_sval, 0, h->lam, h->val2, 0));
+    GN_HIP(h, hipStreamSynchronize(st));
+    h->n = n;
+    h->nv = n_val;
+    return GN_OK;
+}
+
 gn_status gn_residual(gn_handle h, const double *d_theta, double *d_r) {
     if (!h || !d_theta || !d_r) return GN_EINVAL;
     if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
     GN_HIP(h, launch_reset_status(h->stream, h->status));
+    if (h->dim == 2) {
+        GN_TRY(forward2d(h, d_theta));
+        return residual2d_rows(h, d_r, 1, false);
+    }
     GN_TRY(forward_all(h, d_theta));
     return residual_rows(h, d_r, 1, false);
 }
@@ -460,6 +667,11 @@ gn_status gn_jacobian(gn_handle h, const double *d_theta, double *d_J, int64_t l
     if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
     if (ldJ < h->md.P) return fail(h, GN_EINVAL, "ldJ < P%s");
     GN_HIP(h, launch_reset_status(h->stream, h->status));
+    if (h->dim == 2) {
+        GN_TRY(forward2d(h, d_theta));
+        GN_TRY(residual2d_rows(h, d_r ? d_r : h->r2, 1, true));
+        return jac_rows2d(h, d_theta, 0, total_rows(h), d_J, ldJ);
+    }
     return jacobian_into(h, d_theta, d_J, ldJ, d_r, 1);
 }
 
@@ -470,7 +682,7 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
     if (d_r && !d_g) return fail(h, GN_EINVAL, "d_g is required when d_r is given%s");
     if (d_r && p > h->cap) return fail(h, GN_EINVAL, "p exceeds the gradient workspace (P + 1)%s");
     if (h->precision == GN_SPLIT32) {
-        if (!h->Jhi || m > h->n + 1 || ldJ > h->ldJ)
+        if (!h->Jhi || m > (h->dim == 2 ? h->rows_ws : h->n + 1) || ldJ > h->ldJ)
             return fail(h, GN_EINVAL, "split-precision gram needs m <= N + 1 and ldJ <= the workspace ld%s");
         GN_HIP(h, launch_split(h->stream, d_J, m, p, ldJ, h->Jhi, h->Jlo));
         GN_HIP(h, launch_split_gram(h->stream, h->Jhi, h->Jlo, m, p, ldJ, d_G, ldG));
@@ -518,6 +730,16 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
     const int64_t ldJ = h->ldJ;
     mark(h, 0);
     GN_HIP(h, launch_reset_status(st, h->status));
+    if (h->dim == 2) {
+        GN_TRY(forward2d(h, d_theta));
+        GN_TRY(residual2d_rows(h, h->r2, 1, true));
+        GN_TRY(validation2d(h, d_theta));
+        GN_HIP(h, launch_sumsq(st, h->r2, total_rows(h), 1, &h->status->half_sq_norm, h->red_work));
+        mark(h, 1);
+        mark(h, 2);
+        mark(h, 3);
+        GN_TRY(gram2d(h, d_theta));  // Jacobian rows and the Gram, chunk by chunk
+    } else {
     GN_TRY(build_step_jacobian(h, d_theta, true));
     mark(h, 3);
     if (h->precision == GN_SPLIT32) {
@@ -532,6 +754,7 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
         GN_HIP(h, launch_dgemm(st, gram_desc(h)));
     }
     GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
+    }
     mark(h, 4);
     // Cholesky of [[G + mu I, g], [g^T, r^T r]]: last row = (L^{-1} g)^T, Schur complement
     GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, h->G, P + 1, h->ldG, mu, 1, h->linv, h->chol_tmp, h->status));
@@ -559,10 +782,17 @@ gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats) {
     if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
     hipStream_t st = h->stream;
     GN_HIP(h, launch_reset_status(st, h->status));
-    GN_TRY(forward_all(h, d_theta));
-    GN_TRY(residual_rows(h, h->r_tmp, 1, false));
-    GN_HIP(h, launch_sumsq(st, h->r_tmp, h->n + 1, 1, &h->status->half_sq_norm, h->red_work));
-    GN_TRY(validation(h, d_theta));
+    if (h->dim == 2) {
+        GN_TRY(forward2d(h, d_theta));
+        GN_TRY(residual2d_rows(h, h->r2, 1, false));
+        GN_HIP(h, launch_sumsq(st, h->r2, total_rows(h), 1, &h->status->half_sq_norm, h->red_work));
+        GN_TRY(validation2d(h, d_theta));
+    } else {
+        GN_TRY(forward_all(h, d_theta));
+        GN_TRY(residual_rows(h, h->r_tmp, 1, false));
+        GN_HIP(h, launch_sumsq(st, h->r_tmp, h->n + 1, 1, &h->status->half_sq_norm, h->red_work));
+        GN_TRY(validation(h, d_theta));
+    }
     DevStatus ds;
     GN_TRY(read_status(h, &ds));
     memset(h_stats, 0, sizeof *h_stats);
@@ -578,6 +808,18 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
     hipStream_t st = h->stream;
     const int64_t P = h->md.P;
     GN_HIP(h, launch_reset_status(st, h->status));
+    if (h->dim == 2) {
+        GN_TRY(forward2d(h, d_theta));
+        GN_TRY(residual2d_rows(h, h->r2, 1, true));
+        Sweep2DArgs b = sweep2d_args(h);
+        b.nrows = total_rows(h);
+        b.v = d_v;
+        b.partial = h->partial;
+        int64_t nb = 0;
+        GN_HIP(h, launch_jets2d_vjp(st, h->md, d_theta, h->thetaT, b, &nb));
+        GN_HIP(h, launch_reduce_partials(st, h->partial, nb, P, d_out, 0));
+        return GN_OK;
+    }
     GN_TRY(forward_all(h, d_theta));
     GN_TRY(residual_rows(h, h->r_tmp, 1, true));
     // collocation rows: seeds scaled by v_i
@@ -616,7 +858,7 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     if (!hs || n < 1 || !out) return GN_EINVAL;
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
-        if (!hs[i]) return GN_EINVAL;
+        if (!hs[i] || hs[i]->dim != 1) return GN_EINVAL;
         if (hs[i]->n <= 0) return GN_ESTATE;
         if (hs[i]->md.P != hs[0]->md.P || hs[i]->precision != GN_FP64) return GN_EINVAL;
     }

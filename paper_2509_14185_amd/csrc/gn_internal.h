@@ -156,19 +156,19 @@ hipError_t batched_plan_upload(BatchedGemmPlan &p);
 void batched_plan_free(BatchedGemmPlan &p);
 hipError_t launch_batched_plan(hipStream_t st, const BatchedGemmPlan &p);
 
-// g = J^T r (J m x p row-major) via deterministic two-pass reduction;
-// work must hold gemv_t_work_size(m, p) doubles.
+// g = J^T r (J m x p row-major) via deterministic two-pass reduction
+// (accumulate: g += J^T r); work must hold gemv_t_work_size(m, p) doubles.
 int64_t gemv_t_work_size(int64_t m, int64_t p);
 hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj,
-                         const double *r, double *g, double *work);
+                         const double *r, double *g, double *work, int accumulate = 0);
 
 // Split precision: hi = fl32(J), lo = fl32(J - hi) for the first p columns
 // (same leading dimension), and the lower triangle of
 // Jhi^T Jhi + Jhi^T Jlo + Jlo^T Jhi (FP32 MFMA products, FP64 accumulation
-// per 32-row chunk).
+// per 32-row chunk); accumulate adds it to C (streamed row chunks).
 hipError_t launch_split(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, float *hi, float *lo);
 hipError_t launch_split_gram(hipStream_t st, const float *hi, const float *lo, int64_t m, int64_t p, int64_t lda,
-                             double *C, int64_t ldc);
+                             double *C, int64_t ldc, int accumulate = 0);
 
 // Blocked Cholesky of the lower triangle of A (n x n) after adding mu to the
 // first n - border diagonal entries.  border = 1: the last row is a border
@@ -228,4 +228,89 @@ hipError_t launch_copy_strided(hipStream_t st, const double *src, int64_t n, int
 namespace gn {
 hipError_t launch_reset_status(hipStream_t st, DevStatus *s);
 hipError_t launch_mul(hipStream_t st, const double *a, const double *b, double *out, int64_t n, double scale);
+
+// ------------------------------------------------------------ 2D problems
+// Point table (structure of arrays, stride ld): y1, y2 and the input jets
+// of the network inputs q (xin[0..5]) and beta (xin[6..11]), component c of
+// input u at xin[(6u + c) * ld + point].
+struct Pts2D {
+    double *y1, *y2, *xin;
+    int64_t ld;
+};
+
+// Rows of a 2D problem and the point each one is evaluated at.  Table order:
+// n collocation points, n1 d1 points, ne y2 = 0 points, the origin.
+// Rows: n x n_eq equation rows (equations interleaved per point), 2 n1 d1
+// rows (dR/dy1, dR/dy2 per point), ne boundary rows, the normalisation row.
+struct RowMap2D {
+    int64_t n, n1, ne;
+    int n_eq;
+    __host__ __device__ int64_t rows() const { return n * n_eq + 2 * n1 + ne + 1; }
+    __host__ __device__ int64_t point_of(int64_t row, int &kind, int &comp) const {
+        const int64_t e0 = n * n_eq, d0 = e0 + 2 * n1, b0 = d0 + ne;
+        if (row < e0) {
+            kind = 0;
+            comp = (int)(row % n_eq);
+            return row / n_eq;
+        }
+        if (row < d0) {
+            kind = 1;
+            comp = (int)((row - e0) & 1);
+            return n + (row - e0) / 2;
+        }
+        if (row < b0) {
+            kind = 2;
+            comp = 0;
+            return n + n1 + (row - d0);
+        }
+        kind = 3;
+        comp = 0;
+        return n + n1 + ne;
+    }
+};
+
+struct Res2DArgs {
+    int equation;
+    double lam;
+    RowMap2D map;
+    int nout;
+    Pts2D pts;
+    const double *nn;        // output jets [(f*6 + c) * ldn + point]
+    int64_t ldn;
+    double *r;               // scaled rows (may be null)
+    int64_t r_stride;
+    double *seeds;           // [(f*6 + c) * lds + row], scaled (may be null)
+    int64_t lds;
+    unsigned long long *max_out;  // max |R| over equation rows (bit pattern)
+    double c_norm, c_target;
+    double scale_eq, scale_d1, scale_edge;  // row scales sqrt(1/(n n_eq)), sqrt(1/(2 n1)), sqrt(1/ne)
+    int validation;          // only the equation rows, only max |R|
+};
+
+struct Sweep2DArgs {
+    int64_t nrows;           // rows (or points, forward) handled by this launch
+    int64_t row0;            // first row (forward: first point, 0)
+    RowMap2D map;
+    Pts2D pts;
+    const double *seeds;     // rows / vjp
+    int64_t lds;
+    const double *v;         // vjp weights per row
+    double *nn;              // forward output jets
+    int64_t ldn;
+    double *J;               // rows: row (row0 + i) at J + i * ldJ
+    int64_t ldJ;
+    double *partial;         // vjp: one P-vector per workgroup
+};
+
+hipError_t launch_geometry2d(hipStream_t st, int64_t n, const double *s, int edge, double lam, Pts2D p,
+                             int64_t off);
+hipError_t launch_residual2d(hipStream_t st, const Res2DArgs &a);
+hipError_t launch_jets2d_forward(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                                 const Sweep2DArgs &b);
+hipError_t launch_jets2d_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                              const Sweep2DArgs &b);
+hipError_t launch_jets2d_vjp(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
+                             const Sweep2DArgs &b, int64_t *nblocks);
+int64_t jets2d_vjp_partials(const MlpDesc &d, int64_t nrows);
+
 }  // namespace gn

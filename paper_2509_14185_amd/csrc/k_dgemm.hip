@@ -527,20 +527,20 @@ __global__ void gemv_t_partial(const double *__restrict__ J, int64_t m, int64_t 
     work[blockIdx.y * p + c] = acc;
 }
 
-__global__ void gemv_t_final(const double *__restrict__ work, int64_t p, double *__restrict__ g) {
+__global__ void gemv_t_final(const double *__restrict__ work, int64_t p, double *__restrict__ g, int accumulate) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= p) return;
     double acc = 0.0;
     for (int k = 0; k < GEMV_CHUNKS; ++k) acc += work[k * p + c];
-    g[c] = acc;
+    g[c] = accumulate ? g[c] + acc : acc;
 }
 
 hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, const double *r,
-                         double *g, double *work) {
+                         double *g, double *work, int accumulate) {
     if (p <= 0) return hipSuccess;
     dim3 g1((unsigned)((p + 255) / 256), GEMV_CHUNKS);
     hipLaunchKernelGGL(gemv_t_partial, g1, dim3(256), 0, st, J, m, p, ldj, r, work);
-    hipLaunchKernelGGL(gemv_t_final, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, work, p, g);
+    hipLaunchKernelGGL(gemv_t_final, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, work, p, g, accumulate);
     return hipGetLastError();
 }
 

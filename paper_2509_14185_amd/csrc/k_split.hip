@@ -74,7 +74,7 @@ static int64_t split_super_count(int64_t tiles) {
 // C (lower, p x p, FP64) = Ahi^T Ahi + Ahi^T Alo + Alo^T Ahi, A m x p row-major (ld lda, floats).
 __global__ __launch_bounds__(ST) void split_gram_kernel(const float *__restrict__ Ahi, const float *__restrict__ Alo,
                                                         int64_t m, int64_t p, int64_t lda, double *__restrict__ C,
-                                                        int64_t ldc, int tiles) {
+                                                        int64_t ldc, int tiles, int accumulate) {
     constexpr int WAVES_N = 4, WM = SBM / 2, WN = SBM / 4;
     constexpr int FM = WM / 16, FN = WN / 16;
     extern __shared__ float fs[];
@@ -211,13 +211,14 @@ __global__ __launch_bounds__(ST) void split_gram_kernel(const float *__restrict_
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gm = m0 + wm * WM + i * 16 + 4 * fk + r;
-                if (gm < p && gn_ < p && gn_ <= gm) C[gm * ldc + gn_] = acc[i][j][r];
+                if (gm < p && gn_ < p && gn_ <= gm)
+                    C[gm * ldc + gn_] = accumulate ? C[gm * ldc + gn_] + acc[i][j][r] : acc[i][j][r];
             }
         }
 }
 
 hipError_t launch_split_gram(hipStream_t st, const float *hi, const float *lo, int64_t m, int64_t p, int64_t lda,
-                             double *C, int64_t ldc) {
+                             double *C, int64_t ldc, int accumulate) {
     if (p <= 0) return hipSuccess;
     const int tiles = (int)((p + SBM - 1) / SBM);
     const int64_t supers = split_super_count(tiles);
@@ -229,7 +230,8 @@ hipError_t launch_split_gram(hipStream_t st, const float *hi, const float *lo, i
                                   (int)shm);
         attr = true;
     }
-    hipLaunchKernelGGL(split_gram_kernel, dim3((unsigned)blocks), dim3(ST), shm, st, hi, lo, m, p, lda, C, ldc, tiles);
+    hipLaunchKernelGGL(split_gram_kernel, dim3((unsigned)blocks), dim3(ST), shm, st, hi, lo, m, p, lda, C, ldc, tiles,
+                       accumulate);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libgn.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "gn.h")
 
 GN_OK, GN_ENOTPD, GN_EINVAL, GN_ENOMEM, GN_EDEVICE, GN_ENONFINITE, GN_ESTATE = 0, 1, -1, -2, -3, -4, -5
-EQUATIONS = {"ccf1d": 0, "burgers1d": 1}
+EQUATIONS = {"ccf1d": 0, "burgers1d": 1, "ipm2d": 3, "bouss2d": 4}
 PRECISIONS = {"fp64": 0, "split32": 1}
 
 
@@ -33,7 +33,7 @@ class GNError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [("equation", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_layers", ctypes.c_int32),
                 ("widths", ctypes.POINTER(ctypes.c_int32)), ("lam", ctypes.c_double),
-                ("c_norm", ctypes.c_double), ("c_target", ctypes.c_double)]
+                ("c_norm", ctypes.c_double), ("c_target", ctypes.c_double), ("row_chunk", ctypes.c_int64)]
 
 
 class _Stats(ctypes.Structure):
@@ -72,6 +72,7 @@ def load():
         "gn_destroy": (ctypes.c_int, [_VP]),
         "gn_set_stream": (ctypes.c_int, [_VP, _VP]),
         "gn_set_points": (ctypes.c_int, [_VP, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _I64, _VP]),
+        "gn_set_points_2d": (ctypes.c_int, [_VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP]),
         "gn_num_params": (_I64, [_VP]),
         "gn_num_rows": (_I64, [_VP]),
         "gn_residual": (ctypes.c_int, [_VP, _VP, _VP]),
@@ -113,7 +114,7 @@ class Problem:
     """One profile problem bound to a gn handle on the current CUDA (HIP) device."""
 
     def __init__(self, equation: str, widths, lam: float, c_norm: float = 1.0, c_target: float = 1.0,
-                 precision: str = "fp64", device: str = "cuda"):
+                 precision: str = "fp64", device: str = "cuda", row_chunk: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the gn library runs only on the GPU")
         self.lib = load()
@@ -121,7 +122,7 @@ class Problem:
         self.widths = [int(w) for w in widths]
         self._w = (ctypes.c_int32 * len(self.widths))(*self.widths)
         prob = _Problem(EQUATIONS[equation], PRECISIONS[precision], len(self.widths) - 1, self._w,
-                        float(lam), float(c_norm), float(c_target))
+                        float(lam), float(c_norm), float(c_target), int(row_chunk))
         h = _VP()
         with torch.cuda.device(self.device):
             st = self.lib.gn_create(ctypes.byref(prob), ctypes.byref(h))
@@ -164,6 +165,19 @@ class Problem:
         nv = 0 if sval is None else sval.numel()
         st = self.lib.gn_set_points(self.h, n, _ptr(s), _ptr(rho), _ptr(f), mq, _ptr(sq), _ptr(wq), nv, _ptr(sval))
         self._check(st, "gn_set_points")
+        self.n = n
+
+    def set_points_2d(self, s, s1=None, se=None, sval=None):
+        """2D point sets: s (n,2), s1 (n1,2) d1 points, se (ne,) y2 = 0 points, sval (nv,2)."""
+        self._bind()
+        s, s1, se, sval = (_dev(x, self.device) for x in (s, s1, se, sval))
+        n = s.numel() // 2
+        n1 = 0 if s1 is None else s1.numel() // 2
+        ne = 0 if se is None else se.numel()
+        nv = 0 if sval is None else sval.numel() // 2
+        st = self.lib.gn_set_points_2d(self.h, n, _ptr(s), n1, _ptr(s1) if n1 else None, ne,
+                                       _ptr(se) if ne else None, nv, _ptr(sval) if nv else None)
+        self._check(st, "gn_set_points_2d")
         self.n = n
 
     def residual(self, theta, out=None):
