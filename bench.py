@@ -158,6 +158,83 @@ def batched_comparison(steps):
     }
 
 
+def bench_2d(name, steps, warmup, precision="fp64"):
+    """A 2D workload (IPM-style or Boussinesq-type stand-in): steps/s and the
+    Gram + Cholesky FP64 fraction.  With row chunks the Jacobian rows are
+    formed chunk by chunk between the Gram updates, so the "gram" phase then
+    includes the Jacobian sweeps."""
+    import torch
+
+    import workloads
+    from paper_2509_14185_amd import gn
+
+    inp = workloads.make_inputs_2d(name)
+    mu = inp["mu"]
+    prob = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"],
+                      precision=precision, row_chunk=inp.get("row_chunk", 0))
+    prob.set_points_2d(inp["s"], inp["s1"] if inp["n1"] else None, inp["se"], inp["sval"])
+    P, m = prob.P, prob.m
+    theta = torch.from_numpy(inp["theta0"].copy()).cuda()
+    print(f"[bench] {name} ({precision}): P={P} m={m}; warmup {warmup}, {steps} steps", file=sys.stderr, flush=True)
+    ev0 = prob.eval(theta)
+    for _ in range(warmup):
+        prob.step(theta, mu, stats=False)
+    torch.cuda.synchronize()
+    prob.profile_enable(True, steps)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        prob.step(theta, mu, stats=False)
+        if steps > 3:
+            continue
+        torch.cuda.synchronize()
+        print(f"[bench] {name} step {k + 1}/{steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases, nrec = prob.profile_read()
+    prob.profile_enable(False)
+    ev1 = prob.eval(theta)
+    prob.close()
+    fl_gram = float(m) * (P + 1) * (P + 2)
+    fl_chol = (P + 1) ** 3 / 3.0
+    t_gram = phases["gram"] / nrec * 1e-3
+    t_chol = phases["cholesky"] / nrec * 1e-3
+    return {
+        "metric": METRIC,
+        "value": steps / elapsed,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True,
+        "dtype": "f64" if precision == "fp64" else "f64 (Gram products f32 hi/lo)",
+        "data": "synthetic",
+        "config": {
+            "workload": name,
+            "equation": inp["equation"],
+            "widths": inp["widths"],
+            "params": P,
+            "rows": m,
+            "collocation_points": inp["n"],
+            "d1_points": inp["n1"],
+            "boundary_points": inp["ne"],
+            "validation_points": int(len(inp["sval"])),
+            "row_chunk": inp.get("row_chunk", 0),
+            "lam": inp["lam"],
+            "mu": mu,
+            "precision": precision,
+            "max_abs_R_val_initial": ev0["max_abs_R_val"],
+            "max_abs_R_val_final": ev1["max_abs_R_val"],
+            "half_sq_norm_initial": ev0["half_sq_norm"],
+            "half_sq_norm_final": ev1["half_sq_norm"],
+        },
+        "gram_tflops": fl_gram / t_gram / 1e12,
+        "gram_frac": fl_gram / t_gram / 1e12 / PEAK_FP64_TFLOPS,
+        "gram_cholesky_frac": (fl_gram + fl_chol) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS,
+        "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
+    }
+
+
 def cpu_baseline(inp, mu):
     """Oracle step time on a bounded sample of the same workload, extrapolated.
 
@@ -211,6 +288,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched CCF workload")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D IPM-style workload")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split32"],
+                    help="arithmetic of the Gram for --workload ipm2d / bouss2d")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -239,6 +319,9 @@ def main():
     if args.workload == "ccf_batched":
         # the batched workload alone (its figures also appear under "batched" in the default run)
         print(json.dumps(batched_comparison(args.steps)), flush=True)
+        return
+    if args.workload in ("ipm2d", "bouss2d"):
+        print(json.dumps(bench_2d(args.workload, args.steps, args.warmup, args.precision)), flush=True)
         return
     inp = workloads.make_inputs(args.workload)
     mu = inp["mu"]
@@ -318,6 +401,12 @@ def main():
     if not args.no_batched:
         print("[bench] batched CCF workload", file=sys.stderr, flush=True)
         out["batched"] = batched_comparison(10)
+    if not args.no_2d:
+        r2 = bench_2d("ipm2d", 5, 1)
+        out["ipm2d"] = {k: r2[k] for k in ("value", "unit", "ms_per_step", "gram_tflops", "gram_frac",
+                                            "gram_cholesky_frac", "phase_ms_per_step")}
+        out["ipm2d"]["config"] = {k: r2["config"][k] for k in ("widths", "params", "rows", "max_abs_R_val_initial",
+                                                               "max_abs_R_val_final")}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inp, mu)

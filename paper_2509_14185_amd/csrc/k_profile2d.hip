@@ -265,6 +265,7 @@ hipError_t launch_residual2d(hipStream_t st, const Res2DArgs &a) {
 //   zb_2 = s hb_2 - 2t (h_1 hb_12 + 2 h_2 hb_22),
 //   zb_0 = s hb_0 - 2t (h_1 hb_1 + h_2 hb_2) - sum_ab hb_ab (2t h_ab + 2 h_a h_b).
 enum Sweep2DMode { SW2_FORWARD = 0, SW2_ROWS = 1, SW2_VJP = 2 };
+static constexpr int64_t VJP2D_MAX_BLOCKS = 1024;  // partial P-vectors of a VJP
 
 struct Sweep2DLds {
     int in_off;
@@ -307,10 +308,14 @@ __global__ __launch_bounds__(256) void jet_sweep2d_kernel(MlpDesc d, Sweep2DLds 
     extern __shared__ double sm[];
     const int tid = threadIdx.x;
     const int T = lay.tile;
-    const int64_t r0 = (int64_t)blockIdx.x * T;
-    const int nr = (int)((b.nrows - r0) < T ? (b.nrows - r0) : T);
-    if (nr <= 0) return;
     const int L = d.L;
+    // Tiles of T rows; a workgroup takes tiles blockIdx.x, + gridDim.x, ...
+    // (VJP grids are capped; the workgroup's partial sums its tiles in order).
+    const int64_t ntiles = (b.nrows + T - 1) / T;
+    for (int64_t tile = blockIdx.x, it = 0; tile < ntiles; tile += gridDim.x, ++it) {
+    if (it > 0) __syncthreads();  // LDS of the previous tile is no longer read
+    const int64_t r0 = tile * T;
+    const int nr = (int)((b.nrows - r0) < T ? (b.nrows - r0) : T);
     // rows -> points, input jets
     for (int idx = tid; idx < nr * 12; idx += 256) {
         const int t = idx / 12, c = idx - t * 12;
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(256) void jet_sweep2d_kernel(MlpDesc d, Sweep2DLds 
             for (int j = 0; j < win_o; ++j) z = fma(W[o * win_o + j], hin(lo, t, c, j), z);
             b.nn[(o * 6 + c) * b.ldn + r0 + t] = z;
         }
-        return;
+        continue;
     }
     for (int idx = tid; idx < nr * nout * 6; idx += 256) {
         const int t = idx / (nout * 6), rem = idx - t * nout * 6, o = rem / 6, c = rem - o * 6;
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(256) void jet_sweep2d_kernel(MlpDesc d, Sweep2DLds 
                     const int k = idx - wout * win;
                     for (int t = 0; t < nr; ++t) acc += zb[(t * 6) * ldz + k];
                 }
-                out[idx] = acc;
+                out[idx] = (it == 0) ? acc : out[idx] + acc;
             }
         }
         if (l == 0) break;
@@ -445,6 +450,7 @@ __global__ __launch_bounds__(256) void jet_sweep2d_kernel(MlpDesc d, Sweep2DLds 
         zb = zbn;
         zbn = tmp;
     }
+    }
 }
 
 template <int MODE>
@@ -458,7 +464,8 @@ static hipError_t launch_sweep2d(hipStream_t st, const MlpDesc &d, const double 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    const int64_t blocks = (b.nrows + lay.tile - 1) / lay.tile;
+    int64_t blocks = (b.nrows + lay.tile - 1) / lay.tile;
+    if (MODE == SW2_VJP && blocks > VJP2D_MAX_BLOCKS) blocks = VJP2D_MAX_BLOCKS;
     if (nblocks) *nblocks = blocks;
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(jet_sweep2d_kernel<MODE>, dim3((unsigned)blocks), dim3(256), sizeof(double) * lay.total, st, d,
@@ -483,7 +490,9 @@ hipError_t launch_jets2d_vjp(hipStream_t st, const MlpDesc &d, const double *the
 
 int64_t jets2d_vjp_partials(const MlpDesc &d, int64_t nrows) {
     const Sweep2DLds lay = sweep2d_layout(d);
-    return lay.tile < 1 ? 0 : (nrows + lay.tile - 1) / lay.tile;
+    if (lay.tile < 1) return 0;
+    const int64_t blocks = (nrows + lay.tile - 1) / lay.tile;
+    return blocks < VJP2D_MAX_BLOCKS ? blocks : VJP2D_MAX_BLOCKS;
 }
 
 }  // namespace gn
