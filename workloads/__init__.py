@@ -35,17 +35,19 @@ WORKLOADS = {
 
 # 2D stand-ins (the paper's IPM and Boussinesq residuals are in its missing
 # supplementary material): blow-up rates of the first unstable profiles
-# (paper, main text, table of lambda_n fits, n = 1).
+# (paper, main text, table of lambda_n fits, n = 1).  Damping mu = 0.1: with
+# 1e-3 the fixed-damping step from the Glorot start overshoots on these
+# stand-ins (the objective rises); 0.1 decreases it monotonically.
 LAM_IPM1 = 0.4721
 LAM_BOUSS1 = 1.3992
 
 WORKLOADS_2D = {
     # IPM-style: one field, second-order jets, d1 rows, symmetry rows.
     "ipm2d": dict(equation="ipm2d", widths=[2, 64, 64, 64, 64, 1], lam=LAM_IPM1, n=65536, n1=16384, ne=256,
-                  seed=3, mu=1e-3, steps=10, c_norm=1.0, c_target=1.0),
+                  seed=3, mu=1e-1, steps=10, c_norm=1.0, c_target=1.0),
     # Boussinesq-type: three fields from one network, streamed row chunks.
     "bouss2d": dict(equation="bouss2d", widths=[2, 128, 128, 128, 128, 3], lam=LAM_BOUSS1, n=262144, n1=0,
-                    ne=256, seed=5, mu=1e-3, steps=20, c_norm=1.0, c_target=1.0, row_chunk=32768),
+                    ne=256, seed=5, mu=1e-1, steps=20, c_norm=1.0, c_target=1.0, row_chunk=32768),
 }
 
 # Batched CCF: independent instances with their own blow-up rate lambda drawn
