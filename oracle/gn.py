@@ -60,3 +60,87 @@ def backward_error(G, mu, g, delta):
     A[np.diag_indices_from(A)] += mu
     res = dense.symv_lower(np.tril(A), delta) + g
     return float(np.linalg.norm(res) / (np.linalg.norm(A) * np.linalg.norm(delta) + np.linalg.norm(g)))
+
+
+LM_DEFAULTS = dict(mu_min=1e-12, mu_max=1e12, up=2.0, down=3.0, rho_lo=0.25, rho_hi=0.75, max_tries=20)
+
+
+def _residual(prob, theta):
+    if hasattr(prob, "residual_rows"):
+        return np.asarray(prob.residual_rows(theta), dtype=np.float64)
+    return p1.residual_rows(prob, theta)
+
+
+def _jacobian(prob, theta):
+    if hasattr(prob, "jacobian"):
+        return np.asarray(prob.jacobian(theta), dtype=np.float64)
+    return p1.jacobian(prob, theta)
+
+
+def lm_step(prob, theta, mu, **kw):
+    """One step with Levenberg-Marquardt damping.
+
+    Paper: Methods, "Second-order Optimizer": the damping decides how far the
+    local quadratic model of the objective is trusted and is adjusted during
+    training, by the classical Levenberg-Marquardt method for some problems.
+    The rule is the one stated in the literature the paper cites (Levenberg
+    1944, Marquardt 1963), in gain-ratio form:
+
+    - delta(mu) = -(G + mu I)^{-1} g with G = J^T J, g = J^T r at theta
+      (formed once; only the damped system is solved again);
+    - rho = (h(theta) - h(theta + delta)) / (h(theta) - |r + J delta|^2 / 2),
+      h = |r|^2 / 2: the actual decrease over the decrease of the
+      Gauss-Newton (linear) model;
+    - a trial is accepted iff h(theta + delta) is finite and rho > 0.  Then
+      mu <- max(mu / down, mu_min) if rho > rho_hi, mu <- min(mu * up, mu_max)
+      if rho < rho_lo;
+    - otherwise (including a failed factorisation) the trial is rejected;
+      if mu already equals mu_max the step ends with theta unchanged, else
+      mu <- min(max(mu * up, mu_min), mu_max) and the solve is repeated, at
+      most max_tries factorisations in all.
+
+    rho_lo = rho_hi = 0 with up = down is Marquardt's rule (decrease: mu / nu,
+    increase: mu nu and retry).  Returns (theta_next, out) with out: status
+    ("ok", "rejected" or "nonfinite"), mu (damping for the next step), tries,
+    rho (of the last trial), mus (the damping of each trial), infos (Cholesky
+    info of each trial), half_sq_norm (at theta), half_sq_norm_new (at
+    theta_next), delta (the accepted update or None).
+    """
+    o = dict(LM_DEFAULTS)
+    o.update(kw)
+    theta = np.asarray(theta, dtype=np.float64)
+    r = _residual(prob, theta)
+    h0 = 0.5 * float(r @ r)
+    out = dict(status="rejected", mu=mu, tries=0, rho=float("nan"), mus=[], infos=[], half_sq_norm=h0,
+               half_sq_norm_new=h0, delta=None)
+    if not np.isfinite(h0):
+        out["status"] = "nonfinite"
+        return theta.copy(), out
+    J = _jacobian(prob, theta)
+    G, g = gram_and_gradient(J, r)
+    while out["tries"] < o["max_tries"]:
+        out["tries"] += 1
+        out["mus"].append(mu)
+        delta, info = damped_solve(G, g, mu)
+        out["infos"].append(info)
+        rho, h1 = float("-inf"), float("nan")
+        if delta is not None and np.all(np.isfinite(delta)):
+            trial = theta + delta
+            r1 = _residual(prob, trial)
+            h1 = 0.5 * float(r1 @ r1)
+            lin = r + J @ delta
+            pred = h0 - 0.5 * float(lin @ lin)
+            rho = (h0 - h1) / pred if pred > 0 else float("-inf")
+        out["rho"] = rho
+        if np.isfinite(h1) and rho > 0:
+            if rho > o["rho_hi"]:
+                mu = max(mu / o["down"], o["mu_min"])
+            elif rho < o["rho_lo"]:
+                mu = min(mu * o["up"], o["mu_max"])
+            out.update(status="ok", mu=mu, half_sq_norm_new=h1, delta=delta)
+            return trial, out
+        if mu >= o["mu_max"]:
+            break
+        mu = min(max(mu * o["up"], o["mu_min"]), o["mu_max"])
+        out["mu"] = mu
+    return theta.copy(), out
