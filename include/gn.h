@@ -46,6 +46,7 @@ typedef struct gn_context *gn_handle;
 typedef enum {
     GN_OK = 0,
     GN_ENOTPD = 1,       /* Cholesky pivot not positive: G + mu I is not numerically PD */
+    GN_EREJECTED = 2,    /* gn_step_lm: no trial decreased the objective; theta unchanged */
     GN_EINVAL = -1,      /* bad argument (null pointer, size, leading dimension, widths) */
     GN_ENOMEM = -2,      /* workspace allocation failed */
     GN_EDEVICE = -3,     /* HIP runtime error */
@@ -189,6 +190,43 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu,
  * (may be NULL: then it does not synchronise and returns GN_OK after
  * enqueueing; failures still leave theta unchanged). */
 gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats);
+
+/* Levenberg-Marquardt damping for gn_step_lm.  Paper: Methods, "Second-order
+ * Optimizer": the damping sets how far the local quadratic model is trusted
+ * and is adapted during training, by the classical Levenberg-Marquardt
+ * method for some problems.  The rule, in gain-ratio form: with delta(mu) =
+ * -(G + mu I)^{-1} g and h = |r|^2 / 2,
+ *   rho = (h(theta) - h(theta + delta)) / (h(theta) - |r + J delta|^2 / 2)
+ * (actual over predicted decrease of the Gauss-Newton model).  A trial is
+ * accepted iff h(theta + delta) is finite and rho > 0; then mu <- max(mu /
+ * down, mu_min) if rho > rho_hi, mu <- min(mu * up, mu_max) if rho < rho_lo.
+ * A rejected trial (or a failed factorisation) ends the step if mu == mu_max,
+ * else mu <- min(max(mu * up, mu_min), mu_max) and the damped system is
+ * solved again with the same G and g.  rho_lo = rho_hi = 0, up = down is
+ * Marquardt's rule. */
+typedef struct {
+    double mu;               /* in: first damping tried (0 <= mu <= mu_max); out: damping for the next step */
+    double mu_min;           /* > 0: floor of an increased damping */
+    double mu_max;           /* >= mu_min: ceiling; a rejection at mu_max ends the step */
+    double up;               /* > 1: factor after a rejection and when rho < rho_lo */
+    double down;             /* >= 1: divisor when rho > rho_hi */
+    double rho_lo, rho_hi;   /* 0 <= rho_lo <= rho_hi */
+    int32_t max_tries;       /* >= 1: factorisations at most */
+    int32_t tries;           /* out: factorisations done */
+    double rho;              /* out: gain ratio of the last trial (-inf if its solve failed) */
+    double half_sq_norm_new; /* out: |r|^2 / 2 at the returned theta */
+} gn_lm;
+
+/* One step with Levenberg-Marquardt damping (rule above), theta updated in
+ * place on acceptance.  r, J and the bordered Gram are formed once; each
+ * trial factors G + mu I again (a copy of G is kept in its own strictly upper
+ * triangle, so no extra matrix is allocated) and evaluates the residual at
+ * theta + delta.  Synchronises once after forming G and once per trial.
+ * *h_stats (may be NULL) describes the input theta and the last trial.
+ * Returns GN_OK (accepted), GN_EREJECTED (theta unchanged; lm->mu is the
+ * increased damping), GN_ENONFINITE (non-finite residual at theta), or
+ * GN_EINVAL for constants outside the ranges above. */
+gn_status gn_step_lm(gn_handle h, double *d_theta, gn_lm *lm, gn_stats *h_stats);
 
 /* Residual statistics at theta (half_sq_norm, max_abs_R, max_abs_R_val).
  * Synchronises. */

@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -30,6 +32,7 @@ struct gn_context {
     // P-dependent workspace (gn_create)
     int64_t cap = 0;                  // largest p accepted by gn_gram/gn_solve work buffers (P + 1)
     double *thetaT = nullptr, *linv = nullptr, *ybuf = nullptr, *zbuf = nullptr, *delta = nullptr;
+    double *theta_trial = nullptr, *gdiag = nullptr;   // damping retries: trial point, saved diagonal of G
     double *gemv_work = nullptr, *red_work = nullptr, *chol_tmp = nullptr, *one_x = nullptr, *nn_one = nullptr, *seed_one = nullptr;
     DevStatus *status = nullptr;
     // point-set data (gn_set_points)
@@ -401,6 +404,7 @@ extern "C" {
 
 const char *gn_status_string(int32_t s) {
     if (s == GN_ENOTPD) return "matrix not positive definite";
+    if (s == GN_EREJECTED) return "no trial step decreased the objective";
     if (s <= 0 && s >= -5) return kStatusText[-s];
     return "unknown status";
 }
@@ -458,6 +462,8 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->ybuf, h->cap);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->zbuf, h->cap);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->delta, h->cap);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->theta_trial, P);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gdiag, h->cap);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gemv_work, gemv_t_work_size(0, h->cap));
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->red_work, 1024);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->chol_tmp, chol_tmp_size());
@@ -720,10 +726,11 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, 
     return GN_OK;
 }
 
-gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
-    if (!h || !d_theta) return GN_EINVAL;
-    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
-    if (!(mu >= 0.0)) return fail(h, GN_EINVAL, "mu must be >= 0%s");
+namespace {
+
+// r, J (or its chunks) and the bordered Gram [[G, g], [g^T, r^T r]] at theta,
+// with the residual statistics; phase marks 0-4.
+gn_status form_system(gn_handle h, const double *d_theta) {
     hipStream_t st = h->stream;
     const int64_t P = h->md.P, m_rows = h->n + 1;
     double *J = h->J;
@@ -740,30 +747,67 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
         mark(h, 3);
         GN_TRY(gram2d(h, d_theta));  // Jacobian rows and the Gram, chunk by chunk
     } else {
-    GN_TRY(build_step_jacobian(h, d_theta, true));
-    mark(h, 3);
-    if (h->precision == GN_SPLIT32) {
-        // G from FP32 hi/lo products; the border row g = J^T r and r^T r stay FP64
-        double *Grow = h->G + P * h->ldG;
-        GN_HIP(h, launch_split(st, J, m_rows, P, ldJ, h->Jhi, h->Jlo));
-        GN_HIP(h, launch_split_gram(st, h->Jhi, h->Jlo, m_rows, P, ldJ, h->G, h->ldG));
-        GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
-        GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
-        GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
-    } else {
-        GN_HIP(h, launch_dgemm(st, gram_desc(h)));
-    }
-    GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
+        GN_TRY(build_step_jacobian(h, d_theta, true));
+        mark(h, 3);
+        if (h->precision == GN_SPLIT32) {
+            // G from FP32 hi/lo products; the border row g = J^T r and r^T r stay FP64
+            double *Grow = h->G + P * h->ldG;
+            GN_HIP(h, launch_split(st, J, m_rows, P, ldJ, h->Jhi, h->Jlo));
+            GN_HIP(h, launch_split_gram(st, h->Jhi, h->Jlo, m_rows, P, ldJ, h->G, h->ldG));
+            GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
+            GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
+            GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
+        } else {
+            GN_HIP(h, launch_dgemm(st, gram_desc(h)));
+        }
+        GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     }
     mark(h, 4);
-    // Cholesky of [[G + mu I, g], [g^T, r^T r]]: last row = (L^{-1} g)^T, Schur complement
-    GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, h->G, P + 1, h->ldG, mu, 1, h->linv, h->chol_tmp, h->status));
+    return GN_OK;
+}
+
+// Cholesky of [[G + mu I, g], [g^T, r^T r]]: its last row is (L^{-1} g)^T and
+// its corner the Schur complement r^T r - |L^{-1} g|^2; then delta =
+// -L^{-T} L^{-1} g into h->delta.  Phase mark 5.
+gn_status solve_system(gn_handle h, double mu) {
+    hipStream_t st = h->stream;
+    const int64_t P = h->md.P;
+    GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, h->G, P + 1, h->ldG, mu, 1, h->linv, h->chol_tmp,
+                              h->status));
     mark(h, 5);
     double *w = h->G + P * h->ldG;
     GN_HIP(h, launch_sumsq(st, w, P, 1, &h->status->grad_dot_delta, h->red_work));
     GN_HIP(h, launch_copy_strided(st, w + P, 1, 1, &h->status->model_sq_norm, 1, 1.0));
     GN_HIP(h, launch_copy_strided(st, w, P, 1, h->ybuf, 1, -1.0));
     GN_HIP(h, launch_solve_upper(st, h->G, P, h->ldG, h->linv, h->ybuf, h->delta, h->status));
+    return GN_OK;
+}
+
+// |r|^2 at theta into status->half_sq_trial (no Jacobian, no seeds).
+gn_status trial_objective(gn_handle h, const double *theta) {
+    hipStream_t st = h->stream;
+    if (h->dim == 2) {
+        GN_TRY(forward2d(h, theta));
+        GN_TRY(residual2d_rows(h, h->r2, 1, false));
+        GN_HIP(h, launch_sumsq(st, h->r2, total_rows(h), 1, &h->status->half_sq_trial, h->red_work));
+    } else {
+        GN_TRY(forward_all(h, theta));
+        GN_TRY(residual_rows(h, h->r_tmp, 1, false));
+        GN_HIP(h, launch_sumsq(st, h->r_tmp, h->n + 1, 1, &h->status->half_sq_trial, h->red_work));
+    }
+    return GN_OK;
+}
+
+}  // namespace
+
+gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
+    if (!h || !d_theta) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (!(mu >= 0.0)) return fail(h, GN_EINVAL, "mu must be >= 0%s");
+    hipStream_t st = h->stream;
+    const int64_t P = h->md.P;
+    GN_TRY(form_system(h, d_theta));
+    GN_TRY(solve_system(h, mu));
     GN_HIP(h, launch_finalize_step(st, d_theta, h->delta, nullptr, P, 1, h->status));
     mark(h, 6);
     if (h->prof_count < h->prof_max) ++h->prof_count;
@@ -774,6 +818,77 @@ gn_status gn_step(gn_handle h, double *d_theta, double mu, gn_stats *h_stats) {
     const gn_status s = (gn_status)h_stats->status;
     if (s == GN_ENOTPD) return fail(h, s, "Cholesky pivot %s is not positive", std::to_string(ds.chol_info).c_str());
     if (s == GN_ENONFINITE) return fail(h, s, "non-finite residual or update%s");
+    return GN_OK;
+}
+
+gn_status gn_step_lm(gn_handle h, double *d_theta, gn_lm *lm, gn_stats *h_stats) {
+    if (!h || !d_theta || !lm) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    const bool ok = lm->mu_min > 0.0 && lm->mu_max >= lm->mu_min && lm->mu >= 0.0 && lm->mu <= lm->mu_max &&
+                    lm->up > 1.0 && lm->down >= 1.0 && lm->rho_lo >= 0.0 && lm->rho_hi >= lm->rho_lo &&
+                    lm->max_tries >= 1 && std::isfinite(lm->mu_max) && std::isfinite(lm->up) &&
+                    std::isfinite(lm->down) && std::isfinite(lm->rho_hi);
+    if (!ok) return fail(h, GN_EINVAL, "Levenberg-Marquardt constants out of range%s");
+    hipStream_t st = h->stream;
+    const int64_t P = h->md.P;
+    lm->tries = 0;
+    lm->rho = std::nan("");
+    GN_TRY(form_system(h, d_theta));
+    DevStatus ds0, ds;
+    GN_TRY(read_status(h, &ds0));
+    const double h0 = 0.5 * ds0.half_sq_norm;
+    lm->half_sq_norm_new = h0;
+    ds = ds0;
+    bool accepted = false;
+    double mu = lm->mu, h1 = h0;
+    if (std::isfinite(h0)) {
+        GN_HIP(h, launch_tri_save(st, h->G, P + 1, h->ldG, h->gdiag));
+        while (lm->tries < lm->max_tries) {
+            if (lm->tries++ > 0) GN_HIP(h, launch_tri_restore(st, h->G, P + 1, h->ldG, h->gdiag));
+            GN_HIP(h, launch_reset_solve_status(st, h->status));
+            GN_TRY(solve_system(h, mu));
+            // trial point theta + delta (left equal to theta when the solve failed)
+            GN_HIP(h, hipMemcpyAsync(h->theta_trial, d_theta, sizeof(double) * P, hipMemcpyDeviceToDevice, st));
+            GN_HIP(h, launch_finalize_step(st, h->theta_trial, h->delta, nullptr, P, 1, h->status));
+            GN_HIP(h, launch_sumsq(st, h->delta, P, 1, &h->status->delta_sq_norm, h->red_work));
+            GN_TRY(trial_objective(h, h->theta_trial));
+            GN_TRY(read_status(h, &ds));
+            double rho = -INFINITY;
+            h1 = 0.5 * ds.half_sq_trial;
+            if (!ds.flag && !ds.nonfinite && ds.updated) {
+                // h(theta) - |r + J delta|^2 / 2 = (|L^{-1} g|^2 + mu |delta|^2) / 2
+                const double pred = 0.5 * (ds.grad_dot_delta + mu * ds.delta_sq_norm);
+                if (pred > 0.0) rho = (h0 - h1) / pred;
+            }
+            lm->rho = rho;
+            if (std::isfinite(h1) && rho > 0.0) {
+                GN_HIP(h, hipMemcpyAsync(d_theta, h->theta_trial, sizeof(double) * P, hipMemcpyDeviceToDevice, st));
+                if (rho > lm->rho_hi) mu = std::max(mu / lm->down, lm->mu_min);
+                else if (rho < lm->rho_lo) mu = std::min(mu * lm->up, lm->mu_max);
+                accepted = true;
+                break;
+            }
+            if (mu >= lm->mu_max) break;
+            mu = std::min(std::max(mu * lm->up, lm->mu_min), lm->mu_max);
+        }
+    }
+    mark(h, 5);
+    mark(h, 6);
+    if (h->prof_count < h->prof_max) ++h->prof_count;
+    lm->mu = mu;
+    if (accepted) lm->half_sq_norm_new = h1;
+    GN_HIP(h, hipStreamSynchronize(st));
+    if (h_stats) {
+        fill_stats(ds0, h_stats);
+        h_stats->grad_dot_delta = -ds.grad_dot_delta;
+        h_stats->model_sq_norm = ds.model_sq_norm;
+        h_stats->chol_info = ds.chol_info;
+        h_stats->updated = accepted ? 1 : 0;
+        h_stats->status = accepted ? GN_OK : (std::isfinite(h0) ? GN_EREJECTED : GN_ENONFINITE);
+    }
+    if (!std::isfinite(h0)) return fail(h, GN_ENONFINITE, "non-finite residual%s");
+    if (!accepted) return fail(h, GN_EREJECTED, "no trial decreased the objective (last mu %s)",
+                               std::to_string(mu).c_str());
     return GN_OK;
 }
 

@@ -57,6 +57,8 @@ struct DevStatus {
     double half_sq_norm;
     double grad_dot_delta;
     double model_sq_norm;
+    double delta_sq_norm;          // |delta|^2 (damping retries)
+    double half_sq_trial;          // |r|^2 at a trial theta + delta (damping retries)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -227,6 +229,11 @@ hipError_t launch_copy_strided(hipStream_t st, const double *src, int64_t n, int
 
 namespace gn {
 hipError_t launch_reset_status(hipStream_t st, DevStatus *s);
+hipError_t launch_reset_solve_status(hipStream_t st, DevStatus *s);
+// Copy of the lower triangle of the n x n matrix A into its strictly upper
+// triangle (transposed), the diagonal into diag (n); restore writes it back.
+hipError_t launch_tri_save(hipStream_t st, double *A, int64_t n, int64_t lda, double *diag);
+hipError_t launch_tri_restore(hipStream_t st, double *A, int64_t n, int64_t lda, const double *diag);
 hipError_t launch_mul(hipStream_t st, const double *a, const double *b, double *out, int64_t n, double scale);
 
 // ------------------------------------------------------------ 2D problems

@@ -855,7 +855,87 @@ __global__ void reset_status_kernel(DevStatus *s) {
         s->half_sq_norm = 0.0;
         s->grad_dot_delta = 0.0;
         s->model_sq_norm = 0.0;
+        s->delta_sq_norm = 0.0;
+        s->half_sq_trial = 0.0;
     }
+}
+
+// Clears the factorisation and update fields of the status before another
+// solve of the same system (the statistics of the residual are kept).
+__global__ void reset_solve_status_kernel(DevStatus *s) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        s->chol_info = 0;
+        s->flag = 0;
+        s->nonfinite = 0;
+        s->updated = 0;
+        s->grad_dot_delta = 0.0;
+        s->model_sq_norm = 0.0;
+        s->delta_sq_norm = 0.0;
+        s->half_sq_trial = 0.0;
+    }
+}
+
+hipError_t launch_reset_solve_status(hipStream_t st, DevStatus *s) {
+    hipLaunchKernelGGL(reset_solve_status_kernel, dim3(1), dim3(64), 0, st, s);
+    return hipGetLastError();
+}
+
+// Keeps a copy of a symmetric matrix's lower triangle in its strictly upper
+// triangle (transposed) and the diagonal in diag (SAVE), or writes it back
+// (restore).  Nothing the Gram and the Cholesky write lies above the
+// diagonal, so the copy survives a factorisation.  One 64 x 64 tile of the
+// lower triangle per workgroup (tile row blockIdx.y, tile column blockIdx.x,
+// upper tiles exit), transposed through LDS so that every global access runs
+// along a row.  Reads and writes of a tile pair are disjoint (strictly lower
+// versus strictly upper positions), so tiles need no ordering.
+template <bool SAVE>
+__global__ __launch_bounds__(256) void tri_mirror_kernel(double *A, int64_t n, int64_t lda, double *diag) {
+    __shared__ double t[64][65];
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    if (bj > bi) return;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)bi * 64, c0 = (int64_t)bj * 64;
+    if (SAVE) {
+        // t[i][j] = A[r0 + i][c0 + j] on and below the diagonal
+        for (int k = ty; k < 64; k += 4) {
+            const int64_t r = r0 + k, c = c0 + tx;
+            t[k][tx] = (r < n && c <= r) ? A[r * lda + c] : 0.0;
+        }
+        __syncthreads();
+        // A[c][r] = A[r][c] for c < r: destination row c0 + k, column r0 + tx
+        for (int k = ty; k < 64; k += 4) {
+            const int64_t c = c0 + k, r = r0 + tx;
+            if (r < n && c < r) A[c * lda + r] = t[tx][k];
+            if (bi == bj && r < n && c == r) diag[r] = t[tx][k];
+        }
+    } else {
+        // t[i][j] = A[c0 + i][r0 + j] strictly above the diagonal
+        for (int k = ty; k < 64; k += 4) {
+            const int64_t c = c0 + k, r = r0 + tx;
+            t[k][tx] = (r < n && c < r) ? A[c * lda + r] : 0.0;
+        }
+        __syncthreads();
+        // A[r][c] = A[c][r] for c < r, diagonal from diag: row r0 + k, column c0 + tx
+        for (int k = ty; k < 64; k += 4) {
+            const int64_t r = r0 + k, c = c0 + tx;
+            if (r < n && c < r) A[r * lda + c] = t[tx][k];
+            else if (r < n && c == r) A[r * lda + c] = diag[r];
+        }
+    }
+}
+
+hipError_t launch_tri_save(hipStream_t st, double *A, int64_t n, int64_t lda, double *diag) {
+    if (n <= 0) return hipSuccess;
+    const unsigned T = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(tri_mirror_kernel<true>, dim3(T, T), dim3(256), 0, st, A, n, lda, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_restore(hipStream_t st, double *A, int64_t n, int64_t lda, const double *diag) {
+    if (n <= 0) return hipSuccess;
+    const unsigned T = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(tri_mirror_kernel<false>, dim3(T, T), dim3(256), 0, st, A, n, lda, (double *)diag);
+    return hipGetLastError();
 }
 
 // Clears the step status with a kernel (no memset node, so the sequence can

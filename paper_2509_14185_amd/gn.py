@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libgn.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "gn.h")
 
 GN_OK, GN_ENOTPD, GN_EINVAL, GN_ENOMEM, GN_EDEVICE, GN_ENONFINITE, GN_ESTATE = 0, 1, -1, -2, -3, -4, -5
+GN_EREJECTED = 2
 EQUATIONS = {"ccf1d": 0, "burgers1d": 1, "ipm2d": 3, "bouss2d": 4}
 PRECISIONS = {"fp64": 0, "split32": 1}
 
@@ -45,6 +46,16 @@ class _Stats(ctypes.Structure):
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
+
+class _LM(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("mu_min", ctypes.c_double), ("mu_max", ctypes.c_double),
+                ("up", ctypes.c_double), ("down", ctypes.c_double), ("rho_lo", ctypes.c_double),
+                ("rho_hi", ctypes.c_double), ("max_tries", ctypes.c_int32), ("tries", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("half_sq_norm_new", ctypes.c_double)]
+
+
+# Levenberg-Marquardt constants used when the caller gives none
+LM_DEFAULTS = dict(mu_min=1e-12, mu_max=1e12, up=2.0, down=3.0, rho_lo=0.25, rho_hi=0.75, max_tries=20)
 
 _lib = None
 _VP = ctypes.c_void_p
@@ -80,6 +91,7 @@ def load():
         "gn_gram": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I64, _VP, _VP, _I64, _VP]),
         "gn_solve": (ctypes.c_int, [_VP, _VP, _I64, _I64, _D, _VP, _VP, ctypes.POINTER(_I64)]),
         "gn_step": (ctypes.c_int, [_VP, _VP, _D, ctypes.POINTER(_Stats)]),
+        "gn_step_lm": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_LM), ctypes.POINTER(_Stats)]),
         "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
         "gn_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
         "gn_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
@@ -228,6 +240,25 @@ class Problem:
             return d
         self._check(st, "gn_step")
         return None
+
+    def step_lm(self, theta, mu, **kw):
+        """One step with Levenberg-Marquardt damping (gn_step_lm); theta updated
+        in place on acceptance.  Keyword constants default to LM_DEFAULTS.
+        Returns the stats dict plus rc, mu (damping for the next step), tries,
+        rho and half_sq_norm_new."""
+        self._bind()
+        o = dict(LM_DEFAULTS)
+        o.update(kw)
+        lm = _LM(mu=float(mu), mu_min=float(o["mu_min"]), mu_max=float(o["mu_max"]), up=float(o["up"]),
+                 down=float(o["down"]), rho_lo=float(o["rho_lo"]), rho_hi=float(o["rho_hi"]),
+                 max_tries=int(o["max_tries"]))
+        s = _Stats()
+        st = self.lib.gn_step_lm(self.h, _ptr(theta), ctypes.byref(lm), ctypes.byref(s))
+        if st not in (GN_OK, GN_EREJECTED, GN_ENONFINITE):
+            self._check(st, "gn_step_lm")
+        d = s.as_dict()
+        d.update(rc=st, mu=lm.mu, tries=lm.tries, rho=lm.rho, half_sq_norm_new=lm.half_sq_norm_new)
+        return d
 
     def eval(self, theta):
         self._bind()
