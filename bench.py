@@ -102,6 +102,55 @@ def split_comparison(inp, mu, steps, target, fp64_elapsed):
     }
 
 
+def lm_comparison(inp, mu, steps, target):
+    """Levenberg-Marquardt damping (gn_step_lm) from the same start as the
+    fixed-damping run: steps/s counting every step (a step may factor the
+    damped system several times), factorisations and rejected trials, and the
+    steps and time to reach the fixed-damping run's final validation
+    max-norm (within 5%)."""
+    import torch
+
+    from paper_2509_14185_amd import gn
+
+    prob = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
+    prob.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+    theta = torch.from_numpy(inp["theta0"].copy()).cuda()
+    prob.step_lm(theta.clone(), mu)  # warm-up on a copy
+    torch.cuda.synchronize()
+    m_k, tries, done, reached, t_reached = mu, 0, 0, None, None
+    elapsed = 0.0
+    for k in range(steps):
+        t0 = time.perf_counter()
+        st = prob.step_lm(theta, m_k)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        tries += st["tries"]
+        done += 1
+        m_k = st["mu"]
+        if st["rc"] != gn.GN_OK:
+            break
+        if reached is None and prob.eval(theta)["max_abs_R_val"] <= 1.05 * target:
+            reached, t_reached = k + 1, elapsed
+    ev = prob.eval(theta)
+    prob.close()
+    return {
+        "value": done / elapsed,
+        "unit": "steps/s",
+        "ms_per_step": 1e3 * elapsed / done,
+        "steps": done,
+        "factorisations": tries,
+        "rejected_trials": tries - done if st["rc"] == gn.GN_OK else tries - done + 1,
+        "mu_initial": mu,
+        "mu_final": m_k,
+        "last_status": st["rc"],
+        "max_abs_R_val_final": ev["max_abs_R_val"],
+        "half_sq_norm_final": ev["half_sq_norm"],
+        "target_max_abs_R_val": target,
+        "steps_to_target": reached,
+        "time_to_target_s": t_reached,
+    }
+
+
 def batched_comparison(steps):
     """Batched CCF workload (independent instances with their own lambda and
     point count, shared widths): batched steps (gn_step_batched) against the
@@ -158,11 +207,13 @@ def batched_comparison(steps):
     }
 
 
-def bench_2d(name, steps, warmup, precision="fp64"):
+def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
     """A 2D workload (IPM-style or Boussinesq-type stand-in): steps/s and the
     Gram + Cholesky FP64 fraction.  With row chunks the Jacobian rows are
     formed chunk by chunk between the Gram updates, so the "gram" phase then
-    includes the Jacobian sweeps."""
+    includes the Jacobian sweeps.  damping "lm": Levenberg-Marquardt steps
+    from the workload's damping (the phases then cover every factorisation,
+    and the objective after each step is recorded)."""
     import torch
 
     import workloads
@@ -177,13 +228,23 @@ def bench_2d(name, steps, warmup, precision="fp64"):
     theta = torch.from_numpy(inp["theta0"].copy()).cuda()
     print(f"[bench] {name} ({precision}): P={P} m={m}; warmup {warmup}, {steps} steps", file=sys.stderr, flush=True)
     ev0 = prob.eval(theta)
+    lm = damping == "lm"
     for _ in range(warmup):
-        prob.step(theta, mu, stats=False)
+        if lm:
+            prob.step_lm(theta.clone(), mu)
+        else:
+            prob.step(theta, mu, stats=False)
     torch.cuda.synchronize()
     prob.profile_enable(True, steps)
+    trace, tries, mu_k = [], 0, mu
     t0 = time.perf_counter()
     for k in range(steps):
-        prob.step(theta, mu, stats=False)
+        if lm:
+            st = prob.step_lm(theta, mu_k)
+            mu_k, tries = st["mu"], tries + st["tries"]
+            trace.append(st["half_sq_norm_new"])
+        else:
+            prob.step(theta, mu, stats=False)
         if steps > 3:
             continue
         torch.cuda.synchronize()
@@ -198,7 +259,7 @@ def bench_2d(name, steps, warmup, precision="fp64"):
     fl_chol = (P + 1) ** 3 / 3.0
     t_gram = phases["gram"] / nrec * 1e-3
     t_chol = phases["cholesky"] / nrec * 1e-3
-    return {
+    res = {
         "metric": METRIC,
         "value": steps / elapsed,
         "unit": "steps/s",
@@ -227,12 +288,18 @@ def bench_2d(name, steps, warmup, precision="fp64"):
             "max_abs_R_val_final": ev1["max_abs_R_val"],
             "half_sq_norm_initial": ev0["half_sq_norm"],
             "half_sq_norm_final": ev1["half_sq_norm"],
+            "damping": damping,
         },
         "gram_tflops": fl_gram / t_gram / 1e12,
         "gram_frac": fl_gram / t_gram / 1e12 / PEAK_FP64_TFLOPS,
         "gram_cholesky_frac": (fl_gram + fl_chol) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS,
         "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
     }
+    if lm:
+        # the "cholesky" phase then spans every trial: factorisations and trial residuals
+        res["lm"] = {"factorisations": tries, "mu_final": mu_k, "half_sq_norm_after_each_step": trace}
+        res["gram_cholesky_frac"] = (fl_gram + fl_chol * tries / steps) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS
+    return res
 
 
 def cpu_baseline(inp, mu):
@@ -289,6 +356,9 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched CCF workload")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D IPM-style workload")
+    ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt runs")
+    ap.add_argument("--damping", default="fixed", choices=["fixed", "lm"],
+                    help="damping of the steps for --workload ipm2d / bouss2d")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split32"],
                     help="arithmetic of the Gram for --workload ipm2d / bouss2d")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -321,7 +391,7 @@ def main():
         print(json.dumps(batched_comparison(args.steps)), flush=True)
         return
     if args.workload in ("ipm2d", "bouss2d"):
-        print(json.dumps(bench_2d(args.workload, args.steps, args.warmup, args.precision)), flush=True)
+        print(json.dumps(bench_2d(args.workload, args.steps, args.warmup, args.precision, args.damping)), flush=True)
         return
     inp = workloads.make_inputs(args.workload)
     mu = inp["mu"]
@@ -398,6 +468,9 @@ def main():
     }
     if not args.no_split:
         out["split32"] = split_comparison(inp, mu, args.steps, ev1["max_abs_R_val"], elapsed)
+    if not args.no_lm:
+        print("[bench] Levenberg-Marquardt damping", file=sys.stderr, flush=True)
+        out["lm"] = lm_comparison(inp, mu, args.steps, ev1["max_abs_R_val"])
     if not args.no_batched:
         print("[bench] batched CCF workload", file=sys.stderr, flush=True)
         out["batched"] = batched_comparison(10)
@@ -406,7 +479,14 @@ def main():
         out["ipm2d"] = {k: r2[k] for k in ("value", "unit", "ms_per_step", "gram_tflops", "gram_frac",
                                             "gram_cholesky_frac", "phase_ms_per_step")}
         out["ipm2d"]["config"] = {k: r2["config"][k] for k in ("widths", "params", "rows", "max_abs_R_val_initial",
-                                                               "max_abs_R_val_final")}
+                                                               "max_abs_R_val_final", "half_sq_norm_initial",
+                                                               "half_sq_norm_final", "mu")}
+        if not args.no_lm:
+            r3 = bench_2d("ipm2d", 5, 1, damping="lm")
+            out["ipm2d_lm"] = {k: r3[k] for k in ("value", "unit", "ms_per_step", "lm")}
+            out["ipm2d_lm"]["config"] = {k: r3["config"][k] for k in ("max_abs_R_val_initial", "max_abs_R_val_final",
+                                                                      "half_sq_norm_initial", "half_sq_norm_final",
+                                                                      "mu")}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inp, mu)
