@@ -13,7 +13,10 @@ Contents:
   complex-step derivative (numpy).
 - dense (dense.c): compensated Gram and gradient, textbook Cholesky, forward
   and back substitution (plain C, built with gcc).
-- gn: the damped Gauss-Newton step composed from the two.
+- gn: the damped Gauss-Newton step composed from the two, and the step with
+  Levenberg-Marquardt damping.
+- rank1: the stochastic full-matrix Gauss-Newton step (moving average of
+  rank-1 curvature estimates, closed-form learning rate and momentum).
 
 Every function is pinned by tests/test_oracle_*.py against closed forms,
 complex-step derivatives, brute force or library routines, never against the

@@ -109,6 +109,12 @@ def perturbation(p: int, seed: int) -> np.ndarray:
     return v / np.linalg.norm(v)
 
 
+def rademacher(m: int, seed: int) -> np.ndarray:
+    """m random signs +-1 (FP64), E[v v^T] = I: the probe vectors of the
+    rank-1 curvature estimate, drawn here and passed to both sides."""
+    return np.random.default_rng(seed).integers(0, 2, size=m).astype(np.float64) * 2.0 - 1.0
+
+
 def make_inputs(name: str, n: int | None = None, m_quad: int | None = None,
                 widths=None) -> dict:
     """All arrays for one named workload (sizes may be overridden for tests)."""
