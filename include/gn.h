@@ -228,6 +228,50 @@ typedef struct {
  * GN_EINVAL for constants outside the ranges above. */
 gn_status gn_step_lm(gn_handle h, double *d_theta, gn_lm *lm, gn_stats *h_stats);
 
+/* Stochastic full-matrix Gauss-Newton step (1D problems).  Paper: Methods,
+ * "Second-order Optimizer": G is estimated by an exponential moving average,
+ * across iterations, of an unbiased rank-1 estimate from one product with
+ * the Jacobian, and the learning rate and momentum are set in closed form each
+ * iteration (Martens and Grosse 2015, section 7).  One call:
+ *   u = J^T v;  G_ema <- beta G_ema + (1 - beta) u u^T (lower triangle);
+ *   if refactor: factor G_ema + gamma I (kept in the handle's workspace);
+ *   Delta = -(G_ema + gamma I)^{-1} g,  g = J^T r;
+ *   (alpha, mu) minimise M(d) = g^T d + d^T (J^T J + gamma I) d / 2 over
+ *   d = alpha Delta + mu d_prev, with J Delta and J d_prev formed exactly
+ *   (without momentum, d_prev = 0 or a 2 x 2 determinant at most 1e-12 of
+ *   its diagonal product: mu = 0 and alpha alone);
+ *   d_prev <- d;  theta <- theta + d.
+ * d_G_ema: P x P (ldG >= P), caller-owned state, lower triangle read and
+ * written (start from zeros).  d_prev: P, the previous update (zeros at the
+ * first step), overwritten with this one.  d_v: gn_num_rows entries with
+ * E[v v^T] = I (e.g. random signs), drawn by the caller.  The factor lives in
+ * the handle's Gram workspace, so gn_step, gn_step_lm, gn_solve, a batched
+ * step or new points discard it: refactor = 0 then returns GN_ESTATE.
+ * Synchronises once.  Errors: GN_EINVAL (2D handle, ldG < P, beta outside
+ * [0, 1], gamma <= 0, P > 65535), GN_ENOTPD (factorisation failed; theta and
+ * d_prev unchanged, G_ema updated), GN_ENONFINITE. */
+typedef struct {
+    double beta;        /* moving-average decay, 0 <= beta <= 1 */
+    double gamma;       /* damping, > 0 */
+    int32_t refactor;   /* nonzero: factor G_ema + gamma I on this step */
+    int32_t momentum;   /* nonzero: use d_prev in the closed-form coefficients */
+} gn_rank1_args;
+
+typedef struct {
+    double half_sq_norm;     /* |r|^2 / 2 at the input theta */
+    double max_abs_R;        /* max |R_i| over collocation points */
+    double max_abs_R_val;    /* max |R| over the validation grid */
+    double alpha;            /* learning rate */
+    double mu;               /* momentum coefficient */
+    double model;            /* M(d), the predicted change of h (<= 0) */
+    int64_t chol_info;       /* 0, or 1-based first bad pivot of G_ema + gamma I */
+    int32_t used_momentum;   /* 1 if the 2 x 2 system was solved */
+    int32_t status;          /* gn_status of the step */
+} gn_rank1_stats;
+
+gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t ldG, double *d_prev,
+                        const double *d_v, const gn_rank1_args *args, gn_rank1_stats *h_stats);
+
 /* Residual statistics at theta (half_sq_norm, max_abs_R, max_abs_R_val).
  * Synchronises. */
 gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats);

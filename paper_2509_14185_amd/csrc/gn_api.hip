@@ -33,6 +33,10 @@ struct gn_context {
     int64_t cap = 0;                  // largest p accepted by gn_gram/gn_solve work buffers (P + 1)
     double *thetaT = nullptr, *linv = nullptr, *ybuf = nullptr, *zbuf = nullptr, *delta = nullptr;
     double *theta_trial = nullptr, *gdiag = nullptr;   // damping retries: trial point, saved diagonal of G
+    double *r1_g = nullptr, *r1_u = nullptr, *r1_D = nullptr, *r1_b = nullptr;  // stochastic step vectors (P)
+    double *r1_dots = nullptr, *r1_work = nullptr;
+    double *r1_w1 = nullptr, *r1_w2 = nullptr;           // J Delta, J d_prev (rows)
+    bool r1_factored = false;                           // the Gram workspace holds the factor of G_ema + gamma I
     double *gemv_work = nullptr, *red_work = nullptr, *chol_tmp = nullptr, *one_x = nullptr, *nn_one = nullptr, *seed_one = nullptr;
     DevStatus *status = nullptr;
     // point-set data (gn_set_points)
@@ -463,6 +467,12 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->zbuf, h->cap);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->delta, h->cap);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->theta_trial, P);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_g, P);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_u, P);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_D, P);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_b, P);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_dots, DOT_MAX);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_work, dots_work_size());
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gdiag, h->cap);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gemv_work, gemv_t_work_size(0, h->cap));
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->red_work, 1024);
@@ -527,6 +537,7 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     GN_HIP(h, hipStreamSynchronize(h->stream));
     free_list(h->pt_allocs);
     ++h->points_gen;
+    h->r1_factored = false;
     h->n = h->m = h->nv = 0;
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
@@ -562,6 +573,8 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     if (s == GN_OK) s = dev_alloc(h, A, &h->seed1, n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->cscale, n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->r_tmp, m_rows);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->r1_w1, m_rows);
+    if (s == GN_OK) s = dev_alloc(h, A, &h->r1_w2, m_rows);
     if (s == GN_OK) s = dev_alloc(h, A, &h->vseed0, n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->vseed1, n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->useed, m_quad);
@@ -604,6 +617,7 @@ gn_status gn_set_points_2d(gn_handle h, int64_t n, const double *d_s, int64_t n1
     GN_HIP(h, hipStreamSynchronize(h->stream));
     free_list(h->pt_allocs);
     ++h->points_gen;
+    h->r1_factored = false;
     h->n = h->m = h->nv = 0;
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
@@ -712,6 +726,7 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, 
     if (p > h->cap) return fail(h, GN_EINVAL, "p exceeds the solver workspace (P + 1)%s");
     if (!(mu >= 0.0)) return fail(h, GN_EINVAL, "mu must be >= 0%s");
     hipStream_t st = h->stream;
+    h->r1_factored = false;  // linv is shared with the stochastic step's factor
     GN_HIP(h, launch_reset_status(st, h->status));
     GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, d_G, p, ldG, mu, 0, h->linv, h->chol_tmp, h->status));
     GN_HIP(h, launch_copy_strided(st, d_g, p, 1, h->ybuf, 1, -1.0));
@@ -732,6 +747,7 @@ namespace {
 // with the residual statistics; phase marks 0-4.
 gn_status form_system(gn_handle h, const double *d_theta) {
     hipStream_t st = h->stream;
+    h->r1_factored = false;  // the Gram overwrites the stochastic step's factor
     const int64_t P = h->md.P, m_rows = h->n + 1;
     double *J = h->J;
     const int64_t ldJ = h->ldJ;
@@ -763,6 +779,16 @@ gn_status form_system(gn_handle h, const double *d_theta) {
         GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     }
     mark(h, 4);
+    return GN_OK;
+}
+
+// r (column P of the workspace J), J and the residual statistics at theta
+// (1D problems; no Gram).
+gn_status form_jacobian(gn_handle h, const double *d_theta) {
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_reset_status(st, h->status));
+    GN_TRY(build_step_jacobian(h, d_theta, false));
+    GN_HIP(h, launch_sumsq(st, h->J + h->md.P, h->n + 1, h->ldJ, &h->status->half_sq_norm, h->red_work));
     return GN_OK;
 }
 
@@ -889,6 +915,90 @@ gn_status gn_step_lm(gn_handle h, double *d_theta, gn_lm *lm, gn_stats *h_stats)
     if (!std::isfinite(h0)) return fail(h, GN_ENONFINITE, "non-finite residual%s");
     if (!accepted) return fail(h, GN_EREJECTED, "no trial decreased the objective (last mu %s)",
                                std::to_string(mu).c_str());
+    return GN_OK;
+}
+
+gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t ldG, double *d_prev,
+                        const double *d_v, const gn_rank1_args *a, gn_rank1_stats *h_stats) {
+    if (!h || !d_theta || !d_G_ema || !d_prev || !d_v || !a) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    const int64_t P = h->md.P, m_rows = h->n + 1;
+    if (h->dim != 1) return fail(h, GN_EINVAL, "the stochastic step takes 1D problems%s");
+    if (ldG < P) return fail(h, GN_EINVAL, "ldG < P%s");
+    if (P > 65535) return fail(h, GN_EINVAL, "P above 65535%s");
+    if (!(a->beta >= 0.0 && a->beta <= 1.0) || !(a->gamma > 0.0) || !std::isfinite(a->gamma))
+        return fail(h, GN_EINVAL, "need 0 <= beta <= 1 and a finite gamma > 0%s");
+    if (!a->refactor && !h->r1_factored)
+        return fail(h, GN_ESTATE, "no factor of G_ema + gamma I is kept: refactor first%s");
+    hipStream_t st = h->stream;
+    double *J = h->J;
+    const int64_t ldJ = h->ldJ;
+    GN_TRY(form_jacobian(h, d_theta));
+    // g = J^T r, u = J^T v
+    GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
+    GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, h->r1_g, h->gemv_work));
+    GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, d_v, h->r1_u, h->gemv_work));
+    GN_HIP(h, launch_ema_rank1(st, d_G_ema, P, ldG, a->beta, h->r1_u));
+    if (a->refactor) {
+        GN_HIP(h, launch_copy_lower(st, d_G_ema, ldG, h->G, h->ldG, P));
+        GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, h->G, P, h->ldG, a->gamma, 0, h->linv,
+                                  h->chol_tmp, h->status));
+    }
+    // Delta = -(G_ema + gamma I)^{-1} g
+    GN_HIP(h, launch_copy_strided(st, h->r1_g, P, 1, h->r1_b, 1, -1.0));
+    GN_HIP(h, launch_solve_lower(st, h->G, P, h->ldG, h->linv, h->r1_b, h->zbuf, h->status));
+    GN_HIP(h, launch_solve_upper(st, h->G, P, h->ldG, h->linv, h->zbuf, h->r1_D, h->status));
+    // exact curvature along Delta and d_prev
+    GN_HIP(h, launch_gemv_n2(st, J, m_rows, P, ldJ, h->r1_D, d_prev, h->r1_w1, h->r1_w2));
+    DotPairs dp{};
+    const double *xs[8] = {h->r1_w1, h->r1_w1, h->r1_w2, h->r1_D, h->r1_D, d_prev, h->r1_g, h->r1_g};
+    const double *ys[8] = {h->r1_w1, h->r1_w2, h->r1_w2, h->r1_D, d_prev, d_prev, h->r1_D, d_prev};
+    dp.count = 3;
+    for (int k = 0; k < 3; ++k) { dp.x[k] = xs[k]; dp.y[k] = ys[k]; }
+    GN_HIP(h, launch_dots(st, dp, m_rows, h->r1_dots, h->r1_work));
+    dp.count = 5;
+    for (int k = 0; k < 5; ++k) { dp.x[k] = xs[3 + k]; dp.y[k] = ys[3 + k]; }
+    GN_HIP(h, launch_dots(st, dp, P, h->r1_dots + 3, h->r1_work));
+    DevStatus ds;
+    double dots[8];
+    GN_HIP(h, hipMemcpyAsync(dots, h->r1_dots, sizeof dots, hipMemcpyDeviceToHost, st));
+    GN_TRY(read_status(h, &ds));
+    gn_rank1_stats o{};
+    o.half_sq_norm = 0.5 * ds.half_sq_norm;
+    o.max_abs_R = bits_to_double(ds.max_R);
+    o.max_abs_R_val = bits_to_double(ds.max_R_val);
+    o.chol_info = ds.chol_info;
+    gn_status rc = GN_OK;
+    if (a->refactor) h->r1_factored = !ds.flag;
+    if (ds.flag) {
+        rc = GN_ENOTPD;
+    } else {
+        // the 2 x 2 model in (alpha, mu): C = J^T J + gamma I
+        const double g = a->gamma;
+        const double a11 = dots[0] + g * dots[3], b1 = dots[6];
+        const double a12 = dots[1] + g * dots[4], a22 = dots[2] + g * dots[5], b2 = dots[7];
+        double alpha = -b1 / a11, mu = 0.0, model = 0.5 * alpha * alpha * a11 + alpha * b1;
+        const double det = a11 * a22 - a12 * a12;
+        if (a->momentum && dots[5] > 0.0 && det > 1e-12 * a11 * a22) {
+            alpha = (-b1 * a22 + b2 * a12) / det;
+            mu = (-b2 * a11 + b1 * a12) / det;
+            model = 0.5 * (alpha * alpha * a11 + 2 * alpha * mu * a12 + mu * mu * a22) + alpha * b1 + mu * b2;
+            o.used_momentum = 1;
+        }
+        o.alpha = alpha;
+        o.mu = mu;
+        o.model = model;
+        if (!std::isfinite(alpha) || !std::isfinite(mu) || !std::isfinite(o.half_sq_norm)) {
+            rc = GN_ENONFINITE;
+        } else {
+            GN_HIP(h, launch_rank1_update(st, d_theta, d_prev, h->r1_D, alpha, mu, P));
+        }
+    }
+    o.status = rc;
+    if (h_stats) *h_stats = o;
+    if (rc == GN_ENOTPD)
+        return fail(h, rc, "G_ema + gamma I: pivot %s is not positive", std::to_string(ds.chol_info).c_str());
+    if (rc == GN_ENONFINITE) return fail(h, rc, "non-finite residual or coefficients%s");
     return GN_OK;
 }
 
@@ -1027,6 +1137,7 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
         if (!d_thetas[i]) return GN_EINVAL;
         if (b->hs[i]->points_gen != b->gen[i]) return GN_ESTATE;
     }
+    for (int i = 0; i < n; ++i) b->hs[i]->r1_factored = false;
     // parameter pointers live in the device descriptors; re-upload when they change
     bool changed = false;
     for (int i = 0; i < n; ++i) changed |= (b->uploaded_thetas[i] != d_thetas[i]);

@@ -236,6 +236,27 @@ hipError_t launch_tri_save(hipStream_t st, double *A, int64_t n, int64_t lda, do
 hipError_t launch_tri_restore(hipStream_t st, double *A, int64_t n, int64_t lda, const double *diag);
 hipError_t launch_mul(hipStream_t st, const double *a, const double *b, double *out, int64_t n, double scale);
 
+// ------------------------------------------- stochastic full-matrix GN step
+// Lower triangle of G <- beta G + (1 - beta) u u^T (p <= 65535).
+hipError_t launch_ema_rank1(hipStream_t st, double *G, int64_t p, int64_t ldg, double beta, const double *u);
+// Lower triangle (with the diagonal) of the n x n src into dst (n <= 65535).
+hipError_t launch_copy_lower(hipStream_t st, const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n);
+// y1 = J x1, y2 = J x2 (J row-major m x p, leading dimension ld).
+hipError_t launch_gemv_n2(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ld, const double *x1,
+                          const double *x2, double *y1, double *y2);
+// out[k] = x[k] . y[k] (length n) for k < count <= DOT_MAX; work of dots_work_size() doubles.
+constexpr int DOT_MAX = 8;
+struct DotPairs {
+    const double *x[DOT_MAX];
+    const double *y[DOT_MAX];
+    int count;
+};
+hipError_t launch_dots(hipStream_t st, const DotPairs &d, int64_t n, double *out, double *work);
+int64_t dots_work_size();
+// delta = alpha D + mu prev (over prev), theta += delta.
+hipError_t launch_rank1_update(hipStream_t st, double *theta, double *prev, const double *D, double alpha, double mu,
+                               int64_t p);
+
 // ------------------------------------------------------------ 2D problems
 // Point table (structure of arrays, stride ld): y1, y2 and the input jets
 // of the network inputs q (xin[0..5]) and beta (xin[6..11]), component c of

@@ -54,6 +54,21 @@ class _LM(ctypes.Structure):
                 ("rho", ctypes.c_double), ("half_sq_norm_new", ctypes.c_double)]
 
 
+class _R1Args(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("gamma", ctypes.c_double), ("refactor", ctypes.c_int32),
+                ("momentum", ctypes.c_int32)]
+
+
+class _R1Stats(ctypes.Structure):
+    _fields_ = [("half_sq_norm", ctypes.c_double), ("max_abs_R", ctypes.c_double),
+                ("max_abs_R_val", ctypes.c_double), ("alpha", ctypes.c_double), ("mu", ctypes.c_double),
+                ("model", ctypes.c_double), ("chol_info", ctypes.c_int64), ("used_momentum", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # Levenberg-Marquardt constants used when the caller gives none
 LM_DEFAULTS = dict(mu_min=1e-12, mu_max=1e12, up=2.0, down=3.0, rho_lo=0.25, rho_hi=0.75, max_tries=20)
 
@@ -92,6 +107,8 @@ def load():
         "gn_solve": (ctypes.c_int, [_VP, _VP, _I64, _I64, _D, _VP, _VP, ctypes.POINTER(_I64)]),
         "gn_step": (ctypes.c_int, [_VP, _VP, _D, ctypes.POINTER(_Stats)]),
         "gn_step_lm": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_LM), ctypes.POINTER(_Stats)]),
+        "gn_step_rank1": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP, ctypes.POINTER(_R1Args),
+                                         ctypes.POINTER(_R1Stats)]),
         "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
         "gn_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
         "gn_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
@@ -258,6 +275,23 @@ class Problem:
             self._check(st, "gn_step_lm")
         d = s.as_dict()
         d.update(rc=st, mu=lm.mu, tries=lm.tries, rho=lm.rho, half_sq_norm_new=lm.half_sq_norm_new)
+        return d
+
+    def step_rank1(self, theta, G_ema, prev, v, beta, gamma, refactor=True, momentum=True):
+        """One stochastic full-matrix GN step (gn_step_rank1).  theta, G_ema
+        (P x P, lower triangle, ldG = G_ema.stride(0)) and prev are updated in
+        place; v holds the m probe values.  Returns the stats dict plus rc;
+        raises on argument and runtime errors."""
+        self._bind()
+        assert G_ema.dtype == torch.float64 and G_ema.stride(1) == 1
+        a = _R1Args(beta=float(beta), gamma=float(gamma), refactor=int(bool(refactor)), momentum=int(bool(momentum)))
+        s = _R1Stats()
+        st = self.lib.gn_step_rank1(self.h, _ptr(theta), _ptr(G_ema), int(G_ema.stride(0)), _ptr(prev),
+                                    _ptr(v.contiguous()), ctypes.byref(a), ctypes.byref(s))
+        if st not in (GN_OK, GN_ENOTPD, GN_ENONFINITE):
+            self._check(st, "gn_step_rank1")
+        d = s.as_dict()
+        d["rc"] = st
         return d
 
     def eval(self, theta):

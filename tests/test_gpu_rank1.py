@@ -1,0 +1,160 @@
+"""GPU parity of the stochastic full-matrix Gauss-Newton step
+(gn_step_rank1) against the oracle (oracle/rank1.py) on identical seeded
+inputs, the probe signs drawn by workloads.rademacher for both.  Each side
+runs its own trajectory of 4 steps (the factor refreshed every second step).
+Per step: G_ema (relative 1e-12, Frobenius), alpha, mu and the model value
+(relative 1e-9), the momentum decision, and theta (the update's forward error
+<= max(1e-10, 10 kappa eps), kappa of G_ema + gamma I).  At any size: with
+the exact Gram injected as the estimate (beta = 1 keeps it) the learning rate
+is 1, the momentum 0 and the step equals gn_step's damped step (relative
+1e-8 small, 1e-5 on the medium CCF workload, where the two routes, plain and
+bordered, differ by the conditioning of J^T J + gamma I).  Error paths: no kept factor,
+discarded factor, bad constants, a 2D handle, an indefinite estimate."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import profile1d as p1
+from oracle import rank1
+from paper_2509_14185_amd import gn
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+CASES = {
+    "ccf_small": ("ccf_small", {}, "ccf1d"),
+    "ccf_ragged": ("ccf_small", dict(n=1000, m_quad=100, widths=[1, 24, 17, 1]), "ccf1d"),
+    "burgers": ("ccf_small", dict(n=777, widths=[1, 16, 16, 1]), "burgers1d"),
+}
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def build(key):
+    name, over, eq = CASES[key]
+    inp = workloads.make_inputs(name, **over)
+    if eq == "burgers1d":
+        inp["c_target"] = -1.0
+    po = p1.Problem.from_inputs(inp, equation=eq)
+    pg = gn.Problem(eq, inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
+    ccf = eq == "ccf1d"
+    pg.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"] if ccf else None, inp["wq"] if ccf else None,
+                  inp["sval"])
+    return inp, po, pg
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("key", list(CASES))
+def test_rank1_trajectory(key):
+    print(f"\n[gpu rank1] {key}", flush=True)
+    inp, po, pg = build(key)
+    P, m = pg.P, pg.m
+    beta, gamma = 0.9, 1e-3
+    theta = inp["theta0"].copy()
+    st = rank1.State(P)
+    t, G, prev = dev(theta), torch.zeros((P, P), dtype=torch.float64, device="cuda"), torch.zeros(
+        P, dtype=torch.float64, device="cuda")
+    for k in range(4):
+        v = workloads.rademacher(m, 500 + k)
+        refactor = k % 2 == 0
+        theta_in = t.cpu().numpy()
+        ref, info = rank1.step(po, theta, st, v, beta, gamma, refactor)
+        s = pg.step_rank1(t, G, prev, dev(v), beta, gamma, refactor)
+        print(f"  step {k}: alpha {s['alpha']:.9g} / {info['alpha']:.9g}, mu {s['mu']:.6g} / {info['mu']:.6g}",
+              flush=True)
+        assert s["rc"] == gn.GN_OK
+        Gg = torch.tril(G).cpu().numpy()
+        assert rel(Gg, np.tril(st.G)) < 1e-12
+        assert bool(s["used_momentum"]) == info["used_momentum"]
+        assert s["alpha"] == pytest.approx(info["alpha"], rel=1e-9)
+        assert s["mu"] == pytest.approx(info["mu"], rel=1e-9, abs=1e-12)
+        assert s["model"] == pytest.approx(info["model"], rel=1e-9)
+        assert s["half_sq_norm"] == pytest.approx(info["half_sq_norm"], rel=1e-12)
+        A = st.G + gamma * np.eye(P)
+        kappa = np.linalg.cond(A)
+        d, dref = t.cpu().numpy() - theta_in, ref - theta
+        assert np.linalg.norm(d - dref) <= max(1e-10, 10 * kappa * EPS) * np.linalg.norm(dref)
+        assert rel(prev.cpu().numpy(), st.prev) <= max(1e-10, 10 * kappa * EPS)
+        theta = ref
+    pg.close()
+
+
+def exact_curvature_check(pg, theta0, gamma):
+    """Inject G_ema = J^T J: alpha = 1, mu = 0 and theta equals gn_step's step."""
+    P = pg.P
+    J, _ = pg.jacobian(dev(theta0))
+    G, _ = pg.gram(J)                       # lower triangle of J^T J, P x P contiguous
+    assert G.stride(0) == P
+    prev = dev(np.random.default_rng(1).standard_normal(P))
+    t = dev(theta0)
+    s = pg.step_rank1(t, G, prev, dev(np.ones(pg.m)), 1.0, gamma, True)
+    assert s["rc"] == gn.GN_OK
+    assert s["alpha"] == pytest.approx(1.0, abs=1e-8)
+    assert abs(s["mu"]) < 1e-8
+    t2 = dev(theta0)
+    pg.step(t2, gamma)
+    d1, d2 = t.cpu().numpy() - theta0, t2.cpu().numpy() - theta0
+    print(f"  exact curvature: alpha - 1 = {s['alpha'] - 1:.3g}, mu = {s['mu']:.3g}, "
+          f"step difference {rel(d1, d2):.3g}", flush=True)
+    return rel(d1, d2)
+
+
+def test_exact_curvature_small():
+    inp, po, pg = build("ccf_ragged")
+    assert exact_curvature_check(pg, inp["theta0"], 1e-3) < 1e-8
+    pg.close()
+
+
+def test_exact_curvature_medium():
+    print("\n[gpu rank1] medium CCF, exact curvature", flush=True)
+    inp = workloads.make_inputs("ccf_medium")
+    pg = gn.Problem("ccf1d", inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
+    pg.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+    # two solves of the same system by different routes (plain and bordered):
+    # they differ by the conditioning of J^T J + 1e-3 I times eps
+    assert exact_curvature_check(pg, inp["theta0"], 1e-3) < 1e-5
+    pg.close()
+
+
+def test_rank1_error_paths():
+    inp, po, pg = build("ccf_small")
+    P, m = pg.P, pg.m
+    t = dev(inp["theta0"])
+    G = torch.zeros((P, P), dtype=torch.float64, device="cuda")
+    prev = torch.zeros(P, dtype=torch.float64, device="cuda")
+    v = dev(workloads.rademacher(m, 3))
+    with pytest.raises(gn.GNError) as e:       # no factor kept yet
+        pg.step_rank1(t, G, prev, v, 0.9, 1e-3, refactor=False)
+    assert e.value.status == gn.GN_ESTATE
+    for beta, gamma in ((1.5, 1e-3), (0.9, 0.0), (0.9, -1.0)):
+        with pytest.raises(gn.GNError) as e:
+            pg.step_rank1(t, G, prev, v, beta, gamma)
+        assert e.value.status == gn.GN_EINVAL
+    assert pg.step_rank1(t, G, prev, v, 0.9, 1e-3)["rc"] == gn.GN_OK
+    assert pg.step_rank1(t, G, prev, v, 0.9, 1e-3, refactor=False)["rc"] == gn.GN_OK
+    pg.step(t.clone(), 1e-3, stats=False)      # the Gram workspace now holds another matrix
+    with pytest.raises(gn.GNError) as e:
+        pg.step_rank1(t, G, prev, v, 0.9, 1e-3, refactor=False)
+    assert e.value.status == gn.GN_ESTATE
+    # an indefinite estimate: the factorisation fails, theta and prev stay
+    G.copy_(-10.0 * torch.eye(P, dtype=torch.float64, device="cuda"))
+    t0, p0 = t.clone(), prev.clone()
+    s = pg.step_rank1(t, G, prev, v, 1.0, 1e-3)
+    assert s["rc"] == gn.GN_ENOTPD and s["chol_info"] == 1
+    assert torch.equal(t, t0) and torch.equal(prev, p0)
+    pg.close()
+    inp2 = workloads.make_inputs_2d("ipm2d", n=64, n1=16, ne=8, widths=[2, 12, 12, 1], nval=64)
+    p2 = gn.Problem(inp2["equation"], inp2["widths"], inp2["lam"], inp2["c_norm"], inp2["c_target"])
+    p2.set_points_2d(inp2["s"], inp2["s1"], inp2["se"], inp2["sval"])
+    P2 = p2.P
+    with pytest.raises(gn.GNError) as e:
+        p2.step_rank1(dev(inp2["theta0"]), torch.zeros((P2, P2), dtype=torch.float64, device="cuda"),
+                      torch.zeros(P2, dtype=torch.float64, device="cuda"), dev(np.ones(p2.m)), 0.9, 1e-3)
+    assert e.value.status == gn.GN_EINVAL
+    p2.close()
