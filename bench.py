@@ -151,6 +151,66 @@ def lm_comparison(inp, mu, steps, target):
     }
 
 
+def rank1_comparison(inp, steps, target, period=10, beta=0.95, gamma=1e-3):
+    """The paper's stochastic full-matrix GN (gn_step_rank1: moving average of
+    rank-1 curvature estimates, factor refreshed every `period` steps,
+    closed-form learning rate and momentum) from the same start: steps/s,
+    the time of refresh and plain steps, and the steps and time to reach the
+    exact-Gram run's final validation max-norm (within 5%).  Probe signs are
+    drawn before the timed region."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2509_14185_amd import gn
+
+    prob = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
+    prob.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+    P, m = prob.P, prob.m
+    vs = torch.from_numpy(np.stack([workloads.rademacher(m, 1000 + k) for k in range(steps)])).cuda()
+    theta = torch.from_numpy(inp["theta0"].copy()).cuda()
+    G = torch.zeros((P, P), dtype=torch.float64, device="cuda")
+    prev = torch.zeros(P, dtype=torch.float64, device="cuda")
+    prob.step_rank1(theta.clone(), G.clone(), prev.clone(), vs[0], beta, gamma, True)  # warm-up on copies
+    torch.cuda.synchronize()
+    t_ref, t_plain, n_ref, reached, t_reached, elapsed = 0.0, 0.0, 0, None, None, 0.0
+    for k in range(steps):
+        refactor = k % period == 0
+        t0 = time.perf_counter()
+        st = prob.step_rank1(theta, G, prev, vs[k], beta, gamma, refactor)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        elapsed += dt
+        if refactor:
+            t_ref, n_ref = t_ref + dt, n_ref + 1
+        else:
+            t_plain += dt
+        if st["rc"] != gn.GN_OK:
+            break
+        if reached is None and prob.eval(theta)["max_abs_R_val"] <= 1.05 * target:
+            reached, t_reached = k + 1, elapsed
+    ev = prob.eval(theta)
+    prob.close()
+    done = k + 1
+    return {
+        "value": done / elapsed,
+        "unit": "steps/s",
+        "ms_per_step": 1e3 * elapsed / done,
+        "ms_per_refresh_step": 1e3 * t_ref / max(n_ref, 1),
+        "ms_per_plain_step": 1e3 * t_plain / max(done - n_ref, 1),
+        "steps": done,
+        "refresh_period": period,
+        "beta": beta,
+        "gamma": gamma,
+        "last_status": st["rc"],
+        "max_abs_R_val_final": ev["max_abs_R_val"],
+        "half_sq_norm_final": ev["half_sq_norm"],
+        "target_max_abs_R_val": target,
+        "steps_to_target": reached,
+        "time_to_target_s": t_reached,
+    }
+
+
 def batched_comparison(steps):
     """Batched CCF workload (independent instances with their own lambda and
     point count, shared widths): batched steps (gn_step_batched) against the
@@ -357,6 +417,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched CCF workload")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D IPM-style workload")
     ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt runs")
+    ap.add_argument("--no-rank1", action="store_true", help="skip the stochastic (rank-1 estimate) run")
     ap.add_argument("--damping", default="fixed", choices=["fixed", "lm"],
                     help="damping of the steps for --workload ipm2d / bouss2d")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split32"],
@@ -471,6 +532,9 @@ def main():
     if not args.no_lm:
         print("[bench] Levenberg-Marquardt damping", file=sys.stderr, flush=True)
         out["lm"] = lm_comparison(inp, mu, args.steps, ev1["max_abs_R_val"])
+    if not args.no_rank1:
+        print("[bench] stochastic full-matrix GN (rank-1 estimates)", file=sys.stderr, flush=True)
+        out["rank1"] = rank1_comparison(inp, 3 * args.steps, ev1["max_abs_R_val"])
     if not args.no_batched:
         print("[bench] batched CCF workload", file=sys.stderr, flush=True)
         out["batched"] = batched_comparison(10)

@@ -450,14 +450,33 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
 // forms z_{I+1} = X_{I+1} b_{I+1}.  Back L^T x = y mirrors it column-wise.
 
 __device__ void block_lower_apply(const double *__restrict__ Xb, const double *bs, double *out, int kb) {
-    // out[t] = sum_{c <= t} X[t][c] bs[c]; a wave per output row, lanes over c
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = wave; t < kb; t += 4) {
-        double v = 0.0;
-        for (int c = lane; c <= t; c += 64) v = fma(Xb[t * CB + c], bs[c], v);
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) out[t] = v;
+    // out[t] = sum_{c <= t} X[t][c] bs[c]: X staged through LDS in chunks of
+    // 32 columns (coalesced row segments), two threads per row
+    constexpr int KC = 32;
+    __shared__ double xt[CB][KC + 1];
+    __shared__ double part2[256];
+    const int tid = threadIdx.x, row = tid & (CB - 1), half = tid >> 7;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < kb; k0 += KC) {
+        double v[CB * KC / 256];
+#pragma unroll
+        for (int e = 0; e < CB * KC / 256; ++e) {
+            const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
+            v[e] = (rr < kb && k0 + kk < kb) ? Xb[rr * CB + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < CB * KC / 256; ++e) {
+            const int idx = tid + e * 256;
+            xt[idx / KC][idx % KC] = v[e];
+        }
+        __syncthreads();
+        const int kend = (kb - k0) < KC ? kb - k0 : KC;
+        for (int kk = half; kk < kend; kk += 2) acc = fma(xt[row][kk], bs[k0 + kk], acc);
     }
+    part2[tid] = acc;
+    __syncthreads();
+    if (half == 0 && row < kb) out[row] = part2[row] + part2[row + CB];
 }
 
 __device__ void block_upper_apply(const double *__restrict__ Xb, const double *ys, double *out, int kb) {
@@ -488,30 +507,52 @@ __global__ __launch_bounds__(256) void fwd_init_kernel(const double *linv, const
     block_lower_apply(linv, bs, z, kb);
 }
 
+// Rows of block w = I + 1 + blockIdx.x: b_w -= L_wI z_I.  The 128 x kbI tile
+// L_wI is staged through LDS in chunks of 32 columns (coalesced row
+// segments, all loads of a thread issued before its stores); two threads
+// per row each sum half of a chunk's columns.  The workgroup of block I + 1
+// then forms z_{I+1} = X_{I+1} b_{I+1}.
 __global__ __launch_bounds__(256) void fwd_update_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
                                                          const double *__restrict__ linv, double *b, double *z,
                                                          int64_t I, const DevStatus *status) {
     if (status->flag) return;
+    constexpr int KC = 32;
     __shared__ double zs[CB];
     __shared__ double bs[CB];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ double tile[CB][KC + 1];
+    __shared__ double part[256];
+    const int tid = threadIdx.x;
     const int64_t r0 = I * CB;
     const int kbI = (int)((n - r0) < CB ? (n - r0) : CB);
     const int64_t w = I + 1 + blockIdx.x;
     const int64_t w0 = w * CB;
     const int kbw = (int)((n - w0) < CB ? (n - w0) : CB);
     if (tid < kbI) zs[tid] = z[r0 + tid];
-    __syncthreads();
-    for (int rr = wave; rr < kbw; rr += 4) {
-        const int64_t row = w0 + rr;
-        double v = 0.0;
-        for (int k = lane; k < kbI; k += 64) v = fma(L[row * ldl + r0 + k], zs[k], v);
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) {
-            const double nb = b[row] - v;
-            b[row] = nb;
-            bs[rr] = nb;
+    const int row = tid & (CB - 1), half = tid >> 7;  // row of the tile, half of a chunk's columns
+    double acc = 0.0;
+    for (int k0 = 0; k0 < kbI; k0 += KC) {
+        double v[CB * KC / 256];
+#pragma unroll
+        for (int e = 0; e < CB * KC / 256; ++e) {
+            const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
+            v[e] = (rr < kbw && k0 + kk < kbI) ? L[(w0 + rr) * ldl + r0 + k0 + kk] : 0.0;
         }
+        __syncthreads();  // previous chunk consumed (and zs written, first pass)
+#pragma unroll
+        for (int e = 0; e < CB * KC / 256; ++e) {
+            const int idx = tid + e * 256;
+            tile[idx / KC][idx % KC] = v[e];
+        }
+        __syncthreads();
+        const int kend = (kbI - k0) < KC ? kbI - k0 : KC;
+        for (int kk = half; kk < kend; kk += 2) acc = fma(tile[row][kk], zs[k0 + kk], acc);
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (half == 0 && row < kbw) {
+        const double nb = b[w0 + row] - (part[row] + part[row + CB]);
+        b[w0 + row] = nb;
+        bs[row] = nb;
     }
     if (w != I + 1) return;
     __syncthreads();
