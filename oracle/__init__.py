@@ -11,6 +11,9 @@ Contents:
 - profile2d: 2D coordinates, second-order network jets in y (Taylor mode),
   IPM-style and Boussinesq-type residual rows, parameter Jacobian by the
   complex-step derivative (numpy).
+- deriv1d: d1 and d2 loss rows of the 1D problems (Taylor-mode field
+  derivatives to third order, odd and even half-line Hilbert quadrature,
+  complex-step Jacobian).
 - dense (dense.c): compensated Gram and gradient, textbook Cholesky, forward
   and back substitution (plain C, built with gcc).
 - gn: the damped Gauss-Newton step composed from the two, and the step with
