@@ -143,6 +143,26 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
                         const double *d_f, int64_t m_quad, const double *d_sq,
                         const double *d_wq, int64_t n_val, const double *d_sval);
 
+/* gn_set_points plus derivative (d1, d2) rows for 1D problems.  Paper:
+ * Methods, "Training Loss": losses on the first and second y-derivatives of
+ * the residual, each on its own point batch, weighted 1/(N_d1 N_E d) and
+ * 1/(N_d2 N_E d^2) (here d = N_E = 1) times c_d1, c_d2.  d_s1 (n1) and d_s2
+ * (n2): mapped coordinates s in [0, 1) of the d1 and d2 points (device).
+ * Rows, in order: the n d0 rows, n1 rows sqrt(c_d1/n1) R'(y), n2 rows
+ * sqrt(c_d2/n2) R''(y), the normalisation row; gn_num_rows = n + n1 + n2 + 1.
+ * R' = (1 + U') Theta' + V Theta'', R'' = U'' Theta' + (2 + lam + 2 U') Theta''
+ * + V Theta''' with V = (1+lam) y + U; for CCF U' = H[Theta'] by the odd
+ * half-line form (1/pi) int (t f(t) - y f(y)) 2/(y^2 - t^2) dt and
+ * U'' = H[Theta''] by the even form, on the same nodes; U = Theta for the
+ * local variant.  The validation max-norm and max_abs_R stay on R.
+ * Errors: as gn_set_points, and GN_EINVAL for n1 or n2 < 0, missing point
+ * arrays, negative weights, or more than 65535 nodes with derivative rows.
+ * Handles with derivative rows cannot join a batch. */
+gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const double *d_rho, const double *d_f,
+                           int64_t m_quad, const double *d_sq, const double *d_wq, int64_t n_val,
+                           const double *d_sval, int64_t n1, const double *d_s1, int64_t n2, const double *d_s2,
+                           double c_d1, double c_d2);
+
 /*
  * Point sets of a 2D problem (GN_EQ_IPM2D, GN_EQ_BOUSS2D), s-coordinates in
  * [0,1) mapped per axis to y = s / (1 - s):
@@ -271,6 +291,16 @@ typedef struct {
 
 gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t ldG, double *d_prev,
                         const double *d_v, const gn_rank1_args *args, gn_rank1_stats *h_stats);
+
+/* Blow-up rate implied by the profile at the origin (1D CCF).  Paper:
+ * Methods, "Identifying Admissible lambda Values" (lambda inference: the
+ * derivatives of the self-similar equation at the origin must vanish).  For
+ * an even profile R'(0) = 0 identically and R''(0) = Theta''(0)
+ * (2 + lam + 2 U'(0)), so *h_lam = -2 (1 + U'(0)), U'(0) = H[Theta'](0) =
+ * -(2/pi) int_0^inf Theta'(t)/t dt on the Hilbert nodes (also returned in
+ * *h_dU0 when not NULL).  Synchronises.  Errors: GN_EINVAL (not 1D CCF),
+ * GN_ESTATE. */
+gn_status gn_lambda_estimate(gn_handle h, const double *d_theta, double *h_lam, double *h_dU0);
 
 /* Residual statistics at theta (half_sq_norm, max_abs_R, max_abs_R_val).
  * Synchronises. */

@@ -200,3 +200,20 @@ class Problem(p1.Problem):
             tc[k] += 1j * h
             out[:, k] = np.imag(self.residual_rows(tc)) / h
         return out
+
+
+# ------------------------------------------------------------ lambda inference
+def lambda_estimate(prob, theta):
+    """Blow-up rate implied at the origin (Methods, "Identifying Admissible
+    lambda Values", lambda inference: derivatives of the self-similar
+    equation at the origin must vanish, which ties lambda to field values
+    there).  For the even CCF profile R'(0) = 0 identically; with
+    Theta = a y^2 + ..., U = c y + ..., R''(0) = 2a (2 + lam + 2c), so an exact
+    profile has U'(0) = -(1 + lam/2):
+    lam_hat = -2 (1 + U'(0)), with U'(0) = H[Theta'](0) by the odd half-line
+    form at y = 0, -(2/pi) int_0^inf Theta'(t) / t dt, on the problem's nodes."""
+    if prob.equation != p1.CCF:
+        raise ValueError("lambda inference is defined for the CCF problem")
+    Ft = field_derivs(theta, prob.widths, prob.t, prob.lam, prob.equation)
+    U1_0 = hilbert_odd(np.zeros(1), prob.t, prob.what, Ft[1], np.zeros(1))[0]
+    return -2.0 * (1.0 + U1_0), U1_0

@@ -59,6 +59,17 @@ struct gn_context {
     double *origin_s = nullptr;       // (0, 0): the normalisation point
     double *nn2 = nullptr, *nn2v = nullptr, *seeds2 = nullptr, *r2 = nullptr;
     int64_t ldn2 = 0, ldnv2 = 0, rows_ws = 0;
+    // 1D derivative rows (gn_set_points_ex): d1 rows then d2 rows after the d0 rows
+    int64_t nd1 = 0, nd2 = 0;
+    double c_d1 = 1.0, c_d2 = 1.0;
+    Geo3 geo3{}, geo3n{};              // derivative points; Hilbert nodes
+    double *nn3 = nullptr, *nn3n = nullptr;   // NN^(c) (4 x nd, 4 x m)
+    double *nfield = nullptr;          // Theta, Theta', Theta'' at the nodes (3 x m)
+    double *dseed = nullptr, *dvseed = nullptr, *dcoef = nullptr;  // 4 x nd, 4 x nd, 3 x nd
+    double *bseed = nullptr;           // seeds of the node Jacobians B1, B2 (4 x 2m)
+    double *dAT = nullptr;             // coupling matrix of the derivative rows (3m x ldA)
+    int64_t ldA = 0;
+    double *nvseed = nullptr;          // node seeds of the coupling adjoint (4 x m)
     // phase timing
     std::vector<hipEvent_t> events;   // max_steps x (GN_PHASE_COUNT + 1)
     int32_t prof_max = 0, prof_count = 0;
@@ -113,7 +124,9 @@ void free_list(std::vector<void *> &list) {
 
 bool points_ready(gn_handle h) { return h->n > 0; }
 
-int64_t total_rows(gn_handle h) { return h->dim == 2 ? h->map2.rows() : h->n + 1; }
+// 1D rows: d0 rows (n), d1 rows, d2 rows, then the normalisation row.
+int64_t norm_row(gn_handle h) { return h->n + h->nd1 + h->nd2; }
+int64_t total_rows(gn_handle h) { return h->dim == 2 ? h->map2.rows() : norm_row(h) + 1; }
 
 // Forward jets at the nodes (CCF), the collocation points and q = 1.
 gn_status forward_all(gn_handle h, const double *theta) {
@@ -130,7 +143,30 @@ gn_status forward_all(gn_handle h, const double *theta) {
     SweepBatch o{};
     o.x = h->one_x; o.n = 1; o.nn = h->nn_one;
     GN_HIP(h, launch_mlp_forward(st, h->md, theta, h->thetaT, o));
+    if (h->nd1 + h->nd2 > 0) {
+        // third-order jets at the derivative points (and Theta, Theta', Theta'' at the nodes)
+        Sweep3 d{};
+        d.x = h->geo3.q; d.n = h->nd1 + h->nd2; d.nn = h->nn3;
+        GN_HIP(h, launch_jet3_forward(st, h->md, theta, h->thetaT, d));
+        if (h->equation == GN_EQ_CCF1D) {
+            Sweep3 nb{};
+            nb.x = h->geo3n.q; nb.n = h->m; nb.nn = h->nn3n;
+            GN_HIP(h, launch_jet3_forward(st, h->md, theta, h->thetaT, nb));
+            GN_HIP(h, launch_node_fields(st, h->m, h->nn3n, h->geo3n, h->nfield));
+        }
+    }
     return GN_OK;
+}
+
+DerivArgs deriv_args(gn_handle h) {
+    DerivArgs a{};
+    a.equation = h->equation; a.lam = h->lam;
+    a.n1 = h->nd1; a.n2 = h->nd2; a.m = h->m;
+    a.geo = h->geo3; a.nn = h->nn3;
+    a.nodes_y = h->nodes.y; a.nodes_wh = h->nodes.wh; a.node_fields = h->nfield;
+    a.scale1 = h->nd1 > 0 ? sqrt(h->c_d1 / (double)h->nd1) : 0.0;
+    a.scale2 = h->nd2 > 0 ? sqrt(h->c_d2 / (double)h->nd2) : 0.0;
+    return a;
 }
 
 // Residual rows into r (stride r_stride); seeds/cscale when `seeds`.
@@ -145,7 +181,43 @@ gn_status residual_rows(gn_handle h, double *r, int64_t r_stride, bool seeds) {
     a.cscale = seeds ? h->cscale : nullptr;
     a.max_out = &h->status->max_R;
     GN_HIP(h, launch_residual(h->stream, a));
-    GN_HIP(h, launch_norm_row(h->stream, h->nn_one, sqrt(h->c_norm), h->c_target, r + h->n * r_stride));
+    if (h->nd1 + h->nd2 > 0) {
+        DerivArgs d = deriv_args(h);
+        d.r = r + h->n * r_stride; d.r_stride = r_stride;
+        d.seed = seeds ? h->dseed : nullptr;
+        d.coef = seeds ? h->dcoef : nullptr;
+        GN_HIP(h, launch_deriv_residual(h->stream, d));
+    }
+    GN_HIP(h, launch_norm_row(h->stream, h->nn_one, sqrt(h->c_norm), h->c_target, r + norm_row(h) * r_stride));
+    return GN_OK;
+}
+
+// Jacobian rows of the derivative rows (after residual_rows with seeds and,
+// for CCF, the node Jacobian B in rows 0..m-1 of Bm): local rows by the jet
+// sweep, then the coupling with B, B1 = t dTheta'/dtheta, B2 = dTheta''/dtheta.
+gn_status deriv_jacobian(gn_handle h, const double *theta, double *J, int64_t ldJ) {
+    const int64_t nd = h->nd1 + h->nd2;
+    if (nd <= 0) return GN_OK;
+    hipStream_t st = h->stream;
+    Sweep3 d{};
+    d.x = h->geo3.q; d.seed = h->dseed; d.seed_ld = nd; d.n = nd; d.rows = J + h->n * ldJ; d.ld = ldJ;
+    GN_HIP(h, launch_jet3_rows(st, h->md, theta, h->thetaT, d));
+    if (h->equation != GN_EQ_CCF1D) return GN_OK;
+    const int64_t m = h->m;
+    for (int k = 0; k < 2; ++k) {
+        Sweep3 nb{};
+        nb.x = h->geo3n.q; nb.seed = h->bseed + k * m; nb.seed_ld = 2 * m; nb.n = m;
+        nb.rows = h->Bm + (1 + k) * m * h->ldJ; nb.ld = h->ldJ;
+        GN_HIP(h, launch_jet3_rows(st, h->md, theta, h->thetaT, nb));
+    }
+    GN_HIP(h, launch_deriv_coupling(st, nd, m, h->geo3.y, h->nodes.y, h->nodes.wh, h->dcoef, h->dAT, h->ldA));
+    GemmDesc g{};
+    g.M = nd; g.N = h->md.P; g.K = 3 * m;
+    g.A = h->dAT; g.lda = h->ldA; g.la = 1;
+    g.B = h->Bm; g.ldb = h->ldJ; g.lb = 0;
+    g.C = J + h->n * ldJ; g.ldc = ldJ;
+    g.alpha = 1.0; g.beta = 1.0;
+    GN_HIP(h, launch_dgemm(st, g));
     return GN_OK;
 }
 
@@ -174,7 +246,7 @@ gn_status jacobian_into(gn_handle h, const double *theta, double *J, int64_t ldJ
     b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
     GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, b));
     SweepBatch o{};
-    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + h->n * ldJ; o.ld = ldJ;
+    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + norm_row(h) * ldJ; o.ld = ldJ;
     GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, o));
     if (h->equation == GN_EQ_CCF1D) {
         // B_j = dTheta(t_j)/dtheta = E_j dNN(t_j)/dtheta, then J[:N] += diag(sc Theta_y) Q B
@@ -189,6 +261,7 @@ gn_status jacobian_into(gn_handle h, const double *theta, double *J, int64_t ldJ
         g.alpha = 1.0; g.beta = 1.0; g.rowscale = h->cscale;
         GN_HIP(h, launch_dgemm(st, g));
     }
+    GN_TRY(deriv_jacobian(h, theta, J, ldJ));
     return GN_OK;
 }
 
@@ -221,7 +294,7 @@ GemmDesc coupling_desc(gn_handle h) {
 GemmDesc gram_desc(gn_handle h) {
     const int64_t P = h->md.P;
     GemmDesc g{};
-    g.M = P + 1; g.N = P + 1; g.K = h->n + 1;
+    g.M = P + 1; g.N = P + 1; g.K = total_rows(h);
     g.A = h->J; g.lda = h->ldJ; g.la = 1;
     g.B = h->J; g.ldb = h->ldJ; g.lb = 0;
     g.C = h->G; g.ldc = h->ldG;
@@ -242,7 +315,7 @@ gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks, bo
     b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
     GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, b));
     SweepBatch o{};
-    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + h->n * ldJ; o.ld = ldJ;
+    o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + norm_row(h) * ldJ; o.ld = ldJ;
     GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, o));
     if (h->equation == GN_EQ_CCF1D) {
         SweepBatch nb{};
@@ -251,6 +324,7 @@ gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks, bo
     }
     if (marks) mark(h, 2);
     if (coupling && h->equation == GN_EQ_CCF1D) GN_HIP(h, launch_dgemm(st, coupling_desc(h)));
+    GN_TRY(deriv_jacobian(h, d_theta, J, ldJ));
     return GN_OK;
 }
 
@@ -527,25 +601,41 @@ int64_t gn_num_rows(gn_handle h) { return (h && h->n > 0) ? total_rows(h) : -1; 
 gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double *d_rho, const double *d_f,
                         int64_t m_quad, const double *d_sq, const double *d_wq, int64_t n_val,
                         const double *d_sval) {
+    return gn_set_points_ex(h, n, d_s, d_rho, d_f, m_quad, d_sq, d_wq, n_val, d_sval, 0, nullptr, 0, nullptr, 1.0,
+                            1.0);
+}
+
+gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const double *d_rho, const double *d_f,
+                           int64_t m_quad, const double *d_sq, const double *d_wq, int64_t n_val,
+                           const double *d_sval, int64_t n1, const double *d_s1, int64_t n2, const double *d_s2,
+                           double c_d1, double c_d2) {
     if (!h) return GN_EINVAL;
     if (h->dim != 1) return fail(h, GN_EINVAL, "2D problems take gn_set_points_2d%s");
     if (n < 1 || !d_s) return fail(h, GN_EINVAL, "need n >= 1 collocation points%s");
     if (h->equation == GN_EQ_CCF1D && (m_quad < 1 || !d_sq || !d_wq))
         return fail(h, GN_EINVAL, "the CCF Hilbert term needs m_quad >= 1 nodes and weights%s");
     if (n_val < 0 || (n_val > 0 && !d_sval)) return fail(h, GN_EINVAL, "bad validation grid%s");
+    if (n1 < 0 || n2 < 0 || (n1 > 0 && !d_s1) || (n2 > 0 && !d_s2))
+        return fail(h, GN_EINVAL, "bad derivative point sets%s");
+    if (!(c_d1 >= 0.0) || !(c_d2 >= 0.0)) return fail(h, GN_EINVAL, "derivative loss weights must be >= 0%s");
     if (h->equation != GN_EQ_CCF1D) m_quad = 0;
+    if (m_quad > 65535 && n1 + n2 > 0) return fail(h, GN_EINVAL, "at most 65535 nodes with derivative rows%s");
     GN_HIP(h, hipStreamSynchronize(h->stream));
     free_list(h->pt_allocs);
     ++h->points_gen;
     h->r1_factored = false;
     h->n = h->m = h->nv = 0;
+    h->nd1 = h->nd2 = 0;
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
-    const int64_t m_rows = n + 1;
+    const int64_t nd = n1 + n2;
+    const int64_t m_rows = n + nd + 1;
     h->ldJ = round_up(P + 1, 32);
     h->ldG = round_up(P + 1, 32);
     h->ldQ = round_up(n, 2);  // Q^T: m_quad rows of n points (even stride: 16-byte aligned rows)
-    const int64_t nparts = mlp_vjp_partials(h->md, n) + mlp_vjp_partials(h->md, 1) + mlp_vjp_partials(h->md, m_quad);
+    h->ldA = round_up(nd, 2);
+    const int64_t nparts = mlp_vjp_partials(h->md, n) + mlp_vjp_partials(h->md, 1) + mlp_vjp_partials(h->md, m_quad) +
+                           (nd > 0 ? jet3_vjp_partials(nd) + jet3_vjp_partials(m_quad) : 0);
     auto geo = [&](Geo1D &g, int64_t cnt, bool with_w) -> gn_status {
         GN_TRY(dev_alloc(h, A, &g.y, cnt));
         GN_TRY(dev_alloc(h, A, &g.q, cnt));
@@ -579,7 +669,30 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
     if (s == GN_OK) s = dev_alloc(h, A, &h->vseed1, n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->useed, m_quad);
     if (s == GN_OK) s = dev_alloc(h, A, &h->J, m_rows * h->ldJ);
-    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Bm, m_quad * h->ldJ);
+    // node Jacobians B (and B1, B2 for the derivative rows), stacked
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Bm, (nd > 0 ? 3 : 1) * m_quad * h->ldJ);
+    if (nd > 0) {
+        auto geo3 = [&](Geo3 &g, int64_t cnt) -> gn_status {
+            g.ld = cnt;
+            GN_TRY(dev_alloc(h, A, &g.y, cnt));
+            GN_TRY(dev_alloc(h, A, &g.q, 4 * cnt));
+            GN_TRY(dev_alloc(h, A, &g.E, 4 * cnt));
+            return GN_OK;
+        };
+        if (s == GN_OK) s = geo3(h->geo3, nd);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->nn3, 4 * nd);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->dseed, 4 * nd);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->dvseed, 4 * nd);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->dcoef, 3 * nd);
+        if (m_quad > 0) {
+            if (s == GN_OK) s = geo3(h->geo3n, m_quad);
+            if (s == GN_OK) s = dev_alloc(h, A, &h->nn3n, 4 * m_quad);
+            if (s == GN_OK) s = dev_alloc(h, A, &h->nfield, 3 * m_quad);
+            if (s == GN_OK) s = dev_alloc(h, A, &h->bseed, 8 * m_quad);
+            if (s == GN_OK) s = dev_alloc(h, A, &h->dAT, 3 * m_quad * h->ldA);
+            if (s == GN_OK) s = dev_alloc(h, A, &h->nvseed, 4 * m_quad);
+        }
+    }
     if (s == GN_OK) s = dev_alloc(h, A, &h->G, (P + 1) * h->ldG);
     if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jhi, m_rows * h->ldJ);
     if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jlo, m_rows * h->ldJ);
@@ -598,10 +711,24 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
         GN_HIP(h, launch_hilbert_matrix(st, n, m_quad, h->pts.y, h->nodes.y, h->nodes.wh, h->Q, h->ldQ));
     }
     if (n_val > 0) GN_HIP(h, launch_geometry(st, h->equation, h->lam, n_val, d_sval, nullptr, h->val));
+    if (nd > 0) {
+        Geo3 g2 = h->geo3;  // the d2 points follow the d1 points
+        g2.y += n1; g2.q += n1; g2.E += n1;
+        GN_HIP(h, launch_geometry3(st, h->equation, h->lam, n1, d_s1, h->geo3));
+        GN_HIP(h, launch_geometry3(st, h->equation, h->lam, n2, d_s2, g2));
+        if (m_quad > 0) {
+            GN_HIP(h, launch_geometry3(st, h->equation, h->lam, m_quad, d_sq, h->geo3n));
+            GN_HIP(h, launch_node_seeds(st, m_quad, h->geo3n, h->nodes.y, h->bseed, 2 * m_quad));
+        }
+    }
     GN_HIP(h, hipStreamSynchronize(st));
     h->n = n;
     h->m = m_quad;
     h->nv = n_val;
+    h->nd1 = n1;
+    h->nd2 = n2;
+    h->c_d1 = c_d1;
+    h->c_d2 = c_d2;
     return GN_OK;
 }
 
@@ -702,7 +829,7 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
     if (d_r && !d_g) return fail(h, GN_EINVAL, "d_g is required when d_r is given%s");
     if (d_r && p > h->cap) return fail(h, GN_EINVAL, "p exceeds the gradient workspace (P + 1)%s");
     if (h->precision == GN_SPLIT32) {
-        if (!h->Jhi || m > (h->dim == 2 ? h->rows_ws : h->n + 1) || ldJ > h->ldJ)
+        if (!h->Jhi || m > (h->dim == 2 ? h->rows_ws : total_rows(h)) || ldJ > h->ldJ)
             return fail(h, GN_EINVAL, "split-precision gram needs m <= N + 1 and ldJ <= the workspace ld%s");
         GN_HIP(h, launch_split(h->stream, d_J, m, p, ldJ, h->Jhi, h->Jlo));
         GN_HIP(h, launch_split_gram(h->stream, h->Jhi, h->Jlo, m, p, ldJ, d_G, ldG));
@@ -748,7 +875,7 @@ namespace {
 gn_status form_system(gn_handle h, const double *d_theta) {
     hipStream_t st = h->stream;
     h->r1_factored = false;  // the Gram overwrites the stochastic step's factor
-    const int64_t P = h->md.P, m_rows = h->n + 1;
+    const int64_t P = h->md.P, m_rows = total_rows(h);
     double *J = h->J;
     const int64_t ldJ = h->ldJ;
     mark(h, 0);
@@ -788,7 +915,7 @@ gn_status form_jacobian(gn_handle h, const double *d_theta) {
     hipStream_t st = h->stream;
     GN_HIP(h, launch_reset_status(st, h->status));
     GN_TRY(build_step_jacobian(h, d_theta, false));
-    GN_HIP(h, launch_sumsq(st, h->J + h->md.P, h->n + 1, h->ldJ, &h->status->half_sq_norm, h->red_work));
+    GN_HIP(h, launch_sumsq(st, h->J + h->md.P, total_rows(h), h->ldJ, &h->status->half_sq_norm, h->red_work));
     return GN_OK;
 }
 
@@ -819,7 +946,7 @@ gn_status trial_objective(gn_handle h, const double *theta) {
     } else {
         GN_TRY(forward_all(h, theta));
         GN_TRY(residual_rows(h, h->r_tmp, 1, false));
-        GN_HIP(h, launch_sumsq(st, h->r_tmp, h->n + 1, 1, &h->status->half_sq_trial, h->red_work));
+        GN_HIP(h, launch_sumsq(st, h->r_tmp, total_rows(h), 1, &h->status->half_sq_trial, h->red_work));
     }
     return GN_OK;
 }
@@ -922,7 +1049,7 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
                         const double *d_v, const gn_rank1_args *a, gn_rank1_stats *h_stats) {
     if (!h || !d_theta || !d_G_ema || !d_prev || !d_v || !a) return GN_EINVAL;
     if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
-    const int64_t P = h->md.P, m_rows = h->n + 1;
+    const int64_t P = h->md.P, m_rows = total_rows(h);
     if (h->dim != 1) return fail(h, GN_EINVAL, "the stochastic step takes 1D problems%s");
     if (ldG < P) return fail(h, GN_EINVAL, "ldG < P%s");
     if (P > 65535) return fail(h, GN_EINVAL, "P above 65535%s");
@@ -1002,6 +1129,25 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     return GN_OK;
 }
 
+gn_status gn_lambda_estimate(gn_handle h, const double *d_theta, double *h_lam, double *h_dU0) {
+    if (!h || !d_theta || !h_lam) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (h->dim != 1 || h->equation != GN_EQ_CCF1D)
+        return fail(h, GN_EINVAL, "lambda inference is defined for the 1D CCF problem%s");
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_transpose_weights(st, h->md, d_theta, h->thetaT));
+    SweepBatch b{};
+    b.x = h->nodes.q; b.n = h->m; b.nn = h->nn_nodes;
+    GN_HIP(h, launch_mlp_forward(st, h->md, d_theta, h->thetaT, b));
+    GN_HIP(h, launch_lambda_estimate(st, h->m, h->nodes, h->nn_nodes, h->r1_dots));
+    double out[2];
+    GN_HIP(h, hipMemcpyAsync(out, h->r1_dots, sizeof out, hipMemcpyDeviceToHost, st));
+    GN_HIP(h, hipStreamSynchronize(st));
+    *h_lam = out[0];
+    if (h_dU0) *h_dU0 = out[1];
+    return GN_OK;
+}
+
 gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats) {
     if (!h || !d_theta || !h_stats) return GN_EINVAL;
     if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
@@ -1015,7 +1161,7 @@ gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats) {
     } else {
         GN_TRY(forward_all(h, d_theta));
         GN_TRY(residual_rows(h, h->r_tmp, 1, false));
-        GN_HIP(h, launch_sumsq(st, h->r_tmp, h->n + 1, 1, &h->status->half_sq_norm, h->red_work));
+        GN_HIP(h, launch_sumsq(st, h->r_tmp, total_rows(h), 1, &h->status->half_sq_norm, h->red_work));
         GN_TRY(validation(h, d_theta));
     }
     DevStatus ds;
@@ -1054,8 +1200,8 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
     SweepBatch b{};
     b.x = h->pts.q; b.s0 = h->vseed0; b.s1 = h->vseed1; b.n = h->n;
     GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, b, h->partial, &c0));
-    // normalisation row: seed v_N sqrt(c_norm)
-    GN_HIP(h, launch_copy_strided(st, d_v + h->n, 1, 1, h->seed_one, 1, sqrt(h->c_norm)));
+    // normalisation row: seed v_last sqrt(c_norm)
+    GN_HIP(h, launch_copy_strided(st, d_v + norm_row(h), 1, 1, h->seed_one, 1, sqrt(h->c_norm)));
     SweepBatch o{};
     o.x = h->one_x; o.s0 = h->seed_one; o.s1c = 0.0; o.n = 1;
     GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, o, h->partial + c0 * P, &c1));
@@ -1067,7 +1213,26 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
         nb.x = h->nodes.q; nb.s0 = h->useed; nb.s1c = 0.0; nb.n = h->m;
         GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, nb, h->partial + (c0 + c1) * P, &c2));
     }
-    GN_HIP(h, launch_reduce_partials(st, h->partial, c0 + c1 + c2, P, d_out, 0));
+    int64_t c3 = 0, c4 = 0;
+    const int64_t nd = h->nd1 + h->nd2;
+    if (nd > 0) {
+        // derivative rows: seeds scaled by v, then the adjoint of their coupling
+        const double *vd = d_v + h->n;
+        GN_HIP(h, launch_scale_seeds(st, nd, vd, h->dseed, h->dvseed));
+        Sweep3 d{};
+        d.x = h->geo3.q; d.seed = h->dvseed; d.seed_ld = nd; d.n = nd;
+        GN_HIP(h, launch_jet3_vjp(st, h->md, d_theta, h->thetaT, d, h->partial + (c0 + c1 + c2) * P, &c3));
+        if (h->equation == GN_EQ_CCF1D) {
+            const int64_t m = h->m;
+            GN_HIP(h, launch_deriv_coupling(st, nd, m, h->geo3.y, h->nodes.y, h->nodes.wh, h->dcoef, h->dAT, h->ldA));
+            GN_HIP(h, launch_deriv_coupling_adjoint(st, nd, m, h->dAT, h->ldA, vd, h->nodes.E, h->bseed, 2 * m,
+                                                    h->nvseed, m));
+            Sweep3 nb{};
+            nb.x = h->geo3n.q; nb.seed = h->nvseed; nb.seed_ld = m; nb.n = m;
+            GN_HIP(h, launch_jet3_vjp(st, h->md, d_theta, h->thetaT, nb, h->partial + (c0 + c1 + c2 + c3) * P, &c4));
+        }
+    }
+    GN_HIP(h, launch_reduce_partials(st, h->partial, c0 + c1 + c2 + c3 + c4, P, d_out, 0));
     return GN_OK;
 }
 
@@ -1085,6 +1250,7 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     for (int i = 0; i < n; ++i) {
         if (!hs[i] || hs[i]->dim != 1) return GN_EINVAL;
         if (hs[i]->n <= 0) return GN_ESTATE;
+        if (hs[i]->nd1 + hs[i]->nd2 > 0) return GN_EINVAL;  // derivative rows are not batched
         if (hs[i]->md.P != hs[0]->md.P || hs[i]->precision != GN_FP64) return GN_EINVAL;
     }
     gn_batch b = new (std::nothrow) gn_batch_context();
@@ -1155,7 +1321,7 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
         gn_status e = GN_OK;
         if (launch_reset_status(st, h->status) != hipSuccess) e = GN_EDEVICE;
         if (e == GN_OK) e = build_step_jacobian(h, d_thetas[i], false, false);
-        if (e == GN_OK && launch_sumsq(st, h->J + P, h->n + 1, h->ldJ, &h->status->half_sq_norm, h->red_work) != hipSuccess)
+        if (e == GN_OK && launch_sumsq(st, h->J + P, total_rows(h), h->ldJ, &h->status->half_sq_norm, h->red_work) != hipSuccess)
             e = GN_EDEVICE;
         h->stream = own;
         if (e != GN_OK) return e;

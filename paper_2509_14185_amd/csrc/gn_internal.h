@@ -236,6 +236,63 @@ hipError_t launch_tri_save(hipStream_t st, double *A, int64_t n, int64_t lda, do
 hipError_t launch_tri_restore(hipStream_t st, double *A, int64_t n, int64_t lda, const double *diag);
 hipError_t launch_mul(hipStream_t st, const double *a, const double *b, double *out, int64_t n, double scale);
 
+// ------------------------------------------------ 1D derivative (d1, d2) rows
+// Geometry to third order: y, then q^(k) and E^(k) (k = 0..3, y-derivatives)
+// at q[k * ld + i], E[k * ld + i].
+struct Geo3 {
+    double *y;
+    double *q;
+    double *E;
+    int64_t ld;
+};
+hipError_t launch_geometry3(hipStream_t st, int equation, double lam, int64_t n, const double *s, Geo3 g);
+
+// Third-order jet sweep of the 1D network in its input q: forward outputs
+// nn[c * n + i] (NN^(c), q-derivatives), rows with seeds seed[c * seed_ld + i]
+// on them, or per-workgroup gradient partials.
+struct Sweep3 {
+    const double *x;
+    const double *seed;
+    int64_t seed_ld;
+    int64_t n;
+    double *rows;
+    int64_t ld;
+    double *nn;
+};
+hipError_t launch_jet3_forward(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT, Sweep3 b);
+hipError_t launch_jet3_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT, Sweep3 b);
+int64_t jet3_vjp_partials(int64_t n);
+hipError_t launch_jet3_vjp(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT, Sweep3 b,
+                           double *partial, int64_t *n_partials);
+// Theta, Theta', Theta'' at the nodes (out[k * m + j]) from their NN jets.
+hipError_t launch_node_fields(hipStream_t st, int64_t m, const double *nn, Geo3 g, double *out);
+// Seeds of B1_j = t_j dTheta'(t_j)/dtheta (columns 0..m-1) and B2_j = dTheta''(t_j)/dtheta (m..2m-1).
+hipError_t launch_node_seeds(hipStream_t st, int64_t m, Geo3 g, const double *t, double *seed, int64_t ld);
+
+struct DerivArgs {
+    int equation;
+    double lam;
+    int64_t n1, n2, m;             // d1 points, d2 points, Hilbert nodes
+    Geo3 geo;                      // geometry of the n1 + n2 points
+    const double *nn;              // NN^(c) at the points, [c * (n1 + n2) + i]
+    const double *nodes_y, *nodes_wh, *node_fields;
+    double scale1, scale2;         // sqrt(c_d1 / n1), sqrt(c_d2 / n2)
+    double *r;                     // scaled rows (stride r_stride), may be null
+    int64_t r_stride;
+    double *seed;                  // seeds on NN^(c) per row [c * nd + i], may be null
+    double *coef;                  // coupling coefficients [k * nd + i], k: B, B1, B2, may be null
+};
+hipError_t launch_deriv_residual(hipStream_t st, const DerivArgs &a);
+// AT (3m x ld, node-major) of the derivative rows' coupling product.
+hipError_t launch_deriv_coupling(hipStream_t st, int64_t nd, int64_t m, const double *y, const double *t,
+                                 const double *wh, const double *coef, double *AT, int64_t ld);
+hipError_t launch_deriv_coupling_adjoint(hipStream_t st, int64_t nd, int64_t m, const double *AT, int64_t ld,
+                                         const double *v, const double *nodeE, const double *bseed, int64_t sld,
+                                         double *out, int64_t old);
+hipError_t launch_scale_seeds(hipStream_t st, int64_t n, const double *v, const double *seed, double *out);
+// out[0] = -2 (1 + U'(0)), out[1] = U'(0) from NN, NN_q at the nodes (nn: 2m).
+hipError_t launch_lambda_estimate(hipStream_t st, int64_t m, Geo1D nodes, const double *nn, double *out);
+
 // ------------------------------------------- stochastic full-matrix GN step
 // Lower triangle of G <- beta G + (1 - beta) u u^T (p <= 65535).
 hipError_t launch_ema_rank1(hipStream_t st, double *G, int64_t p, int64_t ldg, double beta, const double *u);

@@ -99,6 +99,8 @@ def load():
         "gn_set_stream": (ctypes.c_int, [_VP, _VP]),
         "gn_set_points": (ctypes.c_int, [_VP, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _I64, _VP]),
         "gn_set_points_2d": (ctypes.c_int, [_VP, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP]),
+        "gn_set_points_ex": (ctypes.c_int, [_VP, _I64, _VP, _VP, _VP, _I64, _VP, _VP, _I64, _VP, _I64, _VP, _I64, _VP,
+                                            _D, _D]),
         "gn_num_params": (_I64, [_VP]),
         "gn_num_rows": (_I64, [_VP]),
         "gn_residual": (ctypes.c_int, [_VP, _VP, _VP]),
@@ -110,6 +112,7 @@ def load():
         "gn_step_rank1": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP, ctypes.POINTER(_R1Args),
                                          ctypes.POINTER(_R1Stats)]),
         "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
+        "gn_lambda_estimate": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "gn_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
         "gn_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
         "gn_batch_destroy": (ctypes.c_int, [_VP]),
@@ -186,14 +189,24 @@ class Problem:
         return int(self.lib.gn_num_rows(self.h))
 
     # ------------------------------------------------------------ ABI calls
-    def set_points(self, s, rho=None, f=None, sq=None, wq=None, sval=None):
+    def set_points(self, s, rho=None, f=None, sq=None, wq=None, sval=None, s1=None, s2=None, c_d1=1.0, c_d2=1.0):
+        """1D point sets; s1 / s2 (optional) add d1 / d2 derivative rows
+        (gn_set_points_ex) with loss weights c_d1 / c_d2."""
         self._bind()
-        s, rho, f, sq, wq, sval = (_dev(x, self.device) for x in (s, rho, f, sq, wq, sval))
+        s, rho, f, sq, wq, sval, s1, s2 = (_dev(x, self.device) for x in (s, rho, f, sq, wq, sval, s1, s2))
         n = s.numel()
         mq = 0 if sq is None else sq.numel()
         nv = 0 if sval is None else sval.numel()
-        st = self.lib.gn_set_points(self.h, n, _ptr(s), _ptr(rho), _ptr(f), mq, _ptr(sq), _ptr(wq), nv, _ptr(sval))
-        self._check(st, "gn_set_points")
+        n1 = 0 if s1 is None else s1.numel()
+        n2 = 0 if s2 is None else s2.numel()
+        if n1 or n2:
+            st = self.lib.gn_set_points_ex(self.h, n, _ptr(s), _ptr(rho), _ptr(f), mq, _ptr(sq), _ptr(wq), nv,
+                                           _ptr(sval), n1, _ptr(s1), n2, _ptr(s2), float(c_d1), float(c_d2))
+            self._check(st, "gn_set_points_ex")
+        else:
+            st = self.lib.gn_set_points(self.h, n, _ptr(s), _ptr(rho), _ptr(f), mq, _ptr(sq), _ptr(wq), nv,
+                                        _ptr(sval))
+            self._check(st, "gn_set_points")
         self.n = n
 
     def set_points_2d(self, s, s1=None, se=None, sval=None):
@@ -293,6 +306,14 @@ class Problem:
         d = s.as_dict()
         d["rc"] = st
         return d
+
+    def lambda_estimate(self, theta):
+        """(lambda_hat, U'(0)) implied at the origin (gn_lambda_estimate, 1D CCF)."""
+        self._bind()
+        lam, du = _D(), _D()
+        self._check(self.lib.gn_lambda_estimate(self.h, _ptr(theta), ctypes.byref(lam), ctypes.byref(du)),
+                    "gn_lambda_estimate")
+        return lam.value, du.value
 
     def eval(self, theta):
         self._bind()

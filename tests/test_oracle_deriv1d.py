@@ -149,3 +149,20 @@ def test_step_with_derivative_rows_decreases_the_model():
     th, st = ogn.step(prob, inp["theta0"], 1e-3)
     r, J, d = st["r"], st["J"], st["delta"]
     assert float(np.sum((r + J @ d) ** 2)) < float(r @ r)
+
+
+def test_lambda_estimate_reads_the_odd_transform_at_the_origin():
+    # Theta = y^2/(1+y^2): H[Theta'] = d/dy (-y/(1+y^2)), which is -1 at 0, so lam_hat = 0;
+    # the same through the odd quadrature directly, and an affine check on the formula
+    sq, wq = workloads.quadrature_s(1024)
+    t, what = p1.hilbert_weights(sq, wq, LAM)
+    dth = lambda s: 2 * s / (1 + s * s) ** 2
+    U1_0 = d1.hilbert_odd(np.zeros(1), t, what, dth(t), np.zeros(1))[0]
+    assert U1_0 == pytest.approx(-1.0, abs=1e-9)
+    inp, prob = _small(p1.CCF)
+    lam_hat, u = d1.lambda_estimate(prob, inp["theta0"])
+    assert lam_hat == pytest.approx(-2.0 * (1.0 + u), rel=1e-15)
+    # U'(0) equals the limit of U'(y) from the d1 machinery at small y
+    F = d1.field_derivs(inp["theta0"], prob.widths, np.array([1e-7]), prob.lam, prob.equation)
+    _, U1, _ = d1.transform_derivs(prob, inp["theta0"], np.array([1e-7]), F)
+    assert U1[0] == pytest.approx(u, rel=1e-6, abs=1e-9)
