@@ -292,6 +292,13 @@ typedef struct {
 gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t ldG, double *d_prev,
                         const double *d_v, const gn_rank1_args *args, gn_rank1_stats *h_stats);
 
+/* Maximum d1 and d2 residuals on the validation grid (1D): *h_max_d1 =
+ * max |R'|, *h_max_d2 = max |R''| (raw, unscaled; R', R'' as for
+ * gn_set_points_ex).  Paper: Methods, "Validation Metrics for Solutions"
+ * (the maximum dn residual).  Synchronises.  Errors: GN_EINVAL (2D handle),
+ * GN_ESTATE (no points or no validation grid). */
+gn_status gn_eval_derivs(gn_handle h, const double *d_theta, double *h_max_d1, double *h_max_d2);
+
 /* Blow-up rate implied by the profile at the origin (1D CCF).  Paper:
  * Methods, "Identifying Admissible lambda Values" (lambda inference: the
  * derivatives of the self-similar equation at the origin must vanish).  For

@@ -70,6 +70,8 @@ struct gn_context {
     double *dAT = nullptr;             // coupling matrix of the derivative rows (3m x ldA)
     int64_t ldA = 0;
     double *nvseed = nullptr;          // node seeds of the coupling adjoint (4 x m)
+    Geo3 geo3v{};                      // validation grid (derivative maxima)
+    double *nn3v = nullptr;            // NN^(c) on the validation grid (4 x nv)
     // phase timing
     std::vector<hipEvent_t> events;   // max_steps x (GN_PHASE_COUNT + 1)
     int32_t prof_max = 0, prof_count = 0;
@@ -671,23 +673,30 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     if (s == GN_OK) s = dev_alloc(h, A, &h->J, m_rows * h->ldJ);
     // node Jacobians B (and B1, B2 for the derivative rows), stacked
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Bm, (nd > 0 ? 3 : 1) * m_quad * h->ldJ);
+    auto geo3 = [&](Geo3 &g, int64_t cnt) -> gn_status {
+        g.ld = cnt;
+        GN_TRY(dev_alloc(h, A, &g.y, cnt));
+        GN_TRY(dev_alloc(h, A, &g.q, 4 * cnt));
+        GN_TRY(dev_alloc(h, A, &g.E, 4 * cnt));
+        return GN_OK;
+    };
+    // third-order data of the nodes and the validation grid (derivative rows and maxima)
+    if (m_quad > 0) {
+        if (s == GN_OK) s = geo3(h->geo3n, m_quad);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->nn3n, 4 * m_quad);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->nfield, 3 * m_quad);
+    }
+    if (n_val > 0) {
+        if (s == GN_OK) s = geo3(h->geo3v, n_val);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->nn3v, 4 * n_val);
+    }
     if (nd > 0) {
-        auto geo3 = [&](Geo3 &g, int64_t cnt) -> gn_status {
-            g.ld = cnt;
-            GN_TRY(dev_alloc(h, A, &g.y, cnt));
-            GN_TRY(dev_alloc(h, A, &g.q, 4 * cnt));
-            GN_TRY(dev_alloc(h, A, &g.E, 4 * cnt));
-            return GN_OK;
-        };
         if (s == GN_OK) s = geo3(h->geo3, nd);
         if (s == GN_OK) s = dev_alloc(h, A, &h->nn3, 4 * nd);
         if (s == GN_OK) s = dev_alloc(h, A, &h->dseed, 4 * nd);
         if (s == GN_OK) s = dev_alloc(h, A, &h->dvseed, 4 * nd);
         if (s == GN_OK) s = dev_alloc(h, A, &h->dcoef, 3 * nd);
         if (m_quad > 0) {
-            if (s == GN_OK) s = geo3(h->geo3n, m_quad);
-            if (s == GN_OK) s = dev_alloc(h, A, &h->nn3n, 4 * m_quad);
-            if (s == GN_OK) s = dev_alloc(h, A, &h->nfield, 3 * m_quad);
             if (s == GN_OK) s = dev_alloc(h, A, &h->bseed, 8 * m_quad);
             if (s == GN_OK) s = dev_alloc(h, A, &h->dAT, 3 * m_quad * h->ldA);
             if (s == GN_OK) s = dev_alloc(h, A, &h->nvseed, 4 * m_quad);
@@ -711,15 +720,14 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
         GN_HIP(h, launch_hilbert_matrix(st, n, m_quad, h->pts.y, h->nodes.y, h->nodes.wh, h->Q, h->ldQ));
     }
     if (n_val > 0) GN_HIP(h, launch_geometry(st, h->equation, h->lam, n_val, d_sval, nullptr, h->val));
+    if (m_quad > 0) GN_HIP(h, launch_geometry3(st, h->equation, h->lam, m_quad, d_sq, h->geo3n));
+    if (n_val > 0) GN_HIP(h, launch_geometry3(st, h->equation, h->lam, n_val, d_sval, h->geo3v));
     if (nd > 0) {
         Geo3 g2 = h->geo3;  // the d2 points follow the d1 points
         g2.y += n1; g2.q += n1; g2.E += n1;
         GN_HIP(h, launch_geometry3(st, h->equation, h->lam, n1, d_s1, h->geo3));
         GN_HIP(h, launch_geometry3(st, h->equation, h->lam, n2, d_s2, g2));
-        if (m_quad > 0) {
-            GN_HIP(h, launch_geometry3(st, h->equation, h->lam, m_quad, d_sq, h->geo3n));
-            GN_HIP(h, launch_node_seeds(st, m_quad, h->geo3n, h->nodes.y, h->bseed, 2 * m_quad));
-        }
+        if (m_quad > 0) GN_HIP(h, launch_node_seeds(st, m_quad, h->geo3n, h->nodes.y, h->bseed, 2 * m_quad));
     }
     GN_HIP(h, hipStreamSynchronize(st));
     h->n = n;
@@ -1126,6 +1134,37 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     if (rc == GN_ENOTPD)
         return fail(h, rc, "G_ema + gamma I: pivot %s is not positive", std::to_string(ds.chol_info).c_str());
     if (rc == GN_ENONFINITE) return fail(h, rc, "non-finite residual or coefficients%s");
+    return GN_OK;
+}
+
+gn_status gn_eval_derivs(gn_handle h, const double *d_theta, double *h_max_d1, double *h_max_d2) {
+    if (!h || !d_theta || !h_max_d1 || !h_max_d2) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (h->dim != 1) return fail(h, GN_EINVAL, "derivative maxima are defined for 1D problems%s");
+    if (h->nv <= 0) return fail(h, GN_ESTATE, "no validation grid%s");
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_reset_status(st, h->status));
+    GN_HIP(h, launch_transpose_weights(st, h->md, d_theta, h->thetaT));
+    if (h->equation == GN_EQ_CCF1D) {
+        Sweep3 nb{};
+        nb.x = h->geo3n.q; nb.n = h->m; nb.nn = h->nn3n;
+        GN_HIP(h, launch_jet3_forward(st, h->md, d_theta, h->thetaT, nb));
+        GN_HIP(h, launch_node_fields(st, h->m, h->nn3n, h->geo3n, h->nfield));
+    }
+    Sweep3 v{};
+    v.x = h->geo3v.q; v.n = h->nv; v.nn = h->nn3v;
+    GN_HIP(h, launch_jet3_forward(st, h->md, d_theta, h->thetaT, v));
+    DerivArgs a = deriv_args(h);
+    a.geo = h->geo3v; a.nn = h->nn3v;
+    a.scale1 = a.scale2 = 1.0;
+    a.n1 = h->nv; a.n2 = 0; a.max_out = &h->status->max_d1_val;
+    GN_HIP(h, launch_deriv_residual(st, a));
+    a.n1 = 0; a.n2 = h->nv; a.max_out = &h->status->max_d2_val;
+    GN_HIP(h, launch_deriv_residual(st, a));
+    DevStatus ds;
+    GN_TRY(read_status(h, &ds));
+    *h_max_d1 = bits_to_double(ds.max_d1_val);
+    *h_max_d2 = bits_to_double(ds.max_d2_val);
     return GN_OK;
 }
 

@@ -45,6 +45,14 @@ struct SweepBatch {
     double *nn;    // forward outputs (2n: NN then NN_x), forward mode only
 };
 
+// max |v| into *p as the bit pattern of a non-negative double (such patterns
+// order as integers); NaN counts as +inf so that it is visible.
+__device__ __forceinline__ void atomic_max_abs(unsigned long long *p, double v) {
+    v = fabs(v);
+    if (!(v == v)) v = __builtin_inf();
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
 // Device-side status shared by the kernels of one step.
 struct DevStatus {
     unsigned long long max_R;      // bit pattern of max |R| (collocation); non-negative doubles order as integers
@@ -59,6 +67,8 @@ struct DevStatus {
     double model_sq_norm;
     double delta_sq_norm;          // |delta|^2 (damping retries)
     double half_sq_trial;          // |r|^2 at a trial theta + delta (damping retries)
+    unsigned long long max_d1_val; // max |R'| and max |R''| on the validation grid (bit patterns)
+    unsigned long long max_d2_val;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -281,6 +291,7 @@ struct DerivArgs {
     int64_t r_stride;
     double *seed;                  // seeds on NN^(c) per row [c * nd + i], may be null
     double *coef;                  // coupling coefficients [k * nd + i], k: B, B1, B2, may be null
+    unsigned long long *max_out;   // max |raw row| (bit pattern), may be null
 };
 hipError_t launch_deriv_residual(hipStream_t st, const DerivArgs &a);
 // AT (3m x ld, node-major) of the derivative rows' coupling product.

@@ -453,6 +453,7 @@ __global__ __launch_bounds__(256) void deriv_residual_kernel(DerivArgs a) {
     const bool second = i >= a.n1;
     const double R = second ? U2 * T[1] + (2.0 + lam + 2.0 * U1) * T[2] + V * T[3] : (1.0 + U1) * T[1] + V * T[2];
     const double sc = second ? a.scale2 : a.scale1;
+    if (a.max_out) atomic_max_abs(a.max_out, R);
     if (a.r) a.r[i * a.r_stride] = sc * R;
     if (!a.seed) return;
     // seeds on Theta^(k) at the point and the coupling coefficients of

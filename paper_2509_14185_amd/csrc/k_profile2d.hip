@@ -116,12 +116,6 @@ hipError_t launch_geometry2d(hipStream_t st, int64_t n, const double *s, int edg
 }
 
 // ------------------------------------------------------------ residual rows and seeds
-__device__ __forceinline__ void atomic_max_abs(unsigned long long *p, double v) {
-    v = fabs(v);
-    if (!(v == v)) v = __builtin_inf();  // NaN counts as +inf so it is visible
-    atomicMax(p, (unsigned long long)__double_as_longlong(v));
-}
-
 // Seeds on the network-output jets from seeds on the field jets
 // (Phi = E N by the product rule, transposed).
 __device__ __forceinline__ void field_to_output_seeds(const J6 &E, const double *sp, double *sn) {

@@ -898,6 +898,8 @@ __global__ void reset_status_kernel(DevStatus *s) {
         s->model_sq_norm = 0.0;
         s->delta_sq_norm = 0.0;
         s->half_sq_trial = 0.0;
+        s->max_d1_val = 0;
+        s->max_d2_val = 0;
     }
 }
 

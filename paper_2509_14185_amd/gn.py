@@ -113,6 +113,7 @@ def load():
                                          ctypes.POINTER(_R1Stats)]),
         "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
         "gn_lambda_estimate": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+        "gn_eval_derivs": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "gn_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
         "gn_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
         "gn_batch_destroy": (ctypes.c_int, [_VP]),
@@ -306,6 +307,13 @@ class Problem:
         d = s.as_dict()
         d["rc"] = st
         return d
+
+    def eval_derivs(self, theta):
+        """(max |R'|, max |R''|) on the validation grid (gn_eval_derivs, 1D)."""
+        self._bind()
+        a, b = _D(), _D()
+        self._check(self.lib.gn_eval_derivs(self.h, _ptr(theta), ctypes.byref(a), ctypes.byref(b)), "gn_eval_derivs")
+        return a.value, b.value
 
     def lambda_estimate(self, theta):
         """(lambda_hat, U'(0)) implied at the origin (gn_lambda_estimate, 1D CCF)."""

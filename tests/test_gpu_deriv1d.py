@@ -130,3 +130,11 @@ def test_lambda_estimate(case):
     ref_lam, ref_du = d1.lambda_estimate(po, case["theta"])
     assert du == pytest.approx(ref_du, rel=1e-12, abs=1e-15)
     assert lam == pytest.approx(ref_lam, rel=1e-12, abs=1e-15)
+
+
+def test_validation_derivative_maxima(case):
+    po, pg, theta = case["po"], case["pg"], case["theta"]
+    m1, m2 = pg.eval_derivs(dev(theta))
+    R1, R2 = d1.deriv_residuals(po, theta, po.sval, po.sval)
+    assert m1 == pytest.approx(np.max(np.abs(R1)), rel=1e-12)
+    assert m2 == pytest.approx(np.max(np.abs(R2)), rel=1e-12)
