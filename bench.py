@@ -211,6 +211,53 @@ def rank1_comparison(inp, steps, target, period=10, beta=0.95, gamma=1e-3):
     }
 
 
+def deriv_rows_bench(inp, steps, mu):
+    """The medium CCF workload with d1 and d2 rows (N/4 points each): steps/s,
+    phases, the Gram rate, and the validation maxima of R, R' and R'' before
+    and after, with the blow-up rate implied at the origin."""
+    import torch
+
+    import workloads
+    from paper_2509_14185_amd import gn
+
+    n1 = n2 = inp["n"] // 4
+    s1, s2 = workloads.derivative_points(n1, n2)
+    prob = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
+    prob.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"], s1=s1, s2=s2)
+    P, m = prob.P, prob.m
+    theta = torch.from_numpy(inp["theta0"].copy()).cuda()
+    ev0, dv0 = prob.eval(theta), prob.eval_derivs(theta)
+    prob.step(theta.clone(), mu, stats=False)  # warm-up on a copy
+    torch.cuda.synchronize()
+    prob.profile_enable(True, steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.step(theta, mu, stats=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phases, nrec = prob.profile_read()
+    prob.profile_enable(False)
+    ev1, dv1 = prob.eval(theta), prob.eval_derivs(theta)
+    lam_hat, du0 = prob.lambda_estimate(theta)
+    prob.close()
+    t_gram = phases["gram"] / nrec * 1e-3
+    return {
+        "value": steps / el,
+        "unit": "steps/s",
+        "ms_per_step": 1e3 * el / steps,
+        "rows": m,
+        "d1_points": n1,
+        "d2_points": n2,
+        "gram_tflops": float(m) * (P + 1) * (P + 2) / t_gram / 1e12,
+        "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
+        "max_abs_R_val": [ev0["max_abs_R_val"], ev1["max_abs_R_val"]],
+        "max_abs_dR_val": [dv0[0], dv1[0]],
+        "max_abs_d2R_val": [dv0[1], dv1[1]],
+        "lambda_hat_final": lam_hat,
+        "lambda": inp["lam"],
+    }
+
+
 def batched_comparison(steps):
     """Batched CCF workload (independent instances with their own lambda and
     point count, shared widths): batched steps (gn_step_batched) against the
@@ -418,6 +465,7 @@ def main():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D IPM-style workload")
     ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt runs")
     ap.add_argument("--no-rank1", action="store_true", help="skip the stochastic (rank-1 estimate) run")
+    ap.add_argument("--no-deriv", action="store_true", help="skip the run with d1/d2 rows")
     ap.add_argument("--damping", default="fixed", choices=["fixed", "lm"],
                     help="damping of the steps for --workload ipm2d / bouss2d")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split32"],
@@ -532,6 +580,9 @@ def main():
     if not args.no_lm:
         print("[bench] Levenberg-Marquardt damping", file=sys.stderr, flush=True)
         out["lm"] = lm_comparison(inp, mu, args.steps, ev1["max_abs_R_val"])
+    if not args.no_deriv:
+        print("[bench] d1/d2 rows", file=sys.stderr, flush=True)
+        out["d12"] = deriv_rows_bench(inp, 10, mu)
     if not args.no_rank1:
         print("[bench] stochastic full-matrix GN (rank-1 estimates)", file=sys.stderr, flush=True)
         out["rank1"] = rank1_comparison(inp, 3 * args.steps, ev1["max_abs_R_val"])

@@ -109,6 +109,15 @@ def perturbation(p: int, seed: int) -> np.ndarray:
     return v / np.linalg.norm(v)
 
 
+def derivative_points(n1: int, n2: int):
+    """Point batches of the d1 and d2 rows (1D): Chebyshev-clustered like the
+    d0 points of the medium workload, shifted by a quarter and three quarters
+    of a cell so the three batches are distinct."""
+    s1 = (1.0 - np.cos(np.pi * (np.arange(n1) + 0.25) / max(n1, 1))) / 2.0
+    s2 = (1.0 - np.cos(np.pi * (np.arange(n2) + 0.75) / max(n2, 1))) / 2.0
+    return s1, s2
+
+
 def rademacher(m: int, seed: int) -> np.ndarray:
     """m random signs +-1 (FP64), E[v v^T] = I: the probe vectors of the
     rank-1 curvature estimate, drawn here and passed to both sides."""
