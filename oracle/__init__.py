@@ -14,6 +14,8 @@ Contents:
 - deriv1d: d1 and d2 loss rows of the 1D problems (Taylor-mode field
   derivatives to third order, odd and even half-line Hilbert quadrature,
   complex-step Jacobian).
+- stage2: second stage of multi-stage training (equation linearised around a
+  fixed first stage, Fourier feature network, complex-step Jacobian).
 - dense (dense.c): compensated Gram and gradient, textbook Cholesky, forward
   and back substitution (plain C, built with gcc).
 - gn: the damped Gauss-Newton step composed from the two, and the step with
