@@ -96,6 +96,11 @@ typedef struct {
     double c_target;         /* target value of NN (output 0) at q = 1, beta = 0 (the origin) */
     int64_t row_chunk;       /* 2D: rows of J formed at a time in gn_step (0: all); the
                                 Gram is accumulated over the chunks (streamed J) */
+    int32_t n_fourier;       /* 1D: F > 0 feeds the network Fourier features [cos(b_k q),
+                                sin(b_k q)] of its input q (widths[0] = 2F <= GN_MAX_WIDTH),
+                                the second-stage network of the paper (Methods, "Multi-stage
+                                Training"); 0: the plain input q */
+    const double *fourier_b; /* host, F frequencies b_k (copied at gn_create) */
 } gn_problem;
 
 typedef struct {
@@ -291,6 +296,29 @@ typedef struct {
 
 gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t ldG, double *d_prev,
                         const double *d_v, const gn_rank1_args *args, gn_rank1_stats *h_stats);
+
+/* Fields of a 1D first stage at its collocation points (which = 0, n
+ * entries) or validation grid (which = 1, n_val entries): the raw residual
+ * R, V = (1+lam) y + U and Theta' (device outputs), for gn_set_stage1.
+ * Synchronises.  Errors: GN_EINVAL (2D or second-stage handle), GN_ESTATE. */
+gn_status gn_fields(gn_handle h, const double *d_theta, int32_t which, double *d_R, double *d_V, double *d_Ty);
+
+/* Make h (1D, without derivative rows) the second stage of multi-stage
+ * training around a fixed first stage.  Paper: Methods, "Multi-stage
+ * Training": the solution is Theta_1 + eps Theta_2 and, to first order in
+ * eps, Theta_2 solves the equation linearised around Theta_1.  The d0 rows
+ * become sqrt(rho_i/N) (R_1 + eps D[Theta_1] Theta_2) with
+ * D Phi = -lam Phi + V_1 Phi' + U[Phi] Theta_1' (U[Phi] = H Phi for CCF, Phi
+ * for the local variant), the validation max-norm uses the same expression;
+ * the normalisation row is unchanged (use c_target = 0: NN_2(q = 1) = 0 keeps
+ * the first stage's normalisation).  d_R1, d_V1, d_T1y: the first stage's R,
+ * V and Theta' at h's collocation points (n each, from gn_fields on a handle
+ * with the same points), d_R1v, d_V1v, d_T1yv at its validation grid (n_val
+ * each, required when n_val > 0); copied.  gn_set_points ends the second
+ * stage.  Errors: GN_EINVAL (2D, derivative rows, missing arrays, eps not
+ * finite), GN_ESTATE, GN_ENOMEM. */
+gn_status gn_set_stage1(gn_handle h, double eps, const double *d_R1, const double *d_V1, const double *d_T1y,
+                        const double *d_R1v, const double *d_V1v, const double *d_T1yv);
 
 /* Maximum d1 and d2 residuals on the validation grid (1D): *h_max_d1 =
  * max |R'|, *h_max_d2 = max |R''| (raw, unscaled; R', R'' as for

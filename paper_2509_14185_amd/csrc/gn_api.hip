@@ -70,6 +70,14 @@ struct gn_context {
     double *dAT = nullptr;             // coupling matrix of the derivative rows (3m x ldA)
     int64_t ldA = 0;
     double *nvseed = nullptr;          // node seeds of the coupling adjoint (4 x m)
+    // Fourier feature input (gn_problem.n_fourier > 0): features of q per point set
+    int nf = 0;
+    double *fb = nullptr;              // frequencies b_k (nf)
+    double *phi_one = nullptr, *phi_pts = nullptr, *phi_nodes = nullptr, *phi_val = nullptr;
+    // second stage (gn_set_stage1): first-stage R, V, Theta' at the points and the validation grid
+    bool stage2 = false;
+    double s1eps = 0.0;
+    double *s1R = nullptr, *s1V = nullptr, *s1T = nullptr, *s1Rv = nullptr, *s1Vv = nullptr, *s1Tv = nullptr;
     Geo3 geo3v{};                      // validation grid (derivative maxima)
     double *nn3v = nullptr;            // NN^(c) on the validation grid (4 x nv)
     // phase timing
@@ -130,6 +138,23 @@ bool points_ready(gn_handle h) { return h->n > 0; }
 int64_t norm_row(gn_handle h) { return h->n + h->nd1 + h->nd2; }
 int64_t total_rows(gn_handle h) { return h->dim == 2 ? h->map2.rows() : norm_row(h) + 1; }
 
+// Fourier feature input of a 1D sweep over a point set (no-op without features).
+void with_phi(gn_handle h, SweepBatch &b, const double *phi, int64_t ld) {
+    if (h->nf > 0) {
+        b.phi = phi;
+        b.phi_ld = ld;
+    }
+}
+
+// First-stage fields of a second-stage residual (no-op otherwise).
+void with_stage1(gn_handle h, ResidualArgs &a, bool validation_grid) {
+    if (!h->stage2) return;
+    a.R1 = validation_grid ? h->s1Rv : h->s1R;
+    a.V1 = validation_grid ? h->s1Vv : h->s1V;
+    a.T1y = validation_grid ? h->s1Tv : h->s1T;
+    a.eps = h->s1eps;
+}
+
 // Forward jets at the nodes (CCF), the collocation points and q = 1.
 gn_status forward_all(gn_handle h, const double *theta) {
     hipStream_t st = h->stream;
@@ -137,13 +162,16 @@ gn_status forward_all(gn_handle h, const double *theta) {
     if (h->equation == GN_EQ_CCF1D) {
         SweepBatch b{};
         b.x = h->nodes.q; b.n = h->m; b.nn = h->nn_nodes;
+        with_phi(h, b, h->phi_nodes, h->m);
         GN_HIP(h, launch_mlp_forward(st, h->md, theta, h->thetaT, b));
     }
     SweepBatch b{};
     b.x = h->pts.q; b.n = h->n; b.nn = h->nn_pts;
+    with_phi(h, b, h->phi_pts, h->n);
     GN_HIP(h, launch_mlp_forward(st, h->md, theta, h->thetaT, b));
     SweepBatch o{};
     o.x = h->one_x; o.n = 1; o.nn = h->nn_one;
+    with_phi(h, o, h->phi_one, 1);
     GN_HIP(h, launch_mlp_forward(st, h->md, theta, h->thetaT, o));
     if (h->nd1 + h->nd2 > 0) {
         // third-order jets at the derivative points (and Theta, Theta', Theta'' at the nodes)
@@ -182,6 +210,7 @@ gn_status residual_rows(gn_handle h, double *r, int64_t r_stride, bool seeds) {
     a.seed0 = seeds ? h->seed0 : nullptr; a.seed1 = seeds ? h->seed1 : nullptr;
     a.cscale = seeds ? h->cscale : nullptr;
     a.max_out = &h->status->max_R;
+    with_stage1(h, a, false);
     GN_HIP(h, launch_residual(h->stream, a));
     if (h->nd1 + h->nd2 > 0) {
         DerivArgs d = deriv_args(h);
@@ -228,6 +257,7 @@ gn_status validation(gn_handle h, const double *theta) {
     if (h->nv <= 0) return GN_OK;
     SweepBatch b{};
     b.x = h->val.q; b.n = h->nv; b.nn = h->nn_val;
+    with_phi(h, b, h->phi_val, h->nv);
     GN_HIP(h, launch_mlp_forward(h->stream, h->md, theta, h->thetaT, b));
     ResidualArgs a{};
     a.equation = h->equation; a.lam = h->lam; a.n = h->nv; a.m = h->m;
@@ -235,6 +265,7 @@ gn_status validation(gn_handle h, const double *theta) {
     a.nn = h->nn_val; a.nn_nodes = h->nn_nodes;
     a.inv_n = 1.0;
     a.max_out = &h->status->max_R_val;
+    with_stage1(h, a, true);
     GN_HIP(h, launch_residual(h->stream, a));
     return GN_OK;
 }
@@ -246,14 +277,17 @@ gn_status jacobian_into(gn_handle h, const double *theta, double *J, int64_t ldJ
     hipStream_t st = h->stream;
     SweepBatch b{};
     b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
+    with_phi(h, b, h->phi_pts, h->n);
     GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, b));
     SweepBatch o{};
     o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + norm_row(h) * ldJ; o.ld = ldJ;
+    with_phi(h, o, h->phi_one, 1);
     GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, o));
     if (h->equation == GN_EQ_CCF1D) {
         // B_j = dTheta(t_j)/dtheta = E_j dNN(t_j)/dtheta, then J[:N] += diag(sc Theta_y) Q B
         SweepBatch nb{};
         nb.x = h->nodes.q; nb.s0 = h->nodes.E; nb.s1c = 0.0; nb.n = h->m; nb.rows = h->Bm; nb.ld = h->ldJ;
+        with_phi(h, nb, h->phi_nodes, h->m);
         GN_HIP(h, launch_mlp_rows(st, h->md, theta, h->thetaT, nb));
         GemmDesc g{};
         g.M = h->n; g.N = h->md.P; g.K = h->m;
@@ -315,13 +349,16 @@ gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks, bo
     if (marks) mark(h, 1);
     SweepBatch b{};
     b.x = h->pts.q; b.s0 = h->seed0; b.s1 = h->seed1; b.n = h->n; b.rows = J; b.ld = ldJ;
+    with_phi(h, b, h->phi_pts, h->n);
     GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, b));
     SweepBatch o{};
     o.x = h->one_x; o.s0c = sqrt(h->c_norm); o.s1c = 0.0; o.n = 1; o.rows = J + norm_row(h) * ldJ; o.ld = ldJ;
+    with_phi(h, o, h->phi_one, 1);
     GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, o));
     if (h->equation == GN_EQ_CCF1D) {
         SweepBatch nb{};
         nb.x = h->nodes.q; nb.s0 = h->nodes.E; nb.s1c = 0.0; nb.n = h->m; nb.rows = h->Bm; nb.ld = ldJ;
+        with_phi(h, nb, h->phi_nodes, h->m);
         GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, nb));
     }
     if (marks) mark(h, 2);
@@ -506,10 +543,13 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
         for (int l = 1; l < L; ++l)
             if (prob->widths[l] < 1 || prob->widths[l] > GN_MAX_WIDTH_2D) return GN_EINVAL;
     } else {
-        if (prob->widths[0] != 1 || prob->widths[L] != 1) return GN_EINVAL;
+        const int nf = prob->n_fourier;
+        if (nf < 0 || (nf > 0 && (!prob->fourier_b || 2 * nf > GN_MAX_WIDTH))) return GN_EINVAL;
+        if (prob->widths[0] != (nf > 0 ? 2 * nf : 1) || prob->widths[L] != 1) return GN_EINVAL;
         for (int l = 1; l < L; ++l)
             if (prob->widths[l] < 1 || prob->widths[l] > GN_MAX_WIDTH) return GN_EINVAL;
     }
+    if (two_d && prob->n_fourier != 0) return GN_EINVAL;
     gn_handle h = new (std::nothrow) gn_context();
     if (!h) return GN_ENOMEM;
     h->equation = prob->equation;
@@ -557,16 +597,30 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->nn_one, 2);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->seed_one, 1);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->status, 1);
+    if (!two_d && prob->n_fourier > 0) {
+        h->nf = prob->n_fourier;
+        if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->fb, h->nf);
+        if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->phi_one, 4 * h->nf);
+    }
     if (s != GN_OK) {
         free_list(h->allocs);
         delete h;
         return s;
     }
     const double one = 1.0;
-    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_trail, hipEventDisableTiming) != hipSuccess ||
-        hipMemcpy(h->one_x, &one, sizeof one, hipMemcpyHostToDevice) != hipSuccess) {
+    bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&h->ev_trail, hipEventDisableTiming) == hipSuccess &&
+              hipMemcpy(h->one_x, &one, sizeof one, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && h->nf > 0) {
+        ok = hipMemcpy(h->fb, prob->fourier_b, sizeof(double) * h->nf, hipMemcpyHostToDevice) == hipSuccess &&
+             launch_fourier_features(nullptr, 1, h->one_x, h->nf, h->fb, h->phi_one, 1) == hipSuccess &&
+             hipStreamSynchronize(nullptr) == hipSuccess;
+    }
+    if (!ok) {
+        if (h->side) (void)hipStreamDestroy(h->side);
+        if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
+        if (h->ev_trail) (void)hipEventDestroy(h->ev_trail);
         free_list(h->allocs);
         delete h;
         return GN_EDEVICE;
@@ -622,12 +676,15 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     if (!(c_d1 >= 0.0) || !(c_d2 >= 0.0)) return fail(h, GN_EINVAL, "derivative loss weights must be >= 0%s");
     if (h->equation != GN_EQ_CCF1D) m_quad = 0;
     if (m_quad > 65535 && n1 + n2 > 0) return fail(h, GN_EINVAL, "at most 65535 nodes with derivative rows%s");
+    if (h->nf > 0 && n1 + n2 > 0) return fail(h, GN_EINVAL, "derivative rows take the plain network input%s");
     GN_HIP(h, hipStreamSynchronize(h->stream));
     free_list(h->pt_allocs);
     ++h->points_gen;
     h->r1_factored = false;
     h->n = h->m = h->nv = 0;
     h->nd1 = h->nd2 = 0;
+    h->stage2 = false;
+    h->s1R = h->s1V = h->s1T = h->s1Rv = h->s1Vv = h->s1Tv = nullptr;
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
     const int64_t nd = n1 + n2;
@@ -680,6 +737,11 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
         GN_TRY(dev_alloc(h, A, &g.E, 4 * cnt));
         return GN_OK;
     };
+    if (h->nf > 0) {
+        if (s == GN_OK) s = dev_alloc(h, A, &h->phi_pts, 4 * h->nf * n);
+        if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->phi_nodes, 4 * h->nf * m_quad);
+        if (s == GN_OK && n_val > 0) s = dev_alloc(h, A, &h->phi_val, 4 * h->nf * n_val);
+    }
     // third-order data of the nodes and the validation grid (derivative rows and maxima)
     if (m_quad > 0) {
         if (s == GN_OK) s = geo3(h->geo3n, m_quad);
@@ -720,6 +782,11 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
         GN_HIP(h, launch_hilbert_matrix(st, n, m_quad, h->pts.y, h->nodes.y, h->nodes.wh, h->Q, h->ldQ));
     }
     if (n_val > 0) GN_HIP(h, launch_geometry(st, h->equation, h->lam, n_val, d_sval, nullptr, h->val));
+    if (h->nf > 0) {
+        GN_HIP(h, launch_fourier_features(st, n, h->pts.q, h->nf, h->fb, h->phi_pts, n));
+        if (m_quad > 0) GN_HIP(h, launch_fourier_features(st, m_quad, h->nodes.q, h->nf, h->fb, h->phi_nodes, m_quad));
+        if (n_val > 0) GN_HIP(h, launch_fourier_features(st, n_val, h->val.q, h->nf, h->fb, h->phi_val, n_val));
+    }
     if (m_quad > 0) GN_HIP(h, launch_geometry3(st, h->equation, h->lam, m_quad, d_sq, h->geo3n));
     if (n_val > 0) GN_HIP(h, launch_geometry3(st, h->equation, h->lam, n_val, d_sval, h->geo3v));
     if (nd > 0) {
@@ -1137,10 +1204,77 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     return GN_OK;
 }
 
+gn_status gn_fields(gn_handle h, const double *d_theta, int32_t which, double *d_R, double *d_V, double *d_Ty) {
+    if (!h || !d_theta || !d_R || !d_V || !d_Ty || (which != 0 && which != 1)) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (h->dim != 1 || h->stage2) return fail(h, GN_EINVAL, "fields are exported by 1D first-stage handles%s");
+    if (which == 1 && h->nv <= 0) return fail(h, GN_ESTATE, "no validation grid%s");
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_reset_status(st, h->status));
+    GN_TRY(forward_all(h, d_theta));
+    if (which == 1) {
+        SweepBatch b{};
+        b.x = h->val.q; b.n = h->nv; b.nn = h->nn_val;
+        with_phi(h, b, h->phi_val, h->nv);
+        GN_HIP(h, launch_mlp_forward(st, h->md, d_theta, h->thetaT, b));
+    }
+    ResidualArgs a{};
+    a.equation = h->equation; a.lam = h->lam; a.m = h->m;
+    a.nodes = h->nodes; a.nn_nodes = h->nn_nodes;
+    a.n = which ? h->nv : h->n;
+    a.pts = which ? h->val : h->pts;
+    a.nn = which ? h->nn_val : h->nn_pts;
+    a.inv_n = 1.0;
+    a.R = d_R; a.V_out = d_V; a.Ty_out = d_Ty;
+    a.max_out = &h->status->max_R;
+    GN_HIP(h, launch_residual(st, a));
+    GN_HIP(h, hipStreamSynchronize(st));
+    return GN_OK;
+}
+
+gn_status gn_set_stage1(gn_handle h, double eps, const double *d_R1, const double *d_V1, const double *d_T1y,
+                        const double *d_R1v, const double *d_V1v, const double *d_T1yv) {
+    if (!h || !d_R1 || !d_V1 || !d_T1y) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (h->dim != 1 || h->nd1 + h->nd2 > 0) return fail(h, GN_EINVAL, "second stages take 1D d0 problems%s");
+    if (!std::isfinite(eps)) return fail(h, GN_EINVAL, "eps must be finite%s");
+    if (h->nv > 0 && (!d_R1v || !d_V1v || !d_T1yv)) return fail(h, GN_EINVAL, "validation-grid fields needed%s");
+    auto &A = h->pt_allocs;
+    const int64_t n = h->n, nv = h->nv;
+    if (!h->s1R) {
+        gn_status s = GN_OK;
+        if (s == GN_OK) s = dev_alloc(h, A, &h->s1R, n);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->s1V, n);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->s1T, n);
+        if (s == GN_OK && nv > 0) s = dev_alloc(h, A, &h->s1Rv, nv);
+        if (s == GN_OK && nv > 0) s = dev_alloc(h, A, &h->s1Vv, nv);
+        if (s == GN_OK && nv > 0) s = dev_alloc(h, A, &h->s1Tv, nv);
+        if (s != GN_OK) {
+            h->s1R = nullptr;
+            return s;
+        }
+    }
+    hipStream_t st = h->stream;
+    const size_t bn = sizeof(double) * n, bv = sizeof(double) * nv;
+    GN_HIP(h, hipMemcpyAsync(h->s1R, d_R1, bn, hipMemcpyDeviceToDevice, st));
+    GN_HIP(h, hipMemcpyAsync(h->s1V, d_V1, bn, hipMemcpyDeviceToDevice, st));
+    GN_HIP(h, hipMemcpyAsync(h->s1T, d_T1y, bn, hipMemcpyDeviceToDevice, st));
+    if (nv > 0) {
+        GN_HIP(h, hipMemcpyAsync(h->s1Rv, d_R1v, bv, hipMemcpyDeviceToDevice, st));
+        GN_HIP(h, hipMemcpyAsync(h->s1Vv, d_V1v, bv, hipMemcpyDeviceToDevice, st));
+        GN_HIP(h, hipMemcpyAsync(h->s1Tv, d_T1yv, bv, hipMemcpyDeviceToDevice, st));
+    }
+    GN_HIP(h, hipStreamSynchronize(st));
+    h->s1eps = eps;
+    h->stage2 = true;
+    return GN_OK;
+}
+
 gn_status gn_eval_derivs(gn_handle h, const double *d_theta, double *h_max_d1, double *h_max_d2) {
     if (!h || !d_theta || !h_max_d1 || !h_max_d2) return GN_EINVAL;
     if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
-    if (h->dim != 1) return fail(h, GN_EINVAL, "derivative maxima are defined for 1D problems%s");
+    if (h->dim != 1 || h->nf > 0 || h->stage2)
+        return fail(h, GN_EINVAL, "derivative maxima are defined for 1D first-stage problems%s");
     if (h->nv <= 0) return fail(h, GN_ESTATE, "no validation grid%s");
     hipStream_t st = h->stream;
     GN_HIP(h, launch_reset_status(st, h->status));
@@ -1171,12 +1305,13 @@ gn_status gn_eval_derivs(gn_handle h, const double *d_theta, double *h_max_d1, d
 gn_status gn_lambda_estimate(gn_handle h, const double *d_theta, double *h_lam, double *h_dU0) {
     if (!h || !d_theta || !h_lam) return GN_EINVAL;
     if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
-    if (h->dim != 1 || h->equation != GN_EQ_CCF1D)
+    if (h->dim != 1 || h->equation != GN_EQ_CCF1D || h->stage2)
         return fail(h, GN_EINVAL, "lambda inference is defined for the 1D CCF problem%s");
     hipStream_t st = h->stream;
     GN_HIP(h, launch_transpose_weights(st, h->md, d_theta, h->thetaT));
     SweepBatch b{};
     b.x = h->nodes.q; b.n = h->m; b.nn = h->nn_nodes;
+    with_phi(h, b, h->phi_nodes, h->m);
     GN_HIP(h, launch_mlp_forward(st, h->md, d_theta, h->thetaT, b));
     GN_HIP(h, launch_lambda_estimate(st, h->m, h->nodes, h->nn_nodes, h->r1_dots));
     double out[2];
@@ -1238,11 +1373,13 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
     int64_t c0 = 0, c1 = 0, c2 = 0;
     SweepBatch b{};
     b.x = h->pts.q; b.s0 = h->vseed0; b.s1 = h->vseed1; b.n = h->n;
+    with_phi(h, b, h->phi_pts, h->n);
     GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, b, h->partial, &c0));
     // normalisation row: seed v_last sqrt(c_norm)
     GN_HIP(h, launch_copy_strided(st, d_v + norm_row(h), 1, 1, h->seed_one, 1, sqrt(h->c_norm)));
     SweepBatch o{};
     o.x = h->one_x; o.s0 = h->seed_one; o.s1c = 0.0; o.n = 1;
+    with_phi(h, o, h->phi_one, 1);
     GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, o, h->partial + c0 * P, &c1));
     if (h->equation == GN_EQ_CCF1D) {
         // Hilbert coupling adjoint: node seeds E_j sum_i Q_ij v_i sc_i Theta_y,i
@@ -1250,6 +1387,7 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
                                          nullptr));
         SweepBatch nb{};
         nb.x = h->nodes.q; nb.s0 = h->useed; nb.s1c = 0.0; nb.n = h->m;
+        with_phi(h, nb, h->phi_nodes, h->m);
         GN_HIP(h, launch_mlp_vjp(st, h->md, d_theta, h->thetaT, nb, h->partial + (c0 + c1) * P, &c2));
     }
     int64_t c3 = 0, c4 = 0;
@@ -1289,7 +1427,8 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     for (int i = 0; i < n; ++i) {
         if (!hs[i] || hs[i]->dim != 1) return GN_EINVAL;
         if (hs[i]->n <= 0) return GN_ESTATE;
-        if (hs[i]->nd1 + hs[i]->nd2 > 0) return GN_EINVAL;  // derivative rows are not batched
+        // derivative rows, Fourier inputs and second stages are not batched
+        if (hs[i]->nd1 + hs[i]->nd2 > 0 || hs[i]->nf > 0 || hs[i]->stage2) return GN_EINVAL;
         if (hs[i]->md.P != hs[0]->md.P || hs[i]->precision != GN_FP64) return GN_EINVAL;
     }
     gn_batch b = new (std::nothrow) gn_batch_context();

@@ -43,6 +43,8 @@ struct SweepBatch {
     double *rows;
     int64_t ld;
     double *nn;    // forward outputs (2n: NN then NN_x), forward mode only
+    const double *phi;  // Fourier feature input (rows 0..w0-1 phi, w0..2w0-1 phi_x, stride phi_ld), or null
+    int64_t phi_ld;
 };
 
 // max |v| into *p as the bit pattern of a non-negative double (such patterns
@@ -115,7 +117,15 @@ struct ResidualArgs {
     double *seed0, *seed1;   // Jacobian seeds on NN, NN_x (scaled), may be null
     double *cscale;          // sc_i * Theta_y,i (row scale of the Hilbert coupling), may be null
     unsigned long long *max_out;  // max |R| (bit pattern)
+    // second stage (all null otherwise): R = R1 + eps D[Theta_1] Theta with the
+    // first stage's R1, V1 = (1+lam) y + U_1 and Theta_1' at these points
+    const double *R1, *V1, *T1y;
+    double eps;
+    double *V_out, *Ty_out;       // V and Theta' of the field, may be null
 };
+// Fourier features (rows: cos, sin, d cos/dq, d sin/dq; F each) of q.
+hipError_t launch_fourier_features(hipStream_t st, int64_t n, const double *q, int F, const double *b, double *out,
+                                   int64_t ld);
 hipError_t launch_residual(hipStream_t st, const ResidualArgs &a);
 // Normalisation row: r = sqrt(c) (NN(1) - target), written to r_out.
 hipError_t launch_norm_row(hipStream_t st, const double *nn1, double sqrt_c, double target,

@@ -149,7 +149,14 @@ __global__ __launch_bounds__(SWEEP_THREADS) void mlp_sweep_kernel(MlpDesc d, Swe
         for (int idx = tid; idx < np * wout; idx += SWEEP_THREADS) {
             const int pt = idx / wout, k = idx - pt * wout;
             double z = bias[k], zx = 0.0;
-            if (l == 0) {
+            if (l == 0 && b.phi) {
+                // Fourier feature input: z = W phi + b, z_x = W phi_x
+                for (int j = 0; j < win; ++j) {
+                    const double w = Wt[j * wout + k];
+                    z = fma(w, b.phi[j * b.phi_ld + p0 + pt], z);
+                    zx = fma(w, b.phi[(win + j) * b.phi_ld + p0 + pt], zx);
+                }
+            } else if (l == 0) {
                 const double x = b.x[p0 + pt];
                 z = fma(Wt[k], x, z);
                 zx = Wt[k];
@@ -180,7 +187,12 @@ __global__ __launch_bounds__(SWEEP_THREADS) void mlp_sweep_kernel(MlpDesc d, Swe
         const int wave = tid >> 6, lane = tid & 63;
         for (int pt = wave; pt < np; pt += SWEEP_THREADS / 64) {
             double z = 0.0, zx = 0.0;
-            if (l == 0) {
+            if (l == 0 && b.phi) {
+                for (int j = lane; j < win; j += 64) {
+                    z = fma(W[j], b.phi[j * b.phi_ld + p0 + pt], z);
+                    zx = fma(W[j], b.phi[(win + j) * b.phi_ld + p0 + pt], zx);
+                }
+            } else if (l == 0) {
                 if (lane == 0) {
                     z = W[0] * b.x[p0 + pt];
                     zx = W[0];
@@ -224,13 +236,16 @@ __global__ __launch_bounds__(SWEEP_THREADS) void mlp_sweep_kernel(MlpDesc d, Swe
                 double *row = b.rows + (p0 + pt) * b.ld + d.off[l];
                 const double *zr = zb + pt * ldz;
                 const double *zxr = zbx + pt * ldz;
-                const double xin = (l == 0) ? b.x[p0 + pt] : 0.0;
+                const double xin = (l == 0 && !b.phi) ? b.x[p0 + pt] : 0.0;
                 for (int idx = tid; idx < nseg; idx += SWEEP_THREADS) {
                     double v;
                     if (idx < wout * win) {
                         const int k = idx / win, j = idx - k * win;
                         double h, hx;
-                        if (l == 0) {
+                        if (l == 0 && b.phi) {
+                            h = b.phi[j * b.phi_ld + p0 + pt];
+                            hx = b.phi[(win + j) * b.phi_ld + p0 + pt];
+                        } else if (l == 0) {
                             h = xin;
                             hx = 1.0;
                         } else {
@@ -252,7 +267,10 @@ __global__ __launch_bounds__(SWEEP_THREADS) void mlp_sweep_kernel(MlpDesc d, Swe
                     const int k = idx / win, j = idx - k * win;
                     for (int pt = 0; pt < np; ++pt) {
                         double h, hx;
-                        if (l == 0) {
+                        if (l == 0 && b.phi) {
+                            h = b.phi[j * b.phi_ld + p0 + pt];
+                            hx = b.phi[(win + j) * b.phi_ld + p0 + pt];
+                        } else if (l == 0) {
                             h = b.x[p0 + pt];
                             hx = 1.0;
                         } else {
@@ -356,6 +374,30 @@ hipError_t launch_mlp_vjp(hipStream_t st, const MlpDesc &d, const double *theta,
     return launch_sweep_mode<SWEEP_VJP>(st, d, theta, thetaT, b, partial);
 }
 
+// Fourier features of the network input q: rows k < F cos(b_k q), F <= k < 2F
+// sin(b_k q), then their q-derivatives in rows 2F .. 4F-1 (out[k * ld + i]).
+__global__ void fourier_features_kernel(int64_t n, const double *__restrict__ q, int F, const double *__restrict__ b,
+                                        double *__restrict__ out, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = q[i];
+    for (int k = 0; k < F; ++k) {
+        double sn, cs;
+        sincos(b[k] * x, &sn, &cs);
+        out[k * ld + i] = cs;
+        out[(F + k) * ld + i] = sn;
+        out[(2 * F + k) * ld + i] = -b[k] * sn;
+        out[(3 * F + k) * ld + i] = b[k] * cs;
+    }
+}
+
+hipError_t launch_fourier_features(hipStream_t st, int64_t n, const double *q, int F, const double *b, double *out,
+                                   int64_t ld) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fourier_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, q, F, b, out, ld);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ residual
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double v) {
     if (p == nullptr) return;
@@ -389,19 +431,25 @@ __global__ __launch_bounds__(256) void ccf_residual_kernel(ResidualArgs a) {
     const double NNq = a.nn[a.n + i];
     const double Eyi = a.pts.Ey[i], qyi = a.pts.qy[i];
     const double Thy = Eyi * NNi + Ei * qyi * NNq;
-    const double V = (1.0 + lam) * yi + U;
-    const double R = -lam * Thi + V * Thy;
+    // second stage: R_1 + eps D[Theta_1] Theta, D Phi = -lam Phi + V_1 Phi' + U[Phi] Theta_1'
+    const bool lin = a.R1 != nullptr;
+    const double V = lin ? a.V1[i] : (1.0 + lam) * yi + U;
+    const double Ty = lin ? a.T1y[i] : Thy;     // coefficient of U (and its seed)
+    const double g = lin ? a.eps : 1.0;
+    const double R = lin ? a.R1[i] + a.eps * (-lam * Thi + V * Thy + U * Ty) : -lam * Thi + V * Thy;
     if (a.R) a.R[i] = R;
+    if (a.V_out) a.V_out[i] = V;
+    if (a.Ty_out) a.Ty_out[i] = Thy;
     atomic_max_nonneg(a.max_out, fabs(R));
     if (a.r) {
         const double sc = sqrt((a.rho ? a.rho[i] : 1.0) * a.inv_n);
         a.r[i * a.r_stride] = sc * (R - (a.f ? a.f[i] : 0.0));
         if (a.seed0) {
             // dR/dNN_i (including U's dependence on Theta_i via -c_i E_i) and dR/dNN_q,i
-            a.seed0[i] = sc * (-lam * Ei + V * Eyi - Thy * c * Ei);
-            a.seed1[i] = sc * (V * Ei * qyi);
+            a.seed0[i] = sc * g * (-lam * Ei + V * Eyi - Ty * c * Ei);
+            a.seed1[i] = sc * g * (V * Ei * qyi);
         }
-        if (a.cscale) a.cscale[i] = sc * Thy;
+        if (a.cscale) a.cscale[i] = sc * g * Ty;
     }
 }
 
@@ -414,16 +462,22 @@ __global__ void burgers_residual_kernel(ResidualArgs a) {
     const double NNi = a.nn[i], NNq = a.nn[a.n + i];
     const double Th = Ei * NNi;
     const double Thy = Eyi * NNi + Ei * qyi * NNq;
-    const double V = (1.0 + lam) * yi + Th;
-    const double R = -lam * Th + V * Thy;
+    // second stage (U[Phi] = Phi): R_1 + eps (-lam Phi + V_1 Phi' + Phi Theta_1')
+    const bool lin = a.R1 != nullptr;
+    const double V = lin ? a.V1[i] : (1.0 + lam) * yi + Th;
+    const double Ty = lin ? a.T1y[i] : Thy;
+    const double g = lin ? a.eps : 1.0;
+    const double R = lin ? a.R1[i] + a.eps * (-lam * Th + V * Thy + Th * Ty) : -lam * Th + V * Thy;
     if (a.R) a.R[i] = R;
+    if (a.V_out) a.V_out[i] = V;
+    if (a.Ty_out) a.Ty_out[i] = Thy;
     atomic_max_nonneg(a.max_out, fabs(R));
     if (a.r) {
         const double sc = sqrt((a.rho ? a.rho[i] : 1.0) * a.inv_n);
         a.r[i * a.r_stride] = sc * (R - (a.f ? a.f[i] : 0.0));
         if (a.seed0) {
-            a.seed0[i] = sc * ((Thy - lam) * Ei + V * Eyi);
-            a.seed1[i] = sc * (V * Ei * qyi);
+            a.seed0[i] = sc * g * ((Ty - lam) * Ei + V * Eyi);
+            a.seed1[i] = sc * g * (V * Ei * qyi);
         }
         if (a.cscale) a.cscale[i] = 0.0;
     }

@@ -34,7 +34,8 @@ class GNError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [("equation", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_layers", ctypes.c_int32),
                 ("widths", ctypes.POINTER(ctypes.c_int32)), ("lam", ctypes.c_double),
-                ("c_norm", ctypes.c_double), ("c_target", ctypes.c_double), ("row_chunk", ctypes.c_int64)]
+                ("c_norm", ctypes.c_double), ("c_target", ctypes.c_double), ("row_chunk", ctypes.c_int64),
+                ("n_fourier", ctypes.c_int32), ("fourier_b", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Stats(ctypes.Structure):
@@ -114,6 +115,8 @@ def load():
         "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
         "gn_lambda_estimate": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "gn_eval_derivs": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+        "gn_fields": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
+        "gn_set_stage1": (ctypes.c_int, [_VP, _D, _VP, _VP, _VP, _VP, _VP, _VP]),
         "gn_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
         "gn_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
         "gn_batch_destroy": (ctypes.c_int, [_VP]),
@@ -147,15 +150,20 @@ class Problem:
     """One profile problem bound to a gn handle on the current CUDA (HIP) device."""
 
     def __init__(self, equation: str, widths, lam: float, c_norm: float = 1.0, c_target: float = 1.0,
-                 precision: str = "fp64", device: str = "cuda", row_chunk: int = 0):
+                 precision: str = "fp64", device: str = "cuda", row_chunk: int = 0, fourier_b=None):
+        """fourier_b: frequencies of Fourier input features (1D second stage;
+        widths[0] must be 2 len(fourier_b))."""
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the gn library runs only on the GPU")
         self.lib = load()
         self.device = torch.device(device)
         self.widths = [int(w) for w in widths]
         self._w = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        nf = 0 if fourier_b is None else len(fourier_b)
+        self._fb = (ctypes.c_double * max(nf, 1))(*([float(x) for x in fourier_b] if nf else [0.0]))
         prob = _Problem(EQUATIONS[equation], PRECISIONS[precision], len(self.widths) - 1, self._w,
-                        float(lam), float(c_norm), float(c_target), int(row_chunk))
+                        float(lam), float(c_norm), float(c_target), int(row_chunk), nf,
+                        ctypes.cast(self._fb, ctypes.POINTER(ctypes.c_double)) if nf else None)
         h = _VP()
         with torch.cuda.device(self.device):
             st = self.lib.gn_create(ctypes.byref(prob), ctypes.byref(h))
@@ -209,6 +217,7 @@ class Problem:
                                         _ptr(sval))
             self._check(st, "gn_set_points")
         self.n = n
+        self.nv = nv
 
     def set_points_2d(self, s, s1=None, se=None, sval=None):
         """2D point sets: s (n,2), s1 (n1,2) d1 points, se (ne,) y2 = 0 points, sval (nv,2)."""
@@ -307,6 +316,23 @@ class Problem:
         d = s.as_dict()
         d["rc"] = st
         return d
+
+    def fields(self, theta, which=0):
+        """(R, V, Theta') of this first stage at the collocation points (which = 0)
+        or the validation grid (which = 1), gn_fields."""
+        self._bind()
+        n = self.n if which == 0 else self.nv
+        R, V, T = (torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(3))
+        self._check(self.lib.gn_fields(self.h, _ptr(theta), int(which), _ptr(R), _ptr(V), _ptr(T)), "gn_fields")
+        return R, V, T
+
+    def set_stage1(self, eps, R, V, Ty, Rv=None, Vv=None, Tyv=None):
+        """Second stage around a fixed first stage (gn_set_stage1)."""
+        self._bind()
+        R, V, Ty, Rv, Vv, Tyv = (_dev(x, self.device) for x in (R, V, Ty, Rv, Vv, Tyv))
+        self._keep_stage1 = (R, V, Ty, Rv, Vv, Tyv)
+        self._check(self.lib.gn_set_stage1(self.h, float(eps), _ptr(R), _ptr(V), _ptr(Ty), _ptr(Rv), _ptr(Vv),
+                                           _ptr(Tyv)), "gn_set_stage1")
 
     def eval_derivs(self, theta):
         """(max |R'|, max |R''|) on the validation grid (gn_eval_derivs, 1D)."""
