@@ -343,15 +343,17 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
             prob.step(theta, mu, stats=False)
     torch.cuda.synchronize()
     prob.profile_enable(True, steps)
-    trace, tries, mu_k = [], 0, mu
+    trace, tries, mu_k, failed = [], 0, mu, 0
     t0 = time.perf_counter()
     for k in range(steps):
+        # every step reports its status (one synchronisation per step; 2D steps are long)
         if lm:
             st = prob.step_lm(theta, mu_k)
             mu_k, tries = st["mu"], tries + st["tries"]
             trace.append(st["half_sq_norm_new"])
         else:
-            prob.step(theta, mu, stats=False)
+            st = prob.step(theta, mu)
+        failed += int(st["rc"] != gn.GN_OK)
         if steps > 3:
             continue
         torch.cuda.synchronize()
@@ -396,6 +398,7 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
             "half_sq_norm_initial": ev0["half_sq_norm"],
             "half_sq_norm_final": ev1["half_sq_norm"],
             "damping": damping,
+            "failed_steps": failed,
         },
         "gram_tflops": fl_gram / t_gram / 1e12,
         "gram_frac": fl_gram / t_gram / 1e12 / PEAK_FP64_TFLOPS,

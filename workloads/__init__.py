@@ -37,7 +37,9 @@ WORKLOADS = {
 # supplementary material): blow-up rates of the first unstable profiles
 # (paper, main text, table of lambda_n fits, n = 1).  Damping mu = 0.1: with
 # 1e-3 the fixed-damping step from the Glorot start overshoots on these
-# stand-ins (the objective rises); 0.1 decreases it monotonically.
+# stand-ins (the objective rises).  0.1 decreases it on the IPM-style
+# workload; the Boussinesq-type one still overshoots at 0.1, so its steps
+# want Levenberg-Marquardt damping.
 LAM_IPM1 = 0.4721
 LAM_BOUSS1 = 1.3992
 
