@@ -49,7 +49,7 @@ __global__ void add_diag_kernel(double *A, int64_t n, int64_t lda, double mu) {
 // the padding column (X(i,c) at s[c*LDS_LD + i + 1], i >= c), so both fit in
 // one 128 x 129 tile.  Rows >= kb are identity padding.  Work is blocked by
 // IB = 32: a one-wave register factorisation of each 32x32 diagonal block
-// (one non-inlined copy, small enough to stay in the instruction cache),
+// (inlined: the leaf loop is not unrolled, so the kernel holds one copy),
 // then loops over the panel and trailing part with all 256 threads.
 static constexpr int IB = 32;
 #define LL(i, c) s[(i) * LDS_LD + (c)]
@@ -97,24 +97,36 @@ __device__ __forceinline__ double4_t lds_mfma(double4_t acc, FA a_at, FB b_at, i
 __device__ __forceinline__ double sel(bool keep, double v) { return keep ? v : 0.0; }
 
 // One wave, lanes 0..31: lane i holds row o+i of the 32x32 diagonal block in
-// registers.  Pivot j: the pivot is read from lane j, every lane scales its
-// entry of column j and stores it to an LDS column buffer (two buffers by
-// parity of j), and every lane reads the column back as broadcasts for its
-// rank-1 update of row i (LDS operations of one wave complete in order, so
-// no barrier is involved).  Entries right of the diagonal are never read, so
-// they are updated without masking.  Row bi (local, or -1) is a border row
-// (updated, diagonal not square-rooted, excluded from X).
+// registers.  Columns are taken KS at a time: every lane reads the KS x KS
+// diagonal block from its lanes (readlane, uniform values) and factors it
+// redundantly (KS dependent reciprocal square roots), forms its own KS
+// entries by a forward substitution with that factor, stores them to an LDS
+// column buffer (two buffers by parity of the step) and reads the entries of
+// the rows below back as broadcasts for its rank-KS update.  One LDS round
+// trip per KS columns instead of one per column, and no branches: a failed
+// pivot is recorded and the step carries on with NaNs.  Entries right of the
+// diagonal are never read, so they are updated without masking.  Row bi
+// (local, or -1) is a border row: its diagonal is not square-rooted (its
+// reciprocal is taken as zero, so the column below it stays zero, as the rows
+// below are identity padding) and it is excluded from X.
 // Then X_oo = L_oo^{-1}: the two 16x16 diagonal blocks are inverted at once
 // (lane c owns column c, rows of L read as LDS broadcasts; a 16-step chain
 // instead of 32) and the off-diagonal block follows from two MFMA products,
 // X21 = -X22 (L21 X11), with t (16 x 17 doubles of LDS) holding L21 X11.
 // Returns -1 or the failing local pivot (uniform).
-__device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *cb, double *t) {
+static constexpr int KS = 4;
+__device__ __forceinline__ int potrf32_wave(double *s, int o, int bi, double *cb, double *t) {
     const int lane = threadIdx.x & 63;
     const bool act = lane < IB;
+    // lanes 32..63 repeat lanes 0..31 (same row, same arithmetic), so loads and
+    // stores need no exec mask
+    const int ln = lane & (IB - 1);
     double row[IB];
 #pragma unroll
-    for (int c = 0; c < IB; ++c) row[c] = (act && c <= lane) ? LL(o + lane, o + c) : 0.0;
+    for (int c = 0; c < IB; ++c) {
+        const double v = LL(o + ln, o + c);
+        row[c] = c <= ln ? v : 0.0;
+    }
     // rl[i]: 1 / l_ii of this lane's group of the inverse below (row g0 + i)
     constexpr int H = IB / 2;
     const int g0 = (lane & H);  // 0 or 16
@@ -123,38 +135,78 @@ __device__ __noinline__ int potrf32_wave(double *s, int o, int bi, double *cb, d
     for (int i = 0; i < H; ++i) rl[i] = 0.0;
     int fail = -1;
 #pragma unroll
-    for (int j = 0; j < IB; ++j) {
-        if (fail < 0 && j != bi) {
-            const double d = readlane_d(row[j], j);
-            if (!(d > 0.0)) {
-                fail = j;
-            } else {
-                const double r = rsqrt_refined(d);
-                if (g0 == (j & H)) rl[j & (H - 1)] = r;
-                const double l = row[j] * r;
-                double *col = cb + (j & 1) * IB;
-                if (act && lane > j) col[lane] = l;
-                // the whole column in flight at once, then the updates
-                const int c0 = (j + 1) & ~1;
-                double2 cv[IB / 2];
+    for (int j = 0; j < IB; j += KS) {
+        // KS x KS diagonal block (lower part), uniform
+        double a[KS][KS];
 #pragma unroll
-                for (int q = 0; q < (IB - c0) / 2; ++q) cv[q] = reinterpret_cast<const double2 *>(col + c0)[q];
+        for (int p = 0; p < KS; ++p)
+#pragma unroll
+            for (int q = 0; q <= p; ++q) a[p][q] = readlane_d(row[j + q], j + p);
+        // its factor: ld[p][q] (q < p), rr[q] = 1 / sqrt of the q-th pivot
+        double ld[KS][KS], rr[KS];
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            double v = a[q][q];
+#pragma unroll
+            for (int k = 0; k < q; ++k) v = fma(-ld[q][k], ld[q][k], v);
+            const bool border = (j + q == bi);
+            fail = (fail < 0 && !border && !(v > 0.0)) ? j + q : fail;
+            const double y = rsqrt_refined(border ? 1.0 : v);  // selects, not a branch
+            rr[q] = border ? 0.0 : y;
+#pragma unroll
+            for (int p = q + 1; p < KS; ++p) {
+                double w = a[p][q];
+#pragma unroll
+                for (int k = 0; k < q; ++k) w = fma(-ld[p][k], ld[q][k], w);
+                ld[p][q] = w * rr[q];
+            }
+            if (g0 == ((j + q) & H)) rl[(j + q) & (H - 1)] = rr[q];
+        }
+        // this lane's entries of the KS columns (on lane j+q the substitution
+        // repeats the factor's arithmetic, so v = d[q] there; the border row
+        // keeps d[q] on its diagonal)
+        double l[KS];
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            double v = row[j + q];
+#pragma unroll
+            for (int k = 0; k < q; ++k) v = fma(-l[k], ld[q][k], v);
+            l[q] = (j + q == bi && ln == bi) ? v : v * rr[q];
+        }
+        if (j + KS < IB) {
+            // all 64 lanes store (lanes >= IB to their own slots), so no exec mask
+            double *col = cb + ((j / KS) & 1) * KS * 64;
+#pragma unroll
+            for (int q = 0; q < KS; ++q) col[q * 64 + lane] = l[q];
+            // row[c] -= sum_q l[q] l_c[q] for c >= j + KS, two columns c per LDS
+            // read, in chunks of CH columns (the reads of a chunk in flight together)
+            constexpr int CH = 8;
+#pragma unroll
+            for (int c0 = j + KS; c0 < IB; c0 += CH) {
+                double2 w[CH / 2][KS];
+#pragma unroll
+                for (int cc = 0; cc < CH && c0 + cc < IB; cc += 2)
+#pragma unroll
+                    for (int q = 0; q < KS; ++q)
+                        w[cc / 2][q] = *reinterpret_cast<const double2 *>(col + q * 64 + c0 + cc);
+#pragma unroll
+                for (int cc = 0; cc < CH && c0 + cc < IB; cc += 2)
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        row[c0 + cc] = fma(-l[q], w[cc / 2][q].x, row[c0 + cc]);
+                        row[c0 + cc + 1] = fma(-l[q], w[cc / 2][q].y, row[c0 + cc + 1]);
+                    }
                 __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int c = j + 1; c < IB; ++c) {
-                    const double2 w = cv[(c - c0) / 2];
-                    row[c] = fma(-l, ((c - c0) & 1) ? w.y : w.x, row[c]);
-                }
-                row[j] = (lane == j) ? d * r : l;
             }
         }
+#pragma unroll
+        for (int q = 0; q < KS; ++q) row[j + q] = l[q];
     }
     if (fail >= 0) return fail;
-    if (act) {
+    // the whole 32-wide row: right of the diagonal lies the storage of this
+    // block's columns of X, written below
 #pragma unroll
-        for (int c = 0; c < IB; ++c)
-            if (c <= lane) LL(o + lane, o + c) = row[c];
-    }
+    for (int c = 0; c < IB; ++c) LL(o + ln, o + c) = row[c];
     // diagonal 16x16 blocks of X: lane c (group g = c / 16) forms column c of
     // X_gg, X[16g+i][c] = (delta - sum_{k<i} L[16g+i][16g+k] X[16g+k][c]) / L[16g+i][16g+i]
     const int cl = lane & (H - 1);
@@ -247,19 +299,27 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
     if (status->flag) return;
     extern __shared__ double s[];
     __shared__ int fail_sh;
-    __shared__ __align__(16) double colbuf[2 * IB];
+    __shared__ __align__(16) double colbuf[2 * KS * 64];
     __shared__ double W[(CB / IB - 1) * IB * (IB + 1)];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over tiles stay scalar
     const int fr = lane & 15, fk = lane >> 4;
     const int bi = border_here ? kb - 1 : -1;
     {
-        // all 64 loads of a thread are issued before any LDS store
+        // all 64 loads of a thread are issued before any LDS store: every lane
+        // loads (indices clamped into the kb x kb block), selects afterwards,
+        // so no load sits behind a branch and a wait for the one before it
         double v[CB * CB / 256];
 #pragma unroll
         for (int e = 0; e < CB * CB / 256; ++e) {
             const int idx = tid + e * 256, r = idx / CB, c = idx % CB;
-            v[e] = (r < kb && c <= r) ? A[(k0 + r) * lda + k0 + c] : ((r >= kb && r == c) ? 1.0 : 0.0);
+            const int rc = r < kb ? r : kb - 1, cc = c < kb ? c : kb - 1;
+            v[e] = A[(k0 + rc) * lda + k0 + cc];
+        }
+#pragma unroll
+        for (int e = 0; e < CB * CB / 256; ++e) {
+            const int idx = tid + e * 256, r = idx / CB, c = idx % CB;
+            v[e] = (r < kb && c <= r) ? v[e] : ((r >= kb && r == c) ? 1.0 : 0.0);
         }
 #pragma unroll
         for (int e = 0; e < CB * CB / 256; ++e) {
@@ -342,13 +402,25 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
     x_blocks_at_distance<1>(s, W, wave);
     x_blocks_at_distance<2>(s, W, wave);
     x_blocks_at_distance<3>(s, W, wave);
-    // ---- write L (rows < kb) and X (zero outside the factor) to global memory
-#pragma unroll 8
-    for (int e = 0; e < CB * CB / 256; ++e) {
-        const int idx = tid + e * 256, r = idx / CB, c = idx % CB;
-        if (r < kb && c <= r) A[(k0 + r) * lda + k0 + c] = LL(r, c);
-        const bool valid = c <= r && r < kb && r != bi && c != bi;
-        X[idx] = valid ? XX(r, c) : 0.0;
+    // ---- write L (rows < kb) and X (zero outside the factor) to global memory,
+    //      16 elements a time: all LDS reads first, then the stores
+    constexpr int SG = 16;
+#pragma unroll 1
+    for (int e0 = 0; e0 < CB * CB / 256; e0 += SG) {
+        double lv[SG], xv[SG];
+#pragma unroll
+        for (int e = 0; e < SG; ++e) {
+            const int idx = tid + (e0 + e) * 256, r = idx / CB, c = idx % CB;
+            lv[e] = LL(r, c);
+            xv[e] = XX(r, c);
+        }
+#pragma unroll
+        for (int e = 0; e < SG; ++e) {
+            const int idx = tid + (e0 + e) * 256, r = idx / CB, c = idx % CB;
+            if (r < kb && c <= r) A[(k0 + r) * lda + k0 + c] = lv[e];
+            const bool valid = c <= r && r < kb && r != bi && c != bi;
+            X[idx] = valid ? xv[e] : 0.0;
+        }
     }
 }
 
