@@ -11,6 +11,9 @@
 // memory waits overlap the other's MFMAs) owns a BM x BN tile of C; each wave
 // owns (BM/2) x (BN/4) as 16x16 MFMA blocks held in registers.
 // K is consumed in chunks of BK = 32 staged through double-buffered LDS.
+// A second configuration uses 256-thread workgroups (2 x 2 waves of 64 x 64)
+// with BK = 16, so that two workgroups (64 KB of LDS each) share a CU and one
+// workgroup's barrier waits overlap the other's MFMAs.
 // Each operand keeps its global orientation in LDS ([k][m] when contiguous
 // along m, else [m][k] with a padded row), so staging is a straight 16-byte
 // copy without bank conflicts and an MFMA fragment read (16 consecutive m or
@@ -89,15 +92,15 @@ __device__ __forceinline__ bool tile_of_block(int64_t b, int lower, int tiles_m,
 // as 16-byte pairs along the operand's contiguous direction.
 //   CONTIG_MN: element (r, k) at base[k*ld + r] (pairs along r)
 //   else:      element (r, k) at base[r*ld + k] (pairs along k)
-template <int R, int BK, bool CONTIG_MN>
+template <int R, int BK, bool CONTIG_MN, int NT>
 struct TileLoader {
     static constexpr int PAIRS = R * BK / 2;
-    static constexpr int PER = PAIRS / GEMM_THREADS;
-    static_assert(PER * GEMM_THREADS == PAIRS, "tile split");
+    static constexpr int PER = PAIRS / NT;
+    static_assert(PER * NT == PAIRS, "tile split");
     double2 v[PER];
 
     __device__ __forceinline__ static void coords(int e, int &r, int &k) {
-        const int idx = threadIdx.x + e * GEMM_THREADS;
+        const int idx = threadIdx.x + e * NT;
         if (CONTIG_MN) { r = 2 * (idx % (R / 2)); k = idx / (R / 2); }
         else           { k = 2 * (idx % (BK / 2)); r = idx / (BK / 2); }
     }
@@ -145,8 +148,8 @@ struct TileLoader {
                                                   int wave) {
         static_assert(CONTIG_MN, "direct copies need the [k][r] layout");
         constexpr int ROWS = 128 / R;                          // k-rows per wave instruction
-        constexpr int PERW = BK / ROWS / (GEMM_THREADS / 64);  // instructions per wave
-        static_assert(PERW * ROWS * (GEMM_THREADS / 64) == BK, "chunk split");
+        constexpr int PERW = BK / ROWS / (NT / 64);  // instructions per wave
+        static_assert(PERW * ROWS * (NT / 64) == BK, "chunk split");
         const int lane = threadIdx.x & 63;
         const int kin = (2 * lane) / R, r = (2 * lane) % R;
 #pragma unroll
@@ -165,8 +168,8 @@ struct TileLoader {
     }
 };
 
-template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
-__global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0,
+template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT>
+__global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0,
                                                                  const GemmDesc *__restrict__ batch,
                                                                  const int4 *__restrict__ work) {
     // batched launches read (problem, tile row, tile column) from a work table
@@ -179,12 +182,12 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
     const GemmDesc g = BATCH ? batch[wi.x] : g0;
     if (g.M <= 0 || g.N <= 0) return;
     if (g.stop_flag != nullptr && *g.stop_flag != 0) return;
-    constexpr int WAVES_M = 2, WAVES_N = 4;
+    constexpr int WAVES_M = 2, WAVES_N = NT / 128;
     constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
     constexpr int FM = WM / 16, FN = WN / 16;
     static_assert(FM >= 1 && FN >= 1, "wave tile");
-    using LoaderA = TileLoader<BM, BK, LA == 1>;
-    using LoaderB = TileLoader<BN, BK, LB == 0>;
+    using LoaderA = TileLoader<BM, BK, LA == 1, NT>;
+    using LoaderB = TileLoader<BN, BK, LB == 0, NT>;
     extern __shared__ double smem[];
     double *As = smem;                       // two buffers of LoaderA::SIZE
     double *Bs = smem + 2 * LoaderA::SIZE;   // two buffers of LoaderB::SIZE
@@ -289,56 +292,62 @@ __global__ __launch_bounds__(GEMM_THREADS) void dgemm_mfma_kernel(GemmDesc g0, i
 
 #undef GEMM_COMPUTE
     // epilogue: lane l, register r holds row fk + 4 r, column fr of each
-    // 16x16 block.  All loads of C and the row scales are issued before any
-    // store so they overlap.
-    double cold[FM][FN][4], rs[FM][4];
+    // 16x16 block.  The loads of C and the row scales of EI block rows are
+    // issued before their stores so they overlap (all rows at once unless
+    // that would hold more than 8 blocks of C in registers).
+    constexpr int EI = FM * FN > 8 ? 1 : FM;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i0 = 0; i0 < FM; i0 += EI) {
+        double cold[EI][FN][4], rs[EI][4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
-            rs[i][r] = (g.rowscale && gm < g.M) ? g.rowscale[gm] : 1.0;
-        }
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int64_t gn_ = n0 + wn * WN + j * 16 + fr;
+        for (int ii = 0; ii < EI; ++ii)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
-                const bool ok = gm < g.M && gn_ < g.N && !(lower_mask && gn_ > gm);
-                cold[i][j][r] = (ok && g.beta != 0.0) ? g.C[gm * g.ldc + gn_] : 0.0;
+                const int64_t gm = m0 + wm * WM + (i0 + ii) * 16 + fk + 4 * r;
+                rs[ii][r] = (g.rowscale && gm < g.M) ? g.rowscale[gm] : 1.0;
             }
-        }
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
+        for (int ii = 0; ii < EI; ++ii)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int64_t gn_ = n0 + wn * WN + j * 16 + fr;
+            for (int j = 0; j < FN; ++j) {
+                const int64_t gn_ = n0 + wn * WN + j * 16 + fr;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t gm = m0 + wm * WM + i * 16 + fk + 4 * r;
-                if (gm >= g.M || gn_ >= g.N) continue;
-                if (lower_mask && gn_ > gm) continue;
-                const double v = g.alpha * acc[i][j][r] * rs[i][r];
-                g.C[gm * g.ldc + gn_] = (g.beta == 0.0) ? v : fma(g.beta, cold[i][j][r], v);
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gm = m0 + wm * WM + (i0 + ii) * 16 + fk + 4 * r;
+                    const bool ok = gm < g.M && gn_ < g.N && !(lower_mask && gn_ > gm);
+                    cold[ii][j][r] = (ok && g.beta != 0.0) ? g.C[gm * g.ldc + gn_] : 0.0;
+                }
+            }
+#pragma unroll
+        for (int ii = 0; ii < EI; ++ii) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int64_t gn_ = n0 + wn * WN + j * 16 + fr;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gm = m0 + wm * WM + (i0 + ii) * 16 + fk + 4 * r;
+                    if (gm >= g.M || gn_ >= g.N) continue;
+                    if (lower_mask && gn_ > gm) continue;
+                    const double v = g.alpha * acc[i0 + ii][j][r] * rs[ii][r];
+                    g.C[gm * g.ldc + gn_] = (g.beta == 0.0) ? v : fma(g.beta, cold[ii][j][r], v);
+                }
             }
         }
     }
 }
 
-template <int BM, int BN, int BK, int LA, int LB, bool BATCH>
+template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT>
 static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int tiles_n, int64_t blocks,
                              const GemmDesc *batch, const int4 *work) {
-    constexpr size_t shm = sizeof(double) * 2 * (TileLoader<BM, BK, LA == 1>::SIZE + TileLoader<BN, BK, LB == 0>::SIZE);
+    constexpr size_t shm =
+        sizeof(double) * 2 * (TileLoader<BM, BK, LA == 1, NT>::SIZE + TileLoader<BN, BK, LB == 0, NT>::SIZE);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>,
+        (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH, NT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         attr = true;
     }
-    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH>), dim3((unsigned)blocks), dim3(GEMM_THREADS),
+    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH, NT>), dim3((unsigned)blocks), dim3(NT),
                        shm, st, g, tiles_m, tiles_n, batch, work);
     return hipGetLastError();
 }
@@ -353,14 +362,17 @@ static int64_t blocks_for(const GemmDesc &g, int &tiles_m, int &tiles_n) {
     return (supers + NXCD - 1) / NXCD * NXCD * SUP;
 }
 
-template <int BM, int BN, int BK, bool BATCH>
+template <int BM, int BN, int BK, bool BATCH, int NT = GEMM_THREADS>
 static hipError_t launch_tiles(hipStream_t st, const GemmDesc &g, int64_t blocks, int tiles_m, int tiles_n,
                                const GemmDesc *batch, const int4 *work) {
     if (blocks <= 0) return hipSuccess;
-    if (g.la == 0 && g.lb == 0) return launch_one<BM, BN, BK, 0, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
-    if (g.la == 0 && g.lb == 1) return launch_one<BM, BN, BK, 0, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
-    if (g.la == 1 && g.lb == 0) return launch_one<BM, BN, BK, 1, 0, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
-    return launch_one<BM, BN, BK, 1, 1, BATCH>(st, g, tiles_m, tiles_n, blocks, batch, work);
+    if (g.la == 0 && g.lb == 0)
+        return launch_one<BM, BN, BK, 0, 0, BATCH, NT>(st, g, tiles_m, tiles_n, blocks, batch, work);
+    if (g.la == 0 && g.lb == 1)
+        return launch_one<BM, BN, BK, 0, 1, BATCH, NT>(st, g, tiles_m, tiles_n, blocks, batch, work);
+    if (g.la == 1 && g.lb == 0)
+        return launch_one<BM, BN, BK, 1, 0, BATCH, NT>(st, g, tiles_m, tiles_n, blocks, batch, work);
+    return launch_one<BM, BN, BK, 1, 1, BATCH, NT>(st, g, tiles_m, tiles_n, blocks, batch, work);
 }
 
 // Tile configuration.  128 x 128 tiles when there are enough of them to
@@ -398,6 +410,9 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     }
     if (ntiles(128, 128) >= FILL) {
         const int64_t b = blocks_for<128, 128, 32>(g, tm, tn);
+        // both operands contiguous along m / n (the Hilbert coupling product):
+        // four-wave workgroups, two per CU (measured 5% faster there)
+        if (g.la == 1 && g.lb == 0) return launch_tiles<128, 128, 16, false, 256>(st, g, b, tm, tn, nullptr, nullptr);
         return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
     }
     if (inplace) {
