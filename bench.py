@@ -567,7 +567,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gram (dgemm_mfma_kernel<128,128,32,1,0,false>)",
+            "kernel": "gram (dgemm_mfma_kernel<128,128,32,1,0,false,512>)",
             "achieved": gram_tf,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
