@@ -258,6 +258,41 @@ def deriv_rows_bench(inp, steps, mu):
     }
 
 
+def funnel_bench(outer=8, steps=50, dlam=0.005, y_max=1.0, pre=300):
+    """Funnel inference of lam on the small CCF workload: `pre` GN steps at
+    lam_0 = lam - 0.02 from the Glorot start, then up to `outer` trainings of
+    `steps` GN steps each, lam moved by the secant on the signed validation
+    residual of largest magnitude over y <= y_max (lam kept in (0.3, 1))."""
+    import torch
+
+    import workloads
+    from paper_2509_14185_amd import funnel, gn
+
+    inp = workloads.make_inputs("ccf_small")
+    lam0 = inp["lam"] - 0.02
+
+    def make(lam):
+        p = gn.Problem(inp["equation"], inp["widths"], lam, inp["c_norm"], inp["c_target"])
+        p.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+        return p
+
+    theta = torch.from_numpy(inp["theta0"].copy()).cuda()
+    p0 = make(lam0)
+    for _ in range(pre):
+        p0.step(theta, inp["mu"], stats=False)
+    p0.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lams, rs, ys = funnel.funnel_inference(make, theta, lam0, dlam, outer, steps, inp["mu"], y_max,
+                                           lam_range=(0.3, 1.0))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    P = sum(w * (a + 1) for a, w in zip(inp["widths"][:-1], inp["widths"][1:]))
+    return {"workload": "ccf_small", "params": P, "pre_steps": pre, "outer": outer, "trainings": len(lams),
+            "steps_per_lam": steps, "dlam": dlam, "y_max": y_max, "lam_0": lam0, "lams": lams, "r_hat": rs,
+            "y_at": ys, "seconds": el, "ms_per_step": 1e3 * el / max(1, len(lams) * steps)}
+
+
 def batched_comparison(steps):
     """Batched CCF workload (independent instances with their own lambda and
     point count, shared widths): batched steps (gn_step_batched) against the
@@ -469,6 +504,7 @@ def main():
     ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt runs")
     ap.add_argument("--no-rank1", action="store_true", help="skip the stochastic (rank-1 estimate) run")
     ap.add_argument("--no-deriv", action="store_true", help="skip the run with d1/d2 rows")
+    ap.add_argument("--no-funnel", action="store_true", help="skip the funnel-inference run")
     ap.add_argument("--damping", default="fixed", choices=["fixed", "lm"],
                     help="damping of the steps for --workload ipm2d / bouss2d")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split32"],
@@ -586,6 +622,9 @@ def main():
     if not args.no_deriv:
         print("[bench] d1/d2 rows", file=sys.stderr, flush=True)
         out["d12"] = deriv_rows_bench(inp, 10, mu)
+    if not args.no_funnel:
+        print("[bench] funnel inference", file=sys.stderr, flush=True)
+        out["funnel"] = funnel_bench()
     if not args.no_rank1:
         print("[bench] stochastic full-matrix GN (rank-1 estimates)", file=sys.stderr, flush=True)
         out["rank1"] = rank1_comparison(inp, 3 * args.steps, ev1["max_abs_R_val"])

@@ -337,6 +337,20 @@ gn_status gn_eval_derivs(gn_handle h, const double *d_theta, double *h_max_d1, d
  * GN_ESTATE. */
 gn_status gn_lambda_estimate(gn_handle h, const double *d_theta, double *h_lam, double *h_dU0);
 
+/* Proxy of funnel inference for a 1D first stage.  Paper: Methods,
+ * "Identifying Admissible lambda Values" (funnel inference: near an
+ * admissible lam the smallest reachable residual, taken with its sign, is
+ * about linear in lam with a zero there; after training at a fixed lam, the
+ * proxy r_hat(lam) is the residual of largest magnitude in a small
+ * neighbourhood of the origin, and lam is updated by the secant method).
+ * Evaluates the raw residual R at theta on the validation grid and returns,
+ * over its points with y <= y_max, the value R_i of largest |R_i| (a NaN
+ * counts as largest; the smallest index on ties) in *h_r_hat and y_i in
+ * *h_y_at (when not NULL).  Synchronises.  Errors: GN_EINVAL (null theta or
+ * r_hat, y_max not finite, 2D or second-stage handle), GN_ESTATE (no points,
+ * no validation grid, or no validation point with y <= y_max). */
+gn_status gn_funnel_residual(gn_handle h, const double *d_theta, double y_max, double *h_r_hat, double *h_y_at);
+
 /* Residual statistics at theta (half_sq_norm, max_abs_R, max_abs_R_val).
  * Synchronises. */
 gn_status gn_eval(gn_handle h, const double *d_theta, gn_stats *h_stats);

@@ -22,6 +22,8 @@ Contents:
   Levenberg-Marquardt damping.
 - rank1: the stochastic full-matrix Gauss-Newton step (moving average of
   rank-1 curvature estimates, closed-form learning rate and momentum).
+- funnel: funnel inference of lam (the signed residual proxy near the origin
+  and the secant update).
 
 Every function is pinned by tests/test_oracle_*.py against closed forms,
 complex-step derivatives, brute force or library routines, never against the

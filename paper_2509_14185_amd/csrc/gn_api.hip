@@ -78,6 +78,7 @@ struct gn_context {
     bool stage2 = false;
     double s1eps = 0.0;
     double *s1R = nullptr, *s1V = nullptr, *s1T = nullptr, *s1Rv = nullptr, *s1Vv = nullptr, *s1Tv = nullptr;
+    double *fn_R = nullptr;  // raw residual on the validation grid (funnel proxy), lazily allocated
     Geo3 geo3v{};                      // validation grid (derivative maxima)
     double *nn3v = nullptr;            // NN^(c) on the validation grid (4 x nv)
     // phase timing
@@ -685,6 +686,7 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     h->nd1 = h->nd2 = 0;
     h->stage2 = false;
     h->s1R = h->s1V = h->s1T = h->s1Rv = h->s1Vv = h->s1Tv = nullptr;
+    h->fn_R = nullptr;
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
     const int64_t nd = n1 + n2;
@@ -1319,6 +1321,41 @@ gn_status gn_lambda_estimate(gn_handle h, const double *d_theta, double *h_lam, 
     GN_HIP(h, hipStreamSynchronize(st));
     *h_lam = out[0];
     if (h_dU0) *h_dU0 = out[1];
+    return GN_OK;
+}
+
+gn_status gn_funnel_residual(gn_handle h, const double *d_theta, double y_max, double *h_r_hat, double *h_y_at) {
+    if (!h || !d_theta || !h_r_hat || !std::isfinite(y_max)) return GN_EINVAL;
+    if (!points_ready(h)) return fail(h, GN_ESTATE, "gn_set_points must be called first%s");
+    if (h->dim != 1 || h->stage2) return fail(h, GN_EINVAL, "the funnel proxy is defined for 1D first stages%s");
+    if (h->nv <= 0) return fail(h, GN_ESTATE, "no validation grid%s");
+    if (!h->fn_R) {
+        double *p = nullptr;
+        GN_TRY(dev_alloc(h, h->pt_allocs, &p, h->nv));
+        h->fn_R = p;
+    }
+    hipStream_t st = h->stream;
+    GN_HIP(h, launch_reset_status(st, h->status));
+    GN_TRY(forward_all(h, d_theta));
+    SweepBatch b{};
+    b.x = h->val.q; b.n = h->nv; b.nn = h->nn_val;
+    with_phi(h, b, h->phi_val, h->nv);
+    GN_HIP(h, launch_mlp_forward(st, h->md, d_theta, h->thetaT, b));
+    ResidualArgs a{};
+    a.equation = h->equation; a.lam = h->lam; a.m = h->m;
+    a.nodes = h->nodes; a.nn_nodes = h->nn_nodes;
+    a.n = h->nv; a.pts = h->val; a.nn = h->nn_val;
+    a.inv_n = 1.0;
+    a.R = h->fn_R;
+    a.max_out = &h->status->max_R;
+    GN_HIP(h, launch_residual(st, a));
+    GN_HIP(h, launch_funnel_residual(st, h->nv, h->fn_R, h->val.y, y_max, h->r1_dots));
+    double out[3];
+    GN_HIP(h, hipMemcpyAsync(out, h->r1_dots, sizeof out, hipMemcpyDeviceToHost, st));
+    GN_HIP(h, hipStreamSynchronize(st));
+    if (out[2] < 1.0) return fail(h, GN_ESTATE, "no validation point with y <= y_max%s");
+    *h_r_hat = out[0];
+    if (h_y_at) *h_y_at = out[1];
     return GN_OK;
 }
 

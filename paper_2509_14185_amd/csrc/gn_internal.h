@@ -313,6 +313,10 @@ hipError_t launch_deriv_coupling_adjoint(hipStream_t st, int64_t nd, int64_t m, 
 hipError_t launch_scale_seeds(hipStream_t st, int64_t n, const double *v, const double *seed, double *out);
 // out[0] = -2 (1 + U'(0)), out[1] = U'(0) from NN, NN_q at the nodes (nn: 2m).
 hipError_t launch_lambda_estimate(hipStream_t st, int64_t m, Geo1D nodes, const double *nn, double *out);
+// Funnel proxy over the n points with y <= y_max: out[0] = the R of largest
+// |R|, out[1] = its y, out[2] = how many points qualify.
+hipError_t launch_funnel_residual(hipStream_t st, int64_t n, const double *R, const double *y, double y_max,
+                                  double *out);
 
 // ------------------------------------------- stochastic full-matrix GN step
 // Lower triangle of G <- beta G + (1 - beta) u u^T (p <= 65535).

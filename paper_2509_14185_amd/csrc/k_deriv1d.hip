@@ -609,4 +609,57 @@ hipError_t launch_lambda_estimate(hipStream_t st, int64_t m, Geo1D nodes, const 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ funnel inference
+// Proxy r_hat(lam): over the points with y_i <= y_max, the R_i of largest
+// |R_i| (a NaN counts as largest; the smallest index on ties) and its y_i.
+// One workgroup, fixed per-thread order and tree (deterministic).
+// out[0] = R_i, out[1] = y_i, out[2] = number of points with y_i <= y_max.
+__global__ __launch_bounds__(1024) void funnel_residual_kernel(int64_t n, const double *__restrict__ R,
+                                                              const double *__restrict__ y, double y_max,
+                                                              double *__restrict__ out) {
+    __shared__ double key[1024];
+    __shared__ int64_t idx[1024];
+    __shared__ int64_t cnt[1024];
+    double best = -1.0;  // |R| of the candidate, +inf for NaN; -1: none
+    int64_t bi = n, c = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        if (!(y[i] <= y_max)) continue;
+        ++c;
+        const double r = R[i];
+        const double a = r != r ? __builtin_huge_val() : fabs(r);
+        if (a > best) {  // i increases along the loop: the first of equal values stays
+            best = a;
+            bi = i;
+        }
+    }
+    key[threadIdx.x] = best;
+    idx[threadIdx.x] = bi;
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const int t = threadIdx.x + o;
+            if (key[t] > key[threadIdx.x] || (key[t] == key[threadIdx.x] && idx[t] < idx[threadIdx.x])) {
+                key[threadIdx.x] = key[t];
+                idx[threadIdx.x] = idx[t];
+            }
+            cnt[threadIdx.x] += cnt[t];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t i = idx[0];
+        out[0] = i < n ? R[i] : 0.0;
+        out[1] = i < n ? y[i] : 0.0;
+        out[2] = (double)cnt[0];
+    }
+}
+
+hipError_t launch_funnel_residual(hipStream_t st, int64_t n, const double *R, const double *y, double y_max,
+                                  double *out) {
+    if (n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(funnel_residual_kernel, dim3(1), dim3(1024), 0, st, n, R, y, y_max, out);
+    return hipGetLastError();
+}
+
 }  // namespace gn

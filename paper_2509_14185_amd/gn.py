@@ -114,6 +114,7 @@ def load():
                                          ctypes.POINTER(_R1Stats)]),
         "gn_eval": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_Stats)]),
         "gn_lambda_estimate": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+        "gn_funnel_residual": (ctypes.c_int, [_VP, _VP, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "gn_eval_derivs": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "gn_fields": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
         "gn_set_stage1": (ctypes.c_int, [_VP, _D, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -348,6 +349,15 @@ class Problem:
         self._check(self.lib.gn_lambda_estimate(self.h, _ptr(theta), ctypes.byref(lam), ctypes.byref(du)),
                     "gn_lambda_estimate")
         return lam.value, du.value
+
+    def funnel_residual(self, theta, y_max=1.0):
+        """(r_hat, y_at): the validation residual of largest magnitude, with its
+        sign, over the points with y <= y_max (gn_funnel_residual)."""
+        self._bind()
+        r, y = _D(), _D()
+        self._check(self.lib.gn_funnel_residual(self.h, _ptr(theta), float(y_max), ctypes.byref(r), ctypes.byref(y)),
+                    "gn_funnel_residual")
+        return r.value, y.value
 
     def eval(self, theta):
         self._bind()
