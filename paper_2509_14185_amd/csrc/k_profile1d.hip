@@ -405,42 +405,62 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double 
     atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
-// One wave per point.  Lanes accumulate a fixed strided subset of the nodes
-// in order, then a fixed butterfly combines them: deterministic.
-__global__ __launch_bounds__(256) void ccf_residual_kernel(ResidualArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= a.n) return;
-    const double yi = a.pts.y[i];
-    const double Ei = a.pts.E[i];
-    const double NNi = a.nn[i];
+// One thread per point, RES_PTS points per workgroup.  The nodes are staged
+// through LDS in chunks of RES_PTS (t_j, w_j, Theta_j) and every thread sums
+// its point's Hilbert terms over them in node order (deterministic); the
+// node values are LDS broadcasts, and consecutive terms are independent, so
+// the divisions pipeline.
+static constexpr int RES_PTS = 256;
+__global__ __launch_bounds__(RES_PTS) void ccf_residual_kernel(ResidualArgs a) {
+    __shared__ double tn[RES_PTS], wn[RES_PTS], thn[RES_PTS];
+    const int64_t i = (int64_t)blockIdx.x * RES_PTS + threadIdx.x;
+    const bool valid = i < a.n;
+    const int64_t ii = valid ? i : a.n - 1;
+    const double yi = a.pts.y[ii];
+    const double Ei = a.pts.E[ii];
+    const double NNi = a.nn[ii];
     const double Thi = Ei * NNi;
+    const double y2 = 2.0 * yi;
     double U = 0.0, c = 0.0;
-    for (int64_t j = lane; j < a.m; j += 64) {
-        const double qij = hilbert_q(yi, a.nodes.y[j], a.nodes.wh[j]);
-        const double Thj = a.nodes.E[j] * a.nn_nodes[j];
-        U = fma(qij, Thj - Thi, U);
-        c += qij;
+    for (int64_t j0 = 0; j0 < a.m; j0 += RES_PTS) {
+        const int64_t j = j0 + threadIdx.x;
+        if (j < a.m) {
+            tn[threadIdx.x] = a.nodes.y[j];
+            wn[threadIdx.x] = a.nodes.wh[j];
+            thn[threadIdx.x] = a.nodes.E[j] * a.nn_nodes[j];
+        }
+        __syncthreads();
+        const int cnt = (a.m - j0) < RES_PTS ? (int)(a.m - j0) : RES_PTS;
+#pragma unroll 4
+        for (int k = 0; k < cnt; ++k) {
+            const double tj = tn[k];
+            const double qij = wn[k] * y2 / ((yi - tj) * (yi + tj));
+            U = fma(qij, thn[k] - Thi, U);
+            c += qij;
+        }
+        __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        U += __shfl_xor(U, o, 64);
-        c += __shfl_xor(c, o, 64);
-    }
-    if (lane != 0) return;
     const double lam = a.lam;
-    const double NNq = a.nn[a.n + i];
-    const double Eyi = a.pts.Ey[i], qyi = a.pts.qy[i];
+    const double NNq = a.nn[a.n + ii];
+    const double Eyi = a.pts.Ey[ii], qyi = a.pts.qy[ii];
     const double Thy = Eyi * NNi + Ei * qyi * NNq;
     // second stage: R_1 + eps D[Theta_1] Theta, D Phi = -lam Phi + V_1 Phi' + U[Phi] Theta_1'
     const bool lin = a.R1 != nullptr;
-    const double V = lin ? a.V1[i] : (1.0 + lam) * yi + U;
-    const double Ty = lin ? a.T1y[i] : Thy;     // coefficient of U (and its seed)
+    const double V = lin ? a.V1[ii] : (1.0 + lam) * yi + U;
+    const double Ty = lin ? a.T1y[ii] : Thy;     // coefficient of U (and its seed)
     const double g = lin ? a.eps : 1.0;
-    const double R = lin ? a.R1[i] + a.eps * (-lam * Thi + V * Thy + U * Ty) : -lam * Thi + V * Thy;
+    const double R = lin ? a.R1[ii] + a.eps * (-lam * Thi + V * Thy + U * Ty) : -lam * Thi + V * Thy;
+    // max |R| over the wave on the bit patterns (a NaN stays largest), one atomic per wave
+    unsigned long long mb = valid ? (unsigned long long)__double_as_longlong(fabs(R)) : 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(mb, o, 64);
+        mb = other > mb ? other : mb;
+    }
+    if ((threadIdx.x & 63) == 0 && mb != 0ull) atomic_max_nonneg(a.max_out, __longlong_as_double((long long)mb));
+    if (!valid) return;
     if (a.R) a.R[i] = R;
     if (a.V_out) a.V_out[i] = V;
     if (a.Ty_out) a.Ty_out[i] = Thy;
-    atomic_max_nonneg(a.max_out, fabs(R));
     if (a.r) {
         const double sc = sqrt((a.rho ? a.rho[i] : 1.0) * a.inv_n);
         a.r[i * a.r_stride] = sc * (R - (a.f ? a.f[i] : 0.0));
@@ -486,7 +506,8 @@ __global__ void burgers_residual_kernel(ResidualArgs a) {
 hipError_t launch_residual(hipStream_t st, const ResidualArgs &a) {
     if (a.n <= 0) return hipSuccess;
     if (a.equation == GN_EQ_CCF1D) {
-        hipLaunchKernelGGL(ccf_residual_kernel, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(ccf_residual_kernel, dim3((unsigned)((a.n + RES_PTS - 1) / RES_PTS)), dim3(RES_PTS), 0, st,
+                           a);
     } else {
         hipLaunchKernelGGL(burgers_residual_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
     }
