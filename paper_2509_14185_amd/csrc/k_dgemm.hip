@@ -412,7 +412,8 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
         const int64_t b = blocks_for<128, 128, 32>(g, tm, tn);
         // both operands contiguous along m / n (the Hilbert coupling product):
         // four-wave workgroups, two per CU (measured 5% faster there)
-        if (g.la == 1 && g.lb == 0) return launch_tiles<128, 128, 16, false, 256>(st, g, b, tm, tn, nullptr, nullptr);
+        if (g.la == 1 && g.lb == 0)
+            return launch_one<128, 128, 16, 1, 0, false, 256>(st, g, tm, tn, b, nullptr, nullptr);
         return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
     }
     if (inplace) {
