@@ -524,8 +524,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU row sharding of the "
-                                   "Gram is designed but not built (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; row sharding of the Gram over "
+                                   "several GPUs is designed but not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
