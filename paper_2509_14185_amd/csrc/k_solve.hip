@@ -440,13 +440,14 @@ __global__ __launch_bounds__(256) void potrf_block_batched_kernel(const BatchCho
 #undef LL
 #undef XX
 
-// Row blocks of the side stream's trailing update per outer panel (measured on
-// the medium CCF step: 1 block 12.0 ms per factorisation, 4 blocks 11.5 ms),
-// and the K extent of each of its launches: the NB columns of the outer panel
-// in two halves, so each tile holds its CU half as long and the critical
-// chain's kernels find free CUs sooner (K = 512: 10.03 ms, 256: 9.76 ms,
-// 128: 11.4 ms).
-static constexpr int SIDE_CHUNKS = 4;
+// Row blocks of the side stream's trailing update per outer panel, and the K
+// extent of each of its launches: the NB columns of the outer panel in two
+// halves, so each tile holds its CU half as long and the critical chain's
+// kernels find free CUs sooner.  Measured on the medium CCF step (ms per
+// factorisation): K = 512 in one launch 10.03, two halves 9.76-9.84, four
+// quarters 11.4; with halves, 3 row blocks 9.69-9.71, 4 blocks 9.80-9.84,
+// 5 blocks 10.4.
+static constexpr int SIDE_CHUNKS = 3;
 static constexpr int64_t SIDE_K = NB / 2;
 
 hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail, double *A,
