@@ -78,8 +78,27 @@ typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1, GN_EQ_IPM2D = 3, GN_EQ_BOUS
  * G = J^T J is formed as hi^T hi + hi^T lo + lo^T hi with FP32 matrix
  * products, summed in FP64 every 32 rows (about 1e-7 relative error in G);
  * the residual, g = J^T r, the Cholesky and the update stay FP64, so the
- * step is an inexact Newton step with the same fixed point. */
-typedef enum { GN_FP64 = 0, GN_SPLIT32 = 1 } gn_precision;
+ * step is an inexact Newton step with the same fixed point.
+ * GN_INT8_CRT (1D problems, at most 130944 rows): G = J^T J from int8 matrix
+ * products by exact modular arithmetic.  Each column of J is scaled by a
+ * power of two and rounded to a b-bit integer (b = 54 for 8193 rows), the
+ * integer Gram is formed exactly from its residues modulo 16 coprime moduli
+ * (int8 products, int32 sums) and rebuilt by the Chinese remainder theorem.
+ * Every entry of J keeps the bits above 2^-b times its column's maximum, the
+ * integer products and sums are exact, and G is rounded once to FP64 (within
+ * 2 ulp of the exact sum of the rounded integers).  A non-finite column gives
+ * NaN in its row and column of G. */
+typedef enum { GN_FP64 = 0, GN_SPLIT32 = 1, GN_INT8_CRT = 2 } gn_precision;
+
+#define GN_INT8_CRT_MAX_ROWS 130944  /* rows of J the int8 Gram accepts: 2^14-bounded
+                                        products summed in int32 stay exact */
+
+/* Host-only parameters of the GN_INT8_CRT Gram for m rows (no GPU call):
+ * *bits = b, the bits kept per column (m 2^(2b) < M / 4), *n_moduli = T and
+ * moduli[0 .. T-1] (caller-owned, room for 32) the pairwise coprime moduli,
+ * M their product.  GN_EINVAL for m < 1, m > GN_INT8_CRT_MAX_ROWS or a NULL
+ * pointer. */
+gn_status gn_int8_crt_params(int64_t m, int32_t *bits, int32_t *n_moduli, int32_t *moduli);
 
 #define GN_MAX_LAYERS 8   /* affine layers */
 #define GN_MAX_WIDTH 64   /* hidden width limit of the 1D kernels */
@@ -198,7 +217,9 @@ gn_status gn_residual(gn_handle h, const double *d_theta, double *d_r);
 gn_status gn_jacobian(gn_handle h, const double *d_theta, double *d_J, int64_t ldJ, double *d_r);
 
 /* Lower triangle of G = J^T J (p x p, ldG >= p) and g = J^T r (p), for any
- * m x p row-major J (ldJ >= p).  d_r may be NULL (then g is not written). */
+ * m x p row-major J (ldJ >= p).  d_r may be NULL (then g is not written).
+ * With GN_INT8_CRT, m may not exceed the handle's row count (N + 1 + the
+ * derivative rows) and p may not exceed P + 1 (GN_EINVAL otherwise). */
 gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t ldJ,
                   const double *d_r, double *d_G, int64_t ldG, double *d_g);
 

@@ -50,6 +50,7 @@ struct gn_context {
     double *vseed0 = nullptr, *vseed1 = nullptr, *useed = nullptr;
     double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
     float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
+    ModgramWork mg{};                        // int8 residue workspaces (GN_INT8_CRT)
     int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
     // 2D problems (gn_set_points_2d)
     int dim = 1, nout = 1, n_eq = 1;
@@ -529,6 +530,14 @@ const char *gn_status_string(int32_t s) {
 
 const char *gn_last_error(gn_handle h) { return h ? h->err.c_str() : "null handle"; }
 
+gn_status gn_int8_crt_params(int64_t m, int32_t *bits, int32_t *n_moduli, int32_t *moduli) {
+    if (m < 1 || m > GN_INT8_CRT_MAX_ROWS || !bits || !n_moduli || !moduli) return GN_EINVAL;
+    *bits = modgram_bits(m);
+    *n_moduli = modgram_moduli();
+    modgram_list(moduli);
+    return GN_OK;
+}
+
 gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (!prob || !out || !prob->widths) return GN_EINVAL;
     *out = nullptr;
@@ -536,7 +545,9 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (L < 1 || L > GN_MAX_LAYERS) return GN_EINVAL;
     const bool two_d = prob->equation == GN_EQ_IPM2D || prob->equation == GN_EQ_BOUSS2D;
     if (!two_d && prob->equation != GN_EQ_CCF1D && prob->equation != GN_EQ_BURGERS1D) return GN_EINVAL;
-    if (prob->precision != GN_FP64 && prob->precision != GN_SPLIT32) return GN_EINVAL;
+    if (prob->precision != GN_FP64 && prob->precision != GN_SPLIT32 && prob->precision != GN_INT8_CRT)
+        return GN_EINVAL;
+    if (prob->precision == GN_INT8_CRT && two_d) return GN_EINVAL;
     if (!(prob->lam > 0.0) || !(prob->c_norm >= 0.0) || prob->row_chunk < 0) return GN_EINVAL;
     if (two_d) {
         const int nout = prob->equation == GN_EQ_IPM2D ? 1 : 3;
@@ -678,6 +689,8 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     if (h->equation != GN_EQ_CCF1D) m_quad = 0;
     if (m_quad > 65535 && n1 + n2 > 0) return fail(h, GN_EINVAL, "at most 65535 nodes with derivative rows%s");
     if (h->nf > 0 && n1 + n2 > 0) return fail(h, GN_EINVAL, "derivative rows take the plain network input%s");
+    if (h->precision == GN_INT8_CRT && n + n1 + n2 + 1 > GN_INT8_CRT_MAX_ROWS)
+        return fail(h, GN_EINVAL, "the int8 Gram takes at most %s rows", std::to_string(GN_INT8_CRT_MAX_ROWS).c_str());
     GN_HIP(h, hipStreamSynchronize(h->stream));
     free_list(h->pt_allocs);
     ++h->points_gen;
@@ -769,6 +782,16 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     if (s == GN_OK) s = dev_alloc(h, A, &h->G, (P + 1) * h->ldG);
     if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jhi, m_rows * h->ldJ);
     if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jlo, m_rows * h->ldJ);
+    h->mg = ModgramWork{};
+    if (h->precision == GN_INT8_CRT) {
+        h->mg.r_bytes = modgram_r_bytes(m_rows, P + 1);
+        h->mg.y_bytes = modgram_y_bytes(P + 1);
+        h->mg.cmax_len = modgram_ppad(P + 1);
+        h->mg.rows = m_rows;
+        if (s == GN_OK) s = dev_alloc(h, A, &h->mg.R, h->mg.r_bytes);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->mg.Y, h->mg.y_bytes);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->mg.cmax, h->mg.cmax_len);
+    }
     if (s == GN_OK) s = dev_alloc(h, A, &h->partial, nparts * P);
     if (s != GN_OK) {
         free_list(A);
@@ -910,6 +933,9 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
             return fail(h, GN_EINVAL, "split-precision gram needs m <= N + 1 and ldJ <= the workspace ld%s");
         GN_HIP(h, launch_split(h->stream, d_J, m, p, ldJ, h->Jhi, h->Jlo));
         GN_HIP(h, launch_split_gram(h->stream, h->Jhi, h->Jlo, m, p, ldJ, d_G, ldG));
+    } else if (h->precision == GN_INT8_CRT) {
+        if (!h->mg.R || m > h->mg.rows) return fail(h, GN_EINVAL, "int8 gram needs m <= the workspace rows%s");
+        GN_HIP(h, launch_modgram(h->stream, d_J, m, p, ldJ, d_G, ldG, h->mg));
     } else {
         GemmDesc g{};
         g.M = p; g.N = p; g.K = m;
@@ -977,6 +1003,8 @@ gn_status form_system(gn_handle h, const double *d_theta) {
             GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
             GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
             GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
+        } else if (h->precision == GN_INT8_CRT) {
+            GN_HIP(h, launch_modgram(st, J, m_rows, P + 1, ldJ, h->G, h->ldG, h->mg));
         } else {
             GN_HIP(h, launch_dgemm(st, gram_desc(h)));
         }

@@ -188,6 +188,26 @@ hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, 
 // (same leading dimension), and the lower triangle of
 // Jhi^T Jhi + Jhi^T Jlo + Jlo^T Jhi (FP32 MFMA products, FP64 accumulation
 // per 32-row chunk); accumulate adds it to C (streamed row chunks).
+// Gram from int8 modular products (k_modgram.hip): workspace sizes in bytes
+// for m rows and p columns, and the launch (GN_INT8_CRT).
+struct ModgramWork {
+    int8_t *R = nullptr;                 // residues, MODS x ppad x kpad
+    int64_t r_bytes = 0;
+    uint8_t *Y = nullptr;                // product residues, MODS x ppad x ppad
+    int64_t y_bytes = 0;
+    unsigned long long *cmax = nullptr;  // column maxima (bit patterns), ppad
+    int64_t cmax_len = 0;
+    int64_t rows = 0;                    // largest m the workspaces hold
+};
+int64_t modgram_r_bytes(int64_t m, int64_t p);
+int64_t modgram_y_bytes(int64_t p);
+int64_t modgram_ppad(int64_t p);
+int modgram_bits(int64_t m);
+int modgram_moduli();
+void modgram_list(int32_t *out);
+hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, double *G, int64_t ldg,
+                          const ModgramWork &w);
+
 hipError_t launch_split(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, float *hi, float *lo);
 hipError_t launch_split_gram(hipStream_t st, const float *hi, const float *lo, int64_t m, int64_t p, int64_t lda,
                              double *C, int64_t ldc, int accumulate = 0);

@@ -1,0 +1,385 @@
+// Gram G = J^T J (lower triangle) to FP64 accuracy from int8 matrix products,
+// by exact modular arithmetic (the Ozaki scheme II of Ozaki, Uchino and
+// Imamura, 2025, specialised to a symmetric product).
+//
+// Why: the Gram is the dominant contraction of the full Gauss-Newton step
+// (paper, Methods, "Second-order Optimizer").  On gfx950 the int8 matrix
+// cores run 64 times as many operations per cycle as the FP64 ones.
+//
+// Steps (J is m x p, row-major, FP64):
+//   1. Column exponents.  E_j = ilogb(max_i |J_ij|) + 1, so that
+//      max_i |J_ij| 2^-E_j lies in [1/2, 1).
+//   2. Integers.  x_ij = rint(J_ij 2^(b - E_j)), |x_ij| <= 2^b, with b chosen
+//      so that m 2^(2b) < M / 4, M = prod_t m_t.  This rounding is the only
+//      inexact step: each entry keeps b bits below its column's maximum.
+//   3. Residues.  For each of the T pairwise coprime moduli m_t <= 256,
+//      r_t = x mod m_t in the balanced range [-128, 127], stored as int8 with
+//      the row index i contiguous (R_t[j][i]).
+//   4. Products.  C_t = R_t R_t^T with v_mfma_i32_16x16x64_i8: |r r'| <= 2^14
+//      and K <= 130944 keep the int32 sums exact; y_t = C_t mod m_t in [0, m_t).
+//   5. Reconstruction (Chinese remainder theorem).  v = sum_i x_ij x_ik is the
+//      unique integer with |v| < M/2 and v = y_t (mod m_t):
+//        v = sum_t y_t W_t - Q M,  W_t = (M/m_t) ((M/m_t)^-1 mod m_t),
+//      Q = rint(sum_t y_t W_t / M) from FP64 fractions f_t = W_t / M (its
+//      error is far below the margin 1/2 - |v|/M >= 1/4), and the difference
+//      evaluated modulo 2^128 in 64-bit limbs, where it is exact because
+//      |v| < 2^127.  G_jk = v 2^(E_j + E_k - 2b), rounded once to FP64
+//      (two roundings of the limbs: within 2 ulp of the exact sum).
+//
+// A column whose maximum is not finite gives NaN in every entry of its row
+// and column of G.
+//
+// Fragment layout of v_mfma_i32_16x16x64_i8 (wave64): lane l holds 16 bytes
+// of row l%16 of A and of column l%16 of B, at the same 16 positions of the
+// 64-deep k range for both (which positions does not matter: the product
+// pairs A and B byte for byte); D (16x16): lane l, register r holds
+// D[4*(l/16) + r][l%16].
+#include "gn_internal.h"
+
+#include <cmath>
+
+namespace gn {
+
+typedef int int4v __attribute__((ext_vector_type(4)));
+
+// 16 pairwise coprime moduli (2^8, 3*5*17, 11*23, 13*19 and primes);
+// M = 2^125.19.
+static constexpr int MODS = 16;
+static constexpr int MODULI[MODS] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191};
+
+static constexpr int MG_BM = 128;        // output tile (rows and columns)
+static constexpr int MG_BK = 64;         // k bytes per LDS stage (one MFMA deep)
+static constexpr int MG_LDS_ROW = MG_BK + 16;  // padded row: fragment reads hit distinct banks
+static constexpr int MG_WM = 2, MG_WN = 2;     // 4 waves, 64 x 64 each
+static constexpr int MG_NT = MG_WM * MG_WN * 64;
+static constexpr int MG_NXCD = 8;
+static constexpr int64_t MG_K_LIMIT = GN_INT8_CRT_MAX_ROWS;  // int32 sums of 2^14-bounded products stay exact
+
+struct ModConsts {
+    int m[MODS];
+    double inv[MODS];  // fl(1 / m_t)
+};
+
+struct CrtConsts {
+    unsigned long long wl[MODS], wh[MODS];  // W_t = wh 2^64 + wl
+    double f[MODS];                         // fl(W_t / M)
+    unsigned long long ml, mh;              // M = mh 2^64 + ml
+};
+
+int64_t modgram_kpad(int64_t m) { return (m + MG_BK - 1) / MG_BK * MG_BK; }
+int64_t modgram_ppad(int64_t p) { return (p + MG_BM - 1) / MG_BM * MG_BM; }
+int64_t modgram_r_bytes(int64_t m, int64_t p) { return (int64_t)MODS * modgram_ppad(p) * modgram_kpad(m); }
+int64_t modgram_y_bytes(int64_t p) { return (int64_t)MODS * modgram_ppad(p) * modgram_ppad(p); }
+int modgram_moduli() { return MODS; }
+void modgram_list(int32_t *out) {
+    for (int t = 0; t < MODS; ++t) out[t] = MODULI[t];
+}
+
+// log2 M, summed in FP64
+static double log2_modulus() {
+    double s = 0.0;
+    for (int t = 0; t < MODS; ++t) s += std::log2((double)MODULI[t]);
+    return s;
+}
+
+// Bits kept per column: the largest b with m 2^(2b) < M / 4 (one bit of
+// margin for the FP64 log2 on top of the factor 4 the quotient estimate
+// needs), at most 58 so that the FP64 quotient x / m_t of the residue step
+// (|x| <= 2^b, m_t >= 191) is within one of its floor.
+int modgram_bits(int64_t m) {
+    if (m < 1) m = 1;
+    const int b = (int)std::floor((log2_modulus() - 3.0 - std::log2((double)m)) / 2.0);
+    return b < 58 ? b : 58;
+}
+
+static ModConsts mod_consts() {
+    ModConsts c{};
+    for (int t = 0; t < MODS; ++t) {
+        c.m[t] = MODULI[t];
+        c.inv[t] = 1.0 / (double)MODULI[t];
+    }
+    return c;
+}
+
+static CrtConsts crt_consts() {
+    typedef unsigned __int128 u128;
+    u128 M = 1;
+    for (int t = 0; t < MODS; ++t) M *= (u128)MODULI[t];
+    CrtConsts c{};
+    for (int t = 0; t < MODS; ++t) {
+        const int mt = MODULI[t];
+        const u128 Mt = M / (u128)mt;
+        const int r = (int)(Mt % (u128)mt);
+        int inv = 0;
+        for (int v = 1; v < mt; ++v)
+            if ((r * v) % mt == 1) { inv = v; break; }
+        const u128 W = Mt * (u128)inv;  // < M: no reduction needed
+        c.wl[t] = (unsigned long long)W;
+        c.wh[t] = (unsigned long long)(W >> 64);
+        c.f[t] = (double)W / (double)M;
+    }
+    c.ml = (unsigned long long)M;
+    c.mh = (unsigned long long)(M >> 64);
+    return c;
+}
+
+static constexpr unsigned long long ABS_MASK = 0x7fffffffffffffffull;
+static constexpr unsigned long long INF_BITS = 0x7ff0000000000000ull;
+
+__global__ void mg_zero_kernel(unsigned long long *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0ull;
+}
+
+// cmax[j] = bits of max_i |J_ij| (ordered like the magnitudes; NaN above Inf)
+static constexpr int MG_COLMAX_ROWS = 256;
+__global__ void mg_colmax_kernel(const double *__restrict__ J, int64_t m, int64_t p, int64_t ldj,
+                                 unsigned long long *__restrict__ cmax) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p) return;
+    const int64_t i0 = (int64_t)blockIdx.y * MG_COLMAX_ROWS;
+    const int64_t i1 = i0 + MG_COLMAX_ROWS < m ? i0 + MG_COLMAX_ROWS : m;
+    unsigned long long mx = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(J[i * ldj + j]) & ABS_MASK;
+        mx = bits > mx ? bits : mx;
+    }
+    if (mx) atomicMax(&cmax[j], mx);
+}
+
+// Exponent shift of column j: x = rint(J 2^(b - E)); false for a column
+// that is zero or not finite (its integers are all zero).
+__device__ __forceinline__ bool column_shift(unsigned long long bits, int b, int &e) {
+    if (bits == 0ull || bits >= INF_BITS) { e = 0; return false; }
+    e = b - (ilogb(__longlong_as_double((long long)bits)) + 1);
+    return true;
+}
+
+// Residues: a 32 (i) x 64 (j) block of J becomes MODS int8 tiles R_t[j][i],
+// transposed through LDS.  Covers i < kpad and j < ppad; entries outside
+// J (i >= m or j >= p) are zero.
+static constexpr int MG_CV_I = 32, MG_CV_J = 64, MG_CV_ROW = MG_CV_I + 4;
+__global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restrict__ J, int64_t m, int64_t p, int64_t ldj,
+                                                         const unsigned long long *__restrict__ cmax, int b,
+                                                         ModConsts mc, int8_t *__restrict__ R, int64_t ldr,
+                                                         int64_t rplane) {
+    __shared__ __attribute__((aligned(16))) int8_t res[MODS * MG_CV_J * MG_CV_ROW];
+    const int tx = threadIdx.x % MG_CV_J, ty = threadIdx.x / MG_CV_J;
+    const int64_t j0 = (int64_t)blockIdx.x * MG_CV_J, i0 = (int64_t)blockIdx.y * MG_CV_I;
+    const int64_t j = j0 + tx;
+    int e = 0;
+    const bool live = j < p && column_shift(cmax[j < p ? j : 0], b, e);
+#pragma unroll 2
+    for (int s = 0; s < MG_CV_I / 4; ++s) {
+        const int il = ty + 4 * s;
+        const int64_t i = i0 + il;
+        const double v = (live && i < m) ? J[i * ldj + j] : 0.0;
+        const double x = rint(ldexp(v, e));
+#pragma unroll
+        for (int t = 0; t < MODS; ++t) {
+            const double md = (double)mc.m[t];
+            const double q = floor(x * mc.inv[t]);
+            double r = fma(-q, md, x);  // exact: |x - q m| < 2m
+            r = r < 0.0 ? r + md : r;
+            r = r >= md ? r - md : r;
+            const int ri = (int)r;
+            res[(t * MG_CV_J + tx) * MG_CV_ROW + il] = (int8_t)(ri >= (mc.m[t] + 1) / 2 ? ri - mc.m[t] : ri);
+        }
+    }
+    __syncthreads();
+    // write-out: per modulus 64 rows (j) of 32 bytes (i), 4 bytes per thread
+    const int c = threadIdx.x % (MG_CV_I / 4), rr = threadIdx.x / (MG_CV_I / 4);  // 8 threads per row, 32 rows per pass
+#pragma unroll 4
+    for (int t = 0; t < MODS; ++t) {
+#pragma unroll
+        for (int h = 0; h < MG_CV_J / 32; ++h) {
+            const int row = rr + 32 * h;
+            const int w = *reinterpret_cast<const int *>(&res[(t * MG_CV_J + row) * MG_CV_ROW + 4 * c]);
+            *reinterpret_cast<int *>(R + t * rplane + (j0 + row) * ldr + i0 + 4 * c) = w;
+        }
+    }
+}
+
+// Work item w (modulus-major, then lower tiles row by row) of block b: the
+// blocks are dealt round-robin over the XCDs, so XCD x takes the contiguous
+// range [x * per, (x + 1) * per) and its L2 sees one modulus's panels at a time.
+__device__ __forceinline__ bool mg_work(int64_t b, int64_t per, int64_t tiles_lower, int &t, int &tm, int &tn) {
+    const int64_t w = (b % MG_NXCD) * per + b / MG_NXCD;
+    if (w >= tiles_lower * MODS) return false;
+    t = (int)(w / tiles_lower);
+    const int64_t idx = w % tiles_lower;
+    int64_t r = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > idx) --r;
+    while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+    tm = (int)r;
+    tn = (int)(idx - r * (r + 1) / 2);
+    return true;
+}
+
+// C_t = R_t R_t^T mod m_t on the lower 128 x 128 tiles; 4 waves of 64 x 64.
+// R rows are kpad bytes long (kpad a multiple of MG_BK); all tiles are
+// interior (the rows and k range are padded with zeros).
+__global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict__ R, int64_t ldr, int64_t rplane,
+                                                        int kchunks, int64_t tiles_lower, int64_t per, ModConsts mc,
+                                                        uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane) {
+    constexpr int WTM = MG_BM / MG_WM, WTN = MG_BM / MG_WN;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int CPR = MG_BK / 16;                 // 16-byte chunks per tile row
+    constexpr int PER = MG_BM * CPR / MG_NT;        // chunks per thread per operand
+    static_assert(PER * MG_NT == MG_BM * CPR, "tile split");
+    __shared__ __attribute__((aligned(16))) int8_t lds[2][2][MG_BM * MG_LDS_ROW];
+
+    int t, tm, tn;
+    if (!mg_work(blockIdx.x, per, tiles_lower, t, tm, tn)) return;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wm = wave / MG_WN, wn = wave % MG_WN;
+    const int8_t *Ag = R + t * rplane + (int64_t)tm * MG_BM * ldr;
+    const int8_t *Bg = R + t * rplane + (int64_t)tn * MG_BM * ldr;
+
+    int4v ra[PER], rb[PER];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int c = threadIdx.x + e * MG_NT;
+            const int64_t off = (int64_t)(c / CPR) * ldr + k0 + (c % CPR) * 16;
+            ra[e] = *reinterpret_cast<const int4v *>(Ag + off);
+            rb[e] = *reinterpret_cast<const int4v *>(Bg + off);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int c = threadIdx.x + e * MG_NT;
+            const int off = (c / CPR) * MG_LDS_ROW + (c % CPR) * 16;
+            *reinterpret_cast<int4v *>(&lds[buf][0][off]) = ra[e];
+            *reinterpret_cast<int4v *>(&lds[buf][1][off]) = rb[e];
+        }
+    };
+
+    int4v acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) acc[i][jj] = int4v{0, 0, 0, 0};
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    const int frag = (lane % 16) * MG_LDS_ROW + (lane / 16) * 16;
+    for (int kc = 0; kc < kchunks; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < kchunks;
+        if (more) gload((int64_t)(kc + 1) * MG_BK);
+        int4v a[FM], bb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            a[i] = *reinterpret_cast<const int4v *>(&lds[buf][0][(wm * WTM + i * 16) * MG_LDS_ROW + frag]);
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj)
+            bb[jj] = *reinterpret_cast<const int4v *>(&lds[buf][1][(wn * WTN + jj * 16) * MG_LDS_ROW + frag]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int jj = 0; jj < FN; ++jj)
+                acc[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], bb[jj], acc[i][jj], 0, 0, 0);
+        if (more) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // y = C mod m_t in [0, m_t): the quotient from FP64 is within one of the
+    // floor and corrected in integers
+    const int md = mc.m[t];
+    const double inv = mc.inv[t];
+    uint8_t *Yt = Y + t * yplane;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = acc[i][jj][r];
+                int y = c - (int)floor((double)c * inv) * md;
+                y = y < 0 ? y + md : y;
+                y = y >= md ? y - md : y;
+                const int64_t row = (int64_t)tm * MG_BM + wm * WTM + i * 16 + (lane / 16) * 4 + r;
+                const int64_t col = (int64_t)tn * MG_BM + wn * WTN + jj * 16 + lane % 16;
+                Yt[row * ldy + col] = (uint8_t)y;
+            }
+}
+
+// G_jk (k <= j < p) from the residues y_t: one row j per blockIdx.y.
+__global__ __launch_bounds__(256) void mg_crt_kernel(const uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane,
+                                                     int64_t p, const unsigned long long *__restrict__ cmax, int b,
+                                                     CrtConsts cc, double *__restrict__ G, int64_t ldg) {
+    const int64_t j = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p || k > j) return;
+    const unsigned long long bj = cmax[j], bk = cmax[k];
+    if (bj >= INF_BITS || bk >= INF_BITS) {
+        G[j * ldg + k] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    int ej = 0, ek = 0;
+    const bool lj = column_shift(bj, b, ej), lk = column_shift(bk, b, ek);
+    if (!lj || !lk) {
+        G[j * ldg + k] = 0.0;
+        return;
+    }
+    unsigned long long y[MODS];
+#pragma unroll
+    for (int t = 0; t < MODS; ++t) y[t] = Y[t * yplane + j * ldy + k];
+    double qs = 0.0;
+#pragma unroll
+    for (int t = 0; t < MODS; ++t) qs = fma((double)y[t], cc.f[t], qs);
+    const unsigned long long Q = (unsigned long long)rint(qs);
+    // u = sum_t y_t W_t - Q M  (mod 2^128)
+    unsigned long long lo = 0, hi = 0;
+#pragma unroll
+    for (int t = 0; t < MODS; ++t) {
+        const unsigned long long a = y[t] * cc.wl[t];
+        const unsigned long long c = __umul64hi(y[t], cc.wl[t]);
+        lo += a;
+        hi += y[t] * cc.wh[t] + c + (lo < a ? 1ull : 0ull);
+    }
+    const unsigned long long ql = Q * cc.ml, qh = Q * cc.mh + __umul64hi(Q, cc.ml);
+    hi = hi - qh - (lo < ql ? 1ull : 0ull);
+    lo = lo - ql;
+    const bool neg = (long long)hi < 0;
+    if (neg) {
+        lo = ~lo + 1ull;
+        hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+    }
+    double v = fma((double)hi, 0x1p64, (double)lo);
+    v = neg ? -v : v;
+    // G = v 2^(E_j - b) 2^(E_k - b) = v 2^(-(e_j + e_k))
+    G[j * ldg + k] = ldexp(v, -(ej + ek));
+}
+
+hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, double *G, int64_t ldg,
+                          const ModgramWork &w) {
+    if (p <= 0) return hipSuccess;
+    if (m > MG_K_LIMIT) return hipErrorInvalidValue;
+    const int64_t kpad = modgram_kpad(m < 1 ? 1 : m), ppad = modgram_ppad(p);
+    if (modgram_r_bytes(m < 1 ? 1 : m, p) > w.r_bytes || modgram_y_bytes(p) > w.y_bytes || ppad > w.cmax_len)
+        return hipErrorInvalidValue;
+    const int b = modgram_bits(m);
+    const int64_t rplane = ppad * kpad, yplane = ppad * ppad;
+    hipLaunchKernelGGL(mg_zero_kernel, dim3((unsigned)((ppad + 255) / 256)), dim3(256), 0, st, w.cmax, ppad);
+    if (m > 0)
+        hipLaunchKernelGGL(mg_colmax_kernel,
+                           dim3((unsigned)((p + 255) / 256), (unsigned)((m + MG_COLMAX_ROWS - 1) / MG_COLMAX_ROWS)),
+                           dim3(256), 0, st, J, m, p, ldj, w.cmax);
+    const ModConsts mc = mod_consts();
+    hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)(kpad / MG_CV_I)), dim3(256), 0,
+                       st, J, m, p, ldj, w.cmax, b, mc, w.R, kpad, rplane);
+    const int64_t tiles = ppad / MG_BM, tiles_lower = tiles * (tiles + 1) / 2;
+    const int64_t per = (tiles_lower * MODS + MG_NXCD - 1) / MG_NXCD;
+    hipLaunchKernelGGL(mg_gemm_kernel, dim3((unsigned)(per * MG_NXCD)), dim3(MG_NT), 0, st, w.R, kpad, rplane,
+                       (int)(kpad / MG_BK), tiles_lower, per, mc, w.Y, ppad, yplane);
+    const CrtConsts cc = crt_consts();
+    hipLaunchKernelGGL(mg_crt_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)p), dim3(256), 0, st, w.Y, ppad,
+                       yplane, p, w.cmax, b, cc, G, ldg);
+    return hipGetLastError();
+}
+
+}  // namespace gn

@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "gn.h")
 GN_OK, GN_ENOTPD, GN_EINVAL, GN_ENOMEM, GN_EDEVICE, GN_ENONFINITE, GN_ESTATE = 0, 1, -1, -2, -3, -4, -5
 GN_EREJECTED = 2
 EQUATIONS = {"ccf1d": 0, "burgers1d": 1, "ipm2d": 3, "bouss2d": 4}
-PRECISIONS = {"fp64": 0, "split32": 1}
+PRECISIONS = {"fp64": 0, "split32": 1, "int8crt": 2}
 
 
 class GNError(RuntimeError):
@@ -122,6 +122,8 @@ def load():
         "gn_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
         "gn_batch_destroy": (ctypes.c_int, [_VP]),
         "gn_step_batched": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), _D, ctypes.POINTER(_Stats)]),
+        "gn_int8_crt_params": (ctypes.c_int, [_I64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]),
         "gn_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
         "gn_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32)]),
@@ -132,6 +134,18 @@ def load():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def int8_crt_params(m: int):
+    """Bits kept per column and the moduli of the GN_INT8_CRT Gram for m rows
+    (host-only; see gn_int8_crt_params)."""
+    lib = load()
+    bits, n = ctypes.c_int32(), ctypes.c_int32()
+    mods = (ctypes.c_int32 * 32)()
+    st = lib.gn_int8_crt_params(int(m), ctypes.byref(bits), ctypes.byref(n), mods)
+    if st != 0:
+        raise GNError(st, lib.gn_status_string(st).decode())
+    return bits.value, [mods[i] for i in range(n.value)]
 
 
 def _ptr(t):
