@@ -47,11 +47,15 @@ typedef int int4v __attribute__((ext_vector_type(4)));
 static constexpr int MODS = 16;
 static constexpr int MODULI[MODS] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191};
 
-static constexpr int MG_BM = 128;        // output tile (rows and columns)
-static constexpr int MG_BK = 64;         // k bytes per LDS stage (one MFMA deep)
-static constexpr int MG_LDS_ROW = MG_BK + 16;  // padded row: fragment reads hit distinct banks
-static constexpr int MG_WM = 2, MG_WN = 2;     // 4 waves, 64 x 64 each
+static constexpr int MG_BM = 256;        // output tile (rows and columns)
+static constexpr int MG_BK = 128;        // k bytes per LDS stage (two MFMA depths of 64)
+static constexpr int MG_STAGES = 2;      // LDS ring: copies run one stage ahead
+static constexpr int MG_WM = 2, MG_WN = 4;     // 8 waves, 128 x 64 each
 static constexpr int MG_NT = MG_WM * MG_WN * 64;
+static constexpr int MG_LDS_BYTES = MG_STAGES * 2 * MG_BM * MG_BK;  // [stage][A, B]
+// s_waitcnt immediate (gfx9 encoding) that waits for vmcnt <= n and leaves
+// expcnt and lgkmcnt unconstrained
+#define MG_VMCNT(n) ((((n) & 0xf) | (((n) >> 4) << 14)) | (0x7 << 4) | (0xf << 8))
 static constexpr int MG_NXCD = 8;
 static constexpr int64_t MG_K_LIMIT = GN_INT8_CRT_MAX_ROWS;  // int32 sums of 2^14-bounded products stay exact
 
@@ -155,48 +159,70 @@ __device__ __forceinline__ bool column_shift(unsigned long long bits, int b, int
     return true;
 }
 
-// Residues: a 32 (i) x 64 (j) block of J becomes MODS int8 tiles R_t[j][i],
-// transposed through LDS.  Covers i < kpad and j < ppad; entries outside
-// J (i >= m or j >= p) are zero.
-static constexpr int MG_CV_I = 32, MG_CV_J = 64, MG_CV_ROW = MG_CV_I + 4;
+// Residues: a 128 (i) x 64 (j) block of J becomes MODS int8 tiles R_t[j][i],
+// transposed through LDS four moduli at a time.  Each thread holds the
+// integers of 8 runs of 4 consecutive rows of one column and packs their
+// residues into one 32-bit LDS word per run (odd row stride: the 64 columns
+// of a wave hit distinct banks); the tiles leave as 128-byte row segments.
+// Covers i < kpad and j < ppad; entries outside J (i >= m, j >= p) are zero.
+static constexpr int MG_CV_I = 128, MG_CV_J = 64, MG_CV_G = 4;
+static constexpr int MG_CV_LD = MG_CV_I / 4 + 1;  // 32-bit words per LDS row
 __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restrict__ J, int64_t m, int64_t p, int64_t ldj,
                                                          const unsigned long long *__restrict__ cmax, int b,
                                                          ModConsts mc, int8_t *__restrict__ R, int64_t ldr,
                                                          int64_t rplane) {
-    __shared__ __attribute__((aligned(16))) int8_t res[MODS * MG_CV_J * MG_CV_ROW];
+    __shared__ uint32_t res[MG_CV_G * MG_CV_J * MG_CV_LD];
     const int tx = threadIdx.x % MG_CV_J, ty = threadIdx.x / MG_CV_J;
     const int64_t j0 = (int64_t)blockIdx.x * MG_CV_J, i0 = (int64_t)blockIdx.y * MG_CV_I;
     const int64_t j = j0 + tx;
     int e = 0;
     const bool live = j < p && column_shift(cmax[j < p ? j : 0], b, e);
-#pragma unroll 2
-    for (int s = 0; s < MG_CV_I / 4; ++s) {
-        const int il = ty + 4 * s;
-        const int64_t i = i0 + il;
-        const double v = (live && i < m) ? J[i * ldj + j] : 0.0;
-        const double x = rint(ldexp(v, e));
+    double x[8][4];  // row i0 + 16 s + 4 ty + q
 #pragma unroll
-        for (int t = 0; t < MODS; ++t) {
-            const double md = (double)mc.m[t];
-            const double q = floor(x * mc.inv[t]);
-            double r = fma(-q, md, x);  // exact: |x - q m| < 2m
-            r = r < 0.0 ? r + md : r;
-            r = r >= md ? r - md : r;
-            const int ri = (int)r;
-            res[(t * MG_CV_J + tx) * MG_CV_ROW + il] = (int8_t)(ri >= (mc.m[t] + 1) / 2 ? ri - mc.m[t] : ri);
-        }
-    }
-    __syncthreads();
-    // write-out: per modulus 64 rows (j) of 32 bytes (i), 4 bytes per thread
-    const int c = threadIdx.x % (MG_CV_I / 4), rr = threadIdx.x / (MG_CV_I / 4);  // 8 threads per row, 32 rows per pass
-#pragma unroll 4
-    for (int t = 0; t < MODS; ++t) {
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
-        for (int h = 0; h < MG_CV_J / 32; ++h) {
-            const int row = rr + 32 * h;
-            const int w = *reinterpret_cast<const int *>(&res[(t * MG_CV_J + row) * MG_CV_ROW + 4 * c]);
-            *reinterpret_cast<int *>(R + t * rplane + (j0 + row) * ldr + i0 + 4 * c) = w;
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + 16 * s + 4 * ty + q;
+            const double v = (live && i < m) ? J[i * ldj + j] : 0.0;
+            x[s][q] = rint(ldexp(v, e));
         }
+    const int wc = threadIdx.x % (MG_CV_I / 4), wr = threadIdx.x / (MG_CV_I / 4);  // 32 words per row, 8 rows per pass
+    const bool wlive = i0 + 4 * wc < ldr;
+#pragma unroll 1
+    for (int g = 0; g < MODS / MG_CV_G; ++g) {
+#pragma unroll
+        for (int tt = 0; tt < MG_CV_G; ++tt) {
+            const int t = g * MG_CV_G + tt;
+            const double md = (double)mc.m[t], inv = mc.inv[t];
+            const int mi = mc.m[t], half = (mc.m[t] + 1) / 2;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double xq = x[s][q];
+                    const double qt = floor(xq * inv);
+                    double r = fma(-qt, md, xq);  // exact: |x - q m| < 2m
+                    r = r < 0.0 ? r + md : r;
+                    r = r >= md ? r - md : r;
+                    int ri = (int)r;
+                    ri = ri >= half ? ri - mi : ri;
+                    w |= ((uint32_t)ri & 0xffu) << (8 * q);
+                }
+                res[(tt * MG_CV_J + tx) * MG_CV_LD + 4 * s + ty] = w;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tt = 0; tt < MG_CV_G; ++tt)
+#pragma unroll
+            for (int h = 0; h < MG_CV_J / 8; ++h) {
+                const int row = wr + 8 * h;
+                if (wlive)
+                    *reinterpret_cast<uint32_t *>(R + (g * MG_CV_G + tt) * rplane + (j0 + row) * ldr + i0 + 4 * wc) =
+                        res[(tt * MG_CV_J + row) * MG_CV_LD + wc];
+            }
+        __syncthreads();
     }
 }
 
@@ -216,18 +242,32 @@ __device__ __forceinline__ bool mg_work(int64_t b, int64_t per, int64_t tiles_lo
     return true;
 }
 
-// C_t = R_t R_t^T mod m_t on the lower 128 x 128 tiles; 4 waves of 64 x 64.
+// C_t = R_t R_t^T mod m_t on the lower MG_BM x MG_BM tiles, MG_WM x MG_WN waves.
 // R rows are kpad bytes long (kpad a multiple of MG_BK); all tiles are
 // interior (the rows and k range are padded with zeros).
+//
+// Operand tiles move from global memory straight into LDS
+// (global_load_lds, 16 bytes per lane, no registers), through a ring of
+// MG_STAGES stages so that the copies of a stage are issued MG_STAGES - 1
+// stages before it is used.  Each copy instruction fills 1 KB of LDS in lane
+// order, i.e. 1024 / MG_BK whole tile rows; lane l takes the global chunk
+// c = (l % CPR) ^ swz(row) of its row, so LDS chunk position c' of row r holds
+// global chunk c' ^ swz(r).  swz spreads the 16 rows of a fragment read over
+// all 64 banks: rows 256 / MG_BK apart share banks, and swz gives them
+// distinct chunk positions.
+__device__ __forceinline__ int mg_swz(int row) { return (row / (256 / MG_BK)) % (MG_BK / 16); }
+
 __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict__ R, int64_t ldr, int64_t rplane,
                                                         int kchunks, int64_t tiles_lower, int64_t per, ModConsts mc,
                                                         uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane) {
     constexpr int WTM = MG_BM / MG_WM, WTN = MG_BM / MG_WN;
     constexpr int FM = WTM / 16, FN = WTN / 16;
-    constexpr int CPR = MG_BK / 16;                 // 16-byte chunks per tile row
-    constexpr int PER = MG_BM * CPR / MG_NT;        // chunks per thread per operand
-    static_assert(PER * MG_NT == MG_BM * CPR, "tile split");
-    __shared__ __attribute__((aligned(16))) int8_t lds[2][2][MG_BM * MG_LDS_ROW];
+    constexpr int CPR = MG_BK / 16;                   // 16-byte chunks per tile row
+    constexpr int ROWS_PER_COPY = 64 / CPR;           // tile rows per copy instruction
+    constexpr int COPIES = MG_BM / ROWS_PER_COPY / (MG_NT / 64);  // per wave, per operand, per stage
+    static_assert(COPIES * ROWS_PER_COPY * (MG_NT / 64) == MG_BM, "tile split");
+    constexpr int TILE = MG_BM * MG_BK;               // bytes of one operand tile
+    extern __shared__ __attribute__((aligned(16))) int8_t mg_lds[];
 
     int t, tm, tn;
     if (!mg_work(blockIdx.x, per, tiles_lower, t, tm, tn)) return;
@@ -236,23 +276,17 @@ __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict
     const int8_t *Ag = R + t * rplane + (int64_t)tm * MG_BM * ldr;
     const int8_t *Bg = R + t * rplane + (int64_t)tn * MG_BM * ldr;
 
-    int4v ra[PER], rb[PER];
-    auto gload = [&](int64_t k0) {
+    // copies of stage kc into ring slot kc % MG_STAGES
+    const int crow = lane / CPR, cpos = lane % CPR;
+    auto issue = [&](int kc) {
+        int8_t *la = mg_lds + (kc % MG_STAGES) * 2 * TILE, *lb = la + TILE;
+        const int64_t k0 = (int64_t)kc * MG_BK;
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int c = threadIdx.x + e * MG_NT;
-            const int64_t off = (int64_t)(c / CPR) * ldr + k0 + (c % CPR) * 16;
-            ra[e] = *reinterpret_cast<const int4v *>(Ag + off);
-            rb[e] = *reinterpret_cast<const int4v *>(Bg + off);
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int c = threadIdx.x + e * MG_NT;
-            const int off = (c / CPR) * MG_LDS_ROW + (c % CPR) * 16;
-            *reinterpret_cast<int4v *>(&lds[buf][0][off]) = ra[e];
-            *reinterpret_cast<int4v *>(&lds[buf][1][off]) = rb[e];
+        for (int q = 0; q < COPIES; ++q) {
+            const int row0 = (wave * COPIES + q) * ROWS_PER_COPY, row = row0 + crow;
+            const int64_t off = (int64_t)row * ldr + k0 + 16 * (cpos ^ mg_swz(row));
+            __builtin_amdgcn_global_load_lds(Ag + off, la + row0 * MG_BK, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(Bg + off, lb + row0 * MG_BK, 16, 0, 0);
         }
     };
 
@@ -262,28 +296,43 @@ __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict
 #pragma unroll
         for (int jj = 0; jj < FN; ++jj) acc[i][jj] = int4v{0, 0, 0, 0};
 
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    const int frag = (lane % 16) * MG_LDS_ROW + (lane / 16) * 16;
+    for (int s = 0; s < MG_STAGES - 1 && s < kchunks; ++s) issue(s);
+    const int frow = lane % 16, fchunk = lane / 16;
     for (int kc = 0; kc < kchunks; ++kc) {
-        const int buf = kc & 1;
-        const bool more = kc + 1 < kchunks;
-        if (more) gload((int64_t)(kc + 1) * MG_BK);
-        int4v a[FM], bb[FN];
+        // this wave's copies of stage kc have landed once at most the copies
+        // of the later stages already issued are outstanding
+        const int later = (kchunks - 1 - kc) < (MG_STAGES - 2) ? (kchunks - 1 - kc) : (MG_STAGES - 2);
+        if (later >= 2) __builtin_amdgcn_s_waitcnt(MG_VMCNT(2 * 2 * COPIES));
+        else if (later == 1) __builtin_amdgcn_s_waitcnt(MG_VMCNT(2 * COPIES));
+        else __builtin_amdgcn_s_waitcnt(MG_VMCNT(0));
+        // Every wave's copies of stage kc have landed and every wave is done
+        // reading slot (kc - 1) % MG_STAGES (its LDS reads completed before
+        // its MFMAs).  A plain s_barrier: __syncthreads() would also wait for
+        // the copies of the later stages still in flight.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kc + MG_STAGES - 1 < kchunks) issue(kc + MG_STAGES - 1);
+        const int8_t *la = mg_lds + (kc % MG_STAGES) * 2 * TILE, *lb = la + TILE;
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-            a[i] = *reinterpret_cast<const int4v *>(&lds[buf][0][(wm * WTM + i * 16) * MG_LDS_ROW + frag]);
+        for (int kk = 0; kk < MG_BK / 64; ++kk) {
+            int4v a[FM], bb[FN];
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj)
-            bb[jj] = *reinterpret_cast<const int4v *>(&lds[buf][1][(wn * WTN + jj * 16) * MG_LDS_ROW + frag]);
+            for (int i = 0; i < FM; ++i) {
+                const int r = wm * WTM + i * 16 + frow;
+                a[i] = *reinterpret_cast<const int4v *>(la + r * MG_BK + 16 * ((kk * 4 + fchunk) ^ mg_swz(r)));
+            }
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+            for (int jj = 0; jj < FN; ++jj) {
+                const int r = wn * WTN + jj * 16 + frow;
+                bb[jj] = *reinterpret_cast<const int4v *>(lb + r * MG_BK + 16 * ((kk * 4 + fchunk) ^ mg_swz(r)));
+            }
 #pragma unroll
-            for (int jj = 0; jj < FN; ++jj)
-                acc[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], bb[jj], acc[i][jj], 0, 0, 0);
-        if (more) lstore(buf ^ 1);
-        __syncthreads();
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int jj = 0; jj < FN; ++jj)
+                    acc[i][jj] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], bb[jj], acc[i][jj], 0, 0, 0);
+        }
     }
 
     // y = C mod m_t in [0, m_t): the quotient from FP64 is within one of the
@@ -370,11 +419,18 @@ hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p,
                            dim3((unsigned)((p + 255) / 256), (unsigned)((m + MG_COLMAX_ROWS - 1) / MG_COLMAX_ROWS)),
                            dim3(256), 0, st, J, m, p, ldj, w.cmax);
     const ModConsts mc = mod_consts();
-    hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)(kpad / MG_CV_I)), dim3(256), 0,
+    hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)((kpad + MG_CV_I - 1) / MG_CV_I)), dim3(256), 0,
                        st, J, m, p, ldj, w.cmax, b, mc, w.R, kpad, rplane);
     const int64_t tiles = ppad / MG_BM, tiles_lower = tiles * (tiles + 1) / 2;
     const int64_t per = (tiles_lower * MODS + MG_NXCD - 1) / MG_NXCD;
-    hipLaunchKernelGGL(mg_gemm_kernel, dim3((unsigned)(per * MG_NXCD)), dim3(MG_NT), 0, st, w.R, kpad, rplane,
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void *)mg_gemm_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, MG_LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(mg_gemm_kernel, dim3((unsigned)(per * MG_NXCD)), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad, rplane,
                        (int)(kpad / MG_BK), tiles_lower, per, mc, w.Y, ppad, yplane);
     const CrtConsts cc = crt_consts();
     hipLaunchKernelGGL(mg_crt_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)p), dim3(256), 0, st, w.Y, ppad,
