@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+PEAK_INT8_TOPS = 5000.0  # MI355X dense int8 MFMA
 METRIC = "Gauss-Newton steps/sec at fixed residual max-norm; Gram+Cholesky % FP64-MFMA peak"
 
 
@@ -99,6 +100,58 @@ def split_comparison(inp, mu, steps, target, fp64_elapsed):
         "time_to_target_s": None if reached is None else reached * el / steps,
         "fp64_steps_to_target": steps,
         "fp64_time_to_target_s": fp64_elapsed,
+    }
+
+
+def int8crt_comparison(inp, mu, steps, warmup, fp64_theta, fp64_final, gram_flops):
+    """Gram from int8 matrix products by exact modular arithmetic (precision
+    "int8crt"; residual, gradient, Cholesky and update FP64) from the same
+    start and over the same warm-up and timed steps as the FP64 run: steps/s,
+    the Gram's time, its FP64-equivalent rate and its int8 rate against the
+    int8 MFMA peak, and how far the final iterate is from the FP64 run's."""
+    import torch
+
+    from paper_2509_14185_amd import gn
+
+    prob = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"],
+                      precision="int8crt")
+    prob.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+    theta = torch.from_numpy(inp["theta0"].copy()).cuda()
+    for _ in range(warmup):
+        prob.step(theta, mu, stats=False)
+    torch.cuda.synchronize()
+    prob.profile_enable(True, steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.step(theta, mu, stats=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phases, nrec = prob.profile_read()
+    prob.profile_enable(False)
+    final = prob.eval(theta)["max_abs_R_val"]
+    m = prob.m
+    prob.close()
+    P1 = len(inp["theta0"]) + 1
+    bits, mods = gn.int8_crt_params(m)
+    ppad = -(-P1 // 256) * 256
+    kpad = -(-m // 128) * 128
+    tiles = ppad // 256
+    int8_ops = len(mods) * tiles * (tiles + 1) // 2 * 256 * 256 * kpad * 2
+    t_gram = phases["gram"] / nrec * 1e-3
+    return {
+        "value": steps / el,
+        "unit": "steps/s",
+        "ms_per_step": 1e3 * el / steps,
+        "gram_ms": 1e3 * t_gram,
+        "gram_fp64_equivalent_tflops": gram_flops / t_gram / 1e12,
+        "moduli": len(mods),
+        "bits_per_column": bits,
+        "int8_ops_per_gram": int8_ops,
+        "int8_tops_incl_residues_and_reconstruction": int8_ops / t_gram / 1e12,
+        "int8_peak_tops": PEAK_INT8_TOPS,
+        "max_abs_R_val_final": final,
+        "fp64_max_abs_R_val_final": fp64_final,
+        "theta_rel_diff_vs_fp64": float(torch.linalg.norm(theta - fp64_theta) / torch.linalg.norm(fp64_theta)),
     }
 
 
@@ -499,6 +552,7 @@ def main():
     ap.add_argument("--workload", default="ccf_medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
+    ap.add_argument("--no-int8", action="store_true", help="skip the int8 modular Gram run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched CCF workload")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D IPM-style workload")
     ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt runs")
@@ -614,6 +668,10 @@ def main():
         "gram_cholesky_frac": (fl["gram"] + fl["cholesky"]) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS,
         "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
     }
+    if not args.no_int8:
+        print("[bench] int8 modular Gram", file=sys.stderr, flush=True)
+        out["int8crt"] = int8crt_comparison(inp, mu, args.steps, args.warmup, theta, ev1["max_abs_R_val"],
+                                            fl["gram"])
     if not args.no_split:
         out["split32"] = split_comparison(inp, mu, args.steps, ev1["max_abs_R_val"], elapsed)
     if not args.no_lm:

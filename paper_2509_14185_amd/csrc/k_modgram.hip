@@ -22,9 +22,9 @@
 //        v = sum_t y_t W_t - Q M,  W_t = (M/m_t) ((M/m_t)^-1 mod m_t),
 //      Q = rint(sum_t y_t W_t / M) from FP64 fractions f_t = W_t / M (its
 //      error is far below the margin 1/2 - |v|/M >= 1/4), and the difference
-//      evaluated modulo 2^128 in 64-bit limbs, where it is exact because
-//      |v| < 2^127.  G_jk = v 2^(E_j + E_k - 2b), rounded once to FP64
-//      (two roundings of the limbs: within 2 ulp of the exact sum).
+//      evaluated exactly in four 40-bit limbs held in FP64, normalised by
+//      exact carries.  G_jk = v 2^(E_j + E_k - 2b), summed from the limbs in
+//      FP64 (within 2 ulp of the exact value).
 //
 // A column whose maximum is not finite gives NaN in every entry of its row
 // and column of G.
@@ -64,10 +64,11 @@ struct ModConsts {
     double inv[MODS];  // fl(1 / m_t)
 };
 
+// W_t and M as four 40-bit limbs held exactly in FP64 (W = sum_k w[k] 2^(40k))
 struct CrtConsts {
-    unsigned long long wl[MODS], wh[MODS];  // W_t = wh 2^64 + wl
-    double f[MODS];                         // fl(W_t / M)
-    unsigned long long ml, mh;              // M = mh 2^64 + ml
+    double w[4][MODS];
+    double f[MODS];  // fl(W_t / M)
+    double mlimb[4];
 };
 
 int64_t modgram_kpad(int64_t m) { return (m + MG_BK - 1) / MG_BK * MG_BK; }
@@ -107,6 +108,7 @@ static ModConsts mod_consts() {
 
 static CrtConsts crt_consts() {
     typedef unsigned __int128 u128;
+    const u128 LIMB_MASK = ((u128)1 << 40) - 1;
     u128 M = 1;
     for (int t = 0; t < MODS; ++t) M *= (u128)MODULI[t];
     CrtConsts c{};
@@ -118,12 +120,10 @@ static CrtConsts crt_consts() {
         for (int v = 1; v < mt; ++v)
             if ((r * v) % mt == 1) { inv = v; break; }
         const u128 W = Mt * (u128)inv;  // < M: no reduction needed
-        c.wl[t] = (unsigned long long)W;
-        c.wh[t] = (unsigned long long)(W >> 64);
+        for (int k = 0; k < 4; ++k) c.w[k][t] = (double)(unsigned long long)((W >> (40 * k)) & LIMB_MASK);
         c.f[t] = (double)W / (double)M;
     }
-    c.ml = (unsigned long long)M;
-    c.mh = (unsigned long long)(M >> 64);
+    for (int k = 0; k < 4; ++k) c.mlimb[k] = (double)(unsigned long long)((M >> (40 * k)) & LIMB_MASK);
     return c;
 }
 
@@ -165,65 +165,122 @@ __device__ __forceinline__ bool column_shift(unsigned long long bits, int b, int
 // residues into one 32-bit LDS word per run (odd row stride: the 64 columns
 // of a wave hit distinct banks); the tiles leave as 128-byte row segments.
 // Covers i < kpad and j < ppad; entries outside J (i >= m, j >= p) are zero.
+//
+// |x| <= 2^58 is split exactly into 18-bit parts, |x| = h 2^36 + u 2^18 + l,
+// so that |x| mod m_t = (h (2^36 mod m_t) + u (2^18 mod m_t) + l) mod m_t
+// is a 32-bit reduction by a compile-time constant; the sign is applied to
+// the residue afterwards.
 static constexpr int MG_CV_I = 128, MG_CV_J = 64, MG_CV_G = 4;
 static constexpr int MG_CV_LD = MG_CV_I / 4 + 1;  // 32-bit words per LDS row
+__host__ __device__ constexpr int mg_modulus(int t) {
+    constexpr int m[MODS] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191};
+    return m[t];
+}
+__host__ __device__ constexpr uint32_t mg_pow2_mod(int e, int m) {
+    uint32_t r = 1;
+    for (int i = 0; i < e; ++i) r = (r * 2) % (uint32_t)m;
+    return r;
+}
+static_assert(mg_modulus(0) == MODULI[0] && mg_modulus(MODS - 1) == MODULI[MODS - 1], "modulus table");
+
+template <int T>
+__device__ __forceinline__ uint32_t mg_residue8(uint32_t h, uint32_t u, uint32_t l, bool neg) {
+    constexpr int M = mg_modulus(T);
+    constexpr uint32_t C36 = mg_pow2_mod(36, M), C18 = mg_pow2_mod(18, M);
+    uint32_t r = (h * C36 + u * C18 + l) % (uint32_t)M;  // h < 2^22, u, l < 2^18: no overflow
+    r = (neg && r != 0u) ? (uint32_t)M - r : r;
+    const int ri = r >= (uint32_t)(M + 1) / 2 ? (int)r - M : (int)r;
+    return (uint32_t)ri & 0xffu;
+}
+
+template <int G>
+__device__ __forceinline__ void mg_residue_group(const uint32_t (&h)[32], const uint32_t (&u)[32],
+                                                 const uint32_t (&l)[32], uint32_t negmask, uint32_t *res, int tx,
+                                                 int ty) {
+#pragma unroll
+    for (int tt = 0; tt < MG_CV_G; ++tt) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = 4 * s + q;
+                uint32_t r;
+                switch (G * MG_CV_G + tt) {  // resolved at compile time
+                    case 0: r = mg_residue8<0>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 1: r = mg_residue8<1>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 2: r = mg_residue8<2>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 3: r = mg_residue8<3>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 4: r = mg_residue8<4>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 5: r = mg_residue8<5>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 6: r = mg_residue8<6>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 7: r = mg_residue8<7>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 8: r = mg_residue8<8>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 9: r = mg_residue8<9>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 10: r = mg_residue8<10>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 11: r = mg_residue8<11>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 12: r = mg_residue8<12>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 13: r = mg_residue8<13>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 14: r = mg_residue8<14>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    default: r = mg_residue8<15>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                }
+                w |= r << (8 * q);
+            }
+            res[(tt * MG_CV_J + tx) * MG_CV_LD + 4 * s + ty] = w;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restrict__ J, int64_t m, int64_t p, int64_t ldj,
                                                          const unsigned long long *__restrict__ cmax, int b,
-                                                         ModConsts mc, int8_t *__restrict__ R, int64_t ldr,
-                                                         int64_t rplane) {
+                                                         int8_t *__restrict__ R, int64_t ldr, int64_t rplane) {
     __shared__ uint32_t res[MG_CV_G * MG_CV_J * MG_CV_LD];
     const int tx = threadIdx.x % MG_CV_J, ty = threadIdx.x / MG_CV_J;
     const int64_t j0 = (int64_t)blockIdx.x * MG_CV_J, i0 = (int64_t)blockIdx.y * MG_CV_I;
     const int64_t j = j0 + tx;
     int e = 0;
     const bool live = j < p && column_shift(cmax[j < p ? j : 0], b, e);
-    double x[8][4];  // row i0 + 16 s + 4 ty + q
+    uint32_t h[32], u[32], l[32], negmask = 0;  // element 4 s + q: row i0 + 16 s + 4 ty + q
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t i = i0 + 16 * s + 4 * ty + q;
             const double v = (live && i < m) ? J[i * ldj + j] : 0.0;
-            x[s][q] = rint(ldexp(v, e));
+            const double x = rint(ldexp(v, e));
+            const double xa = fabs(x);
+            const double hd = floor(xa * 0x1p-36), rem = fma(-hd, 0x1p36, xa);  // exact
+            const double ud = floor(rem * 0x1p-18), ld = fma(-ud, 0x1p18, rem);
+            const int k = 4 * s + q;
+            h[k] = (uint32_t)hd;
+            u[k] = (uint32_t)ud;
+            l[k] = (uint32_t)ld;
+            negmask |= (x < 0.0 ? 1u : 0u) << k;
         }
     const int wc = threadIdx.x % (MG_CV_I / 4), wr = threadIdx.x / (MG_CV_I / 4);  // 32 words per row, 8 rows per pass
     const bool wlive = i0 + 4 * wc < ldr;
-#pragma unroll 1
-    for (int g = 0; g < MODS / MG_CV_G; ++g) {
-#pragma unroll
-        for (int tt = 0; tt < MG_CV_G; ++tt) {
-            const int t = g * MG_CV_G + tt;
-            const double md = (double)mc.m[t], inv = mc.inv[t];
-            const int mi = mc.m[t], half = (mc.m[t] + 1) / 2;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                uint32_t w = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double xq = x[s][q];
-                    const double qt = floor(xq * inv);
-                    double r = fma(-qt, md, xq);  // exact: |x - q m| < 2m
-                    r = r < 0.0 ? r + md : r;
-                    r = r >= md ? r - md : r;
-                    int ri = (int)r;
-                    ri = ri >= half ? ri - mi : ri;
-                    w |= ((uint32_t)ri & 0xffu) << (8 * q);
-                }
-                res[(tt * MG_CV_J + tx) * MG_CV_LD + 4 * s + ty] = w;
-            }
-        }
+    auto flush = [&](int g) {
         __syncthreads();
 #pragma unroll
         for (int tt = 0; tt < MG_CV_G; ++tt)
 #pragma unroll
-            for (int h = 0; h < MG_CV_J / 8; ++h) {
-                const int row = wr + 8 * h;
+            for (int hh = 0; hh < MG_CV_J / 8; ++hh) {
+                const int row = wr + 8 * hh;
                 if (wlive)
                     *reinterpret_cast<uint32_t *>(R + (g * MG_CV_G + tt) * rplane + (j0 + row) * ldr + i0 + 4 * wc) =
                         res[(tt * MG_CV_J + row) * MG_CV_LD + wc];
             }
         __syncthreads();
-    }
+    };
+    static_assert(MODS == 4 * MG_CV_G, "four groups of moduli");
+    mg_residue_group<0>(h, u, l, negmask, res, tx, ty);
+    flush(0);
+    mg_residue_group<1>(h, u, l, negmask, res, tx, ty);
+    flush(1);
+    mg_residue_group<2>(h, u, l, negmask, res, tx, ty);
+    flush(2);
+    mg_residue_group<3>(h, u, l, negmask, res, tx, ty);
+    flush(3);
 }
 
 // Work item w (modulus-major, then lower tiles row by row) of block b: the
@@ -374,31 +431,39 @@ __global__ __launch_bounds__(256) void mg_crt_kernel(const uint8_t *__restrict__
         G[j * ldg + k] = 0.0;
         return;
     }
-    unsigned long long y[MODS];
-#pragma unroll
-    for (int t = 0; t < MODS; ++t) y[t] = Y[t * yplane + j * ldy + k];
-    double qs = 0.0;
-#pragma unroll
-    for (int t = 0; t < MODS; ++t) qs = fma((double)y[t], cc.f[t], qs);
-    const unsigned long long Q = (unsigned long long)rint(qs);
-    // u = sum_t y_t W_t - Q M  (mod 2^128)
-    unsigned long long lo = 0, hi = 0;
+    // v = sum_t y_t W_t - Q M limb by limb: every product y w < 2^48 and
+    // every limb sum < 2^52, so the FP64 sums are exact integers
+    double S[4] = {0.0, 0.0, 0.0, 0.0}, qs = 0.0;
 #pragma unroll
     for (int t = 0; t < MODS; ++t) {
-        const unsigned long long a = y[t] * cc.wl[t];
-        const unsigned long long c = __umul64hi(y[t], cc.wl[t]);
-        lo += a;
-        hi += y[t] * cc.wh[t] + c + (lo < a ? 1ull : 0ull);
+        const double y = (double)Y[t * yplane + j * ldy + k];
+        qs = fma(y, cc.f[t], qs);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) S[l] = fma(y, cc.w[l][t], S[l]);
     }
-    const unsigned long long ql = Q * cc.ml, qh = Q * cc.mh + __umul64hi(Q, cc.ml);
-    hi = hi - qh - (lo < ql ? 1ull : 0ull);
-    lo = lo - ql;
-    const bool neg = (long long)hi < 0;
+    const double Q = rint(qs);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) S[l] = fma(-Q, cc.mlimb[l], S[l]);  // |S| < 2^53, exact
+    // carries: limbs 0-2 into [0, 2^40), the sign into limb 3
+    auto normalise = [&]() {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double c = floor(S[l] * 0x1p-40);
+            S[l] = fma(-c, 0x1p40, S[l]);
+            S[l + 1] += c;
+        }
+    };
+    normalise();
+    const bool neg = S[3] < 0.0;
     if (neg) {
-        lo = ~lo + 1ull;
-        hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) S[l] = -S[l];
+        normalise();
     }
-    double v = fma((double)hi, 0x1p64, (double)lo);
+    // |v| from non-negative limbs, largest first (within 2 ulp)
+    double v = fma(S[2], 0x1p80, S[3] * 0x1p120);
+    v = fma(S[1], 0x1p40, v);
+    v += S[0];
     v = neg ? -v : v;
     // G = v 2^(E_j - b) 2^(E_k - b) = v 2^(-(e_j + e_k))
     G[j * ldg + k] = ldexp(v, -(ej + ek));
@@ -420,7 +485,7 @@ hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p,
                            dim3(256), 0, st, J, m, p, ldj, w.cmax);
     const ModConsts mc = mod_consts();
     hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)((kpad + MG_CV_I - 1) / MG_CV_I)), dim3(256), 0,
-                       st, J, m, p, ldj, w.cmax, b, mc, w.R, kpad, rplane);
+                       st, J, m, p, ldj, w.cmax, b, w.R, kpad, rplane);
     const int64_t tiles = ppad / MG_BM, tiles_lower = tiles * (tiles + 1) / 2;
     const int64_t per = (tiles_lower * MODS + MG_NXCD - 1) / MG_NXCD;
     static bool attr = false;

@@ -23,7 +23,10 @@ def test_moduli_coprime_and_small():
         for b in mods[i + 1:]:
             assert math.gcd(a, b) == 1
     M = math.prod(mods)
-    assert M < 2 ** 127  # the 128-bit evaluation needs |v| < 2^127
+    # W_t < M fit four 40-bit limbs, and 16 residues (< 256) times a limb sum
+    # below 2^53: the limb sums are exact in FP64
+    assert M < 2 ** 160
+    assert 16 * 255 * (2 ** 40 - 1) < 2 ** 53
 
 
 @pytest.mark.parametrize("m", [1, 2, 100, 1000, 8193, 65536, 130944])
