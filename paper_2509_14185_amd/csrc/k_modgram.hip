@@ -283,20 +283,40 @@ __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restric
     flush(3);
 }
 
-// Work item w (modulus-major, then lower tiles row by row) of block b: the
-// blocks are dealt round-robin over the XCDs, so XCD x takes the contiguous
-// range [x * per, (x + 1) * per) and its L2 sees one modulus's panels at a time.
-__device__ __forceinline__ bool mg_work(int64_t b, int64_t per, int64_t tiles_lower, int &t, int &tm, int &tn) {
-    const int64_t w = (b % MG_NXCD) * per + b / MG_NXCD;
-    if (w >= tiles_lower * MODS) return false;
-    t = (int)(w / tiles_lower);
-    const int64_t idx = w % tiles_lower;
-    int64_t r = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
-    while (r * (r + 1) / 2 > idx) --r;
-    while ((r + 1) * (r + 2) / 2 <= idx) ++r;
-    tm = (int)r;
-    tn = (int)(idx - r * (r + 1) / 2);
-    return true;
+// Work of block b.  Blocks are dealt round-robin over the 8 XCDs and each XCD
+// runs its share in order, 32 at a time (one per CU).  Block b goes to
+// super-tile (b / 8 / 32) * 8 + b % 8 and tile (b / 8) % 32 of it: each XCD
+// works on one 4 x 8 block of output tiles of one modulus at a time, so a
+// k-chunk of an operand panel is fetched once for 4 or 8 tiles.  Super-tiles
+// are numbered modulus by modulus; in a modulus, row a of super-tiles holds
+// the super-columns 0 .. (4a + 3) / 8 that touch the lower triangle.
+static constexpr int MG_SUP_M = 4, MG_SUP_N = 8, MG_SUP = MG_SUP_M * MG_SUP_N;
+__host__ __device__ inline int64_t mg_lower_supers(int64_t tiles) {
+    const int64_t nsr = (tiles + MG_SUP_M - 1) / MG_SUP_M, nsc = (tiles + MG_SUP_N - 1) / MG_SUP_N;
+    int64_t n = 0;
+    for (int64_t a = 0; a < nsr; ++a) {
+        const int64_t c = (MG_SUP_M * a + MG_SUP_M - 1) / MG_SUP_N + 1;
+        n += c < nsc ? c : nsc;
+    }
+    return n;
+}
+
+__device__ __forceinline__ bool mg_work(int64_t b, int tiles, int64_t supers, int &t, int &tm, int &tn) {
+    const int64_t sidx = (b / MG_NXCD / MG_SUP) * MG_NXCD + b % MG_NXCD;
+    const int i = (int)((b / MG_NXCD) % MG_SUP);
+    if (sidx >= supers * MODS) return false;
+    t = (int)(sidx / supers);
+    int64_t rem = sidx % supers, a = 0;
+    const int64_t nsr = (tiles + MG_SUP_M - 1) / MG_SUP_M, nsc = (tiles + MG_SUP_N - 1) / MG_SUP_N;
+    for (; a < nsr; ++a) {
+        int64_t c = (MG_SUP_M * a + MG_SUP_M - 1) / MG_SUP_N + 1;
+        if (c > nsc) c = nsc;
+        if (rem < c) break;
+        rem -= c;
+    }
+    tm = (int)(a * MG_SUP_M + i % MG_SUP_M);
+    tn = (int)(rem * MG_SUP_N + i / MG_SUP_M);
+    return tm < tiles && tn <= tm;
 }
 
 // C_t = R_t R_t^T mod m_t on the lower MG_BM x MG_BM tiles, MG_WM x MG_WN waves.
@@ -315,7 +335,7 @@ __device__ __forceinline__ bool mg_work(int64_t b, int64_t per, int64_t tiles_lo
 __device__ __forceinline__ int mg_swz(int row) { return (row / (256 / MG_BK)) % (MG_BK / 16); }
 
 __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict__ R, int64_t ldr, int64_t rplane,
-                                                        int kchunks, int64_t tiles_lower, int64_t per, ModConsts mc,
+                                                        int kchunks, int tiles, int64_t supers, ModConsts mc,
                                                         uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane) {
     constexpr int WTM = MG_BM / MG_WM, WTN = MG_BM / MG_WN;
     constexpr int FM = WTM / 16, FN = WTN / 16;
@@ -327,7 +347,7 @@ __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict
     extern __shared__ __attribute__((aligned(16))) int8_t mg_lds[];
 
     int t, tm, tn;
-    if (!mg_work(blockIdx.x, per, tiles_lower, t, tm, tn)) return;
+    if (!mg_work(blockIdx.x, tiles, supers, t, tm, tn)) return;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int wm = wave / MG_WN, wn = wave % MG_WN;
     const int8_t *Ag = R + t * rplane + (int64_t)tm * MG_BM * ldr;
@@ -486,8 +506,9 @@ hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p,
     const ModConsts mc = mod_consts();
     hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)((kpad + MG_CV_I - 1) / MG_CV_I)), dim3(256), 0,
                        st, J, m, p, ldj, w.cmax, b, w.R, kpad, rplane);
-    const int64_t tiles = ppad / MG_BM, tiles_lower = tiles * (tiles + 1) / 2;
-    const int64_t per = (tiles_lower * MODS + MG_NXCD - 1) / MG_NXCD;
+    const int tiles = (int)(ppad / MG_BM);
+    const int64_t supers = mg_lower_supers(tiles);
+    const int64_t blocks = (supers * MODS + MG_NXCD - 1) / MG_NXCD * MG_NXCD * MG_SUP;
     static bool attr = false;
     if (!attr) {
         const hipError_t e = hipFuncSetAttribute((const void *)mg_gemm_kernel,
@@ -495,8 +516,8 @@ hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p,
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(mg_gemm_kernel, dim3((unsigned)(per * MG_NXCD)), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad, rplane,
-                       (int)(kpad / MG_BK), tiles_lower, per, mc, w.Y, ppad, yplane);
+    hipLaunchKernelGGL(mg_gemm_kernel, dim3((unsigned)blocks), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad, rplane,
+                       (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane);
     const CrtConsts cc = crt_consts();
     hipLaunchKernelGGL(mg_crt_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)p), dim3(256), 0, st, w.Y, ppad,
                        yplane, p, w.cmax, b, cc, G, ldg);
