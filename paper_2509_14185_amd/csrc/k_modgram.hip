@@ -166,37 +166,40 @@ __device__ __forceinline__ bool column_shift(unsigned long long bits, int b, int
 // of a wave hit distinct banks); the tiles leave as 128-byte row segments.
 // Covers i < kpad and j < ppad; entries outside J (i >= m, j >= p) are zero.
 //
-// |x| <= 2^58 is split exactly into 18-bit parts, |x| = h 2^36 + u 2^18 + l,
-// so that |x| mod m_t = (h (2^36 mod m_t) + u (2^18 mod m_t) + l) mod m_t
-// is a 32-bit reduction by a compile-time constant; the sign is applied to
-// the residue afterwards.
+// |x| <= 2^58 is split exactly into four 15-bit parts carrying the sign of
+// x, x = p3 2^45 + p2 2^30 + p1 2^15 + p0 with |p_k| < 2^15.  With the balanced
+// constants c_k = 2^(15k) mod m_t in [-m_t/2, m_t/2], t = sum_k p_k c_k is
+// congruent to x and |t| < 4 2^15 2^7 = 2^24, so the FP32 sums are exact
+// integers; r = t - rint(t / m_t) m_t is then exact as well, and one
+// correction each way brings it into the balanced range.
 static constexpr int MG_CV_I = 128, MG_CV_J = 64, MG_CV_G = 4;
 static constexpr int MG_CV_LD = MG_CV_I / 4 + 1;  // 32-bit words per LDS row
 __host__ __device__ constexpr int mg_modulus(int t) {
     constexpr int m[MODS] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191};
     return m[t];
 }
-__host__ __device__ constexpr uint32_t mg_pow2_mod(int e, int m) {
-    uint32_t r = 1;
-    for (int i = 0; i < e; ++i) r = (r * 2) % (uint32_t)m;
-    return r;
+__host__ __device__ constexpr int mg_pow2_bal(int e, int m) {  // 2^e mod m in [-m/2, m/2]
+    int r = 1;
+    for (int i = 0; i < e; ++i) r = (r * 2) % m;
+    return r > m / 2 ? r - m : r;
 }
 static_assert(mg_modulus(0) == MODULI[0] && mg_modulus(MODS - 1) == MODULI[MODS - 1], "modulus table");
 
 template <int T>
-__device__ __forceinline__ uint32_t mg_residue8(uint32_t h, uint32_t u, uint32_t l, bool neg) {
+__device__ __forceinline__ uint32_t mg_residue8(const float (&pk)[4]) {
     constexpr int M = mg_modulus(T);
-    constexpr uint32_t C36 = mg_pow2_mod(36, M), C18 = mg_pow2_mod(18, M);
-    uint32_t r = (h * C36 + u * C18 + l) % (uint32_t)M;  // h < 2^22, u, l < 2^18: no overflow
-    r = (neg && r != 0u) ? (uint32_t)M - r : r;
-    const int ri = r >= (uint32_t)(M + 1) / 2 ? (int)r - M : (int)r;
-    return (uint32_t)ri & 0xffu;
+    constexpr float C1 = (float)mg_pow2_bal(15, M), C2 = (float)mg_pow2_bal(30, M), C3 = (float)mg_pow2_bal(45, M);
+    constexpr float FM = (float)M, INV = 1.0f / (float)M;
+    constexpr float HI = (float)((M - 1) / 2), LO = -(float)(M / 2);  // balanced range [LO, HI]
+    const float t = fmaf(pk[3], C3, fmaf(pk[2], C2, fmaf(pk[1], C1, pk[0])));
+    float r = fmaf(-rintf(t * INV), FM, t);
+    r = r > HI ? r - FM : r;
+    r = r < LO ? r + FM : r;
+    return (uint32_t)(int)r & 0xffu;
 }
 
 template <int G>
-__device__ __forceinline__ void mg_residue_group(const uint32_t (&h)[32], const uint32_t (&u)[32],
-                                                 const uint32_t (&l)[32], uint32_t negmask, uint32_t *res, int tx,
-                                                 int ty) {
+__device__ __forceinline__ void mg_residue_group(const float (&pk)[32][4], uint32_t *res, int tx, int ty) {
 #pragma unroll
     for (int tt = 0; tt < MG_CV_G; ++tt) {
 #pragma unroll
@@ -207,22 +210,22 @@ __device__ __forceinline__ void mg_residue_group(const uint32_t (&h)[32], const 
                 const int e = 4 * s + q;
                 uint32_t r;
                 switch (G * MG_CV_G + tt) {  // resolved at compile time
-                    case 0: r = mg_residue8<0>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 1: r = mg_residue8<1>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 2: r = mg_residue8<2>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 3: r = mg_residue8<3>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 4: r = mg_residue8<4>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 5: r = mg_residue8<5>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 6: r = mg_residue8<6>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 7: r = mg_residue8<7>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 8: r = mg_residue8<8>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 9: r = mg_residue8<9>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 10: r = mg_residue8<10>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 11: r = mg_residue8<11>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 12: r = mg_residue8<12>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 13: r = mg_residue8<13>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    case 14: r = mg_residue8<14>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
-                    default: r = mg_residue8<15>(h[e], u[e], l[e], (negmask >> e) & 1u); break;
+                    case 0: r = mg_residue8<0>(pk[e]); break;
+                    case 1: r = mg_residue8<1>(pk[e]); break;
+                    case 2: r = mg_residue8<2>(pk[e]); break;
+                    case 3: r = mg_residue8<3>(pk[e]); break;
+                    case 4: r = mg_residue8<4>(pk[e]); break;
+                    case 5: r = mg_residue8<5>(pk[e]); break;
+                    case 6: r = mg_residue8<6>(pk[e]); break;
+                    case 7: r = mg_residue8<7>(pk[e]); break;
+                    case 8: r = mg_residue8<8>(pk[e]); break;
+                    case 9: r = mg_residue8<9>(pk[e]); break;
+                    case 10: r = mg_residue8<10>(pk[e]); break;
+                    case 11: r = mg_residue8<11>(pk[e]); break;
+                    case 12: r = mg_residue8<12>(pk[e]); break;
+                    case 13: r = mg_residue8<13>(pk[e]); break;
+                    case 14: r = mg_residue8<14>(pk[e]); break;
+                    default: r = mg_residue8<15>(pk[e]); break;
                 }
                 w |= r << (8 * q);
             }
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restric
     const int64_t j = j0 + tx;
     int e = 0;
     const bool live = j < p && column_shift(cmax[j < p ? j : 0], b, e);
-    uint32_t h[32], u[32], l[32], negmask = 0;  // element 4 s + q: row i0 + 16 s + 4 ty + q
+    float pk[32][4];  // element 4 s + q: row i0 + 16 s + 4 ty + q
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
@@ -248,14 +251,16 @@ __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restric
             const int64_t i = i0 + 16 * s + 4 * ty + q;
             const double v = (live && i < m) ? J[i * ldj + j] : 0.0;
             const double x = rint(ldexp(v, e));
-            const double xa = fabs(x);
-            const double hd = floor(xa * 0x1p-36), rem = fma(-hd, 0x1p36, xa);  // exact
-            const double ud = floor(rem * 0x1p-18), ld = fma(-ud, 0x1p18, rem);
+            // exact 15-bit parts of |x|, signed like x
+            const double xa = fabs(x), sg = x < 0.0 ? -1.0 : 1.0;
+            const double d3 = floor(xa * 0x1p-45), r3 = fma(-d3, 0x1p45, xa);
+            const double d2 = floor(r3 * 0x1p-30), r2 = fma(-d2, 0x1p30, r3);
+            const double d1 = floor(r2 * 0x1p-15), d0 = fma(-d1, 0x1p15, r2);
             const int k = 4 * s + q;
-            h[k] = (uint32_t)hd;
-            u[k] = (uint32_t)ud;
-            l[k] = (uint32_t)ld;
-            negmask |= (x < 0.0 ? 1u : 0u) << k;
+            pk[k][0] = (float)(sg * d0);
+            pk[k][1] = (float)(sg * d1);
+            pk[k][2] = (float)(sg * d2);
+            pk[k][3] = (float)(sg * d3);
         }
     const int wc = threadIdx.x % (MG_CV_I / 4), wr = threadIdx.x / (MG_CV_I / 4);  // 32 words per row, 8 rows per pass
     const bool wlive = i0 + 4 * wc < ldr;
@@ -273,13 +278,13 @@ __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restric
         __syncthreads();
     };
     static_assert(MODS == 4 * MG_CV_G, "four groups of moduli");
-    mg_residue_group<0>(h, u, l, negmask, res, tx, ty);
+    mg_residue_group<0>(pk, res, tx, ty);
     flush(0);
-    mg_residue_group<1>(h, u, l, negmask, res, tx, ty);
+    mg_residue_group<1>(pk, res, tx, ty);
     flush(1);
-    mg_residue_group<2>(h, u, l, negmask, res, tx, ty);
+    mg_residue_group<2>(pk, res, tx, ty);
     flush(2);
-    mg_residue_group<3>(h, u, l, negmask, res, tx, ty);
+    mg_residue_group<3>(pk, res, tx, ty);
     flush(3);
 }
 
