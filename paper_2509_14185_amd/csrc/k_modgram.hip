@@ -136,7 +136,7 @@ __global__ void mg_zero_kernel(unsigned long long *__restrict__ x, int64_t n) {
 }
 
 // cmax[j] = bits of max_i |J_ij| (ordered like the magnitudes; NaN above Inf)
-static constexpr int MG_COLMAX_ROWS = 256;
+static constexpr int MG_COLMAX_ROWS = 64;
 __global__ void mg_colmax_kernel(const double *__restrict__ J, int64_t m, int64_t p, int64_t ldj,
                                  unsigned long long *__restrict__ cmax) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,6 +144,7 @@ __global__ void mg_colmax_kernel(const double *__restrict__ J, int64_t m, int64_
     const int64_t i0 = (int64_t)blockIdx.y * MG_COLMAX_ROWS;
     const int64_t i1 = i0 + MG_COLMAX_ROWS < m ? i0 + MG_COLMAX_ROWS : m;
     unsigned long long mx = 0;
+#pragma unroll 8
     for (int64_t i = i0; i < i1; ++i) {
         const unsigned long long bits = (unsigned long long)__double_as_longlong(J[i * ldj + j]) & ABS_MASK;
         mx = bits > mx ? bits : mx;
