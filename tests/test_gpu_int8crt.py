@@ -110,6 +110,25 @@ def test_int8_gram_exact(handle, m, p):
     assert np.all(d <= bound[low] + ULP2 * np.abs(Go[low]))
 
 
+def test_int8_gram_strided_with_gradient(handle):
+    """J as a view with ldJ > p, and g = J^T r returned with the Gram."""
+    m, p, ld = 400, 150, 203
+    J = synthetic_J(m, p, seed=9)
+    buf = np.full((m, ld), np.nan)
+    buf[:, :p] = J
+    Jd = dev(buf)[:, :p]
+    r = np.random.default_rng(10).standard_normal(m)
+    G, g = handle.gram(Jd, dev(r))
+    Gd = G.cpu().numpy()
+    b, _ = gn.int8_crt_params(m)
+    pairs = [(j, k) for j in range(p) for k in range(j + 1) if (3 * j + k) % 7 == 0]
+    want = exact_entries(J, b, pairs)
+    got = np.array([Gd[j, k] for j, k in pairs])
+    assert np.all(np.abs(got - want) <= ULP2 * np.abs(want))
+    _, go = ogn.gram_and_gradient(J, r)
+    assert rel(g.cpu().numpy(), go) < 1e-12
+
+
 def test_int8_gram_nonfinite_column(handle):
     m, p = 200, 40
     J = synthetic_J(m, p, seed=3)
