@@ -160,11 +160,11 @@ __device__ __forceinline__ bool column_shift(unsigned long long bits, int b, int
     return true;
 }
 
-// Residues: a 128 (i) x 64 (j) block of J becomes MODS int8 tiles R_t[j][i],
+// Residues: a 64 (i) x 64 (j) block of J becomes MODS int8 tiles R_t[j][i],
 // transposed through LDS four moduli at a time.  Each thread holds the
-// integers of 8 runs of 4 consecutive rows of one column and packs their
+// integers of 4 runs of 4 consecutive rows of one column and packs their
 // residues into one 32-bit LDS word per run (odd row stride: the 64 columns
-// of a wave hit distinct banks); the tiles leave as 128-byte row segments.
+// of a wave hit distinct banks); the tiles leave as 64-byte row segments.
 // Covers i < kpad and j < ppad; entries outside J (i >= m, j >= p) are zero.
 //
 // |x| <= 2^58 is split exactly into four 15-bit parts carrying the sign of
@@ -173,8 +173,9 @@ __device__ __forceinline__ bool column_shift(unsigned long long bits, int b, int
 // congruent to x and |t| < 4 2^15 2^7 = 2^24, so the FP32 sums are exact
 // integers; r = t - rint(t / m_t) m_t is then exact as well, and one
 // correction each way brings it into the balanced range.
-static constexpr int MG_CV_I = 128, MG_CV_J = 64, MG_CV_G = 4;
+static constexpr int MG_CV_I = 64, MG_CV_J = 64, MG_CV_G = 4;
 static constexpr int MG_CV_LD = MG_CV_I / 4 + 1;  // 32-bit words per LDS row
+static constexpr int MG_CV_S = MG_CV_I / 16;       // runs of 4 rows per thread
 __host__ __device__ constexpr int mg_modulus(int t) {
     constexpr int m[MODS] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191};
     return m[t];
@@ -200,11 +201,11 @@ __device__ __forceinline__ uint32_t mg_residue8(const float (&pk)[4]) {
 }
 
 template <int G>
-__device__ __forceinline__ void mg_residue_group(const float (&pk)[32][4], uint32_t *res, int tx, int ty) {
+__device__ __forceinline__ void mg_residue_group(const float (&pk)[4 * MG_CV_S][4], uint32_t *res, int tx, int ty) {
 #pragma unroll
     for (int tt = 0; tt < MG_CV_G; ++tt) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < MG_CV_S; ++s) {
             uint32_t w = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -244,9 +245,9 @@ __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restric
     const int64_t j = j0 + tx;
     int e = 0;
     const bool live = j < p && column_shift(cmax[j < p ? j : 0], b, e);
-    float pk[32][4];  // element 4 s + q: row i0 + 16 s + 4 ty + q
+    float pk[4 * MG_CV_S][4];  // element 4 s + q: row i0 + 16 s + 4 ty + q
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
+    for (int s = 0; s < MG_CV_S; ++s)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t i = i0 + 16 * s + 4 * ty + q;
@@ -263,15 +264,16 @@ __global__ __launch_bounds__(256) void mg_residue_kernel(const double *__restric
             pk[k][2] = (float)(sg * d2);
             pk[k][3] = (float)(sg * d3);
         }
-    const int wc = threadIdx.x % (MG_CV_I / 4), wr = threadIdx.x / (MG_CV_I / 4);  // 32 words per row, 8 rows per pass
+    constexpr int WPR = MG_CV_I / 4, RPP = 256 / WPR;  // words per row, rows per pass
+    const int wc = threadIdx.x % WPR, wr = threadIdx.x / WPR;
     const bool wlive = i0 + 4 * wc < ldr;
     auto flush = [&](int g) {
         __syncthreads();
 #pragma unroll
         for (int tt = 0; tt < MG_CV_G; ++tt)
 #pragma unroll
-            for (int hh = 0; hh < MG_CV_J / 8; ++hh) {
-                const int row = wr + 8 * hh;
+            for (int hh = 0; hh < MG_CV_J / RPP; ++hh) {
+                const int row = wr + RPP * hh;
                 if (wlive)
                     *reinterpret_cast<uint32_t *>(R + (g * MG_CV_G + tt) * rplane + (j0 + row) * ldr + i0 + 4 * wc) =
                         res[(tt * MG_CV_J + row) * MG_CV_LD + wc];
