@@ -465,7 +465,8 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
         "warmup": warmup,
         "ms_per_step": 1e3 * elapsed / steps,
         "higher_is_better": True,
-        "dtype": "f64" if precision == "fp64" else "f64 (Gram products f32 hi/lo)",
+        "dtype": {"fp64": "f64", "split32": "f64 (Gram products f32 hi/lo)",
+                  "int8crt": "f64 (Gram from int8 modular products, FP64-exact)"}[precision],
         "data": "synthetic",
         "config": {
             "workload": name,
@@ -561,7 +562,7 @@ def main():
     ap.add_argument("--no-funnel", action="store_true", help="skip the funnel-inference run")
     ap.add_argument("--damping", default="fixed", choices=["fixed", "lm"],
                     help="damping of the steps for --workload ipm2d / bouss2d")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split32"],
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split32", "int8crt"],
                     help="arithmetic of the Gram for --workload ipm2d / bouss2d")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
@@ -696,6 +697,12 @@ def main():
         out["ipm2d"]["config"] = {k: r2["config"][k] for k in ("widths", "params", "rows", "max_abs_R_val_initial",
                                                                "max_abs_R_val_final", "half_sq_norm_initial",
                                                                "half_sq_norm_final", "mu")}
+        if not args.no_int8:
+            r8 = bench_2d("ipm2d", 5, 1, precision="int8crt")
+            out["ipm2d_int8crt"] = {k: r8[k] for k in ("value", "unit", "ms_per_step", "gram_tflops", "phase_ms_per_step")}
+            out["ipm2d_int8crt"]["gram_tflops_note"] = "FP64-equivalent (FP64 Gram flops / int8 Gram time)"
+            out["ipm2d_int8crt"]["half_sq_norm_final"] = r8["config"]["half_sq_norm_final"]
+            out["ipm2d_int8crt"]["fp64_half_sq_norm_final"] = r2["config"]["half_sq_norm_final"]
         if not args.no_lm:
             r3 = bench_2d("ipm2d", 5, 1, damping="lm")
             out["ipm2d_lm"] = {k: r3[k] for k in ("value", "unit", "ms_per_step", "lm")}

@@ -476,6 +476,9 @@ gn_status gram2d(gn_handle h, const double *theta) {
             GN_HIP(h, launch_split(st, h->J, nr, P, h->ldJ, h->Jhi, h->Jlo));
             GN_HIP(h, launch_split_gram(st, h->Jhi, h->Jlo, nr, P, h->ldJ, h->G, h->ldG, c > 0));
             GN_HIP(h, launch_gemv_t(st, h->J, nr, P, h->ldJ, h->r2 + r0, Grow, h->gemv_work, c > 0));
+        } else if (h->precision == GN_INT8_CRT) {  // one chunk holds every row
+            GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
+            GN_HIP(h, launch_modgram(st, h->J, nr, P + 1, h->ldJ, h->G, h->ldG, h->mg));
         } else {
             GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
             GN_HIP(h, launch_dgemm(st, gram_desc_rows(h, nr, c > 0 ? 1.0 : 0.0)));
@@ -547,7 +550,6 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (!two_d && prob->equation != GN_EQ_CCF1D && prob->equation != GN_EQ_BURGERS1D) return GN_EINVAL;
     if (prob->precision != GN_FP64 && prob->precision != GN_SPLIT32 && prob->precision != GN_INT8_CRT)
         return GN_EINVAL;
-    if (prob->precision == GN_INT8_CRT && two_d) return GN_EINVAL;
     if (!(prob->lam > 0.0) || !(prob->c_norm >= 0.0) || prob->row_chunk < 0) return GN_EINVAL;
     if (two_d) {
         const int nout = prob->equation == GN_EQ_IPM2D ? 1 : 3;
@@ -841,6 +843,12 @@ gn_status gn_set_points_2d(gn_handle h, int64_t n, const double *d_s, int64_t n1
     if (n1 > 0 && h->equation != GN_EQ_IPM2D) return fail(h, GN_EINVAL, "d1 rows are defined for GN_EQ_IPM2D%s");
     if (ne < 0 || (ne > 0 && !d_se)) return fail(h, GN_EINVAL, "bad boundary point set%s");
     if (n_val < 0 || (n_val > 0 && !d_sval)) return fail(h, GN_EINVAL, "bad validation grid%s");
+    if (h->precision == GN_INT8_CRT) {
+        const int64_t rows = RowMap2D{n, n1, ne, h->n_eq}.rows();
+        if ((h->row_chunk > 0 && h->row_chunk < rows) || rows > GN_INT8_CRT_MAX_ROWS)
+            return fail(h, GN_EINVAL, "the int8 Gram takes one row chunk of at most %s rows",
+                        std::to_string(GN_INT8_CRT_MAX_ROWS).c_str());
+    }
     GN_HIP(h, hipStreamSynchronize(h->stream));
     free_list(h->pt_allocs);
     ++h->points_gen;
@@ -874,6 +882,16 @@ gn_status gn_set_points_2d(gn_handle h, int64_t n, const double *d_s, int64_t n1
     if (s == GN_OK) s = dev_alloc(h, A, &h->G, (P + 1) * h->ldG);
     if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jhi, h->rows_ws * h->ldJ);
     if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jlo, h->rows_ws * h->ldJ);
+    h->mg = ModgramWork{};
+    if (h->precision == GN_INT8_CRT) {
+        h->mg.r_bytes = modgram_r_bytes(m, P + 1);
+        h->mg.y_bytes = modgram_y_bytes(P + 1);
+        h->mg.cmax_len = modgram_ppad(P + 1);
+        h->mg.rows = m;
+        if (s == GN_OK) s = dev_alloc(h, A, &h->mg.R, h->mg.r_bytes);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->mg.Y, h->mg.y_bytes);
+        if (s == GN_OK) s = dev_alloc(h, A, &h->mg.cmax, h->mg.cmax_len);
+    }
     if (s == GN_OK) s = dev_alloc(h, A, &h->partial, nparts * P);
     if (s != GN_OK) {
         free_list(A);

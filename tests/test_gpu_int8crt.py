@@ -19,6 +19,7 @@ import torch
 import workloads
 from oracle import gn as ogn
 from oracle import profile1d as p1
+from oracle import profile2d as p2
 from paper_2509_14185_amd import gn
 
 pytestmark = pytest.mark.gpu
@@ -181,9 +182,37 @@ def test_int8_step(case):
     assert abs(st["half_sq_norm"] - ost["half_sq_norm"]) <= 1e-12 * ost["half_sq_norm"]
 
 
-def test_int8_two_d_rejected():
+def _problem_2d(name, over, row_chunk=0):
+    inp = workloads.make_inputs_2d(name, **over)
+    pg = gn.Problem(inp["equation"], inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"],
+                    precision="int8crt", row_chunk=row_chunk)
+    return inp, pg
+
+
+@pytest.mark.parametrize("name,over", [("ipm2d", dict(n=64, n1=16, ne=8, widths=[2, 12, 12, 1], nval=64)),
+                                       ("bouss2d", dict(n=60, ne=8, widths=[2, 10, 10, 3], nval=64))])
+def test_int8_step_2d(name, over):
+    """2D problems whose J is formed in one chunk: the step against the oracle."""
+    inp, pg = _problem_2d(name, over)
+    pg.set_points_2d(inp["s"], inp["s1"] if inp["n1"] else None, inp["se"], inp["sval"])
+    po = p2.Problem.from_inputs(inp)
+    theta, mu = inp["theta0"], 1e-3
+    t = dev(theta)
+    st = pg.step(t, mu)
+    assert st["rc"] == gn.GN_OK and st["updated"] == 1
+    d = t.cpu().numpy() - theta
+    ref, ost = ogn.step(po, theta, mu)
+    assert ogn.backward_error(ost["G"], mu, ost["g"], d) < 5e-14
+    kappa = np.linalg.cond(ost["G"] + mu * np.eye(len(theta)))
+    assert rel(d, ref - theta) < max(1e-12, 10 * kappa * EPS)
+    pg.close()
+
+
+def test_int8_two_d_chunked_rejected():
+    inp, pg = _problem_2d("bouss2d", dict(n=70, ne=6, widths=[2, 9, 11, 3], nval=16), row_chunk=37)
     with pytest.raises(gn.GNError):
-        gn.Problem("ipm2d", [2, 8, 1], 0.4721, precision="int8crt")
+        pg.set_points_2d(inp["s"], None, inp["se"], inp["sval"])
+    pg.close()
 
 
 def test_int8_gram_full_size():
