@@ -79,8 +79,8 @@ typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1, GN_EQ_IPM2D = 3, GN_EQ_BOUS
  * products, summed in FP64 every 32 rows (about 1e-7 relative error in G);
  * the residual, g = J^T r, the Cholesky and the update stay FP64, so the
  * step is an inexact Newton step with the same fixed point.
- * GN_INT8_CRT (at most 130944 rows; 2D problems with J in one row chunk,
- * i.e. row_chunk 0 or at least the row count): G = J^T J from int8 matrix
+ * GN_INT8_CRT (at most 130944 rows per row chunk; a 2D problem streamed in
+ * several chunks forms J twice, once for the column maxima): G = J^T J from int8 matrix
  * products by exact modular arithmetic.  Each column of J is scaled by a
  * power of two and rounded to a b-bit integer (b = 54 for 8193 rows), the
  * integer Gram is formed exactly from its residues modulo 16 coprime moduli

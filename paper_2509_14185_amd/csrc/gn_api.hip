@@ -469,6 +469,23 @@ gn_status gram2d(gn_handle h, const double *theta) {
     hipStream_t st = h->stream;
     const int64_t P = h->md.P, m = total_rows(h);
     double *Grow = h->G + P * h->ldG;
+    if (h->precision == GN_INT8_CRT) {
+        // Column maxima need every row before the first residue: with more
+        // than one chunk, J is formed twice (maxima, then residues).
+        const int b = modgram_bits(m);
+        const bool one = h->rows_ws >= m;
+        GN_HIP(h, launch_modgram_begin(st, P + 1, h->mg));
+        for (int pass = one ? 1 : 0; pass < 2; ++pass)
+            for (int64_t r0 = 0, c = 0; r0 < m; r0 += h->rows_ws, ++c) {
+                const int64_t nr = (m - r0) < h->rows_ws ? (m - r0) : h->rows_ws;
+                GN_TRY(jac_rows2d(h, theta, r0, nr, h->J, h->ldJ));
+                GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
+                if (pass == 0 || one) GN_HIP(h, launch_modgram_colmax(st, h->J, nr, P + 1, h->ldJ, h->mg));
+                if (pass == 1) GN_HIP(h, launch_modgram_chunk(st, h->J, nr, P + 1, h->ldJ, b, h->mg, c > 0));
+            }
+        GN_HIP(h, launch_modgram_finish(st, P + 1, b, h->G, h->ldG, h->mg));
+        return GN_OK;
+    }
     for (int64_t r0 = 0, c = 0; r0 < m; r0 += h->rows_ws, ++c) {
         const int64_t nr = (m - r0) < h->rows_ws ? (m - r0) : h->rows_ws;
         GN_TRY(jac_rows2d(h, theta, r0, nr, h->J, h->ldJ));
@@ -476,9 +493,6 @@ gn_status gram2d(gn_handle h, const double *theta) {
             GN_HIP(h, launch_split(st, h->J, nr, P, h->ldJ, h->Jhi, h->Jlo));
             GN_HIP(h, launch_split_gram(st, h->Jhi, h->Jlo, nr, P, h->ldJ, h->G, h->ldG, c > 0));
             GN_HIP(h, launch_gemv_t(st, h->J, nr, P, h->ldJ, h->r2 + r0, Grow, h->gemv_work, c > 0));
-        } else if (h->precision == GN_INT8_CRT) {  // one chunk holds every row
-            GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
-            GN_HIP(h, launch_modgram(st, h->J, nr, P + 1, h->ldJ, h->G, h->ldG, h->mg));
         } else {
             GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
             GN_HIP(h, launch_dgemm(st, gram_desc_rows(h, nr, c > 0 ? 1.0 : 0.0)));
@@ -845,8 +859,9 @@ gn_status gn_set_points_2d(gn_handle h, int64_t n, const double *d_s, int64_t n1
     if (n_val < 0 || (n_val > 0 && !d_sval)) return fail(h, GN_EINVAL, "bad validation grid%s");
     if (h->precision == GN_INT8_CRT) {
         const int64_t rows = RowMap2D{n, n1, ne, h->n_eq}.rows();
-        if ((h->row_chunk > 0 && h->row_chunk < rows) || rows > GN_INT8_CRT_MAX_ROWS)
-            return fail(h, GN_EINVAL, "the int8 Gram takes one row chunk of at most %s rows",
+        const int64_t chunk = (h->row_chunk > 0 && h->row_chunk < rows) ? h->row_chunk : rows;
+        if (chunk > GN_INT8_CRT_MAX_ROWS)
+            return fail(h, GN_EINVAL, "the int8 Gram takes row chunks of at most %s rows",
                         std::to_string(GN_INT8_CRT_MAX_ROWS).c_str());
     }
     GN_HIP(h, hipStreamSynchronize(h->stream));
@@ -884,10 +899,10 @@ gn_status gn_set_points_2d(gn_handle h, int64_t n, const double *d_s, int64_t n1
     if (s == GN_OK && h->precision == GN_SPLIT32) s = dev_alloc(h, A, &h->Jlo, h->rows_ws * h->ldJ);
     h->mg = ModgramWork{};
     if (h->precision == GN_INT8_CRT) {
-        h->mg.r_bytes = modgram_r_bytes(m, P + 1);
+        h->mg.r_bytes = modgram_r_bytes(h->rows_ws, P + 1);
         h->mg.y_bytes = modgram_y_bytes(P + 1);
         h->mg.cmax_len = modgram_ppad(P + 1);
-        h->mg.rows = m;
+        h->mg.rows = h->rows_ws;
         if (s == GN_OK) s = dev_alloc(h, A, &h->mg.R, h->mg.r_bytes);
         if (s == GN_OK) s = dev_alloc(h, A, &h->mg.Y, h->mg.y_bytes);
         if (s == GN_OK) s = dev_alloc(h, A, &h->mg.cmax, h->mg.cmax_len);

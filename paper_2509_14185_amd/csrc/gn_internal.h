@@ -207,6 +207,12 @@ int modgram_moduli();
 void modgram_list(int32_t *out);
 hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, double *G, int64_t ldg,
                           const ModgramWork &w);
+hipError_t launch_modgram_begin(hipStream_t st, int64_t p, const ModgramWork &w);
+hipError_t launch_modgram_colmax(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj,
+                                 const ModgramWork &w);
+hipError_t launch_modgram_chunk(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, int b,
+                                const ModgramWork &w, int accumulate);
+hipError_t launch_modgram_finish(hipStream_t st, int64_t p, int b, double *G, int64_t ldg, const ModgramWork &w);
 
 hipError_t launch_split(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, float *hi, float *lo);
 hipError_t launch_split_gram(hipStream_t st, const float *hi, const float *lo, int64_t m, int64_t p, int64_t lda,

@@ -344,7 +344,8 @@ __device__ __forceinline__ int mg_swz(int row) { return (row / (256 / MG_BK)) % 
 
 __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict__ R, int64_t ldr, int64_t rplane,
                                                         int kchunks, int tiles, int64_t supers, ModConsts mc,
-                                                        uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane) {
+                                                        uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane,
+                                                        int accumulate) {
     constexpr int WTM = MG_BM / MG_WM, WTN = MG_BM / MG_WN;
     constexpr int FM = WTM / 16, FN = WTN / 16;
     constexpr int CPR = MG_BK / 16;                   // 16-byte chunks per tile row
@@ -437,6 +438,10 @@ __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict
                 y = y >= md ? y - md : y;
                 const int64_t row = (int64_t)tm * MG_BM + wm * WTM + i * 16 + (lane / 16) * 4 + r;
                 const int64_t col = (int64_t)tn * MG_BM + wn * WTN + jj * 16 + lane % 16;
+                if (accumulate) {  // earlier row chunks: residues add modulo m_t
+                    y += Yt[row * ldy + col];
+                    y = y >= md ? y - md : y;
+                }
                 Yt[row * ldy + col] = (uint8_t)y;
             }
 }
@@ -497,23 +502,39 @@ __global__ __launch_bounds__(256) void mg_crt_kernel(const uint8_t *__restrict__
     G[j * ldg + k] = ldexp(v, -(ej + ek));
 }
 
-hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, double *G, int64_t ldg,
-                          const ModgramWork &w) {
+// The Gram in phases, for J formed in row chunks: begin (column maxima
+// cleared), colmax over every chunk, then per chunk the residues and their
+// products (accumulated modulo m_t after the first chunk), and finish (the
+// reconstruction).  b comes from the total row count.
+hipError_t launch_modgram_begin(hipStream_t st, int64_t p, const ModgramWork &w) {
+    const int64_t ppad = modgram_ppad(p);
+    if (p <= 0) return hipSuccess;
+    if (ppad > w.cmax_len) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mg_zero_kernel, dim3((unsigned)((ppad + 255) / 256)), dim3(256), 0, st, w.cmax, ppad);
+    return hipGetLastError();
+}
+
+hipError_t launch_modgram_colmax(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj,
+                                 const ModgramWork &w) {
+    if (p <= 0 || m <= 0) return hipSuccess;
+    if (modgram_ppad(p) > w.cmax_len) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mg_colmax_kernel,
+                       dim3((unsigned)((p + 255) / 256), (unsigned)((m + MG_COLMAX_ROWS - 1) / MG_COLMAX_ROWS)),
+                       dim3(256), 0, st, J, m, p, ldj, w.cmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_modgram_chunk(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, int b,
+                                const ModgramWork &w, int accumulate) {
     if (p <= 0) return hipSuccess;
     if (m > MG_K_LIMIT) return hipErrorInvalidValue;
     const int64_t kpad = modgram_kpad(m < 1 ? 1 : m), ppad = modgram_ppad(p);
     if (modgram_r_bytes(m < 1 ? 1 : m, p) > w.r_bytes || modgram_y_bytes(p) > w.y_bytes || ppad > w.cmax_len)
         return hipErrorInvalidValue;
-    const int b = modgram_bits(m);
     const int64_t rplane = ppad * kpad, yplane = ppad * ppad;
-    hipLaunchKernelGGL(mg_zero_kernel, dim3((unsigned)((ppad + 255) / 256)), dim3(256), 0, st, w.cmax, ppad);
-    if (m > 0)
-        hipLaunchKernelGGL(mg_colmax_kernel,
-                           dim3((unsigned)((p + 255) / 256), (unsigned)((m + MG_COLMAX_ROWS - 1) / MG_COLMAX_ROWS)),
-                           dim3(256), 0, st, J, m, p, ldj, w.cmax);
     const ModConsts mc = mod_consts();
-    hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)((kpad + MG_CV_I - 1) / MG_CV_I)), dim3(256), 0,
-                       st, J, m, p, ldj, w.cmax, b, w.R, kpad, rplane);
+    hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)((kpad + MG_CV_I - 1) / MG_CV_I)),
+                       dim3(256), 0, st, J, m, p, ldj, w.cmax, b, w.R, kpad, rplane);
     const int tiles = (int)(ppad / MG_BM);
     const int64_t supers = mg_lower_supers(tiles);
     const int64_t blocks = (supers * MODS + MG_NXCD - 1) / MG_NXCD * MG_NXCD * MG_SUP;
@@ -525,11 +546,30 @@ hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p,
         attr = true;
     }
     hipLaunchKernelGGL(mg_gemm_kernel, dim3((unsigned)blocks), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad, rplane,
-                       (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane);
+                       (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_modgram_finish(hipStream_t st, int64_t p, int b, double *G, int64_t ldg, const ModgramWork &w) {
+    if (p <= 0) return hipSuccess;
+    const int64_t ppad = modgram_ppad(p);
+    if (modgram_y_bytes(p) > w.y_bytes || ppad > w.cmax_len) return hipErrorInvalidValue;
     const CrtConsts cc = crt_consts();
     hipLaunchKernelGGL(mg_crt_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)p), dim3(256), 0, st, w.Y, ppad,
-                       yplane, p, w.cmax, b, cc, G, ldg);
+                       ppad * ppad, p, w.cmax, b, cc, G, ldg);
     return hipGetLastError();
+}
+
+hipError_t launch_modgram(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, double *G, int64_t ldg,
+                          const ModgramWork &w) {
+    if (p <= 0) return hipSuccess;
+    if (m > MG_K_LIMIT) return hipErrorInvalidValue;
+    const int b = modgram_bits(m);
+    hipError_t e = launch_modgram_begin(st, p, w);
+    if (e == hipSuccess) e = launch_modgram_colmax(st, J, m, p, ldj, w);
+    if (e == hipSuccess) e = launch_modgram_chunk(st, J, m, p, ldj, b, w, 0);
+    if (e == hipSuccess) e = launch_modgram_finish(st, p, b, G, ldg, w);
+    return e;
 }
 
 }  // namespace gn

@@ -208,8 +208,28 @@ def test_int8_step_2d(name, over):
     pg.close()
 
 
-def test_int8_two_d_chunked_rejected():
-    inp, pg = _problem_2d("bouss2d", dict(n=70, ne=6, widths=[2, 9, 11, 3], nval=16), row_chunk=37)
+@pytest.mark.parametrize("chunk", [37, 100])
+def test_int8_step_2d_chunked(chunk):
+    """J streamed in row chunks (formed twice: column maxima, then residues
+    whose products accumulate modulo m_t): the step against the oracle."""
+    inp, pg = _problem_2d("bouss2d", dict(n=70, ne=6, widths=[2, 9, 11, 3], nval=16), row_chunk=chunk)
+    pg.set_points_2d(inp["s"], None, inp["se"], inp["sval"])
+    po = p2.Problem.from_inputs(inp)
+    theta, mu = inp["theta0"], 1e-3
+    t = dev(theta)
+    st = pg.step(t, mu)
+    assert st["rc"] == gn.GN_OK and st["updated"] == 1
+    d = t.cpu().numpy() - theta
+    ref, ost = ogn.step(po, theta, mu)
+    assert ogn.backward_error(ost["G"], mu, ost["g"], d) < 5e-14
+    kappa = np.linalg.cond(ost["G"] + mu * np.eye(len(theta)))
+    assert rel(d, ref - theta) < max(1e-12, 10 * kappa * EPS)
+    pg.close()
+
+
+def test_int8_two_d_oversize_rejected():
+    # 3 x 43700 + 8 + 1 = 131109 rows in one chunk: more than the int8 Gram takes
+    inp, pg = _problem_2d("bouss2d", dict(n=43700, ne=8, widths=[2, 4, 3], nval=16))
     with pytest.raises(gn.GNError):
         pg.set_points_2d(inp["s"], None, inp["se"], inp["sval"])
     pg.close()
