@@ -342,10 +342,10 @@ __device__ __forceinline__ bool mg_work(int64_t b, int tiles, int64_t supers, in
 // distinct chunk positions.
 __device__ __forceinline__ int mg_swz(int row) { return (row / (256 / MG_BK)) % (MG_BK / 16); }
 
+template <bool ACC>
 __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict__ R, int64_t ldr, int64_t rplane,
                                                         int kchunks, int tiles, int64_t supers, ModConsts mc,
-                                                        uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane,
-                                                        int accumulate) {
+                                                        uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane) {
     constexpr int WTM = MG_BM / MG_WM, WTN = MG_BM / MG_WN;
     constexpr int FM = WTM / 16, FN = WTN / 16;
     constexpr int CPR = MG_BK / 16;                   // 16-byte chunks per tile row
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict
                 y = y >= md ? y - md : y;
                 const int64_t row = (int64_t)tm * MG_BM + wm * WTM + i * 16 + (lane / 16) * 4 + r;
                 const int64_t col = (int64_t)tn * MG_BM + wn * WTN + jj * 16 + lane % 16;
-                if (accumulate) {  // earlier row chunks: residues add modulo m_t
+                if (ACC) {  // earlier row chunks: residues add modulo m_t
                     y += Yt[row * ldy + col];
                     y = y >= md ? y - md : y;
                 }
@@ -540,13 +540,20 @@ hipError_t launch_modgram_chunk(hipStream_t st, const double *J, int64_t m, int6
     const int64_t blocks = (supers * MODS + MG_NXCD - 1) / MG_NXCD * MG_NXCD * MG_SUP;
     static bool attr = false;
     if (!attr) {
-        const hipError_t e = hipFuncSetAttribute((const void *)mg_gemm_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, MG_LDS_BYTES);
+        hipError_t e = hipFuncSetAttribute((const void *)mg_gemm_kernel<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, MG_LDS_BYTES);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)mg_gemm_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    MG_LDS_BYTES);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(mg_gemm_kernel, dim3((unsigned)blocks), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad, rplane,
-                       (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane, accumulate);
+    if (accumulate)
+        hipLaunchKernelGGL(mg_gemm_kernel<true>, dim3((unsigned)blocks), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad,
+                           rplane, (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane);
+    else
+        hipLaunchKernelGGL(mg_gemm_kernel<false>, dim3((unsigned)blocks), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad,
+                           rplane, (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane);
     return hipGetLastError();
 }
 
