@@ -189,3 +189,48 @@ def test_oracle_step_on_2d_problem():
     # the step minimises the damped model |r + J d|^2 + mu |d|^2, so it is below d = 0
     d, r, J = nxt - th, st["r"], st["J"]
     assert np.sum((r + J @ d) ** 2) + 1e-3 * d @ d < r @ r
+
+
+def sym_residuals(theta, widths, lam, equation):
+    """The residual expressions of each equation (sympy), from the fields."""
+    F = sym_fields(theta, widths, lam, equation)
+    if equation == p2.IPM2D:
+        Phi = F[0]
+        return [Phi + ((1 + lam) * Y1 + Phi) * sp.diff(Phi, Y1) + (1 + lam) * Y2 * sp.diff(Phi, Y2)]
+    Om, Th, Ps = F
+    V1, V2 = (1 + lam) * Y1 - sp.diff(Ps, Y2), (1 + lam) * Y2 + sp.diff(Ps, Y1)
+    return [Om + V1 * sp.diff(Om, Y1) + V2 * sp.diff(Om, Y2) - sp.diff(Th, Y1),
+            (1 - lam) * Th + V1 * sp.diff(Th, Y1) + V2 * sp.diff(Th, Y2),
+            sp.diff(Ps, Y1, 2) + sp.diff(Ps, Y2, 2) - Om]
+
+
+@pytest.mark.parametrize("equation", [p2.IPM2D, p2.BOUSS2D])
+def test_validation_and_train_max_against_sympy(tiny, equation):
+    """Paper: Methods, "Validation Metrics for Solutions" (max |R| over a
+    grid).  Each grid point is mapped to y = s/(1-s) here and every
+    equation's residual is evaluated symbolically; the maxima must agree, and
+    the validation and collocation maxima must differ (an oracle that mixed up
+    the two grids, or dropped an equation, fails)."""
+    widths, theta = tiny
+    name = "ipm2d" if equation == p2.IPM2D else "bouss2d"
+    if equation == p2.IPM2D:
+        widths = widths[:-1] + [1]
+        theta = theta[:sum(b * (a + 1) for a, b in zip(widths[:-1], widths[1:]))]
+    lam = workloads.WORKLOADS_2D[name]["lam"]
+    inp = workloads.make_inputs_2d(name, n=8, n1=0, ne=2, widths=widths, nval=4)
+    pr = p2.Problem.from_inputs(inp)
+    exprs = sym_residuals(theta, widths, lam, equation)
+
+    def brute(s):
+        pts = [(a / (1 - a), b / (1 - b)) for a, b in s]
+        return max(float(np.max(np.abs(evaluate(e, pts)))) for e in exprs)
+
+    ref_val, ref_train = brute(inp["sval"]), brute(inp["s"])
+    assert abs(pr.validation_max(theta) - ref_val) <= 1e-11 * ref_val
+    assert abs(pr.train_max(theta) - ref_train) <= 1e-11 * ref_train
+    assert abs(ref_val - ref_train) > 1e-6 * ref_val
+    if equation == p2.BOUSS2D:
+        # each equation's maximum differs, so dropping one would change the result
+        pts = [(a / (1 - a), b / (1 - b)) for a, b in inp["sval"]]
+        per = [float(np.max(np.abs(evaluate(e, pts)))) for e in exprs]
+        assert len({round(v, 12) for v in per}) == 3
