@@ -1,0 +1,341 @@
+"""GPU parity at the headline sizes: the kernel instances that the medium CCF
+step runs (network [1, 64, 64, 64, 1], P = 8513) compared with the CPU oracle.
+
+Which instances run here, and why these sizes reach them:
+  - the Gram of the bordered [J | r] (order P + 1 = 8514, 67 x 67 lower
+    128-tiles = 2278 >= 512) takes the 128 x 128 tile configuration;
+  - the Hilbert coupling product (N = 1024 or 8192 rows, K = 1024 nodes,
+    8 x 67 or 64 x 67 output tiles >= 512) takes the 256-thread 128 x 128 x 16
+    configuration;
+  - the damped solve at order 4400 and 8514 runs outer panels of 512 columns
+    whose trailing updates on the side stream use 128 x 128 tiles.
+
+Comparisons are element by element where the workload is too large for the
+oracle to produce every output:
+  - J rows: |dJ_ik| <= 1e-12 Jabs_ik, where Jabs is the same Jacobian
+    formula evaluated with absolute values at every step (seeds, the reverse
+    sweep through the jets, the Hilbert coupling |Q| |B| + |c| |A|): a
+    running bound that stays meaningful for small entries (far-field rows);
+  - Gram entries: |dG_jk| <= gamma_m |J_j|^T |J_k|, gamma_m = m eps / (1 - m eps)
+    (the deterministic bound of an m-term FP64 dot product), for about 4,000
+    entries covering diagonal, edge and interior 128-tiles, the ragged last
+    tile, the g border row and the r^T r corner;
+  - the full step: backward error |(G + mu I) d + g| / (|G + mu I|_F |d| + |g|)
+    <= 5e-14 with (G + mu I) d formed as J^T (J d) + mu d by compensated
+    (Dot2) products of the oracle's J, and |G + mu I|_F replaced by a lower
+    bound (the diagonal part), which only makes the test stricter.
+With N = 1024 collocation points the oracle forms everything: r, J, G, g and
+the step, the latter by the identity (J^T J + mu I)^{-1} J^T = J^T (J J^T + mu I)^{-1}
+on the 1025 x 1025 system.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import dense
+from oracle import gn as ogn
+from oracle import profile1d as p1
+from paper_2509_14185_amd import gn
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+MU = 1e-3
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def gamma(m):
+    u = EPS / 2
+    return m * u / (1 - m * u)
+
+
+def make(n):
+    inp = workloads.make_inputs("ccf_medium", n=n)
+    po = p1.Problem.from_inputs(inp)
+    pg = gn.Problem("ccf1d", inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
+    pg.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"], inp["wq"], inp["sval"])
+    return inp, po, pg
+
+
+def param_rows_abs(theta, widths, x, a0, a1):
+    """Magnitude bound of mlp_param_rows: the reverse sweep with |W|, |seeds|
+    and absolute values of every factor, so each entry bounds the sum of the
+    absolute values of the terms the exact sweep adds up."""
+    layers = p1.unpack(np.abs(theta), widths)
+    _, _, cache = p1.mlp_jets(theta, widths, x)
+    n = np.asarray(x).shape[0]
+    zb = np.abs(a0)[None, :] * np.ones((1, n))
+    zbx = np.abs(a1)[None, :] * np.ones((1, n))
+    blocks = []
+    for l in range(len(layers) - 1, -1, -1):
+        W, _ = layers[l]
+        h, hx, _, _ = cache[l]
+        dW = zb.T[:, :, None] * np.abs(h).T[:, None, :] + zbx.T[:, :, None] * np.abs(hx).T[:, None, :]
+        blocks.append(np.concatenate([dW.reshape(n, -1), zb.T], axis=1))
+        if l > 0:
+            hb, hbx = W.T @ zb, W.T @ zbx
+            _, _, zprev, zxprev = cache[l - 1]
+            t = np.tanh(zprev)
+            d = 1.0 - t * t
+            zbx = hbx * d
+            zb = hb * d + np.abs(2.0 * t * d * zxprev) * hbx
+    return np.concatenate(blocks[::-1], axis=1)
+
+
+def jacobian_abs(po, theta, rows):
+    """Entry-wise magnitude bound Jabs of the oracle's Jacobian rows (CCF):
+    every sum in the row formula replaced by the sum of absolute values."""
+    lam = po.lam
+    _, aux = p1.raw_residual(po, theta)
+    Th, Thy = aux["Th"], aux["Thy"]
+    _, _, E, Ey, qy = aux["parts"]
+    Tt, _, _ = p1.field(theta, po.widths, po.t, lam, po.equation)
+    Qa = np.abs(po.Q)
+    Uabs = (Qa * (np.abs(Tt)[None, :] + np.abs(Th)[:, None])).sum(axis=1)
+    Vabs = (1.0 + lam) * np.abs(po.y) + Uabs
+    a0 = lam * np.abs(E) + Vabs * np.abs(Ey) + np.abs(Thy) * Qa.sum(axis=1) * np.abs(E)
+    a1 = Vabs * np.abs(E * qy)
+    rows = np.asarray(rows)
+    coll = rows[rows < po.n]
+    out = np.zeros((rows.size, po.P))
+    q = p1.q_of_y(po.y[coll], lam)
+    loc = param_rows_abs(theta, po.widths, q, a0[coll], a1[coll])
+    Et, _ = p1.envelope(po.t, lam, po.equation)
+    Babs = param_rows_abs(theta, po.widths, p1.q_of_y(po.t, lam), Et, np.zeros_like(Et))
+    loc = loc + np.abs(Thy[coll])[:, None] * (Qa[coll] @ Babs)
+    sc = np.sqrt(po.rho / po.n)
+    out[rows < po.n] = sc[coll][:, None] * loc
+    if np.any(rows == po.n):
+        d = param_rows_abs(theta, po.widths, np.ones(1), np.ones(1), np.zeros(1))
+        out[rows == po.n] = np.sqrt(po.c_norm) * d[0]
+    return out
+
+
+def check_rows_elementwise(Jg, Jo, Jabs, what):
+    err = np.abs(Jg - Jo)
+    bound = 1e-12 * Jabs + 1e-300
+    worst = float(np.max(err / bound))
+    assert worst <= 1.0, f"{what}: worst entry at {worst:.3g} of its bound"
+    return worst
+
+
+def sample_gram_entries(P1, rng):
+    """(rows, cols) with col <= row in the bordered Gram of order P1: random
+    lower entries, the first diagonal-tile boundary, an interior tile corner,
+    the ragged last tiles with the border row and the corner, the border row."""
+    pairs = set()
+    for _ in range(1200):
+        j = int(rng.integers(0, P1))
+        pairs.add((j, int(rng.integers(0, j + 1))))
+    for j in range(120, 136):
+        for k in range(120, j + 1):
+            pairs.add((j, k))
+    for j in range(4090, 4100):
+        for k in range(1020, 1030):
+            pairs.add((j, k))
+    lo = (P1 // 128 - 1) * 128 + 40
+    for j in range(lo, P1):
+        for k in range(lo, j + 1):
+            pairs.add((j, k))
+    for k in rng.choice(P1, 512, replace=False):
+        pairs.add((P1 - 1, int(k)))
+    pairs.add((P1 - 1, P1 - 1))
+    arr = np.array(sorted(pairs), dtype=np.int64)
+    return arr[:, 0], arr[:, 1]
+
+
+def check_gram_entries(G, Jr, rows, cols):
+    m = Jr.shape[0]
+    ref = dense.gram_entries(Jr, rows, cols)
+    Jabs = np.abs(Jr)
+    mag = np.einsum("ij,ij->j", Jabs[:, rows], Jabs[:, cols])
+    got = G[rows, cols]
+    err = np.abs(got - ref)
+    bound = gamma(m) * mag + 1e-300
+    worst = float(np.max(err / bound))
+    assert worst <= 1.0, f"Gram entry at {worst:.3g} of its bound"
+    return worst
+
+
+def bordered(J, r):
+    P = J.shape[1]
+    ld = (P + 1 + 31) // 32 * 32
+    out = np.zeros((J.shape[0], ld))
+    out[:, :P] = J
+    out[:, P] = r
+    return out
+
+
+def normal_equations_residual(J, r, delta, mu):
+    """J^T (J d) + mu d + J^T r by compensated dot products (Dot2)."""
+    Jd = dense.gradient(np.ascontiguousarray(J.T), delta)
+    return dense.gradient(J, Jd) + mu * delta + dense.gradient(J, r)
+
+
+def gram_frobenius_lower_bound(J, mu):
+    diag = np.einsum("ij,ij->j", J, J) + mu
+    return float(np.sqrt(np.sum(diag * diag)))
+
+
+# --------------------------------------------------------------- N = 1024
+@pytest.fixture(scope="module")
+def medium1024():
+    print("\n[gpu fullsize] ccf_medium widths, N = 1024", flush=True)
+    inp, po, pg = make(1024)
+    theta = inp["theta0"]
+    r = p1.residual_rows(po, theta)
+    J = p1.jacobian(po, theta)
+    yield dict(inp=inp, po=po, pg=pg, theta=theta, r=r, J=J)
+    pg.close()
+
+
+def test_medium_widths_jacobian_elementwise(medium1024):
+    c = medium1024
+    Jg, rg = c["pg"].jacobian(dev(c["theta"]))
+    Jg = Jg.cpu().numpy()
+    assert rel(rg.cpu().numpy(), c["r"]) < 1e-12
+    assert rel(Jg, c["J"]) < 1e-12
+    rows = np.arange(c["po"].m)
+    check_rows_elementwise(Jg, c["J"], jacobian_abs(c["po"], c["theta"], rows), "J (N = 1024)")
+
+
+def test_medium_widths_bordered_gram(medium1024):
+    c = medium1024
+    J, r = c["J"], c["r"]
+    P = J.shape[1]
+    Jr = bordered(J, r)
+    G, _ = c["pg"].gram(dev(Jr)[:, :P + 1], None)
+    G = G.cpu().numpy()
+    Go = dense.gram(Jr[:, :P + 1])
+    assert rel(np.tril(G), np.tril(Go)) < 1e-12
+    rows, cols = sample_gram_entries(P + 1, np.random.default_rng(5))
+    check_gram_entries(G, np.ascontiguousarray(Jr[:, :P + 1]), rows, cols)
+    # every entry of the lower triangle within the m-term bound
+    mag = np.abs(Jr[:, :P + 1]).T @ np.abs(Jr[:, :P + 1])
+    low = np.tril_indices(P + 1)
+    assert np.all(np.abs(G[low] - Go[low]) <= gamma(J.shape[0]) * mag[low] + 1e-300)
+
+
+def test_medium_widths_step(medium1024):
+    c = medium1024
+    J, r, theta, pg = c["J"], c["r"], c["theta"], c["pg"]
+    t = dev(theta)
+    st = pg.step(t, MU)
+    assert st["rc"] == gn.GN_OK and st["updated"] == 1
+    d = t.cpu().numpy() - theta
+    G, g = ogn.gram_and_gradient(J, r)
+    assert ogn.backward_error(G, MU, g, d) < 5e-14
+    # reference step by the m x m identity (J^T J + mu I)^{-1} J^T r = J^T (J J^T + mu I)^{-1} r
+    K = dense.gram(np.ascontiguousarray(J.T))
+    K[np.diag_indices_from(K)] += MU
+    L, info = dense.cholesky(K)
+    assert info == 0
+    y = dense.solve_lower_t(L, dense.solve_lower(L, r))
+    dref = -dense.gradient(J, y)
+    lam = np.linalg.eigvalsh(K)
+    kappa = (lam[-1]) / MU
+    assert rel(d, dref) < max(1e-12, 10 * kappa * EPS)
+    assert abs(st["half_sq_norm"] - 0.5 * r @ r) <= 1e-12 * (0.5 * r @ r)
+    vmax = p1.validation_max(c["po"], theta)
+    assert abs(st["max_abs_R_val"] - vmax) <= 1e-12 * vmax
+
+
+# --------------------------------------------------------------- N = 8192
+@pytest.fixture(scope="module")
+def medium():
+    print("\n[gpu fullsize] ccf_medium (N = 8192, P = 8513)", flush=True)
+    inp, po, pg = make(8192)
+    theta = inp["theta0"]
+    r = p1.residual_rows(po, theta)
+    J = p1.jacobian(po, theta)
+    yield dict(inp=inp, po=po, pg=pg, theta=theta, r=r, J=J)
+    pg.close()
+
+
+def sampled_rows(n):
+    rows = {0, 1, 2, 63, 64, 65, 127, 128, 129, n // 2, n - 129, n - 128, n - 2, n - 1, n}
+    rows |= set(np.random.default_rng(9).choice(n, 49, replace=False).tolist())
+    return np.array(sorted(rows))
+
+
+def test_medium_jacobian_rows_elementwise(medium):
+    c = medium
+    rows = sampled_rows(c["po"].n)
+    Jg, rg = c["pg"].jacobian(dev(c["theta"]))
+    Jr = Jg[torch.from_numpy(rows).cuda()].cpu().numpy()
+    rg = rg.cpu().numpy()
+    del Jg
+    torch.cuda.empty_cache()
+    assert rel(rg, c["r"]) < 1e-12
+    Jo = c["J"][rows]
+    assert rel(Jr, Jo) < 1e-12
+    check_rows_elementwise(Jr, Jo, jacobian_abs(c["po"], c["theta"], rows), "J rows (N = 8192)")
+
+
+def test_medium_bordered_gram_entries(medium):
+    c = medium
+    J, r = c["J"], c["r"]
+    P = J.shape[1]
+    Jr = bordered(J, r)
+    Jd = dev(Jr)
+    G, _ = c["pg"].gram(Jd[:, :P + 1], None)
+    del Jd
+    rows, cols = sample_gram_entries(P + 1, np.random.default_rng(6))
+    Gs = G[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
+    del G
+    torch.cuda.empty_cache()
+    Gfull = np.zeros((P + 1, P + 1))
+    Gfull[rows, cols] = Gs
+    print(f"[gpu fullsize] {rows.size} Gram entries", flush=True)
+    check_gram_entries(Gfull, np.ascontiguousarray(Jr[:, :P + 1]), rows, cols)
+
+
+def test_medium_step_backward_error(medium):
+    c = medium
+    J, r, theta, pg = c["J"], c["r"], c["theta"], c["pg"]
+    t = dev(theta)
+    st = pg.step(t, MU)
+    assert st["rc"] == gn.GN_OK and st["updated"] == 1 and st["chol_info"] == 0
+    d = t.cpu().numpy() - theta
+    res = normal_equations_residual(J, r, d, MU)
+    g = dense.gradient(J, r)
+    be = np.linalg.norm(res) / (gram_frobenius_lower_bound(J, MU) * np.linalg.norm(d) + np.linalg.norm(g))
+    print(f"[gpu fullsize] step backward error (upper estimate) {be:.2e}", flush=True)
+    assert be < 5e-14
+    assert float(g @ d) < 0
+    assert abs(st["half_sq_norm"] - 0.5 * r @ r) <= 1e-12 * (0.5 * r @ r)
+    vmax = p1.validation_max(c["po"], theta)
+    assert abs(st["max_abs_R_val"] - vmax) <= 1e-12 * vmax
+
+
+# --------------------------------------------------------------- solve at order 4400
+def test_solve_order_4400_side_stream_tiles(medium):
+    """The damped solve at order 4400 (outer panels of 512 with 128 x 128
+    trailing tiles on the side stream) against the oracle's Cholesky and
+    substitutions."""
+    n = 4400
+    rng = np.random.default_rng(44)
+    X = rng.standard_normal((700, n)) / np.sqrt(700)
+    G = X.T @ X + np.diag(rng.uniform(0.5, 2.0, n))
+    g = rng.standard_normal(n)
+    mu = 1e-2
+    Gd = dev(np.tril(G))
+    delta, info = medium["pg"].solve(Gd, mu, dev(g))
+    assert info == 0
+    d = delta.cpu().numpy()
+    assert ogn.backward_error(G, mu, g, d) < 5e-14
+    ref, oinfo = ogn.damped_solve(G, g, mu)
+    assert oinfo == 0
+    ev = np.linalg.eigvalsh(G + mu * np.eye(n))
+    kappa = ev[-1] / ev[0]
+    assert rel(d, ref) < max(1e-12, 10 * kappa * EPS)
+    L = np.tril(Gd.cpu().numpy())
+    Lo, _ = dense.cholesky(G + mu * np.eye(n))
+    assert rel(L, np.tril(Lo)) < max(1e-12, 10 * np.sqrt(kappa) * EPS)

@@ -4,7 +4,7 @@ seeded inputs).  Tolerances (normwise, per result):
   solve:  backward error |(G+mu I) d + g| / (|G+mu I| |d| + |g|) <= 5e-14 and
           forward error <= max(1e-12, 10 kappa eps) (kappa from numpy).
 Sizes span several 128-wide tiles and 64-wide Cholesky panels with ragged
-tails; the full-size medium CCF workload is checked on sampled outputs."""
+tails; the headline (medium CCF) sizes are checked in test_gpu_fullsize.py."""
 import numpy as np
 import pytest
 import torch
