@@ -136,7 +136,8 @@ typedef struct {
 
 /* Text for a status code (static storage). */
 const char *gn_status_string(int32_t status);
-/* Text of the last error on this handle (valid until the next call). */
+/* Text of the last error on this handle (valid until the next call); with
+ * h = NULL, of the calling thread's last gn_solve_noalloc call. */
 const char *gn_last_error(gn_handle h);
 
 /* Create a handle for one problem on the current HIP device.  Copies *prob
@@ -230,6 +231,25 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
  * Returns GN_ENOTPD (delta not written) or GN_ENONFINITE. */
 gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu,
                    const double *d_g, double *d_delta, int64_t *h_info);
+
+/* The damped solve of gn_solve for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): it takes no handle and allocates nothing.  Arguments,
+ * results and errors as gn_solve, with the work enqueued on `stream`
+ * (hipStream_t as void*, NULL = default stream), for orders
+ * 1 <= p <= GN_SOLVE_NOALLOC_MAX_ORDER; a larger p returns GN_EINVAL before
+ * any launch.  Its scratch (a status word, the factor's 128 x 128
+ * diagonal-block inverses and the two substitution vectors, 17.1 MB) is a
+ * static device array that the library holds on every GPU it runs on until
+ * the process ends.  All calls on one GPU share that GPU's copy and it keeps
+ * the last call's contents (the status word is cleared at the start of each
+ * call), so calls that overlap on one GPU, from other threads or streams,
+ * race.  The factorisation runs on `stream` alone (no look-ahead stream).
+ * Synchronises once to fill *h_info.  gn_last_error(NULL) gives the text of
+ * the calling thread's last error from this call. */
+#define GN_SOLVE_NOALLOC_MAX_ORDER 16384
+gn_status gn_solve_noalloc(void *stream, double *d_G, int64_t p, int64_t ldG, double mu, const double *d_g,
+                           double *d_delta, int64_t *h_info);
 
 /* One damped GN step in place: theta <- theta - (J^T J + mu I)^{-1} J^T r.
  * theta is left unchanged when the factorisation fails (GN_ENOTPD) or the

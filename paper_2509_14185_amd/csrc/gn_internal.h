@@ -275,6 +275,8 @@ hipError_t launch_copy_strided(hipStream_t st, const double *src, int64_t n, int
 
 namespace gn {
 hipError_t launch_reset_status(hipStream_t st, DevStatus *s);
+// Text of the calling thread's last gn_solve_noalloc error (gn_noalloc.hip).
+const char *noalloc_last_error();
 hipError_t launch_reset_solve_status(hipStream_t st, DevStatus *s);
 // Copy of the lower triangle of the n x n matrix A into its strictly upper
 // triangle (transposed), the diagonal into diag (n); restore writes it back.

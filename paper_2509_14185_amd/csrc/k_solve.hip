@@ -461,6 +461,10 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
                                   (int)shm);
         attr = true;
     }
+    // Without a distinct side stream (side == nullptr or st) every trailing
+    // update goes to st in the same order and no events are used.
+    const bool two = side != nullptr && side != st;
+    if (!two) side = st;
     const int64_t nd = n - border;
     if (mu != 0.0 && nd > 0)
         hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, A, nd, lda, mu);
@@ -514,10 +518,10 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
         if (pe >= n) break;
         const int64_t rest = n - pe, kw = pe - K0;
         const double *lp = A + pe * lda + K0;  // L rows pe.. of the outer panel
-        if ((e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
+        if (two && (e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
         // the next outer panel's columns first (main stream) ...
         const int64_t nb1 = rest < NB ? rest : NB;
-        if (trail_pending) {
+        if (two && trail_pending) {
             if ((e = hipStreamWaitEvent(st, ev_trail, 0)) != hipSuccess) return e;
             trail_pending = false;
         }
@@ -525,16 +529,16 @@ hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel
         // ... the rest of the trailing matrix on the side stream (look-ahead)
         const int64_t r2 = pe + nb1, rest2 = n - r2;
         if (rest2 > 0) {
-            if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
+            if (two && (e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
             const double *l2 = A + r2 * lda + K0;
             // first the columns of the panel after next (rows r2.., lower part of its
             // diagonal block): the main stream's next update of them waits for this part only
             const int64_t nb2 = rest2 < NB ? rest2 : NB;
             if ((e = gemm(side, rest2, nb2, kw, l2, l2, nullptr, A + r2 * lda + r2, -1.0, 1.0, 0, 1)) != hipSuccess)
                 return e;
-            if ((e = hipEventRecord(ev_trail, side)) != hipSuccess) return e;
-            trail_pending = true;
-            side_used = true;
+            if (two && (e = hipEventRecord(ev_trail, side)) != hipSuccess) return e;
+            trail_pending = two;
+            side_used = two;
             // then the rest in SIDE_CHUNKS row blocks (a rectangle left of the diagonal
             // block, then the block's lower triangle): the main stream's panel kernels
             // queued meanwhile are dispatched between the side launches

@@ -108,6 +108,7 @@ def load():
         "gn_jacobian": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP]),
         "gn_gram": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I64, _VP, _VP, _I64, _VP]),
         "gn_solve": (ctypes.c_int, [_VP, _VP, _I64, _I64, _D, _VP, _VP, ctypes.POINTER(_I64)]),
+        "gn_solve_noalloc": (ctypes.c_int, [_VP, _VP, _I64, _I64, _D, _VP, _VP, ctypes.POINTER(_I64)]),
         "gn_step": (ctypes.c_int, [_VP, _VP, _D, ctypes.POINTER(_Stats)]),
         "gn_step_lm": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_LM), ctypes.POINTER(_Stats)]),
         "gn_step_rank1": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP, ctypes.POINTER(_R1Args),
@@ -150,6 +151,25 @@ def int8_crt_params(m: int):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def solve_noalloc(G, mu, g, delta=None, stream=None):
+    """gn_solve_noalloc: (G + mu I) delta = -g without a handle or any
+    allocation in the library (G's lower triangle is overwritten by L).
+    delta may be given (then nothing is allocated here either).  Returns
+    (delta, info); raises GNError on a non-OK status."""
+    lib = load()
+    p = G.shape[0]
+    assert G.stride(1) == 1 and G.dtype == torch.float64
+    if delta is None:
+        delta = torch.empty(p, dtype=torch.float64, device=G.device)
+    st = torch.cuda.current_stream(G.device).cuda_stream if stream is None else stream
+    info = _I64(0)
+    rc = lib.gn_solve_noalloc(ctypes.c_void_p(st), _ptr(G), p, G.stride(0), float(mu), _ptr(g), _ptr(delta),
+                              ctypes.byref(info))
+    if rc != 0:
+        raise GNError(rc, "gn_solve_noalloc: " + lib.gn_last_error(None).decode(), int(info.value))
+    return delta, int(info.value)
 
 
 def _dev(x, device):
