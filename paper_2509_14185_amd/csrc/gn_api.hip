@@ -982,6 +982,17 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
     return GN_OK;
 }
 
+namespace {
+
+// Blocked Cholesky of A + mu I (order n) on the handle's stream, with the
+// look-ahead trailing updates on the side stream.
+hipError_t factor(gn_handle h, double *A, int64_t n, int64_t lda, double mu, int border) {
+    return launch_cholesky(h->stream, h->side, h->ev_panel, h->ev_trail, A, n, lda, mu, border, h->linv, h->chol_tmp,
+                           h->status);
+}
+
+}  // namespace
+
 gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, const double *d_g,
                    double *d_delta, int64_t *h_info) {
     if (!h || !d_G || !d_g || !d_delta || p < 1) return GN_EINVAL;
@@ -991,7 +1002,7 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, 
     hipStream_t st = h->stream;
     h->r1_factored = false;  // linv is shared with the stochastic step's factor
     GN_HIP(h, launch_reset_status(st, h->status));
-    GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, d_G, p, ldG, mu, 0, h->linv, h->chol_tmp, h->status));
+    GN_HIP(h, factor(h, d_G, p, ldG, mu, 0));
     GN_HIP(h, launch_copy_strided(st, d_g, p, 1, h->ybuf, 1, -1.0));
     GN_HIP(h, launch_solve_lower(st, d_G, p, ldG, h->linv, h->ybuf, h->zbuf, h->status));
     GN_HIP(h, launch_solve_upper(st, d_G, p, ldG, h->linv, h->zbuf, d_delta, h->status));
@@ -1063,8 +1074,7 @@ gn_status form_jacobian(gn_handle h, const double *d_theta) {
 gn_status solve_system(gn_handle h, double mu) {
     hipStream_t st = h->stream;
     const int64_t P = h->md.P;
-    GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, h->G, P + 1, h->ldG, mu, 1, h->linv, h->chol_tmp,
-                              h->status));
+    GN_HIP(h, factor(h, h->G, P + 1, h->ldG, mu, 1));
     mark(h, 5);
     double *w = h->G + P * h->ldG;
     GN_HIP(h, launch_sumsq(st, w, P, 1, &h->status->grad_dot_delta, h->red_work));
@@ -1206,8 +1216,7 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     GN_HIP(h, launch_ema_rank1(st, d_G_ema, P, ldG, a->beta, h->r1_u));
     if (a->refactor) {
         GN_HIP(h, launch_copy_lower(st, d_G_ema, ldG, h->G, h->ldG, P));
-        GN_HIP(h, launch_cholesky(st, h->side, h->ev_panel, h->ev_trail, h->G, P, h->ldG, a->gamma, 0, h->linv,
-                                  h->chol_tmp, h->status));
+        GN_HIP(h, factor(h, h->G, P, h->ldG, a->gamma, 0));
     }
     // Delta = -(G_ema + gamma I)^{-1} g
     GN_HIP(h, launch_copy_strided(st, h->r1_g, P, 1, h->r1_b, 1, -1.0));
