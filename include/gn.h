@@ -88,7 +88,9 @@ typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1, GN_EQ_IPM2D = 3, GN_EQ_BOUS
  * Every entry of J keeps the bits above 2^-b times its column's maximum, the
  * integer products and sums are exact, and G is rounded once to FP64 (within
  * 2 ulp of the exact sum of the rounded integers).  A non-finite column gives
- * NaN in its row and column of G. */
+ * NaN in its row and column of G.  In gn_step, gn_step_lm and the 2D steps the
+ * modular Gram covers the P parameter columns; g = J^T r and r^T r are FP64
+ * sums, as for GN_SPLIT32. */
 typedef enum { GN_FP64 = 0, GN_SPLIT32 = 1, GN_INT8_CRT = 2 } gn_precision;
 
 #define GN_INT8_CRT_MAX_ROWS 130944  /* rows of J the int8 Gram accepts: 2^14-bounded
@@ -424,8 +426,20 @@ gn_status gn_batch_destroy(gn_batch b);
  * runtime fails; per-instance failures are reported in h_stats[i].status. */
 gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_stats *h_stats);
 
+/* Measured throughput of the FP64 matrix instructions on the current device
+ * (tracing support, not part of the paper's method: the practical ceiling
+ * reported beside the published peak).  Every CU runs 32 waves of eight
+ * independent v_mfma_f64_16x16x4f64 chains (no memory traffic) for about
+ * 30 ms on `stream` (hipStream_t as void*, NULL = default stream);
+ * *h_tflops receives 2 x 16 x 16 x 4 flops per instruction over the
+ * event-timed span.  Synchronises.  Errors: GN_EINVAL (null pointer),
+ * GN_EDEVICE. */
+gn_status gn_probe_fp64_mfma(void *stream, double *h_tflops);
+
 /* Phase timing of gn_step with HIP events recorded on the handle's stream
- * (tracing support; not part of the paper's method).  Phases: */
+ * (tracing support; not part of the paper's method).  gn_step_batched
+ * records its phases on the first handle of the batch (the local Jacobian
+ * rows are timed with the forward phase).  Phases: */
 typedef enum {
     GN_PHASE_FORWARD = 0,   /* weight transpose, forward jets, residual rows, validation grid */
     GN_PHASE_JLOCAL = 1,    /* per-row reverse sweeps writing the local Jacobian rows */

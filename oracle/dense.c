@@ -62,6 +62,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads for later parallel loops (timing on one core or all cores). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * G = J^T J (full symmetric, both triangles written) with J m x p, row-major,
  * leading dimension ldj.  Columns are first copied to a contiguous

@@ -48,6 +48,7 @@ def _load():
     lib.oracle_solve_lower_t.argtypes = [_D, _I64, _I64, _D]
     lib.oracle_symv_lower.argtypes = [_D, _I64, _I64, _D, _D]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -62,6 +63,11 @@ def _c(a) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the later parallel loops of the C part."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def gram(J: np.ndarray) -> np.ndarray:

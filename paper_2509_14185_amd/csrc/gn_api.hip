@@ -472,18 +472,23 @@ gn_status gram2d(gn_handle h, const double *theta) {
     if (h->precision == GN_INT8_CRT) {
         // Column maxima need every row before the first residue: with more
         // than one chunk, J is formed twice (maxima, then residues).
+        // G from int8 modular products over the P parameter columns; the
+        // border row g = J^T r (chunk by chunk) and r^T r in FP64
         const int b = modgram_bits(m);
         const bool one = h->rows_ws >= m;
-        GN_HIP(h, launch_modgram_begin(st, P + 1, h->mg));
+        GN_HIP(h, launch_modgram_begin(st, P, h->mg));
         for (int pass = one ? 1 : 0; pass < 2; ++pass)
             for (int64_t r0 = 0, c = 0; r0 < m; r0 += h->rows_ws, ++c) {
                 const int64_t nr = (m - r0) < h->rows_ws ? (m - r0) : h->rows_ws;
                 GN_TRY(jac_rows2d(h, theta, r0, nr, h->J, h->ldJ));
-                GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
-                if (pass == 0 || one) GN_HIP(h, launch_modgram_colmax(st, h->J, nr, P + 1, h->ldJ, h->mg));
-                if (pass == 1) GN_HIP(h, launch_modgram_chunk(st, h->J, nr, P + 1, h->ldJ, b, h->mg, c > 0));
+                if (pass == 0 || one) GN_HIP(h, launch_modgram_colmax(st, h->J, nr, P, h->ldJ, h->mg));
+                if (pass == 1) {
+                    GN_HIP(h, launch_modgram_chunk(st, h->J, nr, P, h->ldJ, b, h->mg, c > 0));
+                    GN_HIP(h, launch_gemv_t(st, h->J, nr, P, h->ldJ, h->r2 + r0, Grow, h->gemv_work, c > 0));
+                }
             }
-        GN_HIP(h, launch_modgram_finish(st, P + 1, b, h->G, h->ldG, h->mg));
+        GN_HIP(h, launch_modgram_finish(st, P, b, h->G, h->ldG, h->mg));
+        GN_HIP(h, launch_sumsq(st, h->r2, m, 1, Grow + P, h->red_work));
         return GN_OK;
     }
     for (int64_t r0 = 0, c = 0; r0 < m; r0 += h->rows_ws, ++c) {
@@ -1048,7 +1053,13 @@ gn_status form_system(gn_handle h, const double *d_theta) {
             GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
             GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
         } else if (h->precision == GN_INT8_CRT) {
-            GN_HIP(h, launch_modgram(st, J, m_rows, P + 1, ldJ, h->G, h->ldG, h->mg));
+            // G from int8 modular products over the P parameter columns; the
+            // border row g = J^T r and r^T r in FP64
+            double *Grow = h->G + P * h->ldG;
+            GN_HIP(h, launch_modgram(st, J, m_rows, P, ldJ, h->G, h->ldG, h->mg));
+            GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
+            GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
+            GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
         } else {
             GN_HIP(h, launch_dgemm(st, gram_desc(h)));
         }
@@ -1598,6 +1609,12 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
         GN_HIP(h0, hipMemcpy(b->d_bc, b->h_bc.data(), sizeof(BatchChol) * n, hipMemcpyHostToDevice));
         b->uploaded_thetas.assign(d_thetas, d_thetas + n);
     }
+    // phase events of the batch step go on the first handle's event list
+    auto bmark = [&](int k) {
+        if (h0->prof_count < h0->prof_max)
+            (void)hipEventRecord(h0->events[(size_t)h0->prof_count * (GN_PHASE_COUNT + 1) + k], st);
+    };
+    bmark(GN_PHASE_FORWARD);
     // per instance: residual, validation, local Jacobian rows with r in column P
     for (int i = 0; i < n; ++i) {
         gn_handle h = b->hs[i];
@@ -1612,15 +1629,44 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
         if (e != GN_OK) return e;
     }
     // batched Hilbert coupling, Gram, bordered Cholesky, back substitution and update
+    bmark(GN_PHASE_JLOCAL);  // the local rows are timed with the forward phase
+    bmark(GN_PHASE_COUPLING);
     GN_HIP(h0, launch_batched_plan(st, b->coupling));
+    bmark(GN_PHASE_GRAM);
     GN_HIP(h0, launch_batched_plan(st, b->gram));
+    bmark(GN_PHASE_CHOLESKY);
     GN_HIP(h0, launch_cholesky_batched(st, b->h_bc.data(), b->d_bc, b->chol, n, P + 1, mu, 1));
+    bmark(GN_PHASE_SOLVE);
     GN_HIP(h0, launch_solve_upper_batched(st, b->d_bc, n, P));
+    bmark(GN_PHASE_COUNT);
+    if (h0->prof_count < h0->prof_max) ++h0->prof_count;
     if (!h_stats) return GN_OK;
     for (int i = 0; i < n; ++i)
         GN_HIP(h0, hipMemcpyAsync(&b->ds[i], b->hs[i]->status, sizeof(DevStatus), hipMemcpyDeviceToHost, st));
     GN_HIP(h0, hipStreamSynchronize(st));
     for (int i = 0; i < n; ++i) fill_stats(b->ds[i], &h_stats[i]);
+    return GN_OK;
+}
+
+gn_status gn_probe_fp64_mfma(void *stream, double *h_tflops) {
+    if (!h_tflops) return GN_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                  hipSuccess || cus <= 0)
+        return GN_EDEVICE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double flops = 0.0;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    ok = ok && launch_mfma_probe(st, cus, 256, nullptr) == hipSuccess;  // warm-up
+    ok = ok && hipEventRecord(e0, st) == hipSuccess && launch_mfma_probe(st, cus, 16384, &flops) == hipSuccess &&
+         hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.f;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (!ok) return GN_EDEVICE;
+    *h_tflops = flops / (ms * 1e-3) / 1e12;
     return GN_OK;
 }
 

@@ -153,6 +153,10 @@ struct GemmDesc {
     const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
+// FP64 matrix-instruction throughput probe: cus x 8 workgroups of four waves,
+// each wave iters rounds of 8 independent v_mfma_f64_16x16x4f64 chains;
+// *flops (if not NULL) receives the flop count.
+hipError_t launch_mfma_probe(hipStream_t st, int cus, int iters, double *flops);
 // n independent GEMMs in one launch.  plan_dgemm_batched builds, once per
 // set of shapes, the work table: one int4 (problem, tile row, tile column, 0)
 // per workgroup in dispatch order, entry b running on XCD b % 8, padding

@@ -343,6 +343,34 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     return launch_tiles<64, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
 }
 
+// Throughput probe: independent MFMA chains, nothing read from memory; the
+// sum of the accumulators is stored only under a condition that cannot hold
+// for these inputs, so the chains stay live without a store per wave.
+__device__ double mfma_probe_sink;
+
+__global__ __launch_bounds__(256) void mfma_probe_kernel(int iters) {
+    constexpr int CH = 8;
+    double4_t acc[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc[c] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    const double a = 1.0 + 1e-3 * (threadIdx.x & 63), b = 1.0 - 1e-7 * blockIdx.x;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) sum += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    if (sum < 0.0) mfma_probe_sink = sum;
+}
+
+hipError_t launch_mfma_probe(hipStream_t st, int cus, int iters, double *flops) {
+    const unsigned grid = (unsigned)cus * 8u;
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(grid), dim3(256), 0, st, iters);
+    if (flops) *flops = (double)grid * 4.0 * (double)iters * 8.0 * 16.0 * 16.0 * 4.0 * 2.0;
+    return hipGetLastError();
+}
+
 // Batched tile configuration: 128 x 64 tiles for narrow rectangular products
 // (in-place triangular solves need one tile column), else 128 x 128.
 static bool batched_small_n(const GemmDesc &f) { return !f.lower && f.N <= 64; }

@@ -125,6 +125,7 @@ def load():
         "gn_step_batched": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), _D, ctypes.POINTER(_Stats)]),
         "gn_int8_crt_params": (ctypes.c_int, [_I64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32)]),
+        "gn_probe_fp64_mfma": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
         "gn_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
         "gn_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32)]),
@@ -147,6 +148,18 @@ def int8_crt_params(m: int):
     if st != 0:
         raise GNError(st, lib.gn_status_string(st).decode())
     return bits.value, [mods[i] for i in range(n.value)]
+
+
+def probe_fp64_mfma(stream=None):
+    """Measured FP64 matrix-instruction throughput (TFLOP/s) of the current
+    device (gn_probe_fp64_mfma)."""
+    lib = load()
+    out = ctypes.c_double(0.0)
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    rc = lib.gn_probe_fp64_mfma(ctypes.c_void_p(st), ctypes.byref(out))
+    if rc != 0:
+        raise GNError(rc, "gn_probe_fp64_mfma failed")
+    return out.value
 
 
 def _ptr(t):
