@@ -40,17 +40,25 @@ def flops(P, m, n, mq):
     }
 
 
+def gram_source_sha256():
+    """sha256 over the Gram kernel's sources (k_dgemm.hip, then tile_loader.h)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("k_dgemm.hip", "tile_loader.h"):
+        with open(os.path.join(ROOT, "paper_2509_14185_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def gram_traffic():
     """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (profiles/gram_ccf_medium_pmc.txt, scaled by a plain
     copy of known size), or None if the GEMM source changed since."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "gram_ccf_medium_pmc.txt")
-    src = os.path.join(ROOT, "paper_2509_14185_amd", "csrc", "k_dgemm.hip")
     try:
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("#"))
-        if kv.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        if kv.get("kernel_source_sha256") != gram_source_sha256():
             return None
         return float(kv["gram_hbm_traffic_bytes"])
     except (OSError, KeyError, ValueError):
@@ -707,6 +715,8 @@ def main():
     ap.add_argument("--no-rank1", action="store_true", help="skip the stochastic (rank-1 estimate) run")
     ap.add_argument("--no-deriv", action="store_true", help="skip the run with d1/d2 rows")
     ap.add_argument("--no-funnel", action="store_true", help="skip the funnel-inference run")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the MFMA and copy ceiling probes")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-workload trajectory")
     ap.add_argument("--damping", default="fixed", choices=["fixed", "lm"],
                     help="damping of the steps for --workload ipm2d / bouss2d")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split32", "int8crt"],
@@ -823,11 +833,13 @@ def main():
         "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
         "paper_reference": PAPER_FIGURE,
     }
-    print("[bench] measured ceilings", file=sys.stderr, flush=True)
-    out["ceilings"] = ceilings()
-    out["roofline"]["frac_of_measured_mfma"] = gram_tf / out["ceilings"]["fp64_mfma_measured_tflops"]
-    print("[bench] small CCF trajectory", file=sys.stderr, flush=True)
-    out["ccf_small"] = small_bench()
+    if not args.no_ceilings:
+        print("[bench] measured ceilings", file=sys.stderr, flush=True)
+        out["ceilings"] = ceilings()
+        out["roofline"]["frac_of_measured_mfma"] = gram_tf / out["ceilings"]["fp64_mfma_measured_tflops"]
+    if not args.no_small:
+        print("[bench] small CCF trajectory", file=sys.stderr, flush=True)
+        out["ccf_small"] = small_bench()
     if not args.no_int8:
         print("[bench] int8 modular Gram", file=sys.stderr, flush=True)
         out["int8crt"] = int8crt_comparison(inp, theta_start, mu, args.steps, theta, target, fl["gram"])

@@ -11,6 +11,8 @@ paper notes is viable when G is computed exactly.  mu below is the damping.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from . import dense
@@ -60,6 +62,52 @@ def backward_error(G, mu, g, delta):
     A[np.diag_indices_from(A)] += mu
     res = dense.symv_lower(np.tril(A), delta) + g
     return float(np.linalg.norm(res) / (np.linalg.norm(A) * np.linalg.norm(delta) + np.linalg.norm(g)))
+
+
+def projected_normal_residuals(residual, theta, delta, mu, k=8, seed=0, h=1e-30):
+    """Projections of the normal-equation residual
+    v = (J^T J + mu I) delta + J^T r on k Gaussian directions w, for problems
+    whose J is too large to form (checker; parity of a step at full size).
+
+    residual(t) returns r(t) for a real or complex parameter vector t.  J w
+    and J delta are complex-step directional derivatives (one evaluation
+    each, exact up to rounding), so that
+        w^T v = (J w)^T (J delta + r) + mu w^T delta,
+    the last dot products summed exactly (math.fsum of the rounded terms).
+    Also returned: F2 = mean |J w|^2, the unbiased (Hutchinson) estimate of
+    |J|_F^2, |delta|, |r|, and per direction the rounding bound of the
+    evaluation itself, eps (|J w|^T (|J delta| + |r|) + mu |w|^T |delta|).
+    A step whose normwise backward error is b satisfies
+    |v| <= b ((|J|_F^2 + sqrt(P) mu) |delta| + |J|_F |r|), and |w^T v| is at
+    most 6 |v| for a Gaussian w with probability 1 - 2e-9."""
+    theta = np.asarray(theta, dtype=np.float64)
+    delta = np.asarray(delta, dtype=np.float64)
+
+    def jdir(d):
+        t = theta.astype(np.complex128) + 1j * h * np.asarray(d, dtype=np.float64)
+        return np.asarray(residual(t)).imag / h
+
+    r = np.asarray(residual(theta), dtype=np.float64)
+    Jd = jdir(delta)
+    u = Jd + r
+    W = np.random.default_rng(seed).standard_normal((k, theta.size))
+    proj, err, sq = [], [], []
+    eps = np.finfo(np.float64).eps
+    for w in W:
+        Jw = jdir(w)
+        sq.append(float(Jw @ Jw))
+        proj.append(math.fsum(np.concatenate([Jw * u, [mu * math.fsum(w * delta)]])))
+        err.append(eps * (float(np.abs(Jw) @ (np.abs(Jd) + np.abs(r))) + mu * float(np.abs(w) @ np.abs(delta))))
+    return dict(proj=np.array(proj), F2=float(np.mean(sq)), dnorm=float(np.linalg.norm(delta)),
+                rnorm=float(np.linalg.norm(r)), eval_err=np.array(err), P=theta.size)
+
+
+def projected_bound(pr, mu, b=5e-14):
+    """Largest |w^T v| allowed for a step of backward error b (see
+    projected_normal_residuals): 6 b ((F2 + sqrt(P) mu) |delta| + sqrt(F2) |r|)
+    plus the evaluation's rounding bound."""
+    F2 = pr["F2"]
+    return 6.0 * b * ((F2 + math.sqrt(pr["P"]) * mu) * pr["dnorm"] + math.sqrt(F2) * pr["rnorm"]) + pr["eval_err"]
 
 
 LM_DEFAULTS = dict(mu_min=1e-12, mu_max=1e12, up=2.0, down=3.0, rho_lo=0.25, rho_hi=0.75, max_tries=20)

@@ -46,6 +46,12 @@ static constexpr int NXCD = 8;
 // a time and its L2 serves 12 operand panels instead of up to 33.
 // Lower-triangular GEMMs enumerate only super-tiles that touch the lower
 // triangle (row a of super-tiles holds b = 0 .. (4a+3)/8).
+// Narrow products (fewer than 8 tile columns: the panel solves and panel
+// updates of the Cholesky) use super-tiles of all their tile columns and
+// ceil(tiles_m / 8k) tile rows (k the smallest that fits 32 tiles), so that
+// the grid holds little padding and every XCD gets a share: a padding block
+// costs a dispatch slot, and while the look-ahead update holds the CUs,
+// slots are what the factorisation's critical chain waits for.
 __host__ __device__ inline int64_t lower_super_count(int64_t tiles) {
     const int64_t nsr = (tiles + SUP_M - 1) / SUP_M, nsc = (tiles + SUP_N - 1) / SUP_N;
     int64_t n = 0;
@@ -56,11 +62,29 @@ __host__ __device__ inline int64_t lower_super_count(int64_t tiles) {
     return n;
 }
 
+// Super-tile shape of a product: SUP_M x SUP_N, or (rows, cols) for a narrow
+// one, packed as rows | cols << 8.
+static inline int super_shape(int lower, int tiles_m, int tiles_n) {
+    if (lower || tiles_n >= SUP_N) return SUP_M | (SUP_N << 8);
+    // rows per super-tile: the fewest that give a multiple of 8 super-tiles
+    // within the SUP tiles of one round
+    const int sn = tiles_n < 1 ? 1 : tiles_n;
+    int sm = 1;
+    for (int k = 1;; ++k) {
+        sm = (tiles_m + NXCD * k - 1) / (NXCD * k);
+        if (sm < 1) sm = 1;
+        if (sm * sn <= SUP) break;
+    }
+    return sm | (sn << 8);
+}
+
 // Returns false for padding blocks and tiles outside the (lower) tile set.
-__device__ __forceinline__ bool tile_of_block(int64_t b, int lower, int tiles_m, int tiles_n, int &tm, int &tn) {
+__device__ __forceinline__ bool tile_of_block(int64_t b, int lower, int tiles_m, int tiles_n, int sup, int &tm,
+                                              int &tn) {
+    const int sup_m = sup & 0xff, sup_n = sup >> 8, per = sup_m * sup_n;
     const int64_t x = b % NXCD, pos = b / NXCD;
-    const int64_t sidx = (pos / SUP) * NXCD + x;
-    const int i = (int)(pos % SUP);
+    const int64_t sidx = (pos / per) * NXCD + x;
+    const int i = (int)(pos % per);
     int64_t sm, sn;
     if (lower) {
         const int64_t nsr = (tiles_m + SUP_M - 1) / SUP_M, nsc = (tiles_m + SUP_N - 1) / SUP_N;
@@ -75,20 +99,20 @@ __device__ __forceinline__ bool tile_of_block(int64_t b, int lower, int tiles_m,
         sm = a;
         sn = rem;
     } else {
-        const int64_t nsm = (tiles_m + SUP_M - 1) / SUP_M, nsn = (tiles_n + SUP_N - 1) / SUP_N;
+        const int64_t nsm = (tiles_m + sup_m - 1) / sup_m, nsn = (tiles_n + sup_n - 1) / sup_n;
         if (sidx >= nsm * nsn) return false;
         sm = sidx % nsm;
         sn = sidx / nsm;
     }
-    tm = (int)(sm * SUP_M + i % SUP_M);
-    tn = (int)(sn * SUP_N + i / SUP_M);
+    tm = (int)(sm * sup_m + i % sup_m);
+    tn = (int)(sn * sup_n + i / sup_m);
     if (tm >= tiles_m || tn >= tiles_n) return false;
     if (lower && tn > tm) return false;
     return true;
 }
 
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT>
-__global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0,
+__global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0, int sup0,
                                                                  const GemmDesc *__restrict__ batch,
                                                                  const int4 *__restrict__ work) {
     // batched launches read (problem, tile row, tile column) from a work table
@@ -112,7 +136,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     double *Bs = smem + 2 * LoaderA::SIZE;   // two buffers of LoaderB::SIZE
 
     int tm = wi.y, tn = wi.z;
-    if (!BATCH && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, tm, tn)) return;
+    if (!BATCH && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, sup0, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const bool lower_mask = g.lower || g.mask_lower;
     if (lower_mask && n0 > m0 + BM - 1) return;  // tile entirely above the diagonal
@@ -267,7 +291,7 @@ static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int
         attr = true;
     }
     hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH, NT>), dim3((unsigned)blocks), dim3(NT),
-                       shm, st, g, tiles_m, tiles_n, batch, work);
+                       shm, st, g, tiles_m, tiles_n, super_shape(g.lower, tiles_m, tiles_n), batch, work);
     return hipGetLastError();
 }
 
@@ -276,9 +300,10 @@ static int64_t blocks_for(const GemmDesc &g, int &tiles_m, int &tiles_n) {
     tiles_m = (int)((g.M + BM - 1) / BM);
     tiles_n = (int)((g.N + BN - 1) / BN);
     if (g.M <= 0 || g.N <= 0) return 0;
+    const int sup = super_shape(g.lower, tiles_m, tiles_n), sup_m = sup & 0xff, sup_n = sup >> 8;
     const int64_t supers = g.lower ? lower_super_count(tiles_m)
-                                   : (int64_t)((tiles_m + SUP_M - 1) / SUP_M) * ((tiles_n + SUP_N - 1) / SUP_N);
-    return (supers + NXCD - 1) / NXCD * NXCD * SUP;
+                                   : (int64_t)((tiles_m + sup_m - 1) / sup_m) * ((tiles_n + sup_n - 1) / sup_n);
+    return (supers + NXCD - 1) / NXCD * NXCD * (sup_m * sup_n);
 }
 
 template <int BM, int BN, int BK, bool BATCH, int NT = GEMM_THREADS>
@@ -341,34 +366,6 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     }
     const int64_t b = blocks_for<64, 64, 32>(g, tm, tn);
     return launch_tiles<64, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
-}
-
-// Throughput probe: independent MFMA chains, nothing read from memory; the
-// sum of the accumulators is stored only under a condition that cannot hold
-// for these inputs, so the chains stay live without a store per wave.
-__device__ double mfma_probe_sink;
-
-__global__ __launch_bounds__(256) void mfma_probe_kernel(int iters) {
-    constexpr int CH = 8;
-    double4_t acc[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] = (double4_t){0.0, 0.0, 0.0, 0.0};
-    const double a = 1.0 + 1e-3 * (threadIdx.x & 63), b = 1.0 - 1e-7 * blockIdx.x;
-    for (int i = 0; i < iters; ++i) {
-#pragma unroll
-        for (int c = 0; c < CH; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
-    }
-    double sum = 0.0;
-#pragma unroll
-    for (int c = 0; c < CH; ++c) sum += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
-    if (sum < 0.0) mfma_probe_sink = sum;
-}
-
-hipError_t launch_mfma_probe(hipStream_t st, int cus, int iters, double *flops) {
-    const unsigned grid = (unsigned)cus * 8u;
-    hipLaunchKernelGGL(mfma_probe_kernel, dim3(grid), dim3(256), 0, st, iters);
-    if (flops) *flops = (double)grid * 4.0 * (double)iters * 8.0 * 16.0 * 16.0 * 4.0 * 2.0;
-    return hipGetLastError();
 }
 
 // Batched tile configuration: 128 x 64 tiles for narrow rectangular products

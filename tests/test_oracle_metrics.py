@@ -156,3 +156,49 @@ def test_backward_error_rejects_a_perturbed_solution():
         assert ogn.backward_error(G, mu, g, bad) > 5e-14
     # a sign error in the right-hand side is caught at once
     assert ogn.backward_error(G, mu, -g, d) > 1e-3
+
+
+# ---- projected normal-equation residual (the step checker at sizes where
+#      the oracle cannot form J): pinned against the full-matrix formula
+
+PROJ_CASES = {
+    "bouss2d": dict(n=40, ne=6, widths=[2, 8, 8, 3], nval=8),
+    "ipm2d": dict(n=48, n1=12, ne=6, widths=[2, 10, 9, 1], nval=8),
+}
+
+
+@pytest.mark.parametrize("name", list(PROJ_CASES))
+def test_projected_normal_residuals_against_full_matrices(name):
+    from oracle import profile2d as p2
+
+    inp = workloads.make_inputs_2d(name, **PROJ_CASES[name])
+    po = p2.Problem.from_inputs(inp)
+    theta = inp["theta0"] + 0.05 * np.random.default_rng(5).standard_normal(po.P)
+    r = po.residual_rows(theta)
+    J = po.jacobian(theta)
+    G, g = ogn.gram_and_gradient(J, r)
+    mu = 1e-3
+    d, info = ogn.damped_solve(G, g, mu)
+    assert info == 0
+    k = 8
+    W = np.random.default_rng(1).standard_normal((k, po.P))
+    # formula: for a delta that is not the solution, w^T v equals the
+    # projection of (G + mu I) delta + g formed from the full J
+    dd = d + 0.3 * np.linalg.norm(d) * W[0] / np.linalg.norm(W[0])
+    pr = ogn.projected_normal_residuals(po.residual_rows, theta, dd, mu, k=k, seed=1)
+    ref = W @ (J.T @ (J @ dd + r) + mu * dd)
+    assert np.all(np.abs(pr["proj"] - ref) <= 1e-12 * np.abs(W) @ (np.abs(J.T) @ (np.abs(J @ dd) + np.abs(r)) + mu * np.abs(dd)))
+    # the Hutchinson estimate of |J|_F^2
+    F2 = float(np.sum(J * J))
+    assert 0.2 * F2 < pr["F2"] < 5.0 * F2
+    # the exact solution passes the bound of a 5e-14 backward error ...
+    pr = ogn.projected_normal_residuals(po.residual_rows, theta, d, mu, k=k, seed=1)
+    assert np.all(np.abs(pr["proj"]) <= ogn.projected_bound(pr, mu))
+    # ... a perturbation of 1e-7 |d| in a random direction does not, nor a
+    # step from the wrong sign of the gradient
+    v = np.random.default_rng(9).standard_normal(po.P)
+    bad = d + 1e-7 * np.linalg.norm(d) * v / np.linalg.norm(v)
+    pr = ogn.projected_normal_residuals(po.residual_rows, theta, bad, mu, k=k, seed=1)
+    assert np.any(np.abs(pr["proj"]) > ogn.projected_bound(pr, mu))
+    pr = ogn.projected_normal_residuals(po.residual_rows, theta, -d, mu, k=k, seed=1)
+    assert np.any(np.abs(pr["proj"]) > 1e3 * ogn.projected_bound(pr, mu))
