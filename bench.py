@@ -454,7 +454,7 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
             prob.step(theta, mu, stats=False)
     torch.cuda.synchronize()
     prob.profile_enable(True, steps)
-    trace, tries, mu_k, failed = [], 0, mu, 0
+    trace, tries, mu_k, failed, mus, tries_k = [], 0, mu, 0, [], []
     t0 = time.perf_counter()
     for k in range(steps):
         # every step reports its status (one synchronisation per step; 2D steps are long)
@@ -462,6 +462,8 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
             st = prob.step_lm(theta, mu_k)
             mu_k, tries = st["mu"], tries + st["tries"]
             trace.append(st["half_sq_norm_new"])
+            mus.append(mu_k)
+            tries_k.append(st["tries"])
         else:
             st = prob.step(theta, mu)
         failed += int(st["rc"] != gn.GN_OK)
@@ -531,7 +533,8 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
     }
     if lm:
         # the "cholesky" phase then spans every trial: factorisations and trial residuals
-        res["lm"] = {"factorisations": tries, "mu_final": mu_k, "half_sq_norm_after_each_step": trace}
+        res["lm"] = {"factorisations": tries, "mu_final": mu_k, "half_sq_norm_after_each_step": trace,
+                     "factorisations_each_step": tries_k, "mu_after_each_step": mus}
         res["gram_cholesky_frac"] = (fl_gram + fl_chol * tries / steps) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS
     return res
 

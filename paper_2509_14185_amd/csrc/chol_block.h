@@ -42,8 +42,8 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // FP64 MFMA layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // register r of the result is row l/16 + 4r, column l%16.
 template <int KN, class FA, class FB>
-__device__ __forceinline__ double4_t lds_mfma(double4_t acc, FA a_at, FB b_at, int kbeg) {
-    const int lane = threadIdx.x & 63, fr = lane & 15, fk = lane >> 4;
+__device__ __forceinline__ double4_t lds_mfma(double4_t acc, FA a_at, FB b_at, int kbeg, int lane = threadIdx.x & 63) {
+    const int fr = lane & 15, fk = lane >> 4;
     double a[KN / 4], b[KN / 4];
 #pragma unroll
     for (int q = 0; q < KN / 4; ++q) {
@@ -56,6 +56,16 @@ __device__ __forceinline__ double4_t lds_mfma(double4_t acc, FA a_at, FB b_at, i
 }
 
 __device__ __forceinline__ double sel(bool keep, double v) { return keep ? v : 0.0; }
+
+// The lane index through an opaque copy: the work that waves 1-3 do between
+// the leaves computes its LDS and global addresses where it runs instead of
+// having them hoisted to the kernel's start and kept live (spilled) across
+// the leaves.
+__device__ __forceinline__ int opaque_lane() {
+    int l = threadIdx.x & 63;
+    asm volatile("" : "+v"(l));
+    return l;
+}
 
 // One wave, lanes 0..31: lane i holds row o+i of the 32x32 diagonal block in
 // registers.  Columns are taken KS at a time: every lane reads the KS x KS
@@ -213,96 +223,273 @@ __device__ __forceinline__ int potrf32_wave(double *s, int o, int bi, double *cb
     return -1;
 }
 
-// Off-diagonal blocks X_rs of the inverse of the block's factor at distance
-// D = r - s (in 32-blocks), from the blocks at smaller distances:
-// W = sum_{k=s}^{r-1} L_rk X_ks, then X_rs = -X_rr W.  16x16 MFMA tiles
-// spread over the four waves; W (three 32x33 buffers) holds the sums.
-template <int D, int NW>
-__device__ __forceinline__ void x_blocks_at_distance(double *s, double *W, int wave) {
-    const int lane = threadIdx.x & 63, fr = lane & 15, fk = lane >> 4;
-    constexpr int NBLK = CB / IB - D, NTILE = NBLK * 4;
-    for (int t = wave; t < NTILE; t += NW) {
-        const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
-        const int ro = (q + D) * IB, so = q * IB;
-        const int rm = ro + 16 * ti, cn = so + 16 * tj;
-        double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-        acc = lds_mfma<IB * D>(
-            acc, [&](int m, int k) { return LL(rm + m, k); },
-            [&](int k, int n) { return sel(k >= cn + n, XX(k, cn + n)); }, so);
-        double *Wq = W + q * IB * (IB + 1);
+// Wave-local ordering of LDS traffic: the wave's LDS writes have landed
+// before its next LDS reads (other lanes of the same wave read them).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Rows [R0, R0 + ROWS) of the kb x kb diagonal block into LDS by NT threads
+// (thread index t in [0, NT)): every thread issues all of its loads before
+// any LDS store (indices clamped into the block, values selected after), so
+// no load waits behind a branch; rows >= kb become identity padding.
+template <int R0, int ROWS, int NT>
+__device__ __forceinline__ void load_block_rows(const double *A, int64_t lda, int64_t k0, int kb, double *s, int t) {
+    constexpr int E = ROWS * CB / NT;
+    static_assert(E * NT == ROWS * CB, "rows split evenly over the threads");
+    double v[E];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Wq[(16 * ti + fk + 4 * r) * (IB + 1) + 16 * tj + fr] = acc[r];
+    for (int e = 0; e < E; ++e) {
+        const int idx = t + e * NT, r = R0 + idx / CB, c = idx % CB;
+        const int rc = r < kb ? r : kb - 1, cc = c < kb ? c : kb - 1;
+        v[e] = A[(k0 + rc) * lda + k0 + cc];
     }
-    __syncthreads();
-    for (int t = wave; t < NTILE; t += NW) {
-        const int q = t >> 2, ti = (t >> 1) & 1, tj = t & 1;
-        const int ro = (q + D) * IB, so = q * IB;
-        const double *Wq = W + q * IB * (IB + 1);
-        double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-        acc = lds_mfma<IB>(
-            acc, [&](int m, int k) { return sel(k <= 16 * ti + m, XX(ro + 16 * ti + m, ro + k)); },
-            [&](int k, int n) { return Wq[k * (IB + 1) + 16 * tj + n]; }, 0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) XX(ro + 16 * ti + fk + 4 * r, so + 16 * tj + fr) = -acc[r];
+    for (int e = 0; e < E; ++e) {
+        const int idx = t + e * NT, r = R0 + idx / CB, c = idx % CB;
+        v[e] = (r < kb && c <= r) ? v[e] : ((r >= kb && r == c) ? 1.0 : 0.0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int idx = t + e * NT, r = R0 + idx / CB, c = idx % CB;
+        s[r * LDS_LD + c] = v[e];
+    }
+}
+
+// One 16x16 lower tile of the trailing update by the 32 columns [o, o + IB):
+// A[r][c] -= sum_k L[r][o+k] L[c][o+k] over the region [o + IB, CB)^2, tile t
+// of its lower tiles in row order (t = 0, 1, 2 are the next diagonal block).
+__device__ __forceinline__ void trail_tile(double *s, int o, int t) {
+    const int lane = opaque_lane(), fr = lane & 15, fk = lane >> 4;
+    const int r0 = o + IB;
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    const int rm = r0 + 16 * ti, cn = r0 + 16 * tj;
+    double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+    acc = lds_mfma<IB>(
+        acc, [&](int m, int k) { return LL(rm + m, o + k); }, [&](int k, int n) { return LL(cn + n, o + k); }, 0, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = rm + fk + 4 * r, col = cn + fr;
+        if (col <= row) LL(row, col) -= acc[r];
+    }
+}
+
+// A 32x32 block product in LDS, acc[2 ti + tj] (its four 16x16 tiles) +=
+// A(32 x KN) B(KN x 32) over k in [kbeg, kbeg + KN): per k-step the two A and
+// two B fragments feed four independent MFMAs; all fragments are loaded
+// before the first MFMA.
+template <int KN, class FA, class FB>
+__device__ __forceinline__ void lds_mfma_32x32(double4_t (&acc)[4], FA a_at, FB b_at, int kbeg, int lane) {
+    const int fr = lane & 15, fk = lane >> 4;
+    constexpr int NQ = KN / 4;
+    double a0[NQ], a1[NQ], b0[NQ], b1[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int k = kbeg + 4 * q + fk;
+        a0[q] = a_at(fr, k);
+        a1[q] = a_at(16 + fr, k);
+        b0[q] = b_at(k, fr);
+        b1[q] = b_at(k, 16 + fr);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[q], b0[q], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[q], b1[q], acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[q], b0[q], acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[q], b1[q], acc[3], 0, 0, 0);
+    }
+}
+
+// Off-diagonal blocks X_rs (r > s, 32x32) of the inverse of the block's
+// factor, from the blocks of earlier rows: X_rs = -X_rr W with
+// W = sum_{k=s}^{r-1} L_rk X_ks, by one wave.
+// w_sum_wave forms the part of W over the 32-wide k-blocks [kb0, kb1), into
+// a 32 x 33 slot Wq, or (Wq null) into the storage of X_rs itself, which is
+// free until X_rs is written.
+__device__ __forceinline__ void w_sum_wave(double *s, double *Wq, int r, int sblk, int kb0, int kb1) {
+    const int lane = opaque_lane(), fr = lane & 15, fk = lane >> 4;
+    const int ro = r * IB, so = sblk * IB;
+    double4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int kk = kb0 * IB; kk < kb1 * IB; kk += IB)
+        lds_mfma_32x32<IB>(
+            acc, [&](int m, int k) { return LL(ro + m, k); },
+            [&](int k, int n) { return sel(k >= so + n, XX(k, so + n)); }, kk, lane);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int m = 16 * (t >> 1) + fk + 4 * q, n = 16 * (t & 1) + fr;
+            if (Wq)
+                Wq[m * (IB + 1) + n] = acc[t][q];
+            else
+                XX(ro + m, so + n) = acc[t][q];
+        }
+    wave_lds_fence();
+}
+
+// X_rs = -X_rr W with W the sum of the slot Wq (if not null) and, if
+// in_place, of the partial sum held in X_rs's own storage (read in full
+// before X_rs is written).
+__device__ __forceinline__ void x_from_w_wave(double *s, const double *Wq, bool in_place, int r, int sblk) {
+    const int lane = opaque_lane(), fr = lane & 15, fk = lane >> 4;
+    const int ro = r * IB, so = sblk * IB;
+    double4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    lds_mfma_32x32<IB>(
+        acc, [&](int m, int k) { return sel(k <= m, XX(ro + m, ro + k)); },
+        [&](int k, int n) {
+            const double w = Wq ? Wq[k * (IB + 1) + n] : 0.0;
+            return in_place ? w + XX(ro + k, so + n) : w;
+        },
+        0, lane);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) XX(ro + 16 * (t >> 1) + fk + 4 * q, so + 16 * (t & 1) + fr) = -acc[t][q];
+    wave_lds_fence();
+}
+
+// Block (rb, cb) of X = L^{-1} (32x32, row-major CB x CB in global memory;
+// zero outside the factor and on the border row/column) by one wave.
+__device__ __forceinline__ void store_x_block(double *X, const double *s, int rb, int cb, int kb, int bi) {
+    const int lane = opaque_lane();
+    if (cb > rb) {  // above the diagonal: zeros
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = lane + 64 * q;
+            X[(rb * IB + e / IB) * CB + cb * IB + e % IB] = 0.0;
+        }
+        return;
+    }
+    double xv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = lane + 64 * q, i = rb * IB + e / IB, c = cb * IB + e % IB;
+        xv[q] = XX(i, c);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = lane + 64 * q, i = rb * IB + e / IB, c = cb * IB + e % IB;
+        const bool valid = c <= i && i < kb && i != bi && c != bi;
+        X[i * CB + c] = valid ? xv[q] : 0.0;
+    }
+}
+
+// Block column cb of L (rows 32 cb .. kb - 1, lower part) to A by nt threads
+// (thread index t), 16 elements a time: LDS reads first, then the stores.
+__device__ __forceinline__ void store_l_column(double *A, int64_t lda, int64_t k0, int kb, const double *s, int cb,
+                                               int t, int nt) {
+    const int n = (CB - cb * IB) * IB;
+    constexpr int SG = 16;
+    for (int e0 = t; e0 < n; e0 += SG * nt) {
+        double lv[SG];
+#pragma unroll
+        for (int e = 0; e < SG; ++e) {
+            const int idx = e0 + e * nt, r = cb * IB + idx / IB, c = cb * IB + idx % IB;
+            lv[e] = idx < n ? LL(r, c) : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < SG; ++e) {
+            const int idx = e0 + e * nt, r = cb * IB + idx / IB, c = cb * IB + idx % IB;
+            if (idx < n && r < kb && c <= r) A[(k0 + r) * lda + k0 + c] = lv[e];
+        }
+    }
 }
 
 // Factor one CB x CB diagonal block (rows/cols k0 .. k0+kb) of A and form X =
 // L^{-1} of the block (row-major CB x CB, zero outside the factor and on the
-// border row/column).  Right-looking over four 32-wide sub-blocks: a one-wave
-// leaf factorisation, then the sub-panel solve and the trailing update as
-// 16x16 FP64 MFMA tiles spread over the four waves; finally the off-diagonal
-// blocks of X by distance, X_rs = -X_rr sum_{k=s}^{r-1} L_rk X_ks, as MFMA
-// tiles as well.
-// LDS: s holds CB x LDS_LD doubles, colbuf 2 KS 64 (16-byte aligned), W
-// (CB/IB - 1) IB (IB + 1), fail_sh one int; NTH threads (4 or 8 waves; the
-// leaf factorisations run on wave 0, every wave takes part in the barriers).
+// border row/column).  Right-looking over four 32-wide sub-blocks: wave 0
+// runs the leaf factorisation of sub-block b (with the inverse of its
+// diagonal block) while waves 1-3 do the work that waits on nothing newer:
+// the first leaf overlaps the load of rows 32-127; the later ones overlap the
+// previous sub-block's trailing update below the next diagonal block, the
+// off-diagonal blocks of X in row b - 1 (X_rs = -X_rr sum_{k=s}^{r-1} L_rk X_ks,
+// one wave per block) and the stores of L's block column b - 1 and of X's
+// block row b - 1; the last leaf also overlaps the sums of X's last block
+// row, which leaves one 32 x 32 x 32 product per wave after it.  Between the leaves all four waves solve the sub-panel
+// below the leaf and update the next 32 x 32 diagonal block, as 16x16 FP64
+// MFMA tiles from LDS.
+// LDS: s holds CB x LDS_LD doubles, colbuf 2 KS 64 (16-byte aligned; also
+// the leaf's 16 x 17 coupling buffer), W (CB/IB - 1) IB (IB + 1) (one 32 x 33
+// slot per wave that forms an X block), fail_sh one int.  Four waves.
 static constexpr int POTRF_COLBUF = 2 * KS * 64;
 static constexpr int POTRF_W = (CB / IB - 1) * IB * (IB + 1);
 template <int NTH>
 __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t k0, int kb, int border_here, double *X,
                                                  DevStatus *status, double *s, double *colbuf, double *W,
                                                  int &fail_sh) {
-    static_assert(NTH == 256 || NTH == 512, "four or eight waves");
-    constexpr int NW = NTH / 64;
+    static_assert(NTH == 256, "four waves: the leaves on wave 0, the deferred work on waves 1-3");
+    constexpr int NW = NTH / 64, NB = CB / IB, WSLOT = IB * (IB + 1);
     if (status->flag) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: loops over tiles stay scalar
     const int fr = lane & 15, fk = lane >> 4;
     const int bi = border_here ? kb - 1 : -1;
-    {
-        // all 64 loads of a thread are issued before any LDS store: every lane
-        // loads (indices clamped into the kb x kb block), selects afterwards,
-        // so no load sits behind a branch and a wait for the one before it
-        double v[CB * CB / NTH];
-#pragma unroll
-        for (int e = 0; e < CB * CB / NTH; ++e) {
-            const int idx = tid + e * NTH, r = idx / CB, c = idx % CB;
-            const int rc = r < kb ? r : kb - 1, cc = c < kb ? c : kb - 1;
-            v[e] = A[(k0 + rc) * lda + k0 + cc];
-        }
-#pragma unroll
-        for (int e = 0; e < CB * CB / NTH; ++e) {
-            const int idx = tid + e * NTH, r = idx / CB, c = idx % CB;
-            v[e] = (r < kb && c <= r) ? v[e] : ((r >= kb && r == c) ? 1.0 : 0.0);
-        }
-#pragma unroll
-        for (int e = 0; e < CB * CB / NTH; ++e) {
-            const int idx = tid + e * NTH, r = idx / CB, c = idx % CB;
-            s[r * LDS_LD + c] = v[e];
-        }
-        if (tid < CB) s[tid * LDS_LD + CB] = 0.0;
-    }
+    // rows of the first sub-block (the rest is loaded during the first leaf)
+    load_block_rows<0, IB, NTH>(A, lda, k0, kb, s, tid);
+    if (tid < CB) s[tid * LDS_LD + CB] = 0.0;
     __syncthreads();
-    // ---- blocked right-looking factorisation, inner blocks of IB
 #pragma nounroll
-    for (int sb = 0; sb < CB / IB; ++sb) {
+    for (int sb = 0; sb < NB; ++sb) {
         const int o = sb * IB;
         if (wave == 0) {
             const int lb = (bi >= o && bi < o + IB) ? bi - o : -1;
-            const int f = potrf32_wave(s, o, lb, colbuf, W);
+            const int f = potrf32_wave(s, o, lb, colbuf, colbuf);
             if (lane == 0) fail_sh = f < 0 ? -1 : o + f;
+        } else {
+            // opaque copies: keeps the compiler from hoisting this branch's
+            // per-thread address arithmetic out of the loop (it would stay live
+            // across the leaves and spill)
+            int wt = tid - 64;
+            double *Ab = A, *Xb = X;
+            int64_t k0b = k0, ldab = lda;
+            asm volatile("" : "+v"(wt), "+s"(Ab), "+s"(Xb), "+s"(k0b), "+s"(ldab));
+            const int w1 = wave - 1;
+            constexpr int WN = NTH - 64;
+            if (sb == 0) {
+                load_block_rows<IB, CB - IB, WN>(Ab, ldab, k0b, kb, s, wt);
+            } else {
+                const int ob = o - IB, r = sb - 1;
+                // trailing update by block column ob below the diagonal block sb, on
+                // the waves that form no X block of row r
+                const int nt = (CB - o) / 16, nlow = nt * (nt + 1) / 2;
+                if (w1 >= r)
+                    for (int t = 3 + w1 - r; t < nlow; t += NW - 1 - r) trail_tile(s, ob, t);
+                double *Wq = W + w1 * WSLOT;
+                if (sb < NB - 1) {
+                    // block row r of X: X_{r,w1} (w1 < r) by wave w1 + 1, then the rest of
+                    // the row (X_rr and the zero blocks) and L's block column r
+                    if (w1 < r) {
+                        w_sum_wave(s, Wq, r, w1, w1, r);
+                        x_from_w_wave(s, Wq, false, r, w1);
+                        store_x_block(Xb, s, r, w1, kb, bi);
+                    }
+                    for (int c = r + w1; c < NB; c += NW - 1) store_x_block(Xb, s, r, c, kb, bi);
+                    store_l_column(Ab, ldab, k0b, kb, s, r, wt, WN);
+                } else if (w1 < r) {
+                    // during the last leaf (r = 2), the sums behind X's last block row
+                    // X_3s = -X_33 W_3s, W_3s = sum_{k=s}^{2} L_3k X_ks, spread so that
+                    // each wave does 96-128 MFMAs: wave 1 forms X_20 and the k = 2 term
+                    // of W_30 (slot 0); wave 2 forms X_21 and all of W_31 (slot 1)
+                    w_sum_wave(s, Wq, r, w1, w1, r);
+                    x_from_w_wave(s, Wq, false, r, w1);
+                    store_x_block(Xb, s, r, w1, kb, bi);
+                    w_sum_wave(s, Wq, r + 1, w1, w1 == 0 ? r : w1, r + 1);
+                } else {
+                    // wave 3: the k < 2 part of W_30 and all of W_32, each in the storage
+                    // of its block, then the rest of X's row r and L's column r
+                    w_sum_wave(s, nullptr, r + 1, 0, 0, r);
+                    w_sum_wave(s, nullptr, r + 1, r, r, r + 1);
+                    for (int c = r; c < NB; ++c) store_x_block(Xb, s, r, c, kb, bi);
+                    store_l_column(Ab, ldab, k0b, kb, s, r, lane, 64);
+                }
+            }
         }
         __syncthreads();
         if (fail_sh >= 0) {
@@ -312,8 +499,8 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
             }
             return;
         }
+        if (sb == NB - 1) break;
         const int r0 = o + IB, nr = CB - r0;
-        if (nr <= 0) break;
         // sub-panel: L[r][o+j] = sum_{k<=j} A[r][o+k] X[o+j][o+k]; (nr/16) x 2 tiles, at most 12 / NW per wave
         {
             constexpr int QT = (12 + NW - 1) / NW;
@@ -342,52 +529,23 @@ __device__ __forceinline__ void potrf_block_body(double *A, int64_t lda, int64_t
             }
         }
         __syncthreads();
-        // trailing update (lower tiles): A[r][c] -= sum_k L[r][o+k] L[c][o+k]
-        {
-            const int nt = nr / 16, nlow = nt * (nt + 1) / 2;
-            for (int t = wave; t < nlow; t += NW) {
-                int ti = 0;
-                while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-                const int tj = t - ti * (ti + 1) / 2;
-                const int rm = r0 + 16 * ti, cn = r0 + 16 * tj;
-                double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-                acc = lds_mfma<IB>(
-                    acc, [&](int m, int k) { return LL(rm + m, o + k); },
-                    [&](int k, int n) { return LL(cn + n, o + k); }, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rm + fk + 4 * r, col = cn + fr;
-                    if (col <= row) LL(row, col) -= acc[r];
-                }
-            }
-        }
+        // the next diagonal block's part of the trailing update (the rest
+        // runs on waves 1-3 during the next leaf)
+        if (wave < 3) trail_tile(s, o, wave);
         __syncthreads();
     }
-    // ---- off-diagonal blocks of X by distance d = r - s (all blocks of one
-    //      distance together), 16x16 tiles:
-    //      W = sum_{k=s}^{r-1} L_rk X_ks,  X_rs = -X_rr W
-    x_blocks_at_distance<1, NW>(s, W, wave);
-    x_blocks_at_distance<2, NW>(s, W, wave);
-    x_blocks_at_distance<3, NW>(s, W, wave);
-    // ---- write L (rows < kb) and X (zero outside the factor) to global memory,
-    //      16 elements a time: all LDS reads first, then the stores
-    constexpr int SG = 16;
-#pragma unroll 1
-    for (int e0 = 0; e0 < CB * CB / NTH; e0 += SG) {
-        double lv[SG], xv[SG];
-#pragma unroll
-        for (int e = 0; e < SG; ++e) {
-            const int idx = tid + (e0 + e) * NTH, r = idx / CB, c = idx % CB;
-            lv[e] = LL(r, c);
-            xv[e] = XX(r, c);
-        }
-#pragma unroll
-        for (int e = 0; e < SG; ++e) {
-            const int idx = tid + (e0 + e) * NTH, r = idx / CB, c = idx % CB;
-            if (r < kb && c <= r) A[(k0 + r) * lda + k0 + c] = lv[e];
-            const bool valid = c <= r && r < kb && r != bi && c != bi;
-            X[idx] = valid ? xv[e] : 0.0;
-        }
+    // block row NB - 1 of X from the sums formed during the last leaf (one
+    // block per wave) and the last block column of L
+    const int r = NB - 1;
+    double *Af = A, *Xf = X;
+    asm volatile("" : "+s"(Af), "+s"(Xf));  // computed here, not kept live from the start
+    if (wave < r) {
+        // X_30: slot 0 plus its own storage; X_31: slot 1; X_32: its own storage
+        x_from_w_wave(s, wave < 2 ? W + wave * WSLOT : nullptr, wave != 1, r, wave);
+        store_x_block(Xf, s, r, wave, kb, bi);
+    } else {
+        store_x_block(Xf, s, r, r, kb, bi);
+        store_l_column(Af, lda, k0, kb, s, r, lane, 64);
     }
 }
 
