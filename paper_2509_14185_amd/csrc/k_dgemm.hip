@@ -361,6 +361,12 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
         return launch_tiles<128, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
     }
     if (inplace) {
+        // 32-row tiles while they fit one round on the CUs: the panel solve is
+        // bound by each CU's own MFMA rate, so halving the rows per tile halves it
+        if (ntiles(32, 128) <= 256) {
+            const int64_t b = blocks_for<32, 128, 32>(g, tm, tn);
+            return launch_tiles<32, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+        }
         const int64_t b = blocks_for<64, 128, 32>(g, tm, tn);
         return launch_tiles<64, 128, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
     }
