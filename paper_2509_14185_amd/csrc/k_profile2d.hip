@@ -13,6 +13,7 @@
 //     symmetry rows; Boussinesq-type: three equations per point and y2 = 0
 //     boundary rows), the normalisation row, max |R|.
 #include "gn_internal.h"
+#include "tile_loader.h"
 
 namespace gn {
 
@@ -447,6 +448,131 @@ __global__ __launch_bounds__(256) void jet_sweep2d_kernel(MlpDesc d, Sweep2DLds 
     }
 }
 
+// ---- forward jets on the matrix cores
+// Each layer of the forward sweep is a product: for the six jet components
+// c of 16 points, Z_c = W H_c (+ bias for c = 0), W wout x win, H_c win x 16.
+// A workgroup (four waves) takes 16 points at a time; wave w forms the
+// 16-unit tiles w, w + 4 of Z for all six components with
+// v_mfma_f64_16x16x4f64 (A = W from the transposed weights through L1/L2,
+// B = H_c from LDS), so every lane ends with all six components of its
+// (unit, point) entries and applies the tanh jet rules in registers; the
+// result overwrites H in LDS (after a barrier) as the next layer's input.
+// LDS: H[c][j][t], 6 x wpad x 16 doubles (wpad = the widest layer input
+// rounded up to 16, at most 128).  Units beyond a layer's width come out as
+// tanh(0) = 0 with zero derivatives, which is the zero padding of the next
+// layer's K; the input layer's K is padded from 2 to 4.
+static constexpr int FW2_TP = 16;
+
+template <int UT>
+__global__ __launch_bounds__(256) void jet_forward2d_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta,
+                                                                 const double *__restrict__ thetaT, Sweep2DArgs b) {
+    extern __shared__ double hs[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int fr = lane & 15, fk = lane >> 4;
+    const int L = d.L;
+    auto H = [&](int c, int j, int t) -> double & { return hs[(c * wpad + j) * FW2_TP + t]; };
+    const int64_t ntiles = (b.nrows + FW2_TP - 1) / FW2_TP;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t p0 = tile * FW2_TP;
+        const int nr = (int)((b.nrows - p0) < FW2_TP ? (b.nrows - p0) : FW2_TP);
+        __syncthreads();  // the previous tile's reads of H are done
+        for (int idx = tid; idx < 6 * 4 * FW2_TP; idx += 256) {
+            const int c = idx / (4 * FW2_TP), j = (idx / FW2_TP) & 3, t = idx % FW2_TP;
+            H(c, j, t) = (j < 2 && t < nr) ? b.pts.xin[(j * 6 + c) * b.pts.ld + b.row0 + p0 + t] : 0.0;
+        }
+        __syncthreads();
+        for (int l = 0; l < L; ++l) {
+            const int win = d.w[l], wout = d.w[l + 1];
+            const int kpad = (win + 3) & ~3, nut = (wout + 15) / 16;
+            const double *Wt = thetaT + d.off[l];  // Wt[j][k] = W[k][j]
+            const double *bias = theta + d.off[l] + win * wout;
+            double4_t acc[UT][6];
+#pragma unroll
+            for (int u = 0; u < UT; ++u) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[u][c] = (double4_t){0.0, 0.0, 0.0, 0.0};
+                const int ui = wave + 4 * u;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * ui + fk + 4 * r;
+                    acc[u][0][r] = (ui < nut && k < wout) ? bias[k] : 0.0;
+                }
+            }
+            // K in chunks of four k-steps: the chunk's weight and H fragments are
+            // all loaded before its MFMAs (steps past kpad contribute zeros)
+            for (int s0 = 0; s0 < kpad; s0 += 16) {
+                double bf[4][6], a[UT][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = s0 + 4 * q + fk;
+                    const bool in = s0 + 4 * q < kpad;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) bf[q][c] = in ? H(c, j, fr) : 0.0;
+#pragma unroll
+                    for (int u = 0; u < UT; ++u) {
+                        const int k = 16 * (wave + 4 * u) + fr;
+                        a[u][q] = (in && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UT; ++u) {
+                    if (wave + 4 * u >= nut) continue;  // uniform over the wave
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int c = 0; c < 6; ++c)
+                            acc[u][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][q], bf[q][c], acc[u][c], 0, 0, 0);
+                }
+            }
+            __syncthreads();  // every read of this layer's input is done
+            if (l < L - 1) {
+#pragma unroll
+                for (int u = 0; u < UT; ++u) {
+                    const int ui = wave + 4 * u;
+                    if (ui >= nut) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 16 * ui + fk + 4 * r;
+                        const double z1 = acc[u][1][r], z2 = acc[u][2][r];
+                        const double th = tanh(acc[u][0][r]), sd = 1.0 - th * th;
+                        const double h1 = sd * z1, h2 = sd * z2;
+                        H(0, k, fr) = th;
+                        H(1, k, fr) = h1;
+                        H(2, k, fr) = h2;
+                        H(3, k, fr) = sd * acc[u][3][r] - 2.0 * th * h1 * z1;
+                        H(4, k, fr) = sd * acc[u][4][r] - 2.0 * th * h1 * z2;
+                        H(5, k, fr) = sd * acc[u][5][r] - 2.0 * th * h2 * z2;
+                    }
+                }
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int u = 0; u < UT; ++u) {
+                    const int ui = wave + 4 * u;
+                    if (ui >= nut) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 16 * ui + fk + 4 * r;
+                        if (k < wout && fr < nr)
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) b.nn[(k * 6 + c) * b.ldn + p0 + fr] = acc[u][c][r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// wpad of the matrix-core forward sweep, or 0 if the network does not fit it
+static int forward2d_mfma_wpad(const MlpDesc &d) {
+    if (d.w[0] != 2 || d.L < 1) return 0;
+    int m = 4;
+    for (int l = 1; l < d.L; ++l) m = d.w[l] > m ? d.w[l] : m;
+    const int wpad = (m + 15) / 16 * 16;
+    return (wpad <= 128 && d.w[d.L] <= 16 * 4 * 2) ? wpad : 0;
+}
+
 template <int MODE>
 static hipError_t launch_sweep2d(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
                                  const Sweep2DArgs &b, int64_t *nblocks) {
@@ -469,7 +595,29 @@ static hipError_t launch_sweep2d(hipStream_t st, const MlpDesc &d, const double 
 
 hipError_t launch_jets2d_forward(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
                                  const Sweep2DArgs &b) {
-    return launch_sweep2d<SW2_FORWARD>(st, d, theta, thetaT, b, nullptr);
+    const int wpad = forward2d_mfma_wpad(d);
+    if (wpad == 0) return launch_sweep2d<SW2_FORWARD>(st, d, theta, thetaT, b, nullptr);
+    if (b.nrows <= 0) return hipSuccess;
+    const size_t shm = sizeof(double) * 6 * wpad * FW2_TP;
+    const int64_t ntiles = (b.nrows + FW2_TP - 1) / FW2_TP;
+    const unsigned grid = (unsigned)(ntiles < 16384 ? ntiles : 16384);
+    static bool attr1 = false, attr2 = false;
+    if (wpad <= 64) {
+        if (!attr1) {
+            (void)hipFuncSetAttribute((const void *)jet_forward2d_mfma_kernel<1>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr1 = true;
+        }
+        hipLaunchKernelGGL(jet_forward2d_mfma_kernel<1>, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b);
+    } else {
+        if (!attr2) {
+            (void)hipFuncSetAttribute((const void *)jet_forward2d_mfma_kernel<2>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr2 = true;
+        }
+        hipLaunchKernelGGL(jet_forward2d_mfma_kernel<2>, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_jets2d_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
