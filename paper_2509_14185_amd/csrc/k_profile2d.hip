@@ -564,6 +564,227 @@ __global__ __launch_bounds__(256) void jet_forward2d_mfma_kernel(MlpDesc d, int 
     }
 }
 
+// ---- rows of J on the matrix cores (hidden widths up to 64)
+// A workgroup takes 16 rows at a time, with two LDS planes laid out like H
+// above (row stride 17 so that reads along j spread over the banks): H_l,
+// the activations entering layer l, and ZB, the adjoint of layer l's output
+// jets.  Reverse over the layers: H_l is recomputed by the forward products
+// from the input (the l layers below it, (L-1)L/2 layer products in all, so
+// no activations are kept across layers), the row entries of (W_l, b_l) are
+// sum_c ZB_c[k][t] H_c[j][t] and ZB_0[k][t], and then hb = W_l^T ZB per jet
+// component on the MFMA tiles, through the reverse tanh jet rule with H_l
+// into the next ZB.
+static constexpr int RW2_LD = FW2_TP + 1;
+
+__global__ __launch_bounds__(256) void jet_rows2d_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta,
+                                                              const double *__restrict__ thetaT, Sweep2DArgs b) {
+    extern __shared__ double sm[];
+    __shared__ int64_t pt_sh[FW2_TP];
+    double *hs = sm, *zs = sm + 6 * wpad * RW2_LD;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int fr = lane & 15, fk = lane >> 4;
+    const int L = d.L, nout = d.w[L];
+    auto H = [&](int c, int j, int t) -> double & { return hs[(c * wpad + j) * RW2_LD + t]; };
+    auto Z = [&](int c, int k, int t) -> double & { return zs[(c * wpad + k) * RW2_LD + t]; };
+    const int64_t ntiles = (b.nrows + FW2_TP - 1) / FW2_TP;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t p0 = tile * FW2_TP;
+        const int nr = (int)((b.nrows - p0) < FW2_TP ? (b.nrows - p0) : FW2_TP);
+        __syncthreads();  // the previous tile is done with the LDS planes
+        if (tid < FW2_TP) {
+            int kind, comp;
+            pt_sh[tid] = tid < nr ? b.map.point_of(b.row0 + p0 + tid, kind, comp) : -1;
+        }
+        // the output adjoint: the rows' seeds (zero past nout and past the last row)
+        for (int idx = tid; idx < 6 * 16 * FW2_TP; idx += 256) {
+            const int c = idx / (16 * FW2_TP), o = (idx / FW2_TP) & 15, t = idx % FW2_TP;
+            Z(c, o, t) = (o < nout && t < nr) ? b.seeds[(o * 6 + c) * b.lds + b.row0 + p0 + t] : 0.0;
+        }
+        for (int l = L - 1; l >= 0; --l) {
+            // H_l: the input jets, then the forward products of layers 0 .. l-1
+            __syncthreads();
+            for (int idx = tid; idx < 6 * 4 * FW2_TP; idx += 256) {
+                const int c = idx / (4 * FW2_TP), j = (idx / FW2_TP) & 3, t = idx % FW2_TP;
+                const int64_t pt = pt_sh[t];
+                H(c, j, t) = (j < 2 && pt >= 0) ? b.pts.xin[(j * 6 + c) * b.pts.ld + pt] : 0.0;
+            }
+            __syncthreads();
+            for (int f = 0; f < l; ++f) {
+                const int win = d.w[f], wout = d.w[f + 1];
+                const int kpad = (win + 3) & ~3, nut = (wout + 15) / 16;
+                const double *Wt = thetaT + d.off[f];
+                const double *bias = theta + d.off[f] + win * wout;
+                const bool mine = wave < nut;  // uniform: one 16-unit tile per wave
+                double4_t acc[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[c] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * wave + fk + 4 * r;
+                    acc[0][r] = (mine && k < wout) ? bias[k] : 0.0;
+                }
+                if (mine) {
+                    // the weight fragments of the next chunk are loaded (from L2)
+                    // before the current chunk's MFMAs
+                    const int k = 16 * wave + fr;
+                    double a[4], an[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = 4 * q + fk;
+                        a[q] = (4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
+                    }
+                    for (int s0 = 0; s0 < kpad; s0 += 16) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int j = s0 + 16 + 4 * q + fk;
+                            an[q] = (s0 + 16 + 4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
+                        }
+                        double bf[4][6];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int j = s0 + 4 * q + fk;
+                            const bool in = s0 + 4 * q < kpad;
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) bf[q][c] = in ? H(c, j, fr) : 0.0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int c = 0; c < 6; ++c)
+                                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bf[q][c], acc[c], 0, 0, 0);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) a[q] = an[q];
+                    }
+                }
+                __syncthreads();  // every read of the layer's input is done
+                if (mine) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 16 * wave + fk + 4 * r;
+                        const double z1 = acc[1][r], z2 = acc[2][r];
+                        const double th = tanh(acc[0][r]), sd = 1.0 - th * th;
+                        const double h1 = sd * z1, h2 = sd * z2;
+                        H(0, k, fr) = th;
+                        H(1, k, fr) = h1;
+                        H(2, k, fr) = h2;
+                        H(3, k, fr) = sd * acc[3][r] - 2.0 * th * h1 * z1;
+                        H(4, k, fr) = sd * acc[4][r] - 2.0 * th * h1 * z2;
+                        H(5, k, fr) = sd * acc[5][r] - 2.0 * th * h2 * z2;
+                    }
+                }
+                __syncthreads();
+            }
+            // the rows' entries of W_l (lane = j, wave = k mod 4, four rows at a
+            // time: each lane keeps its H values of the four rows, and the four
+            // rows' sums are independent) and of b_l
+            const int win = d.w[l], wout = d.w[l + 1];
+            double *Jl = b.J + p0 * b.ldJ + d.off[l];
+            if (win < 32) {
+                // narrow inputs (the first layer): entries spread flat over the threads
+                for (int idx = tid; idx < wout * win * nr; idx += 256) {
+                    const int t = idx / (wout * win), e = idx - t * wout * win, k = e / win, j = e - k * win;
+                    double v = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) v = fma(Z(c, k, t), H(c, j, t), v);
+                    Jl[t * b.ldJ + e] = v;
+                }
+            } else if (lane < win) {
+                for (int t0 = 0; t0 < nr; t0 += 4) {
+                    double hv[6][4];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) hv[c][q] = H(c, lane, t0 + q);
+                    for (int k = wave; k < wout; k += 4) {
+                        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int c = 0; c < 6; ++c)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) v[q] = fma(Z(c, k, t0 + q), hv[c][q], v[q]);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (t0 + q < nr) Jl[(t0 + q) * b.ldJ + k * win + lane] = v[q];
+                    }
+                }
+            }
+            for (int idx = tid; idx < wout * nr; idx += 256) {
+                const int t = idx / wout, k = idx - t * wout;
+                Jl[t * b.ldJ + wout * win + k] = Z(0, k, t);
+            }
+            if (l == 0) break;
+            // hb = W_l^T ZB per jet component (j-tile = wave), then back through tanh
+            {
+                const double *W = theta + d.off[l];  // W[k][j], wout x win
+                const int kpad = (wout + 3) & ~3, nut = (win + 15) / 16;
+                const bool mine = wave < nut;
+                double4_t acc[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[c] = (double4_t){0.0, 0.0, 0.0, 0.0};
+                if (mine) {
+                    const int j = 16 * wave + fr;
+                    double a[4], an[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = 4 * q + fk;
+                        a[q] = (4 * q < kpad && k < wout && j < win) ? W[k * win + j] : 0.0;
+                    }
+                    for (int s0 = 0; s0 < kpad; s0 += 16) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = s0 + 16 + 4 * q + fk;
+                            an[q] = (s0 + 16 + 4 * q < kpad && k < wout && j < win) ? W[k * win + j] : 0.0;
+                        }
+                        double bf[4][6];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = s0 + 4 * q + fk;
+                            const bool in = s0 + 4 * q < kpad;
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) bf[q][c] = in ? Z(c, k, fr) : 0.0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int c = 0; c < 6; ++c)
+                                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bf[q][c], acc[c], 0, 0, 0);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) a[q] = an[q];
+                    }
+                }
+                __syncthreads();  // every read of ZB (and of this layer's row entries) is done
+                if (mine) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = 16 * wave + fk + 4 * r;
+                        const double th = H(0, j, fr), h1 = H(1, j, fr), h2 = H(2, j, fr);
+                        const double h11 = H(3, j, fr), h12 = H(4, j, fr), h22 = H(5, j, fr);
+                        const double hb0 = acc[0][r], hb1 = acc[1][r], hb2 = acc[2][r];
+                        const double hb3 = acc[3][r], hb4 = acc[4][r], hb5 = acc[5][r];
+                        const double sd = 1.0 - th * th, t2 = 2.0 * th;
+                        Z(3, j, fr) = sd * hb3;
+                        Z(4, j, fr) = sd * hb4;
+                        Z(5, j, fr) = sd * hb5;
+                        Z(1, j, fr) = sd * hb1 - t2 * (2.0 * h1 * hb3 + h2 * hb4);
+                        Z(2, j, fr) = sd * hb2 - t2 * (h1 * hb4 + 2.0 * h2 * hb5);
+                        Z(0, j, fr) = sd * hb0 - t2 * (h1 * hb1 + h2 * hb2) - hb3 * (t2 * h11 + 2.0 * h1 * h1) -
+                                      hb4 * (t2 * h12 + 2.0 * h1 * h2) - hb5 * (t2 * h22 + 2.0 * h2 * h2);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// wpad of the matrix-core rows sweep (hidden widths up to 64), or 0
+static int rows2d_mfma_wpad(const MlpDesc &d) {
+    if (d.w[0] != 2 || d.L < 1 || d.w[d.L] > 16) return 0;
+    int m = 16;
+    for (int l = 1; l < d.L; ++l) m = d.w[l] > m ? d.w[l] : m;
+    const int wpad = (m + 15) / 16 * 16;
+    return wpad <= 64 ? wpad : 0;
+}
+
 // wpad of the matrix-core forward sweep, or 0 if the network does not fit it
 static int forward2d_mfma_wpad(const MlpDesc &d) {
     if (d.w[0] != 2 || d.L < 1) return 0;
@@ -622,7 +843,21 @@ hipError_t launch_jets2d_forward(hipStream_t st, const MlpDesc &d, const double 
 
 hipError_t launch_jets2d_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
                               const Sweep2DArgs &b) {
-    return launch_sweep2d<SW2_ROWS>(st, d, theta, thetaT, b, nullptr);
+    const int wpad = rows2d_mfma_wpad(d);
+    if (wpad == 0) return launch_sweep2d<SW2_ROWS>(st, d, theta, thetaT, b, nullptr);
+    if (b.nrows <= 0) return hipSuccess;
+    const size_t shm = sizeof(double) * 2 * 6 * wpad * RW2_LD;
+    const int64_t ntiles = (b.nrows + FW2_TP - 1) / FW2_TP;
+    const unsigned grid = (unsigned)(ntiles < 16384 ? ntiles : 16384);
+    static bool attr = false;
+    if (!attr) {
+        // the kernel's static LDS (the rows' point indices) comes on top
+        (void)hipFuncSetAttribute((const void *)jet_rows2d_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  159 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(jet_rows2d_mfma_kernel, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_jets2d_vjp(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
