@@ -405,15 +405,21 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double 
     atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
-// One thread per point, RES_PTS points per workgroup.  The nodes are staged
-// through LDS in chunks of RES_PTS (t_j, w_j, Theta_j) and every thread sums
-// its point's Hilbert terms over them in node order (deterministic); the
-// node values are LDS broadcasts, and consecutive terms are independent, so
-// the divisions pipeline.
-static constexpr int RES_PTS = 256;
+// 64 points per workgroup of four waves.  The nodes are staged through LDS
+// in chunks of RES_PTS (t_j, w_j, Theta_j); each wave sums its points' Hilbert
+// terms over its quarter of every chunk in node order, and the four partial
+// sums are added in wave order (deterministic).  The node values are LDS
+// broadcasts and consecutive terms are independent, so the divisions
+// pipeline; four waves per point give the small point sets (8192 collocation
+// points, or one instance of a batch) four times as many waves as one thread
+// per point would.
+static constexpr int RES_PTS = 256;                 // nodes staged per chunk
+static constexpr int RES_WG_PTS = 64, RES_SPLIT = 4;  // points per workgroup, waves per point
 __global__ __launch_bounds__(RES_PTS) void ccf_residual_kernel(ResidualArgs a) {
     __shared__ double tn[RES_PTS], wn[RES_PTS], thn[RES_PTS];
-    const int64_t i = (int64_t)blockIdx.x * RES_PTS + threadIdx.x;
+    __shared__ double Us[RES_SPLIT][RES_WG_PTS], cs[RES_SPLIT][RES_WG_PTS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * RES_WG_PTS + lane;
     const bool valid = i < a.n;
     const int64_t ii = valid ? i : a.n - 1;
     const double yi = a.pts.y[ii];
@@ -421,6 +427,9 @@ __global__ __launch_bounds__(RES_PTS) void ccf_residual_kernel(ResidualArgs a) {
     const double NNi = a.nn[ii];
     const double Thi = Ei * NNi;
     const double y2 = 2.0 * yi;
+    // the four waves of a workgroup take the same 64 points and a quarter of
+    // each staged chunk of nodes each; their partial sums are added in wave
+    // order (deterministic)
     double U = 0.0, c = 0.0;
     for (int64_t j0 = 0; j0 < a.m; j0 += RES_PTS) {
         const int64_t j = j0 + threadIdx.x;
@@ -431,8 +440,9 @@ __global__ __launch_bounds__(RES_PTS) void ccf_residual_kernel(ResidualArgs a) {
         }
         __syncthreads();
         const int cnt = (a.m - j0) < RES_PTS ? (int)(a.m - j0) : RES_PTS;
+        const int kb = w * (RES_PTS / RES_SPLIT), ke = kb + RES_PTS / RES_SPLIT < cnt ? kb + RES_PTS / RES_SPLIT : cnt;
 #pragma unroll 4
-        for (int k = 0; k < cnt; ++k) {
+        for (int k = kb; k < ke; ++k) {
             const double tj = tn[k];
             const double qij = wn[k] * y2 / ((yi - tj) * (yi + tj));
             U = fma(qij, thn[k] - Thi, U);
@@ -440,6 +450,12 @@ __global__ __launch_bounds__(RES_PTS) void ccf_residual_kernel(ResidualArgs a) {
         }
         __syncthreads();
     }
+    Us[w][lane] = U;
+    cs[w][lane] = c;
+    __syncthreads();
+    if (w != 0) return;
+    U = ((Us[0][lane] + Us[1][lane]) + Us[2][lane]) + Us[3][lane];
+    c = ((cs[0][lane] + cs[1][lane]) + cs[2][lane]) + cs[3][lane];
     const double lam = a.lam;
     const double NNq = a.nn[a.n + ii];
     const double Eyi = a.pts.Ey[ii], qyi = a.pts.qy[ii];
@@ -506,8 +522,8 @@ __global__ void burgers_residual_kernel(ResidualArgs a) {
 hipError_t launch_residual(hipStream_t st, const ResidualArgs &a) {
     if (a.n <= 0) return hipSuccess;
     if (a.equation == GN_EQ_CCF1D) {
-        hipLaunchKernelGGL(ccf_residual_kernel, dim3((unsigned)((a.n + RES_PTS - 1) / RES_PTS)), dim3(RES_PTS), 0, st,
-                           a);
+        hipLaunchKernelGGL(ccf_residual_kernel, dim3((unsigned)((a.n + RES_WG_PTS - 1) / RES_WG_PTS)), dim3(RES_PTS), 0,
+                           st, a);
     } else {
         hipLaunchKernelGGL(burgers_residual_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
     }
