@@ -93,14 +93,17 @@ typedef enum { GN_EQ_CCF1D = 0, GN_EQ_BURGERS1D = 1, GN_EQ_IPM2D = 3, GN_EQ_BOUS
  * sums, as for GN_SPLIT32. */
 typedef enum { GN_FP64 = 0, GN_SPLIT32 = 1, GN_INT8_CRT = 2 } gn_precision;
 
-#define GN_INT8_CRT_MAX_ROWS 130944  /* rows of J the int8 Gram accepts: 2^14-bounded
-                                        products summed in int32 stay exact */
+#define GN_INT8_CRT_MAX_ROWS 130944  /* rows of J per product of the int8 Gram (one
+                                        row chunk): 2^14-bounded products summed in
+                                        int32 stay exact; chunks add modulo m_t */
+#define GN_INT8_CRT_MAX_TOTAL_ROWS 1099511627776LL  /* 2^40 rows in all (b >= 41) */
 
-/* Host-only parameters of the GN_INT8_CRT Gram for m rows (no GPU call):
+/* Host-only parameters of the GN_INT8_CRT Gram for m rows of J in all (the
+ * sum over the row chunks of a streamed 2D problem; no GPU call):
  * *bits = b, the bits kept per column (m 2^(2b) < M / 4), *n_moduli = T and
  * moduli[0 .. T-1] (caller-owned, room for 32) the pairwise coprime moduli,
- * M their product.  GN_EINVAL for m < 1, m > GN_INT8_CRT_MAX_ROWS or a NULL
- * pointer. */
+ * M their product.  GN_EINVAL for m < 1, m > GN_INT8_CRT_MAX_TOTAL_ROWS or a
+ * NULL pointer. */
 gn_status gn_int8_crt_params(int64_t m, int32_t *bits, int32_t *n_moduli, int32_t *moduli);
 
 #define GN_MAX_LAYERS 8   /* affine layers */

@@ -553,7 +553,7 @@ const char *gn_status_string(int32_t s) {
 const char *gn_last_error(gn_handle h) { return h ? h->err.c_str() : noalloc_last_error(); }
 
 gn_status gn_int8_crt_params(int64_t m, int32_t *bits, int32_t *n_moduli, int32_t *moduli) {
-    if (m < 1 || m > GN_INT8_CRT_MAX_ROWS || !bits || !n_moduli || !moduli) return GN_EINVAL;
+    if (m < 1 || m > GN_INT8_CRT_MAX_TOTAL_ROWS || !bits || !n_moduli || !moduli) return GN_EINVAL;
     *bits = modgram_bits(m);
     *n_moduli = modgram_moduli();
     modgram_list(moduli);

@@ -29,7 +29,7 @@ def test_moduli_coprime_and_small():
     assert 16 * 255 * (2 ** 40 - 1) < 2 ** 53
 
 
-@pytest.mark.parametrize("m", [1, 2, 100, 1000, 8193, 65536, 130944])
+@pytest.mark.parametrize("m", [1, 2, 100, 1000, 8193, 65536, 130944, 130945, 786689, 2 ** 30])
 def test_bits_bound(m):
     b, mods = params(m)
     M = math.prod(mods)
@@ -44,7 +44,14 @@ def test_medium_step_bits():
     assert params(8193)[0] == 54
 
 
-@pytest.mark.parametrize("m", [0, -1, 130945])
+def test_streamed_total_rows_bits():
+    # the Boussinesq-type step streams 786,689 rows in 24 chunks; its columns
+    # keep 51 bits (b from the total row count, not a chunk's)
+    assert params(786689)[0] == 51
+    assert params(32768)[0] > params(786689)[0]
+
+
+@pytest.mark.parametrize("m", [0, -1, 2 ** 40 + 1])
 def test_rejects(m):
     with pytest.raises(gn.GNError):
         params(m)
@@ -85,3 +92,41 @@ def test_reconstruction_formula():
             u = (sum(y * w for y, w in zip(ys, W)) - Q * M) % 2 ** 128
             got = u - 2 ** 128 if u >= 2 ** 127 else u
             assert got == v
+
+
+def test_reconstruction_over_row_chunks():
+    """The streamed form at the Boussinesq-type size: 786,689 rows in chunks
+    of 32,768, each chunk's residue products summed exactly in int32, the
+    chunks added modulo m_t, then the reconstruction recovers the exact sum
+    (numpy int64 for the per-row products, Python integers for the rest)."""
+    import numpy as np
+
+    m, chunk = 786689, 32768
+    b, mods = params(m)
+    M = math.prod(mods)
+    W = [(M // mt) * pow((M // mt) % mt, -1, mt) for mt in mods]
+    f = [w / M for w in W]
+    rng = np.random.default_rng(6)
+    lim = 2 ** b
+    for trial in range(3):
+        # integers up to 2^b split into two int64-safe halves for numpy
+        x = [int(v) for v in rng.integers(-lim, lim, size=m, dtype=np.int64)]
+        z = x if trial == 0 else [int(v) for v in rng.integers(-lim, lim, size=m, dtype=np.int64)]
+        v = sum(a * c for a, c in zip(x, z))
+        ys = []
+        for mt in mods:
+            xr = np.array([balanced(a, mt) for a in x], dtype=np.int64)
+            zr = xr if z is x else np.array([balanced(a, mt) for a in z], dtype=np.int64)
+            y = 0
+            for c0 in range(0, m, chunk):
+                c = int(np.dot(xr[c0:c0 + chunk], zr[c0:c0 + chunk]))
+                assert abs(c) < 2 ** 31  # one chunk's int32 sum is exact
+                y = (y + c) % mt
+            ys.append(y)
+        qs = 0.0
+        for y, ft in zip(ys, f):
+            qs = math.fma(y, ft, qs) if hasattr(math, "fma") else qs + y * ft
+        Q = round(qs)
+        u = (sum(y * w for y, w in zip(ys, W)) - Q * M) % 2 ** 128
+        got = u - 2 ** 128 if u >= 2 ** 127 else u
+        assert got == v
