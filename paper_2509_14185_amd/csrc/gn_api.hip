@@ -39,6 +39,7 @@ struct gn_context {
     bool r1_factored = false;                           // the Gram workspace holds the factor of G_ema + gamma I
     double *gemv_work = nullptr, *red_work = nullptr, *chol_tmp = nullptr, *one_x = nullptr, *nn_one = nullptr, *seed_one = nullptr;
     DevStatus *status = nullptr;
+    unsigned *solve_sync = nullptr;   // epoch and published-block markers of the one-launch back substitution
     // point-set data (gn_set_points)
     int64_t n = 0, m = 0, nv = 0;
     Geo1D pts{}, nodes{}, val{};
@@ -306,6 +307,7 @@ gn_status jacobian_into(gn_handle h, const double *theta, double *J, int64_t ldJ
 gn_status read_status(gn_handle h, DevStatus *out) {
     GN_HIP(h, hipMemcpyAsync(out, h->status, sizeof(DevStatus), hipMemcpyDeviceToHost, h->stream));
     GN_HIP(h, hipStreamSynchronize(h->stream));
+    if (out->wait_fail) return fail(h, GN_EDEVICE, "a bounded device wait of the back substitution ran out%s");
     return GN_OK;
 }
 
@@ -630,6 +632,11 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->nn_one, 2);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->seed_one, 1);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->status, 1);
+    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->solve_sync, solve_sync_size(h->cap));
+    if (s == GN_OK && hipMemset(h->solve_sync, 0, sizeof(unsigned) * (size_t)solve_sync_size(h->cap)) != hipSuccess) {
+        (void)hipGetLastError();
+        s = GN_EDEVICE;
+    }
     if (!two_d && prob->n_fourier > 0) {
         h->nf = prob->n_fourier;
         if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->fb, h->nf);
@@ -1010,7 +1017,7 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, 
     GN_HIP(h, factor(h, d_G, p, ldG, mu, 0));
     GN_HIP(h, launch_copy_strided(st, d_g, p, 1, h->ybuf, 1, -1.0));
     GN_HIP(h, launch_solve_lower(st, d_G, p, ldG, h->linv, h->ybuf, h->zbuf, h->status));
-    GN_HIP(h, launch_solve_upper(st, d_G, p, ldG, h->linv, h->zbuf, d_delta, h->status));
+    GN_HIP(h, launch_solve_upper_sync(st, d_G, p, ldG, h->linv, h->zbuf, d_delta, h->status, h->solve_sync));
     GN_HIP(h, launch_check_finite(st, d_delta, p, h->status));
     DevStatus ds;
     GN_TRY(read_status(h, &ds));
@@ -1091,7 +1098,7 @@ gn_status solve_system(gn_handle h, double mu) {
     GN_HIP(h, launch_sumsq(st, w, P, 1, &h->status->grad_dot_delta, h->red_work));
     GN_HIP(h, launch_copy_strided(st, w + P, 1, 1, &h->status->model_sq_norm, 1, 1.0));
     GN_HIP(h, launch_copy_strided(st, w, P, 1, h->ybuf, 1, -1.0));
-    GN_HIP(h, launch_solve_upper(st, h->G, P, h->ldG, h->linv, h->ybuf, h->delta, h->status));
+    GN_HIP(h, launch_solve_upper_sync(st, h->G, P, h->ldG, h->linv, h->ybuf, h->delta, h->status, h->solve_sync));
     return GN_OK;
 }
 
@@ -1232,7 +1239,7 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     // Delta = -(G_ema + gamma I)^{-1} g
     GN_HIP(h, launch_copy_strided(st, h->r1_g, P, 1, h->r1_b, 1, -1.0));
     GN_HIP(h, launch_solve_lower(st, h->G, P, h->ldG, h->linv, h->r1_b, h->zbuf, h->status));
-    GN_HIP(h, launch_solve_upper(st, h->G, P, h->ldG, h->linv, h->zbuf, h->r1_D, h->status));
+    GN_HIP(h, launch_solve_upper_sync(st, h->G, P, h->ldG, h->linv, h->zbuf, h->r1_D, h->status, h->solve_sync));
     // exact curvature along Delta and d_prev
     GN_HIP(h, launch_gemv_n2(st, J, m_rows, P, ldJ, h->r1_D, d_prev, h->r1_w1, h->r1_w2));
     DotPairs dp{};

@@ -63,7 +63,7 @@ struct DevStatus {
     int32_t flag;                  // nonzero: stop (factorisation failed)
     int32_t nonfinite;             // nonzero: non-finite update found
     int32_t updated;
-    int32_t pad;
+    int32_t wait_fail;             // nonzero: a bounded device wait of the solve ran out
     double half_sq_norm;
     double grad_dot_delta;
     double model_sq_norm;
@@ -263,6 +263,14 @@ hipError_t launch_solve_lower(hipStream_t st, const double *L, int64_t n, int64_
                               const double *linv, double *b, double *z, DevStatus *status);
 hipError_t launch_solve_upper(hipStream_t st, const double *L, int64_t n, int64_t ldl,
                               const double *linv, double *y, double *x, DevStatus *status);
+// L^T x = y in one launch (one workgroup per column block, each waiting for
+// the blocks below it to be published); bitwise the result of
+// launch_solve_upper.  sync holds solve_sync_size(n) words, zeroed once when
+// allocated; y is not modified.  Calls that share sync must not overlap.
+int64_t solve_sync_size(int64_t n);
+hipError_t launch_solve_upper_sync(hipStream_t st, const double *L, int64_t n, int64_t ldl,
+                                   const double *linv, const double *y, double *x, DevStatus *status,
+                                   unsigned *sync);
 
 // Small kernels.
 hipError_t launch_sumsq(hipStream_t st, const double *x, int64_t n, int64_t stride, double *out,

@@ -33,7 +33,12 @@
 
 namespace gn {
 
-static constexpr int NB = 4 * CB;      // outer panel width (K of the trailing update)
+// Outer panel width (K of the trailing update).  Measured at n = 8514 (ms per
+// factorisation, two streams): 256 columns 8.83-9.27, 384 columns 8.71-8.83,
+// 512 columns 8.87-8.93, 768 columns 8.97-9.21.  Narrower panels shorten the
+// chain's own products (its update of the next outer panel is rest x NB x NB);
+// wider ones give the side stream longer K.
+static constexpr int NB = 3 * CB;
 
 int64_t chol_linv_size(int64_t n) { return ((n + CB - 1) / CB) * CB * CB; }
 int64_t chol_tmp_size() { return 64 * 64; }
@@ -73,14 +78,16 @@ __global__ __launch_bounds__(256) void potrf_block_batched_kernel(const BatchCho
 }
 
 // Row blocks of the side stream's trailing update per outer panel, and the K
-// extent of each of its launches: the NB columns of the outer panel in two
-// halves, so each tile holds its CU half as long and the critical chain's
-// kernels find free CUs sooner.  Measured on the medium CCF step (ms per
-// factorisation): K = 512 in one launch 10.03, two halves 9.76-9.84, four
-// quarters 11.4; with halves, 3 row blocks 9.69-9.71, 4 blocks 9.80-9.84,
-// 5 blocks 10.4.
-static constexpr int SIDE_CHUNKS = 3;
-static constexpr int64_t SIDE_K = NB / 2;
+// extent of each of its launches (a longer K is cut into pieces, so each tile
+// holds its CU for a shorter time and the critical chain's kernels find free
+// CUs sooner).  Measured at n = 8514 (ms per factorisation): with 512-column
+// panels, K = 512 in one launch 10.03, two halves of 256 9.76-9.84, four
+// quarters 11.4, and 3 row blocks 9.69-9.71 against 4 blocks 9.80-9.84 and 5
+// blocks 10.4 (before the later diagonal-block and panel-solve changes); with
+// 384-column panels (one piece of 384), 2 row blocks 8.71-8.73, 1 block
+// 8.85, 3 blocks 8.78-8.83, 4 blocks 8.80, and pieces of 192 9.34.
+static constexpr int SIDE_CHUNKS = 2;
+static constexpr int64_t SIDE_K = NB;
 
 hipError_t launch_cholesky(hipStream_t st, hipStream_t side, hipEvent_t ev_panel, hipEvent_t ev_trail, double *A,
                            int64_t n, int64_t lda, double mu, int border, double *linv, double *tmp,
@@ -367,6 +374,126 @@ __global__ __launch_bounds__(256) void back_update_kernel(const double *__restri
     back_update_body(L, n, ldl, linv, y, x, I, status);
 }
 
+// Back substitution L^T x = y in one launch.  Workgroup b owns column block
+// w = nblk - 1 - b and keeps y_w in LDS.  For I = nblk - 1 down to w + 1 it
+// issues the loads of L_Iw, waits until x_I is published, and subtracts
+// L_Iw^T x_I with the per-thread sums and the pairing of back_update_body;
+// then x_w = X_w^T y_w in the order of block_upper_apply (X_w staged in LDS
+// before the first wait).  The result is bitwise that of the launch per
+// block row.  A workgroup waits only on lower-numbered ones, which are
+// dispatched first, so the lowest unfinished workgroup can always run.
+//
+// sync[0] is an epoch that the one-thread kernel before the solve advances;
+// sync[1 + I] == epoch marks x_I as published.  Stores of x_w are made
+// visible at device scope (each storing thread fences) before thread 0's
+// release store of the marker; the waiting thread's acquire load and the
+// workgroup barrier after it order the reads of x_I.  Every wait is bounded:
+// past SOLVE_SPIN_LIMIT polls the workgroup records wait_fail and the stop
+// flag in the status and exits; waiting workgroups poll the stop flag too
+// and leave as soon as it is set.
+static constexpr long long SOLVE_SPIN_LIMIT = 1ll << 18;  // polls of about 0.1-1 us each
+
+int64_t solve_sync_size(int64_t n) { return 1 + (n + CB - 1) / CB; }
+
+__global__ void solve_epoch_kernel(unsigned *sync) {
+    if (threadIdx.x == 0) {
+        unsigned e = sync[0] + 1u;
+        if (e == 0u) e = 1u;  // 0 is the value of a marker never written
+        sync[0] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void back_sync_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
+                                                        const double *__restrict__ linv, const double *__restrict__ y,
+                                                        double *x, DevStatus *status, unsigned *sync) {
+    if (status->flag) return;
+    extern __shared__ double Xs[];  // X_w, CB x CB
+    __shared__ double ys[CB];
+    __shared__ double xs[CB];
+    __shared__ double part[256];
+    __shared__ int ok_s;
+    const int tid = threadIdx.x, c = tid & (CB - 1), h = tid >> 7;
+    const unsigned epoch = sync[0];
+    const int64_t nblk = (n + CB - 1) / CB;
+    const int64_t w = nblk - 1 - (int64_t)blockIdx.x;
+    const int64_t w0 = w * CB;
+    const int kbw = (int)((n - w0) < CB ? (n - w0) : CB);
+    {
+        const double2 *src = reinterpret_cast<const double2 *>(linv + w * CB * CB);
+        double2 *dst = reinterpret_cast<double2 *>(Xs);
+#pragma unroll 8
+        for (int e = tid; e < CB * CB / 2; e += 256) dst[e] = src[e];
+    }
+    if (tid < kbw) ys[tid] = y[w0 + tid];
+    const int64_t col = w0 + c;
+    for (int64_t I = nblk - 1; I > w; --I) {
+        const int64_t r0 = I * CB;
+        const int kbI = (int)((n - r0) < CB ? (n - r0) : CB);
+        double lv[CB / 2];
+        if (kbI == CB) {
+#pragma unroll
+            for (int e = 0; e < CB / 2; ++e) lv[e] = L[(r0 + 2 * e + h) * ldl + col];
+        }
+        if (tid == 0) {
+            int ok = 1;
+            long long spins = 0;
+            while (__hip_atomic_load(sync + 1 + I, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                if (__hip_atomic_load(&status->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = -1;  // another workgroup gave up: leave without waiting out the bound
+                    break;
+                }
+                if (++spins > SOLVE_SPIN_LIMIT) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (ok == 0) {
+                __hip_atomic_store(&status->wait_fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&status->flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            ok_s = ok;
+        }
+        __syncthreads();  // also: Xs and ys staged (first pass), part and xs consumed (later passes)
+        if (ok_s != 1) return;
+        if (tid < kbI) xs[tid] = x[r0 + tid];
+        __syncthreads();
+        double v0 = 0.0, v1 = 0.0;
+        if (kbI == CB) {
+#pragma unroll
+            for (int e = 0; e < CB / 2; e += 2) {
+                v0 = fma(lv[e], xs[2 * e + h], v0);
+                v1 = fma(lv[e + 1], xs[2 * e + 2 + h], v1);
+            }
+        } else {
+            for (int i = h; i < kbI; i += 2) v0 = fma(L[(r0 + i) * ldl + col], xs[i], v0);
+        }
+        part[tid] = v0 + v1;
+        __syncthreads();
+        if (h == 0) ys[c] = ys[c] - (part[c] + part[c + CB]);
+    }
+    __syncthreads();
+    // x_w = X_w^T y_w
+    double v0 = 0.0, v1 = 0.0;
+    if (c < kbw) {
+        int cc = c + h;
+#pragma unroll 8
+        for (; cc + 2 < kbw; cc += 4) {
+            v0 = fma(Xs[cc * CB + c], ys[cc], v0);
+            v1 = fma(Xs[(cc + 2) * CB + c], ys[cc + 2], v1);
+        }
+        for (; cc < kbw; cc += 2) v0 = fma(Xs[cc * CB + c], ys[cc], v0);
+    }
+    part[tid] = v0 + v1;
+    __syncthreads();
+    if (h == 0 && c < kbw) {
+        x[w0 + c] = part[c] + part[c + CB];
+        __threadfence();
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(sync + 1 + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // blockIdx.y = instance
 __global__ __launch_bounds__(256) void back_init_batched_kernel(const BatchChol *__restrict__ bc, int64_t n) {
     const BatchChol c = bc[blockIdx.y];
@@ -528,6 +655,24 @@ hipError_t launch_solve_upper(hipStream_t st, const double *L, int64_t n, int64_
     return hipGetLastError();
 }
 
+hipError_t launch_solve_upper_sync(hipStream_t st, const double *L, int64_t n, int64_t ldl, const double *linv,
+                                   const double *y, double *x, DevStatus *status, unsigned *sync) {
+    if (n <= 0) return hipSuccess;
+    static bool attr = false;
+    const size_t shm = sizeof(double) * CB * CB;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void *)back_sync_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int64_t nblk = (n + CB - 1) / CB;
+    hipLaunchKernelGGL(solve_epoch_kernel, dim3(1), dim3(64), 0, st, sync);
+    hipLaunchKernelGGL(back_sync_kernel, dim3((unsigned)nblk), dim3(256), shm, st, L, n, ldl, linv, y, x, status,
+                       sync);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ small kernels
 static constexpr int RED_BLOCKS = 256;
 
@@ -645,7 +790,7 @@ __global__ void reset_status_kernel(DevStatus *s) {
         s->flag = 0;
         s->nonfinite = 0;
         s->updated = 0;
-        s->pad = 0;
+        s->wait_fail = 0;
         s->half_sq_norm = 0.0;
         s->grad_dot_delta = 0.0;
         s->model_sq_norm = 0.0;
@@ -664,6 +809,7 @@ __global__ void reset_solve_status_kernel(DevStatus *s) {
         s->flag = 0;
         s->nonfinite = 0;
         s->updated = 0;
+        s->wait_fail = 0;
         s->grad_dot_delta = 0.0;
         s->model_sq_norm = 0.0;
         s->delta_sq_norm = 0.0;

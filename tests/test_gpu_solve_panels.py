@@ -1,8 +1,8 @@
 """GPU parity of the damped solve at an order with many outer panels of the
-blocked Cholesky (n = 2100: five 512-wide outer panels, the last one ragged), so
+blocked Cholesky (n = 2100: six 384-wide outer panels, the last one ragged), so
 that every part of the schedule runs: the side stream's trailing update in
-row chunks and in two K halves, the panel-after-next columns first, the
-joins.  Against the oracle: the normwise backward error of the solve
+row blocks, the panel-after-next columns first, the joins; and the one-launch
+back substitution over 17 column blocks (the last one ragged).  Against the oracle: the normwise backward error of the solve
 (oracle/gn.backward_error) <= 5e-14, the update against oracle/gn
 damped_solve to max(1e-12, 10 kappa eps), the factor against the oracle's
 textbook Cholesky (oracle/dense.c) to max(1e-12, 10 sqrt(kappa) eps).  G is
@@ -55,3 +55,23 @@ def test_solve_many_panels(big, mu):
     L = np.tril(Gd.cpu().numpy())
     Lo, _ = dense.cholesky(G + mu * np.eye(G.shape[0]))
     assert rel(L, Lo) < max(1e-12, 10 * np.sqrt(kappa) * EPS)
+
+
+def test_solves_in_sequence(big):
+    """Consecutive solves on one handle: the back substitution's published-block
+    markers advance by one epoch per solve, so a later solve of lower order, a
+    failed factorisation in between (no marker written) and the solve after it
+    must all read only their own blocks."""
+    G, g, pg = big
+    for n, mu in [(2100, 1e-6), (1500, 1e-3), (0, 0.0), (900, 1e-2), (2100, 1e-2)]:
+        if n == 0:
+            z = torch.zeros((300, 300), dtype=torch.float64, device="cuda")
+            with pytest.raises(gn.GNError) as e:
+                pg.solve(z, 0.0, torch.ones(300, dtype=torch.float64, device="cuda"))
+            assert e.value.status == gn.GN_ENOTPD
+            continue
+        Gn, gv = G[:n, :n], g[:n]
+        Gd = torch.from_numpy(np.ascontiguousarray(np.tril(Gn))).cuda()
+        delta, info = pg.solve(Gd, mu, torch.from_numpy(np.ascontiguousarray(gv)).cuda())
+        assert info == 0
+        assert ogn.backward_error(Gn, mu, gv, delta.cpu().numpy()) < 5e-14
