@@ -315,6 +315,221 @@ __global__ __launch_bounds__(SWEEP_THREADS) void mlp_sweep_kernel(MlpDesc d, Swe
     }
 }
 
+// ---- Jacobian rows on the matrix cores (scalar input and output, hidden
+// widths up to 64, no Fourier features)
+// A workgroup takes 16 points at a time.  Forward: per hidden layer, the two
+// jet components (value and x-derivative) of the layer's pre-activations,
+// Z_c = W H_c (+ bias for c = 0), as 16-unit x 16-point tiles on
+// v_mfma_f64_16x16x4f64 (wave w takes unit tile w; A = W from the transposed
+// weights through L1/L2, B = H_c from LDS), then th = tanh(z0) and
+// h1 = (1 - th^2) z1 in registers, stored in LDS as the next layer's input
+// (every hidden layer's jets stay in LDS for the reverse sweep).  The input
+// layer (one input, so no product) is formed per lane.  Reverse, from the
+// seeds on NN and NN_x: the row entries of (W_l, b_l) are
+// ZB_0[k] H_0[j] + ZB_1[k] H_1[j] and ZB_0[k] (lane = j, wave = k mod 4,
+// four rows at a time, so each store writes 64 contiguous entries of a row);
+// then hb = W_l^T ZB per component on the MFMA tiles and, through the
+// reverse tanh rule, zb_1 = (1 - th^2) hb_1 and
+// zb_0 = (1 - th^2) hb_0 - 2 th h1 hb_1.
+// LDS: planes [c][j][t] with row stride 17 (reads along j spread over the
+// banks): one per hidden layer output plus ZB, 2 x wpad x 17 doubles each.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+static constexpr int RW1_TP = 16, RW1_LD = RW1_TP + 1;
+
+__global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta,
+                                                            const double *__restrict__ thetaT, SweepBatch b) {
+    extern __shared__ double sm[];
+    __shared__ double xs[RW1_TP];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int fr = lane & 15, fk = lane >> 4;
+    const int L = d.L;
+    const int plane = 2 * wpad * RW1_LD;
+    // H_l (l = 1 .. L-1) at sm + (l - 1) * plane, ZB at sm + (L - 1) * plane
+    auto H = [&](int l, int c, int j, int t) -> double & { return sm[(l - 1) * plane + (c * wpad + j) * RW1_LD + t]; };
+    double *zs = sm + (L - 1) * plane;
+    auto Z = [&](int c, int k, int t) -> double & { return zs[(c * wpad + k) * RW1_LD + t]; };
+    const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t p0 = tile * RW1_TP;
+        const int nr = (int)((b.n - p0) < RW1_TP ? (b.n - p0) : RW1_TP);
+        __syncthreads();  // the previous tile is done with LDS
+        if (tid < RW1_TP) xs[tid] = tid < nr ? b.x[p0 + tid] : 0.0;
+        // seeds on NN (c = 0) and NN_x (c = 1); zero past the output and the last point
+        for (int idx = tid; idx < 2 * 16 * RW1_TP; idx += 256) {
+            const int c = idx / (16 * RW1_TP), o = (idx / RW1_TP) & 15, t = idx % RW1_TP;
+            double v = 0.0;
+            if (o == 0 && t < nr) v = c == 0 ? (b.s0 ? b.s0[p0 + t] : b.s0c) : (b.s1 ? b.s1[p0 + t] : b.s1c);
+            Z(c, o, t) = v;
+        }
+        __syncthreads();
+        // forward through the hidden layers
+        for (int f = 0; f + 1 < L; ++f) {
+            const int win = d.w[f], wout = d.w[f + 1];
+            const int nut = (wout + 15) / 16;
+            const bool mine = wave < nut;  // uniform: one 16-unit tile per wave
+            const double *bias = theta + d.off[f] + win * wout;
+            double4_t acc0 = (double4_t){0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+            if (mine) {
+                if (f == 0) {
+                    // one input: z0 = W x + b, z1 = W
+                    const double *W0 = theta + d.off[0];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 16 * wave + fk + 4 * r;
+                        const double wk = k < wout ? W0[k] : 0.0;
+                        acc0[r] = k < wout ? fma(wk, xs[fr], bias[k]) : 0.0;
+                        acc1[r] = wk;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = 16 * wave + fk + 4 * r;
+                        acc0[r] = k < wout ? bias[k] : 0.0;
+                    }
+                    const double *Wt = thetaT + d.off[f];  // Wt[j][k] = W[k][j]
+                    const int kpad = (win + 3) & ~3;
+                    const int k = 16 * wave + fr;
+                    double a[4], an[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = 4 * q + fk;
+                        a[q] = (4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
+                    }
+                    for (int s0 = 0; s0 < kpad; s0 += 16) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int j = s0 + 16 + 4 * q + fk;
+                            an[q] = (s0 + 16 + 4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
+                        }
+                        double b0[4], b1[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int j = s0 + 4 * q + fk;
+                            const bool in = s0 + 4 * q < kpad;
+                            b0[q] = in ? H(f, 0, j, fr) : 0.0;
+                            b1[q] = in ? H(f, 1, j, fr) : 0.0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b0[q], acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b1[q], acc1, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) a[q] = an[q];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * wave + fk + 4 * r;
+                    const double th = tanh(acc0[r]);
+                    H(f + 1, 0, k, fr) = th;
+                    H(f + 1, 1, k, fr) = (1.0 - th * th) * acc1[r];
+                }
+            }
+            __syncthreads();
+        }
+        // reverse over the layers
+        for (int l = L - 1; l >= 0; --l) {
+            const int win = d.w[l], wout = d.w[l + 1];
+            double *Jl = b.rows + p0 * b.ld + d.off[l];
+            if (l == 0) {
+                // one input: entries Z_0[k] x + Z_1[k] of W_0, then b_0
+                for (int idx = tid; idx < 2 * wout * nr; idx += 256) {
+                    const int t = idx / (2 * wout), e = idx - t * 2 * wout;
+                    const int k = e < wout ? e : e - wout;
+                    Jl[t * b.ld + e] = e < wout ? fma(Z(0, k, t), xs[t], Z(1, k, t)) : Z(0, k, t);
+                }
+                break;
+            }
+            if (wout < 4 || win < 32) {
+                for (int idx = tid; idx < wout * win * nr; idx += 256) {
+                    const int t = idx / (wout * win), e = idx - t * wout * win, k = e / win, j = e - k * win;
+                    Jl[t * b.ld + e] = fma(Z(0, k, t), H(l, 0, j, t), Z(1, k, t) * H(l, 1, j, t));
+                }
+            } else if (lane < win) {
+                for (int t0 = 0; t0 < nr; t0 += 4) {
+                    double h0[4], h1[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        h0[q] = H(l, 0, lane, t0 + q);
+                        h1[q] = H(l, 1, lane, t0 + q);
+                    }
+                    for (int k = wave; k < wout; k += 4) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (t0 + q < nr)
+                                Jl[(t0 + q) * b.ld + k * win + lane] = fma(Z(0, k, t0 + q), h0[q], Z(1, k, t0 + q) * h1[q]);
+                    }
+                }
+            }
+            for (int idx = tid; idx < wout * nr; idx += 256) {
+                const int t = idx / wout, k = idx - t * wout;
+                Jl[t * b.ld + wout * win + k] = Z(0, k, t);
+            }
+            // hb = W_l^T ZB per component (j-tile = wave), then back through tanh
+            const double *W = theta + d.off[l];  // W[k][j], wout x win
+            const int kpad = (wout + 3) & ~3, nut = (win + 15) / 16;
+            const bool mine = wave < nut;
+            double4_t acc0 = (double4_t){0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+            if (mine) {
+                const int j = 16 * wave + fr;
+                double a[4], an[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = 4 * q + fk;
+                    a[q] = (4 * q < kpad && k < wout && j < win) ? W[k * win + j] : 0.0;
+                }
+                for (int s0 = 0; s0 < kpad; s0 += 16) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = s0 + 16 + 4 * q + fk;
+                        an[q] = (s0 + 16 + 4 * q < kpad && k < wout && j < win) ? W[k * win + j] : 0.0;
+                    }
+                    double b0[4], b1[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = s0 + 4 * q + fk;
+                        const bool in = s0 + 4 * q < kpad;
+                        b0[q] = in ? Z(0, k, fr) : 0.0;
+                        b1[q] = in ? Z(1, k, fr) : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b0[q], acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b1[q], acc1, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) a[q] = an[q];
+                }
+            }
+            __syncthreads();  // every read of ZB (this layer's rows and products) is done
+            if (mine) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = 16 * wave + fk + 4 * r;
+                    const double th = H(l, 0, j, fr), h1 = H(l, 1, j, fr);
+                    const double sd = 1.0 - th * th;
+                    Z(1, j, fr) = sd * acc1[r];
+                    Z(0, j, fr) = sd * acc0[r] - 2.0 * th * h1 * acc1[r];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// wpad of the matrix-core rows sweep, or 0 if the network does not fit it
+static int rows1d_mfma_wpad(const MlpDesc &d) {
+    if (d.L < 2 || d.w[0] != 1 || d.w[d.L] != 1) return 0;
+    int m = 16;
+    for (int l = 1; l < d.L; ++l) m = d.w[l] > m ? d.w[l] : m;
+    const int wpad = (m + 15) / 16 * 16;
+    if (wpad > 64) return 0;
+    const size_t bytes = sizeof(double) * (size_t)d.L * 2 * wpad * RW1_LD;
+    return bytes <= 150 * 1024 ? wpad : 0;
+}
+
 // W^T per layer (same offsets as theta; biases copied).
 __global__ void transpose_weights_kernel(MlpDesc d, const double *__restrict__ theta, double *__restrict__ out) {
     for (int l = 0; l < d.L; ++l) {
@@ -364,7 +579,20 @@ hipError_t launch_mlp_forward(hipStream_t st, const MlpDesc &d, const double *th
 hipError_t launch_mlp_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
                            SweepBatch b) {
     if (b.n <= 0) return hipSuccess;
-    return launch_sweep_mode<SWEEP_ROWS>(st, d, theta, thetaT, b, nullptr);
+    const int wpad = b.phi ? 0 : rows1d_mfma_wpad(d);
+    if (wpad == 0) return launch_sweep_mode<SWEEP_ROWS>(st, d, theta, thetaT, b, nullptr);
+    static bool attr = false;
+    if (!attr) {
+        // the kernel's static LDS (the tile's inputs) comes on top
+        (void)hipFuncSetAttribute((const void *)mlp_rows_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  152 * 1024);
+        attr = true;
+    }
+    const size_t shm = sizeof(double) * (size_t)d.L * 2 * wpad * RW1_LD;
+    const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
+    const unsigned grid = (unsigned)(ntiles < 16384 ? ntiles : 16384);
+    hipLaunchKernelGGL(mlp_rows_mfma_kernel, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b);
+    return hipGetLastError();
 }
 int64_t mlp_vjp_partials(const MlpDesc &, int64_t n) { return (n + SWEEP_TILE - 1) / SWEEP_TILE; }
 hipError_t launch_mlp_vjp(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,

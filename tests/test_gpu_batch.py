@@ -73,19 +73,31 @@ def test_batched_step_matches_oracle(small):
 
 
 def test_batched_matches_single(small):
+    """Two batched steps against two single steps per instance.  The first
+    step's residual statistics come from the same kernels at the same theta
+    (equal to 1e-14); its model value and g^T delta come from Grams, factors
+    and solves with other summation orders (compared on the scale of r^T r,
+    of which the bordered factor's corner is a difference; the oracle check
+    takes 1e-8 r^T r).  The second step starts from iterates that differ by
+    the rounding of the first update, so its statistics are compared at
+    1e-10."""
     inps, pgs, b = small
     mu = 1e-3
     ts = [dev(x["theta0"]) for x in inps]
-    for _ in range(2):  # second step: new iterate, same descriptors
-        sts = b.step(ts, mu)
-    for inp, pg, t, st in zip(inps, pgs, ts, sts):
+    sts1 = b.step(ts, mu)
+    sts2 = b.step(ts, mu)  # second step: new iterate, same descriptors
+    for inp, pg, t, st1, st2 in zip(inps, pgs, ts, sts1, sts2):
         u = dev(inp["theta0"])
-        pg.step(u, mu)
         s1 = pg.step(u, mu)
+        s2 = pg.step(u, mu)
         assert rel(t.cpu().numpy(), u.cpu().numpy()) < 1e-12
-        for k in ("half_sq_norm", "max_abs_R", "max_abs_R_val", "model_sq_norm"):
-            assert abs(st[k] - s1[k]) <= 1e-12 * abs(s1[k])
-        assert abs(st["grad_dot_delta"] - s1["grad_dot_delta"]) <= 1e-12 * abs(s1["grad_dot_delta"])
+        rr = 2 * s1["half_sq_norm"]
+        for k in ("half_sq_norm", "max_abs_R", "max_abs_R_val"):
+            assert abs(st1[k] - s1[k]) <= 1e-14 * abs(s1[k])
+            assert abs(st2[k] - s2[k]) <= 1e-10 * abs(s2[k])
+        for k in ("model_sq_norm", "grad_dot_delta"):
+            assert abs(st1[k] - s1[k]) <= 1e-12 * rr
+            assert abs(st2[k] - s2[k]) <= 1e-10 * 2 * s2["half_sq_norm"]
 
 
 def test_batched_new_parameter_buffers_and_determinism(small):
