@@ -516,9 +516,9 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": ("gram (dgemm_mfma_kernel<128,128,32,1,0,false,512>, accumulated over row chunks; the "
+            "kernel": ("gram (dgemm_mfma_kernel<128,128,16,1,0,false,256>, accumulated over row chunks; the "
                        "phase includes the Jacobian sweeps of each chunk)" if inp.get("row_chunk", 0) else
-                       "gram (dgemm_mfma_kernel<128,128,32,1,0,false,512>)"),
+                       "gram (dgemm_mfma_kernel<128,128,16,1,0,false,256>)"),
             "achieved": fl_gram / t_gram / 1e12,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
@@ -824,7 +824,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gram (dgemm_mfma_kernel<128,128,32,1,0,false,512>)",
+            "kernel": "gram (dgemm_mfma_kernel<128,128,16,1,0,false,256>)",
             "achieved": gram_tf,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
