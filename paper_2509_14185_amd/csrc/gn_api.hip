@@ -1016,7 +1016,7 @@ gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu, 
     GN_HIP(h, launch_reset_status(st, h->status));
     GN_HIP(h, factor(h, d_G, p, ldG, mu, 0));
     GN_HIP(h, launch_copy_strided(st, d_g, p, 1, h->ybuf, 1, -1.0));
-    GN_HIP(h, launch_solve_lower(st, d_G, p, ldG, h->linv, h->ybuf, h->zbuf, h->status));
+    GN_HIP(h, launch_solve_lower_sync(st, d_G, p, ldG, h->linv, h->ybuf, h->zbuf, h->status, h->solve_sync));
     GN_HIP(h, launch_solve_upper_sync(st, d_G, p, ldG, h->linv, h->zbuf, d_delta, h->status, h->solve_sync));
     GN_HIP(h, launch_check_finite(st, d_delta, p, h->status));
     DevStatus ds;
@@ -1238,7 +1238,7 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     }
     // Delta = -(G_ema + gamma I)^{-1} g
     GN_HIP(h, launch_copy_strided(st, h->r1_g, P, 1, h->r1_b, 1, -1.0));
-    GN_HIP(h, launch_solve_lower(st, h->G, P, h->ldG, h->linv, h->r1_b, h->zbuf, h->status));
+    GN_HIP(h, launch_solve_lower_sync(st, h->G, P, h->ldG, h->linv, h->r1_b, h->zbuf, h->status, h->solve_sync));
     GN_HIP(h, launch_solve_upper_sync(st, h->G, P, h->ldG, h->linv, h->zbuf, h->r1_D, h->status, h->solve_sync));
     // exact curvature along Delta and d_prev
     GN_HIP(h, launch_gemv_n2(st, J, m_rows, P, ldJ, h->r1_D, d_prev, h->r1_w1, h->r1_w2));

@@ -268,6 +268,12 @@ hipError_t launch_solve_upper(hipStream_t st, const double *L, int64_t n, int64_
 // launch_solve_upper.  sync holds solve_sync_size(n) words, zeroed once when
 // allocated; y is not modified.  Calls that share sync must not overlap.
 int64_t solve_sync_size(int64_t n);
+// L z = b in one launch (one workgroup per row block, each waiting for the
+// blocks above it); bitwise the result of launch_solve_lower; b is not
+// modified.  Same sync words and rules as launch_solve_upper_sync.
+hipError_t launch_solve_lower_sync(hipStream_t st, const double *L, int64_t n, int64_t ldl,
+                                   const double *linv, const double *b, double *z, DevStatus *status,
+                                   unsigned *sync);
 hipError_t launch_solve_upper_sync(hipStream_t st, const double *L, int64_t n, int64_t ldl,
                                    const double *linv, const double *y, double *x, DevStatus *status,
                                    unsigned *sync);

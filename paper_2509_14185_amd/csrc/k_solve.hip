@@ -494,6 +494,114 @@ __global__ __launch_bounds__(256) void back_sync_kernel(const double *__restrict
     if (tid == 0) __hip_atomic_store(sync + 1 + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Forward substitution L z = b in one launch.  Workgroup w owns row block w:
+// it issues the loads of X_w (in the staging order of block_lower_apply) and,
+// for I = 0 .. w-1, the loads of L_wI before it waits for z_I to be
+// published, then subtracts L_wI z_I with the per-thread sums of
+// fwd_update_kernel (32-column chunks staged through LDS, two threads per
+// row) and finally forms z_w = X_w b_w in the order of block_lower_apply, so
+// the result is bitwise that of the launch per block column.  Publication,
+// epochs and bounded waits as in back_sync_kernel; b is not modified.
+__global__ __launch_bounds__(256) void fwd_sync_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
+                                                       const double *__restrict__ linv, const double *__restrict__ b,
+                                                       double *z, DevStatus *status, unsigned *sync) {
+    if (status->flag) return;
+    constexpr int KC = 32, NE = CB * KC / 256;  // loads per thread per chunk
+    __shared__ double tile[CB][KC + 1];
+    __shared__ double zs[CB];
+    __shared__ double bs[CB];
+    __shared__ double part[256];
+    __shared__ int ok_s;
+    const int tid = threadIdx.x, row = tid & (CB - 1), half = tid >> 7;
+    const unsigned epoch = sync[0];
+    const int64_t w = blockIdx.x;
+    const int64_t w0 = w * CB;
+    const int kbw = (int)((n - w0) < CB ? (n - w0) : CB);
+    const double *Xb = linv + w * CB * CB;
+    double xv[CB / KC][NE];
+#pragma unroll
+    for (int ch = 0; ch < CB / KC; ++ch)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC, k0 = ch * KC;
+            xv[ch][e] = (k0 < kbw && rr < kbw && k0 + kk < kbw) ? Xb[rr * CB + k0 + kk] : 0.0;
+        }
+    if (tid < kbw) bs[tid] = b[w0 + tid];
+    for (int64_t I = 0; I < w; ++I) {
+        const int64_t r0 = I * CB;  // block I < w is full
+        double lv[CB / KC][NE];
+#pragma unroll
+        for (int ch = 0; ch < CB / KC; ++ch)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
+                lv[ch][e] = rr < kbw ? L[(w0 + rr) * ldl + r0 + ch * KC + kk] : 0.0;
+            }
+        if (tid == 0) {
+            int ok = 1;
+            long long spins = 0;
+            while (__hip_atomic_load(sync + 1 + I, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                if (__hip_atomic_load(&status->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = -1;
+                    break;
+                }
+                if (++spins > SOLVE_SPIN_LIMIT) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (ok == 0) {
+                __hip_atomic_store(&status->wait_fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&status->flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            ok_s = ok;
+        }
+        __syncthreads();  // also: bs staged (first pass), part and bs updates of the previous pass done
+        if (ok_s != 1) return;
+        if (tid < CB) zs[tid] = z[r0 + tid];
+        double acc = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < CB / KC; ++ch) {
+            __syncthreads();  // previous chunk consumed (and zs written, first chunk)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int idx = tid + e * 256;
+                tile[idx / KC][idx % KC] = lv[ch][e];
+            }
+            __syncthreads();
+            for (int kk = half; kk < KC; kk += 2) acc = fma(tile[row][kk], zs[ch * KC + kk], acc);
+        }
+        part[tid] = acc;
+        __syncthreads();
+        if (half == 0 && row < kbw) bs[row] = bs[row] - (part[row] + part[row + CB]);
+    }
+    // z_w = X_w b_w
+    double acc = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < CB / KC; ++ch) {
+        const int k0 = ch * KC;
+        if (k0 >= kbw) break;  // uniform
+        __syncthreads();  // previous chunk consumed; bs final
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int idx = tid + e * 256;
+            tile[idx / KC][idx % KC] = xv[ch][e];
+        }
+        __syncthreads();
+        const int kend = (kbw - k0) < KC ? kbw - k0 : KC;
+        for (int kk = half; kk < kend; kk += 2) acc = fma(tile[row][kk], bs[k0 + kk], acc);
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (half == 0 && row < kbw) {
+        z[w0 + row] = part[row] + part[row + CB];
+        __threadfence();
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(sync + 1 + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // blockIdx.y = instance
 __global__ __launch_bounds__(256) void back_init_batched_kernel(const BatchChol *__restrict__ bc, int64_t n) {
     const BatchChol c = bc[blockIdx.y];
@@ -670,6 +778,15 @@ hipError_t launch_solve_upper_sync(hipStream_t st, const double *L, int64_t n, i
     hipLaunchKernelGGL(solve_epoch_kernel, dim3(1), dim3(64), 0, st, sync);
     hipLaunchKernelGGL(back_sync_kernel, dim3((unsigned)nblk), dim3(256), shm, st, L, n, ldl, linv, y, x, status,
                        sync);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_lower_sync(hipStream_t st, const double *L, int64_t n, int64_t ldl, const double *linv,
+                                   const double *b, double *z, DevStatus *status, unsigned *sync) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nblk = (n + CB - 1) / CB;
+    hipLaunchKernelGGL(solve_epoch_kernel, dim3(1), dim3(64), 0, st, sync);
+    hipLaunchKernelGGL(fwd_sync_kernel, dim3((unsigned)nblk), dim3(256), 0, st, L, n, ldl, linv, b, z, status, sync);
     return hipGetLastError();
 }
 
