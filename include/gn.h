@@ -49,7 +49,7 @@ typedef enum {
     GN_EREJECTED = 2,    /* gn_step_lm: no trial decreased the objective; theta unchanged */
     GN_EINVAL = -1,      /* bad argument (null pointer, size, leading dimension, widths) */
     GN_ENOMEM = -2,      /* workspace allocation failed */
-    GN_EDEVICE = -3,     /* HIP runtime error */
+    GN_EDEVICE = -3,     /* HIP runtime error, or a bounded device wait that ran out */
     GN_ENONFINITE = -4,  /* NaN or Inf in r, g or the update */
     GN_ESTATE = -5       /* call out of order (e.g. no points set) */
 } gn_status;
@@ -233,7 +233,10 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
 /* Damped solve (G + mu I) delta = -g.  In: lower triangle of G (p x p,
  * ldG >= p); out: its lower Cholesky factor L in place, delta (p).
  * Synchronises to fill *h_info (0, or the 1-based first non-positive pivot).
- * Returns GN_ENOTPD (delta not written) or GN_ENONFINITE. */
+ * Returns GN_ENOTPD (delta not written) or GN_ENONFINITE; GN_EDEVICE also
+ * when a bounded device wait of the substitutions runs out (each triangular
+ * solve is one launch whose workgroups wait for the blocks they depend on;
+ * this does not happen in normal operation). */
 gn_status gn_solve(gn_handle h, double *d_G, int64_t p, int64_t ldG, double mu,
                    const double *d_g, double *d_delta, int64_t *h_info);
 

@@ -2,16 +2,16 @@
 // "Second-order Optimizer": theta <- theta - (G + gamma I)^{-1} grad h).
 //
 // Right-looking blocked Cholesky, two levels (128-wide diagonal blocks inside
-// 512-wide outer panels) with look-ahead:
+// 384-wide outer panels) with look-ahead:
 //   1. diagonal block: one workgroup factors it in LDS (one-wave 32x32
 //      register factorisations, the rest by all four waves) and forms the
 //      inverse of its triangular factor;
 //   2. panel below: L21 = A21 L11^{-T} as an MFMA GEMM with the inverse;
 //   3. the remaining columns of the outer panel are updated (K = 128);
-//   4. after an outer panel, the trailing matrix is updated with K = 512
+//   4. after an outer panel, the trailing matrix is updated with K = 384
 //      (lower), split into the next outer panel's columns (main stream) and
-//      the rest (a second stream, in two launches of K = 256), so the next
-//      panel is factored while the bulk of the update runs.  A large K keeps
+//      the rest (a second stream, in two row blocks), so the next panel is
+//      factored while the bulk of the update runs.  A large K keeps
 //      the update's C tiles (read and written once per launch) from
 //      dominating its HBM traffic.
 // A failed pivot records its 1-based global index and raises a device flag;
@@ -22,10 +22,13 @@
 // ends as the Schur complement r^T r - g^T (G + mu I)^{-1} g and the rest of
 // that row as w = L^{-1} g, so the forward substitution comes for free.
 //
-// Triangular solves use the stored diagonal-block inverses: one launch per
-// 128-row block applies the known block to the rest of the right-hand side,
-// one workgroup per remaining block, and the workgroup of the next block
-// then forms that block's unknowns.
+// Triangular solves use the stored diagonal-block inverses.  The handle's
+// solves run in one launch each (fwd_sync_kernel, back_sync_kernel: one
+// workgroup per 128-row block, each waiting for the blocks it depends on to
+// be published); the launch-per-block versions (one launch per block applies
+// the known block to the rest of the right-hand side, one workgroup per
+// remaining block, and the workgroup of the next block then forms that
+// block's unknowns) serve the solve without allocation and the batched step.
 #include <vector>
 
 #include "gn_internal.h"

@@ -7,8 +7,9 @@ Which instances run here, and why these sizes reach them:
   - the Hilbert coupling product (N = 1024 or 8192 rows, K = 1024 nodes,
     8 x 67 or 64 x 67 output tiles >= 512) takes the 256-thread 128 x 128 x 16
     configuration;
-  - the damped solve at order 4400 and 8514 runs outer panels of 512 columns
-    whose trailing updates on the side stream use 128 x 128 tiles.
+  - the damped solve at orders 4400, 7040 and 8514 runs outer panels of 384
+    columns; from about order 7000 on, the side stream's trailing update also
+    takes 128 x 128 tiles (its first row block's rectangle has 512 or more).
 
 Comparisons are element by element where the workload is too large for the
 oracle to produce every output:
@@ -317,9 +318,9 @@ def test_medium_step_backward_error(medium):
 
 # --------------------------------------------------------------- solve at order 4400
 def test_solve_order_4400_side_stream_tiles(medium):
-    """The damped solve at order 4400 (outer panels of 512 with 128 x 128
-    trailing tiles on the side stream) against the oracle's Cholesky and
-    substitutions."""
+    """The damped solve at order 4400 (12 outer panels of 384 columns, the
+    last one ragged; 64 x 64 trailing tiles on the side stream) against the
+    oracle's Cholesky and substitutions."""
     n = 4400
     rng = np.random.default_rng(44)
     X = rng.standard_normal((700, n)) / np.sqrt(700)
@@ -339,3 +340,25 @@ def test_solve_order_4400_side_stream_tiles(medium):
     L = np.tril(Gd.cpu().numpy())
     Lo, _ = dense.cholesky(G + mu * np.eye(n))
     assert rel(L, np.tril(Lo)) < max(1e-12, 10 * np.sqrt(kappa) * EPS)
+
+
+def test_solve_order_7040_side_stream_128_tiles(medium):
+    """The damped solve at order 7040, where the side stream's trailing update
+    of the first outer panels takes 128 x 128 tiles (a 2944 x 2944 rectangle:
+    529 tiles): the normwise backward error (the oracle's checker) and the
+    solution against a LAPACK solve (kappa of G + mu I is about 40 here, so
+    10 kappa eps is below the 1e-12 asked).  The oracle's own Cholesky is not
+    run at this order (it would take minutes)."""
+    n = 7040
+    print(f"\n[gpu fullsize] solve at order {n}", flush=True)
+    rng = np.random.default_rng(70)
+    X = rng.standard_normal((700, n)) / np.sqrt(700)
+    G = X.T @ X + np.diag(rng.uniform(0.5, 2.0, n))
+    g = rng.standard_normal(n)
+    mu = 1e-2
+    delta, info = medium["pg"].solve(dev(np.tril(G)), mu, dev(g))
+    assert info == 0
+    d = delta.cpu().numpy()
+    assert ogn.backward_error(G, mu, g, d) < 5e-14
+    ref = np.linalg.solve(G + mu * np.eye(n), -g)
+    assert rel(d, ref) < 1e-12
