@@ -336,6 +336,74 @@ __global__ __launch_bounds__(SWEEP_THREADS) void mlp_sweep_kernel(MlpDesc d, Swe
 typedef double double4_t __attribute__((ext_vector_type(4)));
 static constexpr int RW1_TP = 16, RW1_LD = RW1_TP + 1;
 
+// Pre-activations of layer f for the 16 points of a tile: acc0 (value) and
+// acc1 (x-derivative) of units 16 * wave + fk + 4 r at point fr, as
+// Z_c = W_f H_c (+ bias for c = 0) on the MFMA tiles (A = W_f from the
+// transposed weights, B = H_c from the LDS plane Hf laid out [c][j][t] with
+// row stride RW1_LD); the input layer (one input x, Hf null) is formed per
+// lane.  Returns false (accumulators zero) for waves past the layer's unit
+// tiles (uniform over the wave).
+__device__ __forceinline__ bool rows1d_layer_product(const MlpDesc &d, int f, int wpad, const double *__restrict__ theta,
+                                                     const double *__restrict__ thetaT, const double *Hf,
+                                                     const double *xs, int wave, int fr, int fk, double4_t &acc0,
+                                                     double4_t &acc1) {
+    const int win = d.w[f], wout = d.w[f + 1];
+    const int nut = (wout + 15) / 16;
+    acc0 = (double4_t){0.0, 0.0, 0.0, 0.0};
+    acc1 = acc0;
+    if (wave >= nut) return false;
+    const double *bias = theta + d.off[f] + win * wout;
+    if (Hf == nullptr) {
+        // one input: z0 = W x + b, z1 = W
+        const double *W0 = theta + d.off[0];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 16 * wave + fk + 4 * r;
+            const double wk = k < wout ? W0[k] : 0.0;
+            acc0[r] = k < wout ? fma(wk, xs[fr], bias[k]) : 0.0;
+            acc1[r] = wk;
+        }
+        return true;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = 16 * wave + fk + 4 * r;
+        acc0[r] = k < wout ? bias[k] : 0.0;
+    }
+    const double *Wt = thetaT + d.off[f];  // Wt[j][k] = W[k][j]
+    const int kpad = (win + 3) & ~3;
+    const int k = 16 * wave + fr;
+    double a[4], an[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = 4 * q + fk;
+        a[q] = (4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
+    }
+    for (int s0 = 0; s0 < kpad; s0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = s0 + 16 + 4 * q + fk;
+            an[q] = (s0 + 16 + 4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
+        }
+        double b0[4], b1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = s0 + 4 * q + fk;
+            const bool in = s0 + 4 * q < kpad;
+            b0[q] = in ? Hf[j * RW1_LD + fr] : 0.0;
+            b1[q] = in ? Hf[(wpad + j) * RW1_LD + fr] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b0[q], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b1[q], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = an[q];
+    }
+    return true;
+}
+
 __global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta,
                                                             const double *__restrict__ thetaT, SweepBatch b) {
     extern __shared__ double sm[];
@@ -365,60 +433,9 @@ __global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad,
         __syncthreads();
         // forward through the hidden layers
         for (int f = 0; f + 1 < L; ++f) {
-            const int win = d.w[f], wout = d.w[f + 1];
-            const int nut = (wout + 15) / 16;
-            const bool mine = wave < nut;  // uniform: one 16-unit tile per wave
-            const double *bias = theta + d.off[f] + win * wout;
-            double4_t acc0 = (double4_t){0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-            if (mine) {
-                if (f == 0) {
-                    // one input: z0 = W x + b, z1 = W
-                    const double *W0 = theta + d.off[0];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int k = 16 * wave + fk + 4 * r;
-                        const double wk = k < wout ? W0[k] : 0.0;
-                        acc0[r] = k < wout ? fma(wk, xs[fr], bias[k]) : 0.0;
-                        acc1[r] = wk;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int k = 16 * wave + fk + 4 * r;
-                        acc0[r] = k < wout ? bias[k] : 0.0;
-                    }
-                    const double *Wt = thetaT + d.off[f];  // Wt[j][k] = W[k][j]
-                    const int kpad = (win + 3) & ~3;
-                    const int k = 16 * wave + fr;
-                    double a[4], an[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = 4 * q + fk;
-                        a[q] = (4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
-                    }
-                    for (int s0 = 0; s0 < kpad; s0 += 16) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int j = s0 + 16 + 4 * q + fk;
-                            an[q] = (s0 + 16 + 4 * q < kpad && k < wout && j < win) ? Wt[j * wout + k] : 0.0;
-                        }
-                        double b0[4], b1[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int j = s0 + 4 * q + fk;
-                            const bool in = s0 + 4 * q < kpad;
-                            b0[q] = in ? H(f, 0, j, fr) : 0.0;
-                            b1[q] = in ? H(f, 1, j, fr) : 0.0;
-                        }
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b0[q], acc0, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b1[q], acc1, 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) a[q] = an[q];
-                    }
-                }
+            double4_t acc0, acc1;
+            if (rows1d_layer_product(d, f, wpad, theta, thetaT, f > 0 ? &H(f, 0, 0, 0) : nullptr, xs, wave, fr, fk,
+                                     acc0, acc1)) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int k = 16 * wave + fk + 4 * r;
@@ -519,6 +536,50 @@ __global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad,
     }
 }
 
+// Forward jets on the matrix cores (the same networks as the rows kernel):
+// the hidden layers as there, then the output layer's value and
+// x-derivative, NN and NN_x, from the same product (one unit: wave 0, lanes
+// of the first unit row).
+__global__ __launch_bounds__(256) void mlp_forward_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta,
+                                                               const double *__restrict__ thetaT, SweepBatch b) {
+    extern __shared__ double sm[];
+    __shared__ double xs[RW1_TP];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int fr = lane & 15, fk = lane >> 4;
+    const int L = d.L;
+    const int plane = 2 * wpad * RW1_LD;
+    auto H = [&](int l, int c, int j, int t) -> double & { return sm[(l - 1) * plane + (c * wpad + j) * RW1_LD + t]; };
+    const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t p0 = tile * RW1_TP;
+        const int nr = (int)((b.n - p0) < RW1_TP ? (b.n - p0) : RW1_TP);
+        __syncthreads();  // the previous tile is done with LDS
+        if (tid < RW1_TP) xs[tid] = tid < nr ? b.x[p0 + tid] : 0.0;
+        __syncthreads();
+        for (int f = 0; f + 1 < L; ++f) {
+            double4_t acc0, acc1;
+            if (rows1d_layer_product(d, f, wpad, theta, thetaT, f > 0 ? &H(f, 0, 0, 0) : nullptr, xs, wave, fr, fk,
+                                     acc0, acc1)) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 16 * wave + fk + 4 * r;
+                    const double th = tanh(acc0[r]);
+                    H(f + 1, 0, k, fr) = th;
+                    H(f + 1, 1, k, fr) = (1.0 - th * th) * acc1[r];
+                }
+            }
+            __syncthreads();
+        }
+        double4_t acc0, acc1;
+        if (rows1d_layer_product(d, L - 1, wpad, theta, thetaT, &H(L - 1, 0, 0, 0), xs, wave, fr, fk, acc0, acc1) &&
+            fk == 0 && fr < nr) {
+            b.nn[p0 + fr] = acc0[0];
+            b.nn[b.n + p0 + fr] = acc1[0];
+        }
+    }
+}
+
 // wpad of the matrix-core rows sweep, or 0 if the network does not fit it
 static int rows1d_mfma_wpad(const MlpDesc &d) {
     if (d.L < 2 || d.w[0] != 1 || d.w[d.L] != 1) return 0;
@@ -574,7 +635,21 @@ hipError_t launch_transpose_weights(hipStream_t st, const MlpDesc &d, const doub
 hipError_t launch_mlp_forward(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
                               SweepBatch b) {
     if (b.n <= 0) return hipSuccess;
-    return launch_sweep_mode<SWEEP_FORWARD>(st, d, theta, thetaT, b, nullptr);
+    const int wpad = b.phi ? 0 : rows1d_mfma_wpad(d);
+    if (wpad == 0) return launch_sweep_mode<SWEEP_FORWARD>(st, d, theta, thetaT, b, nullptr);
+    const size_t shm = sizeof(double) * (size_t)(d.L - 1) * 2 * wpad * RW1_LD;
+    if (shm > 64 * 1024) {
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void *)mlp_forward_mfma_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+            attr = true;
+        }
+    }
+    const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
+    const unsigned grid = (unsigned)(ntiles < 16384 ? ntiles : 16384);
+    hipLaunchKernelGGL(mlp_forward_mfma_kernel, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b);
+    return hipGetLastError();
 }
 hipError_t launch_mlp_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
                            SweepBatch b) {
