@@ -541,7 +541,14 @@ struct gn_batch_context {
     std::vector<double *> uploaded_thetas;
     std::vector<DevStatus> ds;
     std::vector<uint64_t> gen;  // point-set generation of every handle when the batch was made
+    // the per-instance stage (small, launch-bound kernels) spread over the
+    // batch stream and BATCH_LANES more streams of default priority,
+    // forked from and joined back into the batch stream by events
+    std::vector<hipStream_t> lanes;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
 };
+static constexpr int BATCH_LANES = 3;
 
 extern "C" {
 
@@ -1539,6 +1546,9 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
 }
 
 static void batch_free(gn_batch b) {
+    for (hipStream_t l : b->lanes) (void)hipStreamDestroy(l);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->d_bc) (void)hipFree(b->d_bc);
     batched_plan_free(b->coupling);
     batched_plan_free(b->gram);
@@ -1578,6 +1588,15 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     if (e == hipSuccess) e = batched_plan_upload(b->gram);
     for (auto &p : b->chol)
         if (e == hipSuccess) e = batched_plan_upload(p);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int l = 0; l < BATCH_LANES && e == hipSuccess; ++l) {
+        hipStream_t s_ = nullptr;
+        hipEvent_t j_ = nullptr;
+        e = hipStreamCreateWithFlags(&s_, hipStreamNonBlocking);
+        if (e == hipSuccess) b->lanes.push_back(s_);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&j_, hipEventDisableTiming);
+        if (e == hipSuccess) b->join.push_back(j_);
+    }
     if (e != hipSuccess) {
         batch_free(b);
         return e == hipErrorOutOfMemory ? GN_ENOMEM : GN_EDEVICE;
@@ -1622,19 +1641,31 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
             (void)hipEventRecord(h0->events[(size_t)h0->prof_count * (GN_PHASE_COUNT + 1) + k], st);
     };
     bmark(GN_PHASE_FORWARD);
-    // per instance: residual, validation, local Jacobian rows with r in column P
-    for (int i = 0; i < n; ++i) {
+    // per instance: residual, validation, local Jacobian rows with r in column P;
+    // instance i on the batch stream (i % (lanes + 1) == 0) or on lane i % (lanes + 1) - 1
+    const int nl = (int)b->lanes.size();
+    GN_HIP(h0, hipEventRecord(b->fork, st));
+    for (int l = 0; l < nl; ++l) GN_HIP(h0, hipStreamWaitEvent(b->lanes[l], b->fork, 0));
+    gn_status err = GN_OK;
+    for (int i = 0; i < n && err == GN_OK; ++i) {
         gn_handle h = b->hs[i];
+        const int q = i % (nl + 1);
+        hipStream_t s_ = q == 0 ? st : b->lanes[q - 1];
         hipStream_t own = h->stream;
-        h->stream = st;
-        gn_status e = GN_OK;
-        if (launch_reset_status(st, h->status) != hipSuccess) e = GN_EDEVICE;
-        if (e == GN_OK) e = build_step_jacobian(h, d_thetas[i], false, false);
-        if (e == GN_OK && launch_sumsq(st, h->J + P, total_rows(h), h->ldJ, &h->status->half_sq_norm, h->red_work) != hipSuccess)
-            e = GN_EDEVICE;
+        h->stream = s_;
+        if (launch_reset_status(s_, h->status) != hipSuccess) err = GN_EDEVICE;
+        if (err == GN_OK) err = build_step_jacobian(h, d_thetas[i], false, false);
+        if (err == GN_OK &&
+            launch_sumsq(s_, h->J + P, total_rows(h), h->ldJ, &h->status->half_sq_norm, h->red_work) != hipSuccess)
+            err = GN_EDEVICE;
         h->stream = own;
-        if (e != GN_OK) return e;
     }
+    // join every lane back into the batch stream, also after an error
+    for (int l = 0; l < nl; ++l) {
+        GN_HIP(h0, hipEventRecord(b->join[l], b->lanes[l]));
+        GN_HIP(h0, hipStreamWaitEvent(st, b->join[l], 0));
+    }
+    if (err != GN_OK) return err;
     // batched Hilbert coupling, Gram, bordered Cholesky, back substitution and update
     bmark(GN_PHASE_JLOCAL);  // the local rows are timed with the forward phase
     bmark(GN_PHASE_COUPLING);
