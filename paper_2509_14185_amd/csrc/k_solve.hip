@@ -498,19 +498,22 @@ __global__ __launch_bounds__(256) void back_sync_kernel(const double *__restrict
 }
 
 // Forward substitution L z = b in one launch.  Workgroup w owns row block w:
-// it issues the loads of X_w (in the staging order of block_lower_apply) and,
-// for I = 0 .. w-1, the loads of L_wI before it waits for z_I to be
-// published, then subtracts L_wI z_I with the per-thread sums of
-// fwd_update_kernel (32-column chunks staged through LDS, two threads per
-// row) and finally forms z_w = X_w b_w in the order of block_lower_apply, so
-// the result is bitwise that of the launch per block column.  Publication,
-// epochs and bounded waits as in back_sync_kernel; b is not modified.
+// it loads X_w into registers (in the staging order of block_lower_apply)
+// and, for I = 0 .. w-1, loads L_wI and puts it into an LDS tile before it
+// waits for z_I to be published, then subtracts L_wI z_I with the per-thread
+// sums of fwd_update_kernel (two threads per row, each summing every other
+// column in order) and finally forms z_w = X_w b_w in the order of
+// block_lower_apply, so the result is bitwise that of the launch per block
+// column.  The whole 128 x 128 tile sits in LDS (132 KB), so each block takes
+// three barriers instead of the ten of 32-column chunks.  Publication, epochs
+// and bounded waits as in back_sync_kernel; b is not modified.
 __global__ __launch_bounds__(256) void fwd_sync_kernel(const double *__restrict__ L, int64_t n, int64_t ldl,
                                                        const double *__restrict__ linv, const double *__restrict__ b,
                                                        double *z, DevStatus *status, unsigned *sync) {
     if (status->flag) return;
-    constexpr int KC = 32, NE = CB * KC / 256;  // loads per thread per chunk
-    __shared__ double tile[CB][KC + 1];
+    constexpr int KC = 32, NE = CB * KC / 256;  // loads per thread per 32-column chunk
+    constexpr int LD = CB + 1;
+    extern __shared__ double tile[];             // CB x LD
     __shared__ double zs[CB];
     __shared__ double bs[CB];
     __shared__ double part[256];
@@ -532,14 +535,24 @@ __global__ __launch_bounds__(256) void fwd_sync_kernel(const double *__restrict_
     if (tid < kbw) bs[tid] = b[w0 + tid];
     for (int64_t I = 0; I < w; ++I) {
         const int64_t r0 = I * CB;  // block I < w is full
-        double lv[CB / KC][NE];
+        {
+            double lv[CB / KC][NE];
 #pragma unroll
-        for (int ch = 0; ch < CB / KC; ++ch)
+            for (int ch = 0; ch < CB / KC; ++ch)
 #pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
-                lv[ch][e] = rr < kbw ? L[(w0 + rr) * ldl + r0 + ch * KC + kk] : 0.0;
-            }
+                for (int e = 0; e < NE; ++e) {
+                    const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
+                    lv[ch][e] = rr < kbw ? L[(w0 + rr) * ldl + r0 + ch * KC + kk] : 0.0;
+                }
+            // the previous block's reads of the tile ended before its partial-sum barrier
+#pragma unroll
+            for (int ch = 0; ch < CB / KC; ++ch)
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
+                    tile[rr * LD + ch * KC + kk] = lv[ch][e];
+                }
+        }
         if (tid == 0) {
             int ok = 1;
             long long spins = 0;
@@ -560,41 +573,27 @@ __global__ __launch_bounds__(256) void fwd_sync_kernel(const double *__restrict_
             }
             ok_s = ok;
         }
-        __syncthreads();  // also: bs staged (first pass), part and bs updates of the previous pass done
+        __syncthreads();  // the tile stored; bs staged (first block), bs updates of the previous block done
         if (ok_s != 1) return;
         if (tid < CB) zs[tid] = z[r0 + tid];
+        __syncthreads();
         double acc = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < CB / KC; ++ch) {
-            __syncthreads();  // previous chunk consumed (and zs written, first chunk)
-#pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                const int idx = tid + e * 256;
-                tile[idx / KC][idx % KC] = lv[ch][e];
-            }
-            __syncthreads();
-            for (int kk = half; kk < KC; kk += 2) acc = fma(tile[row][kk], zs[ch * KC + kk], acc);
-        }
+        for (int kk = half; kk < CB; kk += 2) acc = fma(tile[row * LD + kk], zs[kk], acc);
         part[tid] = acc;
         __syncthreads();
         if (half == 0 && row < kbw) bs[row] = bs[row] - (part[row] + part[row + CB]);
     }
-    // z_w = X_w b_w
-    double acc = 0.0;
+    // z_w = X_w b_w (every read of the tile by the last block ended before its partial-sum barrier)
 #pragma unroll
-    for (int ch = 0; ch < CB / KC; ++ch) {
-        const int k0 = ch * KC;
-        if (k0 >= kbw) break;  // uniform
-        __syncthreads();  // previous chunk consumed; bs final
+    for (int ch = 0; ch < CB / KC; ++ch)
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-            const int idx = tid + e * 256;
-            tile[idx / KC][idx % KC] = xv[ch][e];
+            const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
+            tile[rr * LD + ch * KC + kk] = xv[ch][e];
         }
-        __syncthreads();
-        const int kend = (kbw - k0) < KC ? kbw - k0 : KC;
-        for (int kk = half; kk < kend; kk += 2) acc = fma(tile[row][kk], bs[k0 + kk], acc);
-    }
+    __syncthreads();  // the tile stored; bs final
+    double acc = 0.0;
+    for (int kk = half; kk < kbw; kk += 2) acc = fma(tile[row * LD + kk], bs[kk], acc);
     part[tid] = acc;
     __syncthreads();
     if (half == 0 && row < kbw) {
@@ -789,7 +788,17 @@ hipError_t launch_solve_lower_sync(hipStream_t st, const double *L, int64_t n, i
     if (n <= 0) return hipSuccess;
     const int64_t nblk = (n + CB - 1) / CB;
     hipLaunchKernelGGL(solve_epoch_kernel, dim3(1), dim3(64), 0, st, sync);
-    hipLaunchKernelGGL(fwd_sync_kernel, dim3((unsigned)nblk), dim3(256), 0, st, L, n, ldl, linv, b, z, status, sync);
+    static bool attr = false;
+    const size_t shm = sizeof(double) * CB * (CB + 1);
+    if (!attr) {
+        // the kernel's static LDS (z_I, b_w, the partial sums) comes on top
+        const hipError_t e = hipFuncSetAttribute((const void *)fwd_sync_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(fwd_sync_kernel, dim3((unsigned)nblk), dim3(256), shm, st, L, n, ldl, linv, b, z, status,
+                       sync);
     return hipGetLastError();
 }
 
