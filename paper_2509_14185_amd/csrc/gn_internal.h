@@ -197,7 +197,7 @@ hipError_t launch_gemv_t(hipStream_t st, const double *J, int64_t m, int64_t p, 
 struct ModgramWork {
     int8_t *R = nullptr;                 // residues, MODS x ppad x kpad
     int64_t r_bytes = 0;
-    uint8_t *Y = nullptr;                // product residues, MODS x ppad x ppad
+    uint8_t *Y = nullptr;                // product residues, MODS x packed lower 256 x 256 tiles
     int64_t y_bytes = 0;
     unsigned long long *cmax = nullptr;  // column maxima (bit patterns), ppad
     int64_t cmax_len = 0;

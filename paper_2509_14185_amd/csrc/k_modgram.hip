@@ -74,7 +74,17 @@ struct CrtConsts {
 int64_t modgram_kpad(int64_t m) { return (m + MG_BK - 1) / MG_BK * MG_BK; }
 int64_t modgram_ppad(int64_t p) { return (p + MG_BM - 1) / MG_BM * MG_BM; }
 int64_t modgram_r_bytes(int64_t m, int64_t p) { return (int64_t)MODS * modgram_ppad(p) * modgram_kpad(m); }
-int64_t modgram_y_bytes(int64_t p) { return (int64_t)MODS * modgram_ppad(p) * modgram_ppad(p); }
+// product residues: per modulus the lower MG_BM x MG_BM tiles only, packed
+// tile (tm, tn <= tm) at index tm (tm + 1) / 2 + tn, each row-major
+static inline int64_t mg_ytiles(int64_t p) {
+    const int64_t t = modgram_ppad(p) / MG_BM;
+    return t * (t + 1) / 2;
+}
+int64_t modgram_y_bytes(int64_t p) { return (int64_t)MODS * mg_ytiles(p) * MG_BM * MG_BM; }
+__host__ __device__ inline int64_t mg_yoff(int64_t row, int64_t col) {
+    const int64_t tm = row / MG_BM, tn = col / MG_BM;
+    return ((tm * (tm + 1) / 2 + tn) * MG_BM + row % MG_BM) * MG_BM + col % MG_BM;
+}
 int modgram_moduli() { return MODS; }
 void modgram_list(int32_t *out) {
     for (int t = 0; t < MODS; ++t) out[t] = MODULI[t];
@@ -345,7 +355,7 @@ __device__ __forceinline__ int mg_swz(int row) { return (row / (256 / MG_BK)) % 
 template <bool ACC>
 __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict__ R, int64_t ldr, int64_t rplane,
                                                         int kchunks, int tiles, int64_t supers, ModConsts mc,
-                                                        uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane) {
+                                                        uint8_t *__restrict__ Y, int64_t yplane) {
     constexpr int WTM = MG_BM / MG_WM, WTN = MG_BM / MG_WN;
     constexpr int FM = WTM / 16, FN = WTN / 16;
     constexpr int CPR = MG_BK / 16;                   // 16-byte chunks per tile row
@@ -438,16 +448,17 @@ __global__ __launch_bounds__(MG_NT) void mg_gemm_kernel(const int8_t *__restrict
                 y = y >= md ? y - md : y;
                 const int64_t row = (int64_t)tm * MG_BM + wm * WTM + i * 16 + (lane / 16) * 4 + r;
                 const int64_t col = (int64_t)tn * MG_BM + wn * WTN + jj * 16 + lane % 16;
+                const int64_t at = mg_yoff(row, col);
                 if (ACC) {  // earlier row chunks: residues add modulo m_t
-                    y += Yt[row * ldy + col];
+                    y += Yt[at];
                     y = y >= md ? y - md : y;
                 }
-                Yt[row * ldy + col] = (uint8_t)y;
+                Yt[at] = (uint8_t)y;
             }
 }
 
 // G_jk (k <= j < p) from the residues y_t: one row j per blockIdx.y.
-__global__ __launch_bounds__(256) void mg_crt_kernel(const uint8_t *__restrict__ Y, int64_t ldy, int64_t yplane,
+__global__ __launch_bounds__(256) void mg_crt_kernel(const uint8_t *__restrict__ Y, int64_t yplane,
                                                      int64_t p, const unsigned long long *__restrict__ cmax, int b,
                                                      CrtConsts cc, double *__restrict__ G, int64_t ldg) {
     const int64_t j = blockIdx.y;
@@ -469,7 +480,7 @@ __global__ __launch_bounds__(256) void mg_crt_kernel(const uint8_t *__restrict__
     double S[4] = {0.0, 0.0, 0.0, 0.0}, qs = 0.0;
 #pragma unroll
     for (int t = 0; t < MODS; ++t) {
-        const double y = (double)Y[t * yplane + j * ldy + k];
+        const double y = (double)Y[t * yplane + mg_yoff(j, k)];
         qs = fma(y, cc.f[t], qs);
 #pragma unroll
         for (int l = 0; l < 4; ++l) S[l] = fma(y, cc.w[l][t], S[l]);
@@ -531,7 +542,7 @@ hipError_t launch_modgram_chunk(hipStream_t st, const double *J, int64_t m, int6
     const int64_t kpad = modgram_kpad(m < 1 ? 1 : m), ppad = modgram_ppad(p);
     if (modgram_r_bytes(m < 1 ? 1 : m, p) > w.r_bytes || modgram_y_bytes(p) > w.y_bytes || ppad > w.cmax_len)
         return hipErrorInvalidValue;
-    const int64_t rplane = ppad * kpad, yplane = ppad * ppad;
+    const int64_t rplane = ppad * kpad, yplane = mg_ytiles(p) * MG_BM * MG_BM;
     const ModConsts mc = mod_consts();
     hipLaunchKernelGGL(mg_residue_kernel, dim3((unsigned)(ppad / MG_CV_J), (unsigned)((kpad + MG_CV_I - 1) / MG_CV_I)),
                        dim3(256), 0, st, J, m, p, ldj, w.cmax, b, w.R, kpad, rplane);
@@ -550,10 +561,10 @@ hipError_t launch_modgram_chunk(hipStream_t st, const double *J, int64_t m, int6
     }
     if (accumulate)
         hipLaunchKernelGGL(mg_gemm_kernel<true>, dim3((unsigned)blocks), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad,
-                           rplane, (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane);
+                           rplane, (int)(kpad / MG_BK), tiles, supers, mc, w.Y, yplane);
     else
         hipLaunchKernelGGL(mg_gemm_kernel<false>, dim3((unsigned)blocks), dim3(MG_NT), MG_LDS_BYTES, st, w.R, kpad,
-                           rplane, (int)(kpad / MG_BK), tiles, supers, mc, w.Y, ppad, yplane);
+                           rplane, (int)(kpad / MG_BK), tiles, supers, mc, w.Y, yplane);
     return hipGetLastError();
 }
 
@@ -562,8 +573,8 @@ hipError_t launch_modgram_finish(hipStream_t st, int64_t p, int b, double *G, in
     const int64_t ppad = modgram_ppad(p);
     if (modgram_y_bytes(p) > w.y_bytes || ppad > w.cmax_len) return hipErrorInvalidValue;
     const CrtConsts cc = crt_consts();
-    hipLaunchKernelGGL(mg_crt_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)p), dim3(256), 0, st, w.Y, ppad,
-                       ppad * ppad, p, w.cmax, b, cc, G, ldg);
+    hipLaunchKernelGGL(mg_crt_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)p), dim3(256), 0, st, w.Y,
+                       mg_ytiles(p) * MG_BM * MG_BM, p, w.cmax, b, cc, G, ldg);
     return hipGetLastError();
 }
 
