@@ -537,6 +537,7 @@ struct gn_batch_context {
     std::vector<BatchChol> h_bc;
     BatchChol *d_bc = nullptr;
     BatchedGemmPlan coupling, gram;          // Hilbert coupling of the CCF instances, bordered Gram
+    BatchedGemmPlan gram_tail;               // the bordered Gram's last rows when they are few (thin tiles)
     std::vector<BatchedGemmPlan> chol;       // per Cholesky panel: panel solve, trailing update
     std::vector<double *> uploaded_thetas;
     std::vector<DevStatus> ds;
@@ -1552,6 +1553,7 @@ static void batch_free(gn_batch b) {
     if (b->d_bc) (void)hipFree(b->d_bc);
     batched_plan_free(b->coupling);
     batched_plan_free(b->gram);
+    batched_plan_free(b->gram_tail);
     for (auto &p : b->chol) batched_plan_free(p);
     delete b;
 }
@@ -1572,10 +1574,28 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     b->stream = (hipStream_t)stream;
     b->P = hs[0]->md.P;
     const int64_t P = b->P;
+    // A bordered order just above a multiple of 128 (1154 = 9 x 128 + 2 for the
+    // small CCF network) would give the Gram a last row of 128-row tiles with
+    // a few valid rows: those rows go to a second product of 32-row tiles,
+    // masked to the lower triangle (C starts `head` rows below the diagonal).
+    const int64_t order = P + 1, head = order / 128 * 128, tail = order - head;
+    const bool split_tail = head >= 128 && tail >= 1 && tail <= 32;
     for (int i = 0; i < n; ++i) {
         gn_handle h = hs[i];
         if (h->equation == GN_EQ_CCF1D) b->coupling.h_descs.push_back(coupling_desc(h));
-        b->gram.h_descs.push_back(gram_desc(h));
+        GemmDesc g = gram_desc(h);
+        if (split_tail) {
+            GemmDesc t = g;
+            t.M = tail;
+            t.A = h->J + head;
+            t.C = h->G + head * h->ldG;
+            t.lower = 0;
+            t.mask_lower = 1;
+            t.mask_shift = head;
+            b->gram_tail.h_descs.push_back(t);
+            g.M = g.N = head;
+        }
+        b->gram.h_descs.push_back(g);
         BatchChol c{};
         c.A = h->G; c.lda = h->ldG; c.linv = h->linv; c.y = h->ybuf; c.x = h->delta; c.theta = nullptr;
         c.status = h->status;
@@ -1586,6 +1606,7 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     if (e == hipSuccess) e = hipMemcpy(b->d_bc, b->h_bc.data(), sizeof(BatchChol) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = batched_plan_upload(b->coupling);
     if (e == hipSuccess) e = batched_plan_upload(b->gram);
+    if (e == hipSuccess) e = batched_plan_upload(b->gram_tail);
     for (auto &p : b->chol)
         if (e == hipSuccess) e = batched_plan_upload(p);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
@@ -1672,6 +1693,7 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
     GN_HIP(h0, launch_batched_plan(st, b->coupling));
     bmark(GN_PHASE_GRAM);
     GN_HIP(h0, launch_batched_plan(st, b->gram));
+    GN_HIP(h0, launch_batched_plan(st, b->gram_tail));
     bmark(GN_PHASE_CHOLESKY);
     GN_HIP(h0, launch_cholesky_batched(st, b->h_bc.data(), b->d_bc, b->chol, n, P + 1, mu, 1));
     bmark(GN_PHASE_SOLVE);

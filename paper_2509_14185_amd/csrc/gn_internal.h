@@ -149,7 +149,8 @@ struct GemmDesc {
     double alpha, beta;
     const double *rowscale;
     int lower;                 // square lower-triangular tile set (M == N)
-    int mask_lower;            // rectangular tile set, write only n <= m
+    int mask_lower;            // rectangular tile set, write only n <= m + mask_shift
+    int64_t mask_shift;        // with mask_lower: C's first row sits mask_shift rows below the diagonal
     const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);

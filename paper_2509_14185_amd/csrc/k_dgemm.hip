@@ -139,7 +139,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     if (!BATCH && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, sup0, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const bool lower_mask = g.lower || g.mask_lower;
-    if (lower_mask && n0 > m0 + BM - 1) return;  // tile entirely above the diagonal
+    if (lower_mask && n0 > m0 + BM - 1 + g.mask_shift) return;  // tile entirely above the diagonal
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t gm = m0 + wm * WM + (i0 + ii) * 16 + fk + 4 * r;
-                    const bool ok = gm < g.M && gn_ < g.N && !(lower_mask && gn_ > gm);
+                    const bool ok = gm < g.M && gn_ < g.N && !(lower_mask && gn_ > gm + g.mask_shift);
                     cold[ii][j][r] = (ok && g.beta != 0.0) ? g.C[gm * g.ldc + gn_] : 0.0;
                 }
             }
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
                 for (int r = 0; r < 4; ++r) {
                     const int64_t gm = m0 + wm * WM + (i0 + ii) * 16 + fk + 4 * r;
                     if (gm >= g.M || gn_ >= g.N) continue;
-                    if (lower_mask && gn_ > gm) continue;
+                    if (lower_mask && gn_ > gm + g.mask_shift) continue;
                     const double v = g.alpha * acc[i0 + ii][j][r] * rs[ii][r];
                     g.C[gm * g.ldc + gn_] = (g.beta == 0.0) ? v : fma(g.beta, cold[ii][j][r], v);
                 }
@@ -381,18 +381,24 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
 }
 
 // Batched tile configuration: 128 x 64 tiles for narrow rectangular products
-// (in-place triangular solves need one tile column), else 128 x 128.
-static bool batched_small_n(const GemmDesc &f) { return !f.lower && f.N <= 64; }
+// (in-place triangular solves need one tile column), 32 x 128 for products of
+// at most 32 rows (the few last rows of bordered Grams), else 128 x 128.
+enum BatchedShape { BS_SQUARE = 0, BS_SMALL_N = 1, BS_THIN = 2 };
+static int batched_shape(const GemmDesc &f) {
+    if (f.lower) return BS_SQUARE;
+    if (f.N <= 64) return BS_SMALL_N;
+    return f.M <= 32 ? BS_THIN : BS_SQUARE;
+}
 
 int64_t plan_dgemm_batched(const GemmDesc *descs, int n, std::vector<int4> &table) {
     table.clear();
     if (n <= 0) return 0;
     const GemmDesc &f = descs[0];
-    const bool small_n = batched_small_n(f);
-    const int BM = 128, BN = small_n ? 64 : 128;
+    const int shape = batched_shape(f);
+    const int BM = shape == BS_THIN ? 32 : 128, BN = shape == BS_SMALL_N ? 64 : 128;
     for (int i = 0; i < n; ++i) {
         const GemmDesc &g = descs[i];
-        if (g.la != f.la || g.lb != f.lb || g.lower != f.lower || batched_small_n(g) != small_n) return -1;
+        if (g.la != f.la || g.lb != f.lb || g.lower != f.lower || batched_shape(g) != shape) return -1;
         if (g.lower && g.M != g.N) return -1;
     }
     // chunks: a block of tiles of one problem that share operand panels, 4 x 8
@@ -414,7 +420,8 @@ int64_t plan_dgemm_batched(const GemmDesc *descs, int n, std::vector<int4> &tabl
                     for (int t = 0; t < cm * cn; ++t) {
                         const int tm = sm * cm + t % cm, tn = sn * cn + t / cm;
                         if (tm >= tm_n || tn >= tn_n) continue;
-                        if ((g.lower || g.mask_lower) && (int64_t)tn * BN > (int64_t)tm * BM + BM - 1) continue;
+                        if ((g.lower || g.mask_lower) && (int64_t)tn * BN > (int64_t)tm * BM + BM - 1 + g.mask_shift)
+                            continue;
                         c.tiles.push_back(make_int4(i, tm, tn, 0));
                     }
                     if (c.tiles.empty()) continue;
@@ -448,7 +455,9 @@ hipError_t launch_dgemm_batched(hipStream_t st, const GemmDesc *h_descs, const G
                                 const int4 *d_work, int64_t nwork) {
     if (n <= 0 || nwork <= 0) return hipSuccess;
     const GemmDesc &f = h_descs[0];
-    if (batched_small_n(f)) return launch_tiles<128, 64, 32, true>(st, f, nwork, 0, 0, d_descs, d_work);
+    const int shape = batched_shape(f);
+    if (shape == BS_SMALL_N) return launch_tiles<128, 64, 32, true>(st, f, nwork, 0, 0, d_descs, d_work);
+    if (shape == BS_THIN) return launch_tiles<32, 128, 32, true>(st, f, nwork, 0, 0, d_descs, d_work);
     // coupling products (both operands contiguous along m / n): the four-wave
     // configuration, two workgroups per CU (64 instances of the small CCF
     // workload: 27.8 -> 26.1 ms per batch step); the batched Grams keep eight
