@@ -538,6 +538,7 @@ struct gn_batch_context {
     BatchChol *d_bc = nullptr;
     BatchedGemmPlan coupling, gram;          // Hilbert coupling of the CCF instances, bordered Gram
     BatchedGemmPlan gram_tail;               // the bordered Gram's last rows when they are few (thin tiles)
+    BatchedGemmPlan coupling_tail;           // the coupling's last columns when they are few (128 x 64 tiles)
     std::vector<BatchedGemmPlan> chol;       // per Cholesky panel: panel solve, trailing update
     std::vector<double *> uploaded_thetas;
     std::vector<DevStatus> ds;
@@ -1554,6 +1555,7 @@ static void batch_free(gn_batch b) {
     batched_plan_free(b->coupling);
     batched_plan_free(b->gram);
     batched_plan_free(b->gram_tail);
+    batched_plan_free(b->coupling_tail);
     for (auto &p : b->chol) batched_plan_free(p);
     delete b;
 }
@@ -1580,9 +1582,23 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     // masked to the lower triangle (C starts `head` rows below the diagonal).
     const int64_t order = P + 1, head = order / 128 * 128, tail = order - head;
     const bool split_tail = head >= 128 && tail >= 1 && tail <= 32;
+    // likewise the coupling's last columns (P = 1153 = 9 x 128 + 1): 128 x 64 tiles
+    const int64_t chead = P / 128 * 128, ctail = P - chead;
+    const bool split_ctail = chead >= 128 && ctail >= 1 && ctail <= 32;
     for (int i = 0; i < n; ++i) {
         gn_handle h = hs[i];
-        if (h->equation == GN_EQ_CCF1D) b->coupling.h_descs.push_back(coupling_desc(h));
+        if (h->equation == GN_EQ_CCF1D) {
+            GemmDesc c = coupling_desc(h);
+            if (split_ctail) {
+                GemmDesc t = c;
+                t.N = ctail;
+                t.B = h->Bm + chead;
+                t.C = h->J + chead;
+                b->coupling_tail.h_descs.push_back(t);
+                c.N = chead;
+            }
+            b->coupling.h_descs.push_back(c);
+        }
         GemmDesc g = gram_desc(h);
         if (split_tail) {
             GemmDesc t = g;
@@ -1607,6 +1623,7 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
     if (e == hipSuccess) e = batched_plan_upload(b->coupling);
     if (e == hipSuccess) e = batched_plan_upload(b->gram);
     if (e == hipSuccess) e = batched_plan_upload(b->gram_tail);
+    if (e == hipSuccess) e = batched_plan_upload(b->coupling_tail);
     for (auto &p : b->chol)
         if (e == hipSuccess) e = batched_plan_upload(p);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
@@ -1691,6 +1708,7 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
     bmark(GN_PHASE_JLOCAL);  // the local rows are timed with the forward phase
     bmark(GN_PHASE_COUPLING);
     GN_HIP(h0, launch_batched_plan(st, b->coupling));
+    GN_HIP(h0, launch_batched_plan(st, b->coupling_tail));
     bmark(GN_PHASE_GRAM);
     GN_HIP(h0, launch_batched_plan(st, b->gram));
     GN_HIP(h0, launch_batched_plan(st, b->gram_tail));
