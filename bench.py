@@ -406,7 +406,8 @@ def batched_comparison(steps):
     t_chol = phases["cholesky"] / nrec * 1e-3
     return {
         "workload": "ccf_batched",
-        "roofline": {"bound": "mfma", "kernel": "batched gram (dgemm_mfma_kernel<128,128,32,1,0,true,512>)",
+        "roofline": {"bound": "mfma", "kernel": ("batched gram (dgemm_mfma_kernel<128,128,32,1,0,true,512>; the last rows of a bordered "
+                                                       "order at most 32 above a multiple of 128 on <32,128,32,1,0,true,512>)"),
                      "achieved": fl_gram / t_gram / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": fl_gram / t_gram / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
                      "flops_per_step": fl_gram},
