@@ -255,6 +255,8 @@ gn_status deriv_jacobian(gn_handle h, const double *theta, double *J, int64_t ld
     return GN_OK;
 }
 
+gn_status validation_residual(gn_handle h);
+
 // max |R| on the validation grid (theta's weights already transposed).
 gn_status validation(gn_handle h, const double *theta) {
     if (h->nv <= 0) return GN_OK;
@@ -262,6 +264,12 @@ gn_status validation(gn_handle h, const double *theta) {
     b.x = h->val.q; b.n = h->nv; b.nn = h->nn_val;
     with_phi(h, b, h->phi_val, h->nv);
     GN_HIP(h, launch_mlp_forward(h->stream, h->md, theta, h->thetaT, b));
+    return validation_residual(h);
+}
+
+// The validation residual and its max-norm from the forward jets in nn_val.
+gn_status validation_residual(gn_handle h) {
+    if (h->nv <= 0) return GN_OK;
     ResidualArgs a{};
     a.equation = h->equation; a.lam = h->lam; a.n = h->nv; a.m = h->m;
     a.pts = h->val; a.nodes = h->nodes;
@@ -549,6 +557,15 @@ struct gn_batch_context {
     std::vector<hipStream_t> lanes;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;
+    // when the network fits the matrix-core sweeps: the forward jets of every
+    // point set of every instance in one launch, and the Jacobian rows in one
+    // (work tables of 16-point tiles); job k belongs to instance *_inst[k]
+    bool jobs = false;
+    std::vector<SweepJob> h_fjobs, h_rjobs;
+    std::vector<int> fjob_inst, rjob_inst;
+    SweepJob *d_fjobs = nullptr, *d_rjobs = nullptr;
+    int2 *d_fwork = nullptr, *d_rwork = nullptr;
+    int64_t nfwork = 0, nrwork = 0;
 };
 static constexpr int BATCH_LANES = 3;
 
@@ -1548,6 +1565,8 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
 }
 
 static void batch_free(gn_batch b) {
+    for (void *q : {(void *)b->d_fjobs, (void *)b->d_rjobs, (void *)b->d_fwork, (void *)b->d_rwork})
+        if (q) (void)hipFree(q);
     for (hipStream_t l : b->lanes) (void)hipStreamDestroy(l);
     for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -1635,6 +1654,53 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&j_, hipEventDisableTiming);
         if (e == hipSuccess) b->join.push_back(j_);
     }
+    b->jobs = mlp_jobs_supported(hs[0]->md);
+    if (b->jobs) {
+        for (int i = 0; i < n; ++i) {
+            gn_handle h = hs[i];
+            auto fjob = [&](const double *x, int64_t np, double *nn) {
+                SweepJob j{};
+                j.thetaT = h->thetaT;
+                j.b.x = x; j.b.n = np; j.b.nn = nn;
+                b->h_fjobs.push_back(j);
+                b->fjob_inst.push_back(i);
+            };
+            if (h->equation == GN_EQ_CCF1D) fjob(h->nodes.q, h->m, h->nn_nodes);
+            fjob(h->pts.q, h->n, h->nn_pts);
+            fjob(h->one_x, 1, h->nn_one);
+            if (h->nv > 0) fjob(h->val.q, h->nv, h->nn_val);
+            auto rjob = [&](const SweepBatch &sb) {
+                SweepJob j{};
+                j.thetaT = h->thetaT;
+                j.b = sb;
+                b->h_rjobs.push_back(j);
+                b->rjob_inst.push_back(i);
+            };
+            SweepBatch pb{};
+            pb.x = h->pts.q; pb.s0 = h->seed0; pb.s1 = h->seed1; pb.n = h->n; pb.rows = h->J; pb.ld = h->ldJ;
+            rjob(pb);
+            SweepBatch ob{};
+            ob.x = h->one_x; ob.s0c = sqrt(h->c_norm); ob.s1c = 0.0; ob.n = 1; ob.rows = h->J + norm_row(h) * h->ldJ;
+            ob.ld = h->ldJ;
+            rjob(ob);
+            if (h->equation == GN_EQ_CCF1D) {
+                SweepBatch nb{};
+                nb.x = h->nodes.q; nb.s0 = h->nodes.E; nb.s1c = 0.0; nb.n = h->m; nb.rows = h->Bm; nb.ld = h->ldJ;
+                rjob(nb);
+            }
+        }
+        std::vector<int2> fw, rw;
+        mlp_jobs_work(b->h_fjobs, fw);
+        mlp_jobs_work(b->h_rjobs, rw);
+        b->nfwork = (int64_t)fw.size();
+        b->nrwork = (int64_t)rw.size();
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_fjobs, sizeof(SweepJob) * b->h_fjobs.size());
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_rjobs, sizeof(SweepJob) * b->h_rjobs.size());
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_fwork, sizeof(int2) * fw.size());
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_rwork, sizeof(int2) * rw.size());
+        if (e == hipSuccess) e = hipMemcpy(b->d_fwork, fw.data(), sizeof(int2) * fw.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->d_rwork, rw.data(), sizeof(int2) * rw.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         batch_free(b);
         return e == hipErrorOutOfMemory ? GN_ENOMEM : GN_EDEVICE;
@@ -1671,6 +1737,14 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
         GN_HIP(h0, hipStreamSynchronize(st));
         for (int i = 0; i < n; ++i) b->h_bc[i].theta = d_thetas[i];
         GN_HIP(h0, hipMemcpy(b->d_bc, b->h_bc.data(), sizeof(BatchChol) * n, hipMemcpyHostToDevice));
+        if (b->jobs) {
+            for (size_t k = 0; k < b->h_fjobs.size(); ++k) b->h_fjobs[k].theta = d_thetas[b->fjob_inst[k]];
+            for (size_t k = 0; k < b->h_rjobs.size(); ++k) b->h_rjobs[k].theta = d_thetas[b->rjob_inst[k]];
+            GN_HIP(h0, hipMemcpy(b->d_fjobs, b->h_fjobs.data(), sizeof(SweepJob) * b->h_fjobs.size(),
+                                 hipMemcpyHostToDevice));
+            GN_HIP(h0, hipMemcpy(b->d_rjobs, b->h_rjobs.data(), sizeof(SweepJob) * b->h_rjobs.size(),
+                                 hipMemcpyHostToDevice));
+        }
         b->uploaded_thetas.assign(d_thetas, d_thetas + n);
     }
     // phase events of the batch step go on the first handle's event list
@@ -1682,28 +1756,55 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
     // per instance: residual, validation, local Jacobian rows with r in column P;
     // instance i on the batch stream (i % (lanes + 1) == 0) or on lane i % (lanes + 1) - 1
     const int nl = (int)b->lanes.size();
-    GN_HIP(h0, hipEventRecord(b->fork, st));
-    for (int l = 0; l < nl; ++l) GN_HIP(h0, hipStreamWaitEvent(b->lanes[l], b->fork, 0));
-    gn_status err = GN_OK;
-    for (int i = 0; i < n && err == GN_OK; ++i) {
-        gn_handle h = b->hs[i];
-        const int q = i % (nl + 1);
-        hipStream_t s_ = q == 0 ? st : b->lanes[q - 1];
-        hipStream_t own = h->stream;
-        h->stream = s_;
-        if (launch_reset_status(s_, h->status) != hipSuccess) err = GN_EDEVICE;
-        if (err == GN_OK) err = build_step_jacobian(h, d_thetas[i], false, false);
-        if (err == GN_OK &&
-            launch_sumsq(s_, h->J + P, total_rows(h), h->ldJ, &h->status->half_sq_norm, h->red_work) != hipSuccess)
-            err = GN_EDEVICE;
-        h->stream = own;
+    // runs body(h, i, stream) for every instance, spread over the lanes, and
+    // joins every lane back into the batch stream, also after an error
+    auto per_instance = [&](auto body) -> gn_status {
+        GN_HIP(h0, hipEventRecord(b->fork, st));
+        for (int l = 0; l < nl; ++l) GN_HIP(h0, hipStreamWaitEvent(b->lanes[l], b->fork, 0));
+        gn_status err = GN_OK;
+        for (int i = 0; i < n && err == GN_OK; ++i) {
+            gn_handle h = b->hs[i];
+            const int q = i % (nl + 1);
+            hipStream_t s_ = q == 0 ? st : b->lanes[q - 1];
+            hipStream_t own = h->stream;
+            h->stream = s_;
+            err = body(h, i, s_);
+            h->stream = own;
+        }
+        for (int l = 0; l < nl; ++l) {
+            GN_HIP(h0, hipEventRecord(b->join[l], b->lanes[l]));
+            GN_HIP(h0, hipStreamWaitEvent(st, b->join[l], 0));
+        }
+        return err;
+    };
+    auto sumsq = [&](gn_handle h, int, hipStream_t s_) -> gn_status {
+        return launch_sumsq(s_, h->J + P, total_rows(h), h->ldJ, &h->status->half_sq_norm, h->red_work) == hipSuccess
+                   ? GN_OK
+                   : GN_EDEVICE;
+    };
+    if (b->jobs) {
+        // per instance: status, transposed weights; then every forward sweep in
+        // one launch; per instance: residual rows (seeds, r in column P) and the
+        // validation residual; then every Jacobian-row sweep in one launch
+        GN_TRY(per_instance([&](gn_handle h, int i, hipStream_t s_) -> gn_status {
+            if (launch_reset_status(s_, h->status) != hipSuccess) return GN_EDEVICE;
+            return launch_transpose_weights(s_, h->md, d_thetas[i], h->thetaT) == hipSuccess ? GN_OK : GN_EDEVICE;
+        }));
+        GN_HIP(h0, launch_mlp_forward_jobs(st, h0->md, b->d_fjobs, b->d_fwork, b->nfwork));
+        GN_TRY(per_instance([&](gn_handle h, int, hipStream_t) -> gn_status {
+            GN_TRY(residual_rows(h, h->J + P, h->ldJ, true));
+            return validation_residual(h);
+        }));
+        GN_HIP(h0, launch_mlp_rows_jobs(st, h0->md, b->d_rjobs, b->d_rwork, b->nrwork));
+        GN_TRY(per_instance(sumsq));
+    } else {
+        // per instance: residual, validation, local Jacobian rows with r in column P
+        GN_TRY(per_instance([&](gn_handle h, int i, hipStream_t s_) -> gn_status {
+            if (launch_reset_status(s_, h->status) != hipSuccess) return GN_EDEVICE;
+            GN_TRY(build_step_jacobian(h, d_thetas[i], false, false));
+            return sumsq(h, i, s_);
+        }));
     }
-    // join every lane back into the batch stream, also after an error
-    for (int l = 0; l < nl; ++l) {
-        GN_HIP(h0, hipEventRecord(b->join[l], b->lanes[l]));
-        GN_HIP(h0, hipStreamWaitEvent(st, b->join[l], 0));
-    }
-    if (err != GN_OK) return err;
     // batched Hilbert coupling, Gram, bordered Cholesky, back substitution and update
     bmark(GN_PHASE_JLOCAL);  // the local rows are timed with the forward phase
     bmark(GN_PHASE_COUPLING);

@@ -47,6 +47,13 @@ struct SweepBatch {
     int64_t phi_ld;
 };
 
+// One sweep of a multi-sweep launch: its parameters, their transpose and the batch.
+struct SweepJob {
+    const double *theta;
+    const double *thetaT;
+    SweepBatch b;
+};
+
 // max |v| into *p as the bit pattern of a non-negative double (such patterns
 // order as integers); NaN counts as +inf so that it is visible.
 __device__ __forceinline__ void atomic_max_abs(unsigned long long *p, double v) {
@@ -93,6 +100,16 @@ hipError_t launch_mlp_forward(hipStream_t st, const MlpDesc &d, const double *th
                               SweepBatch b);
 hipError_t launch_mlp_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
                            SweepBatch b);
+// Forward jets / Jacobian rows of many sweeps in one launch (the matrix-core
+// kernels: scalar input and output, hidden widths up to 64, no Fourier
+// features), one 16-point tile per workgroup from a work table of (job, tile)
+// pairs built by mlp_jobs_work.
+bool mlp_jobs_supported(const MlpDesc &d);
+void mlp_jobs_work(const std::vector<SweepJob> &jobs, std::vector<int2> &work);
+hipError_t launch_mlp_forward_jobs(hipStream_t st, const MlpDesc &d, const SweepJob *d_jobs, const int2 *d_work,
+                                   int64_t nwork);
+hipError_t launch_mlp_rows_jobs(hipStream_t st, const MlpDesc &d, const SweepJob *d_jobs, const int2 *d_work,
+                                int64_t nwork);
 // VJP: writes ceil(n / tile) partial gradients (P each) to `partial`;
 // returns the number of partials via *n_partials.
 hipError_t launch_mlp_vjp(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,

@@ -404,9 +404,26 @@ __device__ __forceinline__ bool rows1d_layer_product(const MlpDesc &d, int f, in
     return true;
 }
 
-__global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta,
-                                                            const double *__restrict__ thetaT, SweepBatch b) {
+// JOBS: one 16-point tile per workgroup from a work table (job, tile) over
+// many sweeps (the instances of a batch), each with its own parameters.
+template <bool JOBS>
+__global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta0,
+                                                            const double *__restrict__ thetaT0, SweepBatch b0,
+                                                            const SweepJob *__restrict__ jobs,
+                                                            const int2 *__restrict__ work) {
     extern __shared__ double sm[];
+    const double *theta = theta0, *thetaT = thetaT0;
+    SweepBatch b = b0;
+    int64_t tile_first = blockIdx.x, tile_step = gridDim.x;
+    if (JOBS) {
+        const int2 w = work[blockIdx.x];
+        if (w.x < 0) return;
+        theta = jobs[w.x].theta;
+        thetaT = jobs[w.x].thetaT;
+        b = jobs[w.x].b;
+        tile_first = w.y;
+        tile_step = INT64_MAX / 2;
+    }
     __shared__ double xs[RW1_TP];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -418,7 +435,7 @@ __global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad,
     double *zs = sm + (L - 1) * plane;
     auto Z = [&](int c, int k, int t) -> double & { return zs[(c * wpad + k) * RW1_LD + t]; };
     const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = tile_first; tile < ntiles; tile += tile_step) {
         const int64_t p0 = tile * RW1_TP;
         const int nr = (int)((b.n - p0) < RW1_TP ? (b.n - p0) : RW1_TP);
         __syncthreads();  // the previous tile is done with LDS
@@ -540,9 +557,24 @@ __global__ __launch_bounds__(256) void mlp_rows_mfma_kernel(MlpDesc d, int wpad,
 // the hidden layers as there, then the output layer's value and
 // x-derivative, NN and NN_x, from the same product (one unit: wave 0, lanes
 // of the first unit row).
-__global__ __launch_bounds__(256) void mlp_forward_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta,
-                                                               const double *__restrict__ thetaT, SweepBatch b) {
+template <bool JOBS>
+__global__ __launch_bounds__(256) void mlp_forward_mfma_kernel(MlpDesc d, int wpad, const double *__restrict__ theta0,
+                                                               const double *__restrict__ thetaT0, SweepBatch b0,
+                                                               const SweepJob *__restrict__ jobs,
+                                                               const int2 *__restrict__ work) {
     extern __shared__ double sm[];
+    const double *theta = theta0, *thetaT = thetaT0;
+    SweepBatch b = b0;
+    int64_t tile_first = blockIdx.x, tile_step = gridDim.x;
+    if (JOBS) {
+        const int2 w = work[blockIdx.x];
+        if (w.x < 0) return;
+        theta = jobs[w.x].theta;
+        thetaT = jobs[w.x].thetaT;
+        b = jobs[w.x].b;
+        tile_first = w.y;
+        tile_step = INT64_MAX / 2;
+    }
     __shared__ double xs[RW1_TP];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -551,7 +583,7 @@ __global__ __launch_bounds__(256) void mlp_forward_mfma_kernel(MlpDesc d, int wp
     const int plane = 2 * wpad * RW1_LD;
     auto H = [&](int l, int c, int j, int t) -> double & { return sm[(l - 1) * plane + (c * wpad + j) * RW1_LD + t]; };
     const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = tile_first; tile < ntiles; tile += tile_step) {
         const int64_t p0 = tile * RW1_TP;
         const int nr = (int)((b.n - p0) < RW1_TP ? (b.n - p0) : RW1_TP);
         __syncthreads();  // the previous tile is done with LDS
@@ -641,14 +673,15 @@ hipError_t launch_mlp_forward(hipStream_t st, const MlpDesc &d, const double *th
     if (shm > 64 * 1024) {
         static bool attr = false;
         if (!attr) {
-            (void)hipFuncSetAttribute((const void *)mlp_forward_mfma_kernel,
+            (void)hipFuncSetAttribute((const void *)mlp_forward_mfma_kernel<false>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
             attr = true;
         }
     }
     const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
     const unsigned grid = (unsigned)(ntiles < 16384 ? ntiles : 16384);
-    hipLaunchKernelGGL(mlp_forward_mfma_kernel, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b);
+    hipLaunchKernelGGL(mlp_forward_mfma_kernel<false>, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b,
+                       nullptr, nullptr);
     return hipGetLastError();
 }
 hipError_t launch_mlp_rows(hipStream_t st, const MlpDesc &d, const double *theta, const double *thetaT,
@@ -659,14 +692,57 @@ hipError_t launch_mlp_rows(hipStream_t st, const MlpDesc &d, const double *theta
     static bool attr = false;
     if (!attr) {
         // the kernel's static LDS (the tile's inputs) comes on top
-        (void)hipFuncSetAttribute((const void *)mlp_rows_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  152 * 1024);
+        (void)hipFuncSetAttribute((const void *)mlp_rows_mfma_kernel<false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
         attr = true;
     }
     const size_t shm = sizeof(double) * (size_t)d.L * 2 * wpad * RW1_LD;
     const int64_t ntiles = (b.n + RW1_TP - 1) / RW1_TP;
     const unsigned grid = (unsigned)(ntiles < 16384 ? ntiles : 16384);
-    hipLaunchKernelGGL(mlp_rows_mfma_kernel, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b);
+    hipLaunchKernelGGL(mlp_rows_mfma_kernel<false>, dim3(grid), dim3(256), shm, st, d, wpad, theta, thetaT, b, nullptr,
+                       nullptr);
+    return hipGetLastError();
+}
+
+bool mlp_jobs_supported(const MlpDesc &d) { return rows1d_mfma_wpad(d) != 0; }
+
+void mlp_jobs_work(const std::vector<SweepJob> &jobs, std::vector<int2> &work) {
+    work.clear();
+    for (size_t j = 0; j < jobs.size(); ++j)
+        for (int64_t t = 0; t * RW1_TP < jobs[j].b.n; ++t) work.push_back(make_int2((int)j, (int)t));
+}
+
+hipError_t launch_mlp_forward_jobs(hipStream_t st, const MlpDesc &d, const SweepJob *d_jobs, const int2 *d_work,
+                                   int64_t nwork) {
+    const int wpad = rows1d_mfma_wpad(d);
+    if (wpad == 0) return hipErrorInvalidValue;
+    if (nwork <= 0) return hipSuccess;
+    const size_t shm = sizeof(double) * (size_t)(d.L - 1) * 2 * wpad * RW1_LD;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)mlp_forward_mfma_kernel<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(mlp_forward_mfma_kernel<true>, dim3((unsigned)nwork), dim3(256), shm, st, d, wpad, nullptr,
+                       nullptr, SweepBatch{}, d_jobs, d_work);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_rows_jobs(hipStream_t st, const MlpDesc &d, const SweepJob *d_jobs, const int2 *d_work,
+                                int64_t nwork) {
+    const int wpad = rows1d_mfma_wpad(d);
+    if (wpad == 0) return hipErrorInvalidValue;
+    if (nwork <= 0) return hipSuccess;
+    const size_t shm = sizeof(double) * (size_t)d.L * 2 * wpad * RW1_LD;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)mlp_rows_mfma_kernel<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(mlp_rows_mfma_kernel<true>, dim3((unsigned)nwork), dim3(256), shm, st, d, wpad, nullptr,
+                       nullptr, SweepBatch{}, d_jobs, d_work);
     return hipGetLastError();
 }
 int64_t mlp_vjp_partials(const MlpDesc &, int64_t n) { return (n + SWEEP_TILE - 1) / SWEEP_TILE; }
