@@ -203,7 +203,7 @@ DerivArgs deriv_args(gn_handle h) {
 }
 
 // Residual rows into r (stride r_stride); seeds/cscale when `seeds`.
-gn_status residual_rows(gn_handle h, double *r, int64_t r_stride, bool seeds) {
+ResidualArgs residual_args_pts(gn_handle h, double *r, int64_t r_stride, bool seeds) {
     ResidualArgs a{};
     a.equation = h->equation; a.lam = h->lam; a.n = h->n; a.m = h->m;
     a.pts = h->pts; a.nodes = h->nodes;
@@ -214,7 +214,22 @@ gn_status residual_rows(gn_handle h, double *r, int64_t r_stride, bool seeds) {
     a.cscale = seeds ? h->cscale : nullptr;
     a.max_out = &h->status->max_R;
     with_stage1(h, a, false);
-    GN_HIP(h, launch_residual(h->stream, a));
+    return a;
+}
+
+ResidualArgs residual_args_val(gn_handle h) {
+    ResidualArgs a{};
+    a.equation = h->equation; a.lam = h->lam; a.n = h->nv; a.m = h->m;
+    a.pts = h->val; a.nodes = h->nodes;
+    a.nn = h->nn_val; a.nn_nodes = h->nn_nodes;
+    a.inv_n = 1.0;
+    a.max_out = &h->status->max_R_val;
+    with_stage1(h, a, true);
+    return a;
+}
+
+gn_status residual_rows(gn_handle h, double *r, int64_t r_stride, bool seeds) {
+    GN_HIP(h, launch_residual(h->stream, residual_args_pts(h, r, r_stride, seeds)));
     if (h->nd1 + h->nd2 > 0) {
         DerivArgs d = deriv_args(h);
         d.r = r + h->n * r_stride; d.r_stride = r_stride;
@@ -270,14 +285,7 @@ gn_status validation(gn_handle h, const double *theta) {
 // The validation residual and its max-norm from the forward jets in nn_val.
 gn_status validation_residual(gn_handle h) {
     if (h->nv <= 0) return GN_OK;
-    ResidualArgs a{};
-    a.equation = h->equation; a.lam = h->lam; a.n = h->nv; a.m = h->m;
-    a.pts = h->val; a.nodes = h->nodes;
-    a.nn = h->nn_val; a.nn_nodes = h->nn_nodes;
-    a.inv_n = 1.0;
-    a.max_out = &h->status->max_R_val;
-    with_stage1(h, a, true);
-    GN_HIP(h, launch_residual(h->stream, a));
+    GN_HIP(h, launch_residual(h->stream, residual_args_val(h)));
     return GN_OK;
 }
 
@@ -566,6 +574,12 @@ struct gn_batch_context {
     SweepJob *d_fjobs = nullptr, *d_rjobs = nullptr;
     int2 *d_fwork = nullptr, *d_rwork = nullptr;
     int64_t nfwork = 0, nrwork = 0;
+    // CCF batches: the residuals of every instance (collocation points with
+    // their seeds, validation grid) in one launch
+    bool res_jobs = false;
+    ResidualArgs *d_resjobs = nullptr;
+    int2 *d_reswork = nullptr;
+    int64_t nreswork = 0;
 };
 static constexpr int BATCH_LANES = 3;
 
@@ -1565,7 +1579,8 @@ gn_status gn_vjp(gn_handle h, const double *d_theta, const double *d_v, double *
 }
 
 static void batch_free(gn_batch b) {
-    for (void *q : {(void *)b->d_fjobs, (void *)b->d_rjobs, (void *)b->d_fwork, (void *)b->d_rwork})
+    for (void *q : {(void *)b->d_fjobs, (void *)b->d_rjobs, (void *)b->d_fwork, (void *)b->d_rwork,
+                    (void *)b->d_resjobs, (void *)b->d_reswork})
         if (q) (void)hipFree(q);
     for (hipStream_t l : b->lanes) (void)hipStreamDestroy(l);
     for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
@@ -1700,6 +1715,25 @@ gn_status gn_batch_create(gn_handle *hs, int32_t n, void *stream, gn_batch *out)
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_rwork, sizeof(int2) * rw.size());
         if (e == hipSuccess) e = hipMemcpy(b->d_fwork, fw.data(), sizeof(int2) * fw.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(b->d_rwork, rw.data(), sizeof(int2) * rw.size(), hipMemcpyHostToDevice);
+        b->res_jobs = true;
+        for (int i = 0; i < n; ++i) b->res_jobs = b->res_jobs && hs[i]->equation == GN_EQ_CCF1D;
+        if (b->res_jobs) {
+            std::vector<ResidualArgs> ra;
+            for (int i = 0; i < n; ++i) {
+                gn_handle h = hs[i];
+                ra.push_back(residual_args_pts(h, h->J + P, h->ldJ, true));
+                if (h->nv > 0) ra.push_back(residual_args_val(h));
+            }
+            std::vector<int2> resw;
+            residual_jobs_work(ra.data(), (int)ra.size(), resw);
+            b->nreswork = (int64_t)resw.size();
+            if (e == hipSuccess) e = hipMalloc((void **)&b->d_resjobs, sizeof(ResidualArgs) * ra.size());
+            if (e == hipSuccess) e = hipMalloc((void **)&b->d_reswork, sizeof(int2) * resw.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(b->d_resjobs, ra.data(), sizeof(ResidualArgs) * ra.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(b->d_reswork, resw.data(), sizeof(int2) * resw.size(), hipMemcpyHostToDevice);
+        }
     }
     if (e != hipSuccess) {
         batch_free(b);
@@ -1791,10 +1825,20 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
             return launch_transpose_weights(s_, h->md, d_thetas[i], h->thetaT) == hipSuccess ? GN_OK : GN_EDEVICE;
         }));
         GN_HIP(h0, launch_mlp_forward_jobs(st, h0->md, b->d_fjobs, b->d_fwork, b->nfwork));
-        GN_TRY(per_instance([&](gn_handle h, int, hipStream_t) -> gn_status {
-            GN_TRY(residual_rows(h, h->J + P, h->ldJ, true));
-            return validation_residual(h);
-        }));
+        if (b->res_jobs) {
+            // every residual in one launch; the data rows (one value each) on the batch stream
+            GN_HIP(h0, launch_residual_jobs(st, b->d_resjobs, b->d_reswork, b->nreswork));
+            for (int i = 0; i < n; ++i) {
+                gn_handle h = b->hs[i];
+                GN_HIP(h0, launch_norm_row(st, h->nn_one, sqrt(h->c_norm), h->c_target,
+                                           h->J + norm_row(h) * h->ldJ + P));
+            }
+        } else {
+            GN_TRY(per_instance([&](gn_handle h, int, hipStream_t) -> gn_status {
+                GN_TRY(residual_rows(h, h->J + P, h->ldJ, true));
+                return validation_residual(h);
+            }));
+        }
         GN_HIP(h0, launch_mlp_rows_jobs(st, h0->md, b->d_rjobs, b->d_rwork, b->nrwork));
         GN_TRY(per_instance(sumsq));
     } else {

@@ -144,6 +144,10 @@ struct ResidualArgs {
 hipError_t launch_fourier_features(hipStream_t st, int64_t n, const double *q, int F, const double *b, double *out,
                                    int64_t ld);
 hipError_t launch_residual(hipStream_t st, const ResidualArgs &a);
+// The CCF residuals of many point sets in one launch (one 64-point block per
+// workgroup from a work table of (job, block) pairs built by residual_jobs_work).
+void residual_jobs_work(const ResidualArgs *jobs, int n, std::vector<int2> &work);
+hipError_t launch_residual_jobs(hipStream_t st, const ResidualArgs *d_jobs, const int2 *d_work, int64_t nwork);
 // Normalisation row: r = sqrt(c) (NN(1) - target), written to r_out.
 hipError_t launch_norm_row(hipStream_t st, const double *nn1, double sqrt_c, double target,
                            double *r_out);

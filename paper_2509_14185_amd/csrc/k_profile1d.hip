@@ -794,11 +794,22 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *p, double 
 // per point would.
 static constexpr int RES_PTS = 256;                 // nodes staged per chunk
 static constexpr int RES_WG_PTS = 64, RES_SPLIT = 4;  // points per workgroup, waves per point
-__global__ __launch_bounds__(RES_PTS) void ccf_residual_kernel(ResidualArgs a) {
+// JOBS: one 64-point block per workgroup from a work table (job, block) over
+// the residuals of many point sets (the instances of a batch).
+template <bool JOBS>
+__global__ __launch_bounds__(RES_PTS) void ccf_residual_kernel(ResidualArgs a0, const ResidualArgs *__restrict__ jobs,
+                                                               const int2 *__restrict__ work) {
     __shared__ double tn[RES_PTS], wn[RES_PTS], thn[RES_PTS];
     __shared__ double Us[RES_SPLIT][RES_WG_PTS], cs[RES_SPLIT][RES_WG_PTS];
+    int64_t blk = blockIdx.x;
+    if (JOBS) {
+        const int2 wk = work[blockIdx.x];
+        if (wk.x < 0) return;
+        blk = wk.y;
+    }
+    const ResidualArgs a = JOBS ? jobs[work[blockIdx.x].x] : a0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * RES_WG_PTS + lane;
+    const int64_t i = blk * RES_WG_PTS + lane;
     const bool valid = i < a.n;
     const int64_t ii = valid ? i : a.n - 1;
     const double yi = a.pts.y[ii];
@@ -901,11 +912,24 @@ __global__ void burgers_residual_kernel(ResidualArgs a) {
 hipError_t launch_residual(hipStream_t st, const ResidualArgs &a) {
     if (a.n <= 0) return hipSuccess;
     if (a.equation == GN_EQ_CCF1D) {
-        hipLaunchKernelGGL(ccf_residual_kernel, dim3((unsigned)((a.n + RES_WG_PTS - 1) / RES_WG_PTS)), dim3(RES_PTS), 0,
-                           st, a);
+        hipLaunchKernelGGL(ccf_residual_kernel<false>, dim3((unsigned)((a.n + RES_WG_PTS - 1) / RES_WG_PTS)),
+                           dim3(RES_PTS), 0, st, a, nullptr, nullptr);
     } else {
         hipLaunchKernelGGL(burgers_residual_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
     }
+    return hipGetLastError();
+}
+
+void residual_jobs_work(const ResidualArgs *jobs, int n, std::vector<int2> &work) {
+    work.clear();
+    for (int j = 0; j < n; ++j)
+        for (int64_t k = 0; k * RES_WG_PTS < jobs[j].n; ++k) work.push_back(make_int2(j, (int)k));
+}
+
+hipError_t launch_residual_jobs(hipStream_t st, const ResidualArgs *d_jobs, const int2 *d_work, int64_t nwork) {
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ccf_residual_kernel<true>, dim3((unsigned)nwork), dim3(RES_PTS), 0, st, ResidualArgs{}, d_jobs,
+                       d_work);
     return hipGetLastError();
 }
 
