@@ -52,6 +52,7 @@ struct gn_context {
     double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
     float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
     ModgramWork mg{};                        // int8 residue workspaces (GN_INT8_CRT)
+    GramPlan gplan{};                        // work plan of the FP64 Gram of order P + 1 (set at creation)
     int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
     // 2D problems (gn_set_points_2d)
     int dim = 1, nout = 1, n_eq = 1;
@@ -470,6 +471,25 @@ gn_status jac_rows2d(gn_handle h, const double *theta, int64_t row0, int64_t nro
     return GN_OK;
 }
 
+// Work plan of the FP64 Gram of order P + 1 (tiles balanced over the XCDs,
+// the last round's tiles split along K), with its partial-tile workspace.
+gn_status gram_plan_alloc(gn_handle h, std::vector<void *> &A) {
+    h->gplan = GramPlan{};
+    if (h->precision != GN_FP64) return GN_OK;
+    int dev = 0, cus = 0;
+    GN_HIP(h, hipGetDevice(&dev));
+    GN_HIP(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<int4> t;
+    GramPlan p;
+    p.M = h->md.P + 1;
+    if (!plan_gram(p.M, cus, t, p.nwork, p.nsplit, p.pieces)) return GN_OK;
+    GN_TRY(dev_alloc(h, A, &p.d_work, (int64_t)t.size()));
+    if (p.nsplit > 0) GN_TRY(dev_alloc(h, A, &p.ws, gram_plan_ws_doubles(p.nsplit, p.pieces)));
+    GN_HIP(h, hipMemcpy(p.d_work, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
+    h->gplan = p;
+    return GN_OK;
+}
+
 GemmDesc gram_desc_rows(gn_handle h, int64_t rows, double beta) {
     const int64_t P = h->md.P;
     GemmDesc g{};
@@ -518,7 +538,7 @@ gn_status gram2d(gn_handle h, const double *theta) {
             GN_HIP(h, launch_gemv_t(st, h->J, nr, P, h->ldJ, h->r2 + r0, Grow, h->gemv_work, c > 0));
         } else {
             GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
-            GN_HIP(h, launch_dgemm(st, gram_desc_rows(h, nr, c > 0 ? 1.0 : 0.0)));
+            GN_HIP(h, launch_gram(st, gram_desc_rows(h, nr, c > 0 ? 1.0 : 0.0), h->gplan));
         }
     }
     if (h->precision == GN_SPLIT32) GN_HIP(h, launch_sumsq(st, h->r2, m, 1, Grow + P, h->red_work));
@@ -682,6 +702,7 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
         if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->fb, h->nf);
         if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->phi_one, 4 * h->nf);
     }
+    if (s == GN_OK) s = gram_plan_alloc(h, h->allocs);
     if (s != GN_OK) {
         free_list(h->allocs);
         delete h;
@@ -1028,7 +1049,7 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
         g.B = d_J; g.ldb = ldJ; g.lb = 0;
         g.C = d_G; g.ldc = ldG;
         g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
-        GN_HIP(h, launch_dgemm(h->stream, g));
+        GN_HIP(h, launch_gram(h->stream, g, h->gplan));
     }
     if (d_r) GN_HIP(h, launch_gemv_t(h->stream, d_J, m, p, ldJ, d_r, d_g, h->gemv_work));
     return GN_OK;
@@ -1108,7 +1129,7 @@ gn_status form_system(gn_handle h, const double *d_theta) {
             GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
             GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
         } else {
-            GN_HIP(h, launch_dgemm(st, gram_desc(h)));
+            GN_HIP(h, launch_gram(st, gram_desc(h), h->gplan));
         }
         GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     }

@@ -111,16 +111,23 @@ __device__ __forceinline__ bool tile_of_block(int64_t b, int lower, int tiles_m,
     return true;
 }
 
+// K extent of each piece of a split tile: K / pieces rounded up to whole chunks
+__host__ __device__ inline int64_t gram_piece_k(int64_t K, int pieces, int bk) {
+    const int64_t q = pieces > 1 ? (K + pieces - 1) / pieces : K;
+    return (q + bk - 1) / bk * bk;
+}
+
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT>
 __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0, int sup0,
                                                                  const GemmDesc *__restrict__ batch,
                                                                  const int4 *__restrict__ work) {
     // batched launches read (problem, tile row, tile column) from a work table
-    // laid out in dispatch order (entry b runs on XCD b % 8)
+    // laid out in dispatch order (entry b runs on XCD b % 8); a planned Gram
+    // (no batch, a table) reads (unit, tile row, tile column, piece)
     int4 wi = make_int4(0, 0, 0, 0);
-    if (BATCH) {
+    if (BATCH || work != nullptr) {
         wi = work[blockIdx.x];
-        if (wi.x < 0) return;
+        if (BATCH ? wi.x < 0 : wi.y < 0) return;
     }
     const GemmDesc g = BATCH ? batch[wi.x] : g0;
     if (g.M <= 0 || g.N <= 0) return;
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     double *Bs = smem + 2 * LoaderA::SIZE;   // two buffers of LoaderB::SIZE
 
     int tm = wi.y, tn = wi.z;
-    if (!BATCH && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, sup0, tm, tn)) return;
+    if (!BATCH && work == nullptr && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, sup0, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const bool lower_mask = g.lower || g.mask_lower;
     if (lower_mask && n0 > m0 + BM - 1 + g.mask_shift) return;  // tile entirely above the diagonal
@@ -157,11 +164,20 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     const bool b_aligned = ((g.ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0);
     const bool a_rows_in = m0 + BM <= g.M, b_rows_in = n0 + BN <= g.N;
 
-    const int64_t nk = (g.K + BK - 1) / BK;
+    // K range [kb, ke): all of K, or one piece of a split tile
+    const bool piece = !BATCH && work != nullptr && wi.x >= 0;
+    int64_t kb = 0, ke = g.K;
+    if (piece) {
+        const int64_t kp = gram_piece_k(g.K, g.split_pieces, BK);
+        kb = wi.w * kp;
+        ke = kb + kp < g.K ? kb + kp : g.K;
+        if (kb > ke) kb = ke;
+    }
+    const int64_t nk = (ke - kb + BK - 1) / BK;
     auto load_chunk = [&](int64_t k0) {
-        const bool kin = k0 + BK <= g.K;
-        la.load(g.A, g.lda, m0, k0, g.M, g.K, kin && a_rows_in && a_aligned);
-        lb.load(g.B, g.ldb, n0, k0, g.N, g.K, kin && b_rows_in && b_aligned);
+        const bool kin = k0 + BK <= ke;
+        la.load(g.A, g.lda, m0, k0, g.M, ke, kin && a_rows_in && a_aligned);
+        lb.load(g.B, g.ldb, n0, k0, g.N, ke, kin && b_rows_in && b_aligned);
     };
     auto store_chunk = [&](int buf) {
         la.store(As + buf * LoaderA::SIZE);
@@ -192,18 +208,18 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
         // staged through registers on its own after the loop
         if (a_rows_in && b_rows_in && a_aligned && b_aligned) {
             direct_done = true;
-            const int64_t nkf = g.K / BK;
+            const int64_t nkf = (ke - kb) / BK;
             if (nkf > 0) {
-                LoaderA::direct(g.A, g.lda, m0, 0, As, wave);
-                LoaderB::direct(g.B, g.ldb, n0, 0, Bs, wave);
+                LoaderA::direct(g.A, g.lda, m0, kb, As, wave);
+                LoaderB::direct(g.B, g.ldb, n0, kb, Bs, wave);
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
             }
             for (int64_t kt = 0; kt < nkf; ++kt) {
                 const int cur = (int)(kt & 1);
                 if (kt + 1 < nkf) {
-                    LoaderA::direct(g.A, g.lda, m0, (kt + 1) * BK, As + (cur ^ 1) * LoaderA::SIZE, wave);
-                    LoaderB::direct(g.B, g.ldb, n0, (kt + 1) * BK, Bs + (cur ^ 1) * LoaderB::SIZE, wave);
+                    LoaderA::direct(g.A, g.lda, m0, kb + (kt + 1) * BK, As + (cur ^ 1) * LoaderA::SIZE, wave);
+                    LoaderB::direct(g.B, g.ldb, n0, kb + (kt + 1) * BK, Bs + (cur ^ 1) * LoaderB::SIZE, wave);
                 }
                 GEMM_COMPUTE(cur);
                 __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of the next chunk have landed
@@ -211,7 +227,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
             }
             if (nkf < nk) {
                 const int buf = (int)(nkf & 1);
-                load_chunk(nkf * BK);
+                load_chunk(kb + nkf * BK);
                 store_chunk(buf);
                 __syncthreads();
                 GEMM_COMPUTE(buf);
@@ -220,13 +236,13 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     }
     if (!direct_done) {
         if (nk > 0) {
-            load_chunk(0);
+            load_chunk(kb);
             store_chunk(0);
             __syncthreads();
         }
         for (int64_t kt = 0; kt < nk; ++kt) {
             const int cur = (int)(kt & 1);
-            if (kt + 1 < nk) load_chunk((kt + 1) * BK);
+            if (kt + 1 < nk) load_chunk(kb + (kt + 1) * BK);
             GEMM_COMPUTE(cur);
             if (kt + 1 < nk) store_chunk(cur ^ 1);
             __syncthreads();
@@ -234,6 +250,22 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     }
 
 #undef GEMM_COMPUTE
+    if (piece) {
+        // a piece of a split tile: alpha * rowscale * (its partial sum) for the
+        // whole BM x BN tile (zeros outside C), summed by gram_sum_kernel
+        double *W = g.split_ws + (int64_t)wi.x * (BM * BN);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int lr = wm * WM + i * 16 + fk + 4 * r;
+                const int64_t gm = m0 + lr;
+                const double rs = (g.rowscale && gm < g.M) ? g.rowscale[gm] : 1.0;
+#pragma unroll
+                for (int j = 0; j < FN; ++j) W[lr * BN + wn * WN + j * 16 + fr] = g.alpha * acc[i][j][r] * rs;
+            }
+        return;
+    }
     // epilogue: lane l, register r holds row fk + 4 r, column fr of each
     // 16x16 block.  The loads of C and the row scales of EI block rows are
     // issued before their stores so they overlap (all rows at once unless
@@ -378,6 +410,118 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     }
     const int64_t b = blocks_for<64, 64, 32>(g, tm, tn);
     return launch_tiles<64, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
+}
+
+// ------------------------------------------------------------ planned Gram
+static constexpr int GRAM_T = 128;   // tile of the planned Gram (four-wave configuration)
+static constexpr int GRAM_BK = 16;
+static constexpr int GRAM_MAX_PIECES = 4;
+
+int64_t gram_plan_ws_doubles(int nsplit, int pieces) { return (int64_t)nsplit * pieces * GRAM_T * GRAM_T; }
+
+bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces) {
+    table.clear();
+    nwork = 0;
+    nsplit = 0;
+    pieces = 1;
+    const int64_t tiles = (M + GRAM_T - 1) / GRAM_T;
+    // the products launch_dgemm gives to the four-wave configuration
+    if (M <= 0 || tiles * (tiles + 1) / 2 < 2 * 256 || tiles > (1 << 30)) return false;
+    if (cus <= 0 || cus % NXCD != 0) return false;
+    const int64_t slots = 2 * (int64_t)(cus / NXCD);  // resident workgroups per XCD
+    // 4 x 8 super-tiles in the order of tile_of_block (rows of super-tiles,
+    // tiles column by column inside one), each dealt whole to the XCD with
+    // the fewest tiles so far
+    std::vector<std::vector<int4>> per(NXCD);
+    const int64_t nsr = (tiles + SUP_M - 1) / SUP_M, nsc = (tiles + SUP_N - 1) / SUP_N;
+    for (int64_t a = 0; a < nsr; ++a) {
+        const int64_t c = std::min((SUP_M * a + SUP_M - 1) / SUP_N + 1, nsc);
+        for (int64_t b = 0; b < c; ++b) {
+            int x = 0;
+            for (int k = 1; k < NXCD; ++k)
+                if (per[k].size() < per[x].size()) x = k;
+            for (int i = 0; i < SUP; ++i) {
+                const int64_t tm = a * SUP_M + i % SUP_M, tn = b * SUP_N + i / SUP_M;
+                if (tm < tiles && tn <= tm) per[x].push_back(make_int4(-1, (int)tm, (int)tn, 0));
+            }
+        }
+    }
+    // even out the counts (they differ by at most one super-tile): tiles move
+    // from the ends of the longest lists to the ends of the shortest
+    for (;;) {
+        int lo = 0, hi = 0;
+        for (int k = 1; k < NXCD; ++k) {
+            if (per[k].size() < per[lo].size()) lo = k;
+            if (per[k].size() > per[hi].size()) hi = k;
+        }
+        if (per[hi].size() <= per[lo].size() + 1) break;
+        per[lo].push_back(per[hi].back());
+        per[hi].pop_back();
+    }
+    // pieces: as many as the emptiest last round has room for (at most 4)
+    int pc = GRAM_MAX_PIECES;
+    bool any = false;
+    for (int x = 0; x < NXCD; ++x) {
+        const int64_t r = (int64_t)per[x].size() % slots;
+        if (r == 0) continue;
+        any = true;
+        pc = (int)std::min<int64_t>(pc, slots / r);
+    }
+    std::vector<int4> fix;
+    if (any && pc >= 2) {
+        pieces = pc;
+        for (int x = 0; x < NXCD; ++x) {
+            const int64_t n = (int64_t)per[x].size(), r = n % slots;
+            for (int64_t i = n - r; i < n; ++i) {
+                int4 &e = per[x][i];
+                const int unit = nsplit * pieces;
+                e.x = unit;
+                fix.push_back(make_int4(unit, e.y, e.z, 0));
+                for (int q = 1; q < pieces; ++q) per[x].push_back(make_int4(unit + q, e.y, e.z, q));
+                ++nsplit;
+            }
+        }
+    }
+    size_t len = 0;
+    for (auto &v : per) len = std::max(len, v.size());
+    table.assign(len * NXCD, make_int4(-1, -1, 0, 0));
+    for (int x = 0; x < NXCD; ++x)
+        for (size_t q = 0; q < per[x].size(); ++q) table[q * NXCD + x] = per[x][q];
+    nwork = (int64_t)table.size();
+    table.insert(table.end(), fix.begin(), fix.end());
+    return true;
+}
+
+// C = beta C + (sum of the pieces of each split tile, in piece order), lower
+// part only; one workgroup per split tile.
+__global__ __launch_bounds__(256) void gram_sum_kernel(GemmDesc g, const int4 *__restrict__ tiles) {
+    if (g.stop_flag != nullptr && *g.stop_flag != 0) return;
+    const int4 t = tiles[blockIdx.x];
+    constexpr int T = GRAM_T;
+    const double *W = g.split_ws + (int64_t)t.x * (T * T);
+    const int64_t m0 = (int64_t)t.y * T, n0 = (int64_t)t.z * T;
+    for (int e = threadIdx.x; e < T * T; e += 256) {
+        const int64_t gm = m0 + e / T, gn_ = n0 + e % T;
+        if (gm >= g.M || gn_ >= g.N || gn_ > gm + g.mask_shift) continue;
+        double v = W[e];
+        for (int q = 1; q < g.split_pieces; ++q) v += W[(int64_t)q * (T * T) + e];
+        double *c = g.C + gm * g.ldc + gn_;
+        *c = g.beta == 0.0 ? v : fma(g.beta, *c, v);
+    }
+}
+
+hipError_t launch_gram(hipStream_t st, const GemmDesc &g, const GramPlan &p) {
+    if (p.M <= 0 || p.d_work == nullptr || p.nwork <= 0 || g.M != p.M || g.N != p.M || !g.lower || g.la != 1 ||
+        g.lb != 0 || g.mask_shift != 0 || g.C == g.A || g.C == g.B)
+        return launch_dgemm(st, g);
+    if (p.nsplit > 0 && (p.ws == nullptr || p.pieces < 2)) return hipErrorInvalidValue;
+    GemmDesc q = g;
+    q.split_ws = p.ws;
+    q.split_pieces = p.pieces;
+    hipError_t e = launch_one<GRAM_T, GRAM_T, GRAM_BK, 1, 0, false, 256>(st, q, 0, 0, p.nwork, nullptr, p.d_work);
+    if (e != hipSuccess || p.nsplit == 0) return e;
+    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)p.nsplit), dim3(256), 0, st, q, p.d_work + p.nwork);
+    return hipGetLastError();
 }
 
 // Batched tile configuration: 128 x 64 tiles for narrow rectangular products
