@@ -52,15 +52,16 @@ def gram_source_sha256():
 
 
 def gram_traffic():
-    """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (profiles/gram_ccf_medium_pmc.txt, scaled by a plain
-    copy of known size), or None if the GEMM source changed since."""
+    """HBM bytes of one Gram (the product launch plus the launch that sums the
+    split tiles) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (profiles/gram_ccf_medium_pmc.txt, scaled by a plain copy of known size),
+    or None if the GEMM source changed since."""
     path = os.path.join(ROOT, "profiles", "gram_ccf_medium_pmc.txt")
     try:
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("#"))
         if kv.get("kernel_source_sha256") != gram_source_sha256():
             return None
-        return float(kv["gram_hbm_traffic_bytes"])
+        return float(kv["gram_phase_hbm_traffic_bytes"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -517,9 +518,10 @@ def bench_2d(name, steps, warmup, precision="fp64", damping="fixed"):
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": ("gram (dgemm_mfma_kernel<128,128,16,1,0,false,256>, accumulated over row chunks; the "
-                       "phase includes the Jacobian sweeps of each chunk)" if inp.get("row_chunk", 0) else
-                       "gram (dgemm_mfma_kernel<128,128,16,1,0,false,256>)"),
+            "kernel": ("gram (dgemm_mfma_kernel<128,128,16,1,0,false,256> on the XCD-balanced work plan, "
+                       "accumulated over row chunks; the phase includes the Jacobian sweeps of each chunk)"
+                       if inp.get("row_chunk", 0) else
+                       "gram (dgemm_mfma_kernel<128,128,16,1,0,false,256> on the XCD-balanced work plan)"),
             "achieved": fl_gram / t_gram / 1e12,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
@@ -825,7 +827,8 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gram (dgemm_mfma_kernel<128,128,16,1,0,false,256>)",
+            "kernel": ("gram (dgemm_mfma_kernel<128,128,16,1,0,false,256> on the XCD-balanced work plan, "
+                       "then gram_sum_kernel over the tiles split along K)"),
             "achieved": gram_tf,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",

@@ -117,15 +117,18 @@ __host__ __device__ inline int64_t gram_piece_k(int64_t K, int pieces, int bk) {
     return (q + bk - 1) / bk * bk;
 }
 
-template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT>
+// PLAN: the planned Gram (launch_gram); a compile-time switch, so that the
+// other instances carry none of its code.
+template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT, bool PLAN = false>
 __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0, int sup0,
                                                                  const GemmDesc *__restrict__ batch,
                                                                  const int4 *__restrict__ work) {
+    static_assert(!(BATCH && PLAN), "one table kind per instance");
     // batched launches read (problem, tile row, tile column) from a work table
     // laid out in dispatch order (entry b runs on XCD b % 8); a planned Gram
-    // (no batch, a table) reads (unit, tile row, tile column, piece)
+    // reads (unit, tile row, tile column, piece)
     int4 wi = make_int4(0, 0, 0, 0);
-    if (BATCH || work != nullptr) {
+    if (BATCH || PLAN) {
         wi = work[blockIdx.x];
         if (BATCH ? wi.x < 0 : wi.y < 0) return;
     }
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     double *Bs = smem + 2 * LoaderA::SIZE;   // two buffers of LoaderB::SIZE
 
     int tm = wi.y, tn = wi.z;
-    if (!BATCH && work == nullptr && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, sup0, tm, tn)) return;
+    if (!BATCH && !PLAN && !tile_of_block(blockIdx.x, g.lower, tiles_m0, tiles_n0, sup0, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const bool lower_mask = g.lower || g.mask_lower;
     if (lower_mask && n0 > m0 + BM - 1 + g.mask_shift) return;  // tile entirely above the diagonal
@@ -165,13 +168,15 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     const bool a_rows_in = m0 + BM <= g.M, b_rows_in = n0 + BN <= g.N;
 
     // K range [kb, ke): all of K, or one piece of a split tile
-    const bool piece = !BATCH && work != nullptr && wi.x >= 0;
+    const bool piece = PLAN && wi.x >= 0;
     int64_t kb = 0, ke = g.K;
-    if (piece) {
-        const int64_t kp = gram_piece_k(g.K, g.split_pieces, BK);
-        kb = wi.w * kp;
-        ke = kb + kp < g.K ? kb + kp : g.K;
-        if (kb > ke) kb = ke;
+    if constexpr (PLAN) {
+        if (piece) {
+            const int64_t kp = gram_piece_k(g.K, g.split_pieces, BK);
+            kb = wi.w * kp;
+            ke = kb + kp < g.K ? kb + kp : g.K;
+            if (kb > ke) kb = ke;
+        }
     }
     const int64_t nk = (ke - kb + BK - 1) / BK;
     auto load_chunk = [&](int64_t k0) {
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     }
 
 #undef GEMM_COMPUTE
-    if (piece) {
+    if (PLAN && piece) {
         // a piece of a split tile: alpha * rowscale * (its partial sum) for the
         // whole BM x BN tile (zeros outside C), summed by gram_sum_kernel
         double *W = g.split_ws + (int64_t)wi.x * (BM * BN);
@@ -311,18 +316,18 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
     }
 }
 
-template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT>
+template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT, bool PLAN = false>
 static hipError_t launch_one(hipStream_t st, const GemmDesc &g, int tiles_m, int tiles_n, int64_t blocks,
                              const GemmDesc *batch, const int4 *work) {
     constexpr size_t shm =
         sizeof(double) * 2 * (TileLoader<BM, BK, LA == 1, NT>::SIZE + TileLoader<BN, BK, LB == 0, NT>::SIZE);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH, NT>,
+        (void)hipFuncSetAttribute((const void *)dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH, NT, PLAN>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         attr = true;
     }
-    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH, NT>), dim3((unsigned)blocks), dim3(NT),
+    hipLaunchKernelGGL((dgemm_mfma_kernel<BM, BN, BK, LA, LB, BATCH, NT, PLAN>), dim3((unsigned)blocks), dim3(NT),
                        shm, st, g, tiles_m, tiles_n, super_shape(g.lower, tiles_m, tiles_n), batch, work);
     return hipGetLastError();
 }
@@ -518,7 +523,7 @@ hipError_t launch_gram(hipStream_t st, const GemmDesc &g, const GramPlan &p) {
     GemmDesc q = g;
     q.split_ws = p.ws;
     q.split_pieces = p.pieces;
-    hipError_t e = launch_one<GRAM_T, GRAM_T, GRAM_BK, 1, 0, false, 256>(st, q, 0, 0, p.nwork, nullptr, p.d_work);
+    hipError_t e = launch_one<GRAM_T, GRAM_T, GRAM_BK, 1, 0, false, 256, true>(st, q, 0, 0, p.nwork, nullptr, p.d_work);
     if (e != hipSuccess || p.nsplit == 0) return e;
     hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)p.nsplit), dim3(256), 0, st, q, p.d_work + p.nwork);
     return hipGetLastError();
