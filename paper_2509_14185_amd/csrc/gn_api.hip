@@ -50,6 +50,10 @@ struct gn_context {
     double *R = nullptr, *seed0 = nullptr, *seed1 = nullptr, *cscale = nullptr, *r_tmp = nullptr;
     double *vseed0 = nullptr, *vseed1 = nullptr, *useed = nullptr;
     double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
+    // the stochastic step's Hilbert coupling applied through products (1D CCF):
+    // two n-vectors, two m-vectors, and the partial sums of a transposed
+    // product over n columns
+    double *cp_t = nullptr, *cp_z = nullptr, *cp_work = nullptr;
     float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
     ModgramWork mg{};                        // int8 residue workspaces (GN_INT8_CRT)
     GramPlan gplan{};                        // work plan of the FP64 Gram of order P + 1 (set at creation)
@@ -789,6 +793,7 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     h->stage2 = false;
     h->s1R = h->s1V = h->s1T = h->s1Rv = h->s1Vv = h->s1Tv = nullptr;
     h->fn_R = nullptr;
+    h->cp_t = h->cp_z = h->cp_work = nullptr;
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
     const int64_t nd = n1 + n2;
@@ -818,6 +823,9 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     if (s == GN_OK && d_f) s = dev_alloc(h, A, &h->f, n);
     if (s == GN_OK && !d_f) h->f = nullptr;
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Q, m_quad * h->ldQ);
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_t, 2 * n);
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_z, 2 * m_quad);
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_work, gemv_t_work_size(m_quad, n));
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_pts, 2 * n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_nodes, 2 * m_quad);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_val, 2 * n_val);
@@ -1139,10 +1147,12 @@ gn_status form_system(gn_handle h, const double *d_theta) {
 
 // r (column P of the workspace J), J and the residual statistics at theta
 // (1D problems; no Gram).
-gn_status form_jacobian(gn_handle h, const double *d_theta) {
+// coupling = false: the collocation rows leave out the Hilbert coupling
+// diag(cs) Q B (1D CCF), for callers that apply it in their products.
+gn_status form_jacobian(gn_handle h, const double *d_theta, bool coupling = true) {
     hipStream_t st = h->stream;
     GN_HIP(h, launch_reset_status(st, h->status));
-    GN_TRY(build_step_jacobian(h, d_theta, false));
+    GN_TRY(build_step_jacobian(h, d_theta, false, coupling));
     GN_HIP(h, launch_sumsq(st, h->J + h->md.P, total_rows(h), h->ldJ, &h->status->half_sq_norm, h->red_work));
     return GN_OK;
 }
@@ -1287,11 +1297,25 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     hipStream_t st = h->stream;
     double *J = h->J;
     const int64_t ldJ = h->ldJ;
-    GN_TRY(form_jacobian(h, d_theta));
+    // The step uses J only in products, so for the 1D CCF equation the
+    // Hilbert coupling of the collocation rows, diag(cs) Q B (the N x M x P
+    // product that dominates forming J), is applied inside them instead:
+    // J x = J_loc x + cs o Q (B x) and J^T y = J_loc^T y + B^T Q^T (cs o y)
+    // (Q^T is kept as M rows of N, B as M rows of P).
+    const bool implicit = h->equation == GN_EQ_CCF1D && h->m > 0 && h->cp_t != nullptr;
+    const int64_t nc = h->n, mq = h->m;
+    GN_TRY(form_jacobian(h, d_theta, !implicit));
     // g = J^T r, u = J^T v
     GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
     GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, h->r1_g, h->gemv_work));
     GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, d_v, h->r1_u, h->gemv_work));
+    if (implicit) {
+        double *t1 = h->cp_t, *t2 = h->cp_t + nc, *z1 = h->cp_z, *z2 = h->cp_z + mq;
+        GN_HIP(h, launch_diag_scale2(st, nc, h->cscale, h->r_tmp, d_v, t1, t2, 0));
+        GN_HIP(h, launch_gemv_n2(st, h->Q, mq, nc, h->ldQ, t1, t2, z1, z2));
+        GN_HIP(h, launch_gemv_t(st, h->Bm, mq, P, ldJ, z1, h->r1_g, h->gemv_work, 1));
+        GN_HIP(h, launch_gemv_t(st, h->Bm, mq, P, ldJ, z2, h->r1_u, h->gemv_work, 1));
+    }
     GN_HIP(h, launch_ema_rank1(st, d_G_ema, P, ldG, a->beta, h->r1_u));
     if (a->refactor) {
         GN_HIP(h, launch_copy_lower(st, d_G_ema, ldG, h->G, h->ldG, P));
@@ -1303,6 +1327,13 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     GN_HIP(h, launch_solve_upper_sync(st, h->G, P, h->ldG, h->linv, h->zbuf, h->r1_D, h->status, h->solve_sync));
     // exact curvature along Delta and d_prev
     GN_HIP(h, launch_gemv_n2(st, J, m_rows, P, ldJ, h->r1_D, d_prev, h->r1_w1, h->r1_w2));
+    if (implicit) {
+        double *y1 = h->cp_z, *y2 = h->cp_z + mq, *s1 = h->cp_t, *s2 = h->cp_t + nc;
+        GN_HIP(h, launch_gemv_n2(st, h->Bm, mq, P, ldJ, h->r1_D, d_prev, y1, y2));
+        GN_HIP(h, launch_gemv_t(st, h->Q, mq, nc, h->ldQ, y1, s1, h->cp_work));
+        GN_HIP(h, launch_gemv_t(st, h->Q, mq, nc, h->ldQ, y2, s2, h->cp_work));
+        GN_HIP(h, launch_diag_scale2(st, nc, h->cscale, s1, s2, h->r1_w1, h->r1_w2, 1));
+    }
     DotPairs dp{};
     const double *xs[8] = {h->r1_w1, h->r1_w1, h->r1_w2, h->r1_D, h->r1_D, d_prev, h->r1_g, h->r1_g};
     const double *ys[8] = {h->r1_w1, h->r1_w2, h->r1_w2, h->r1_D, d_prev, d_prev, h->r1_D, d_prev};

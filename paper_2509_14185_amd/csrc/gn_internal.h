@@ -435,6 +435,9 @@ struct DotPairs {
 hipError_t launch_dots(hipStream_t st, const DotPairs &d, int64_t n, double *out, double *work);
 int64_t dots_work_size();
 // delta = alpha D + mu prev (over prev), theta += delta.
+// y_k = cs o x_k (accumulate = 0) or y_k += cs o x_k, k = 1, 2, over n entries.
+hipError_t launch_diag_scale2(hipStream_t st, int64_t n, const double *cs, const double *x1, const double *x2,
+                              double *y1, double *y2, int accumulate);
 hipError_t launch_rank1_update(hipStream_t st, double *theta, double *prev, const double *D, double alpha, double mu,
                                int64_t p);
 

@@ -131,6 +131,25 @@ hipError_t launch_dots(hipStream_t st, const DotPairs &d, int64_t n, double *out
 
 int64_t dots_work_size() { return (int64_t)DOT_MAX * DOT_BLOCKS; }
 
+// y_k = cs o x_k (accumulate = 0) or y_k += cs o x_k, k = 1, 2, over n
+// entries: the row scale of the Hilbert coupling applied to two vectors.
+__global__ void diag_scale2_kernel(int64_t n, const double *__restrict__ cs, const double *__restrict__ x1,
+                                   const double *__restrict__ x2, double *y1, double *y2, int accumulate) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double c = cs[i];
+    y1[i] = accumulate ? fma(c, x1[i], y1[i]) : c * x1[i];
+    y2[i] = accumulate ? fma(c, x2[i], y2[i]) : c * x2[i];
+}
+
+hipError_t launch_diag_scale2(hipStream_t st, int64_t n, const double *cs, const double *x1, const double *x2,
+                              double *y1, double *y2, int accumulate) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(diag_scale2_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, cs, x1, x2, y1, y2,
+                       accumulate);
+    return hipGetLastError();
+}
+
 // delta = alpha D + mu prev (written over prev), theta += delta.
 __global__ void rank1_update_kernel(double *theta, double *prev, const double *__restrict__ D, double alpha,
                                     double mu, int64_t p) {
