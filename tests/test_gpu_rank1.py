@@ -2,6 +2,9 @@
 (gn_step_rank1) against the oracle (oracle/rank1.py) on identical seeded
 inputs, the probe signs drawn by workloads.rademacher for both.  Each side
 runs its own trajectory of 4 steps (the factor refreshed every second step).
+On the CCF cases the step applies the Hilbert coupling of the collocation
+rows inside its products with J (J never holds it); the case with d1 and d2
+rows mixes those with derivative rows whose own coupling is formed in J.
 Per step: G_ema (relative 1e-12, Frobenius), alpha, mu and the model value
 (relative 1e-9), the momentum decision, and theta (the update's forward error
 <= max(1e-10, 10 kappa eps), kappa of G_ema + gamma I).  At any size: with
@@ -15,6 +18,7 @@ import pytest
 import torch
 
 import workloads
+from oracle import deriv1d as d1
 from oracle import profile1d as p1
 from oracle import rank1
 from paper_2509_14185_amd import gn
@@ -26,7 +30,9 @@ CASES = {
     "ccf_small": ("ccf_small", {}, "ccf1d"),
     "ccf_ragged": ("ccf_small", dict(n=1000, m_quad=100, widths=[1, 24, 17, 1]), "ccf1d"),
     "burgers": ("ccf_small", dict(n=777, widths=[1, 16, 16, 1]), "burgers1d"),
+    "ccf_d1d2": ("ccf_small", dict(n=300, m_quad=64, widths=[1, 12, 10, 1]), "ccf1d"),
 }
+D12 = {"ccf_d1d2": (37, 29)}  # d1 and d2 point counts
 
 
 def dev(x):
@@ -41,8 +47,15 @@ def build(key):
     po = p1.Problem.from_inputs(inp, equation=eq)
     pg = gn.Problem(eq, inp["widths"], inp["lam"], inp["c_norm"], inp["c_target"])
     ccf = eq == "ccf1d"
+    kw = {}
+    if key in D12:
+        n1, n2 = D12[key]
+        s1 = (np.arange(n1) + 0.5) / n1 * 0.98
+        s2 = (np.arange(n2) + 0.3) / n2 * 0.98
+        po = d1.Problem(po, s1, s2, c_d1=0.8, c_d2=0.4)
+        kw = dict(s1=s1, s2=s2, c_d1=0.8, c_d2=0.4)
     pg.set_points(inp["s"], inp["rho"], inp["f"], inp["sq"] if ccf else None, inp["wq"] if ccf else None,
-                  inp["sval"])
+                  inp["sval"], **kw)
     return inp, po, pg
 
 
