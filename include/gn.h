@@ -146,8 +146,12 @@ const char *gn_status_string(int32_t status);
 const char *gn_last_error(gn_handle h);
 
 /* Create a handle for one problem on the current HIP device.  Copies *prob
- * (including widths).  Errors: GN_EINVAL for bad widths (first/last != 1,
- * hidden width > GN_MAX_WIDTH, L out of range), lam <= 0, c_norm < 0. */
+ * (including widths).  With GN_FP64 and a Gram of order P + 1 large enough
+ * for 128 x 128 tiles (P + 1 above about 4000), the handle also keeps the
+ * Gram's work plan: a tile table and at most one 128 x 128 partial tile per
+ * resident workgroup (64 MB on 256 CUs).  Errors: GN_EINVAL for bad widths
+ * (first/last != 1, hidden width > GN_MAX_WIDTH, L out of range), lam <= 0,
+ * c_norm < 0; GN_ENOMEM. */
 gn_status gn_create(const gn_problem *prob, gn_handle *out);
 gn_status gn_destroy(gn_handle h);
 
@@ -225,6 +229,10 @@ gn_status gn_jacobian(gn_handle h, const double *d_theta, double *d_J, int64_t l
 
 /* Lower triangle of G = J^T J (p x p, ldG >= p) and g = J^T r (p), for any
  * m x p row-major J (ldJ >= p).  d_r may be NULL (then g is not written).
+ * With GN_FP64 and p = P + 1 the product runs on the handle's work plan
+ * (gn_create); some tiles are then summed from K ranges in a fixed order, so
+ * the result is deterministic but may differ in the last bits from another
+ * p's tiling of the same entries.
  * With GN_INT8_CRT, m may not exceed the handle's row count (N + 1 + the
  * derivative rows) and p may not exceed P + 1 (GN_EINVAL otherwise). */
 gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t ldJ,

@@ -1,0 +1,99 @@
+// Host check of the Gram work plan (plan_gram): for many orders and CU counts,
+// every lower 128 x 128 tile appears once, either whole or as all of its
+// pieces; piece units are distinct and in range; the summing entries name the
+// split tiles; per-XCD counts of whole tiles differ by at most one; on every
+// XCD the pieces fit in one round of resident workgroups.  Exit status 0 when
+// all hold.  Pure host code: no device is touched.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <set>
+#include <vector>
+
+#include "gn_internal.h"
+
+int main() {
+    int bad = 0, plans = 0, split = 0;
+    const long orders[] = {1154, 3842, 3969, 4097, 4223, 4548, 4850, 5000, 8514, 9000, 12000, 12738, 16385, 20001, 50308};
+    for (long M : orders) {
+        for (int cus : {256, 304, 240, 80, 8}) {
+            std::vector<int4> t;
+            int64_t nwork = 0;
+            int nsplit = 0, pieces = 0;
+            const long tiles = (M + 127) / 128, lower = tiles * (tiles + 1) / 2;
+            if (!gn::plan_gram(M, cus, t, nwork, nsplit, pieces)) {
+                if (lower >= 512 && cus % 8 == 0) {
+                    printf("M %ld cus %d: no plan\n", M, cus);
+                    ++bad;
+                }
+                continue;
+            }
+            ++plans;
+            split += nsplit > 0;
+            const long slots = 2L * (cus / 8);
+            std::map<std::pair<int, int>, std::set<int>> seen;
+            std::vector<long> whole_x(8, 0), piece_x(8, 0);
+            std::vector<int> unit_seen((size_t)nsplit * pieces, 0);
+            for (long b = 0; b < nwork; ++b) {
+                const int4 e = t[b];
+                if (e.y < 0) continue;
+                if (e.y >= tiles || e.z < 0 || e.z > e.y) {
+                    printf("M %ld: tile (%d, %d) outside the lower triangle\n", M, e.y, e.z);
+                    ++bad;
+                    continue;
+                }
+                std::set<int> &s = seen[{e.y, e.z}];
+                if (e.x < 0) {
+                    if (!s.empty()) ++bad;
+                    s.insert(-1);
+                    ++whole_x[b % 8];
+                } else {
+                    if (e.x >= nsplit * pieces || e.w < 0 || e.w >= pieces || e.x % pieces != e.w) {
+                        printf("M %ld: bad unit %d piece %d\n", M, e.x, e.w);
+                        ++bad;
+                        continue;
+                    }
+                    ++unit_seen[e.x];
+                    if (s.count(e.w) || s.count(-1)) ++bad;
+                    s.insert(e.w);
+                    ++piece_x[b % 8];
+                }
+            }
+            if ((long)seen.size() != lower) {
+                printf("M %ld cus %d: %zu tiles covered of %ld\n", M, cus, seen.size(), lower);
+                ++bad;
+            }
+            for (auto &kv : seen)
+                if (!kv.second.count(-1) && (int)kv.second.size() != pieces) ++bad;
+            for (int u : unit_seen)
+                if (u != 1) {
+                    ++bad;
+                    break;
+                }
+            if ((long)t.size() != nwork + nsplit) ++bad;
+            for (int i = 0; i < nsplit; ++i) {
+                const int4 f = t[nwork + i];
+                auto it = seen.find({f.y, f.z});
+                if (f.x != i * pieces || it == seen.end() || it->second.count(-1)) ++bad;
+            }
+            long lo = 1L << 40, hi = 0;
+            for (int x = 0; x < 8; ++x) {
+                const long tiles_x = whole_x[x] + piece_x[x] / std::max(pieces, 1);
+                lo = std::min(lo, tiles_x);
+                hi = std::max(hi, tiles_x);
+                if (piece_x[x] > slots) {
+                    printf("M %ld cus %d: %ld pieces on XCD %d, %ld slots\n", M, cus, piece_x[x], x, slots);
+                    ++bad;
+                }
+            }
+            if (hi - lo > 1) {
+                printf("M %ld cus %d: tiles per XCD from %ld to %ld\n", M, cus, lo, hi);
+                ++bad;
+            }
+        }
+    }
+    printf("%d plans (%d with split tiles): %s\n", plans, split, bad ? "FAILED" : "all invariants hold");
+    return bad != 0;
+}
