@@ -56,7 +56,8 @@ struct gn_context {
     double *cp_t = nullptr, *cp_z = nullptr, *cp_work = nullptr;
     float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
     ModgramWork mg{};                        // int8 residue workspaces (GN_INT8_CRT)
-    GramPlan gplan{};                        // work plan of the FP64 Gram of order P + 1 (set at creation)
+    TilePlan gplan{};                        // work plan of the FP64 Gram of order P + 1 (set at creation)
+    TilePlan cplan{};                        // work plan of the Hilbert coupling, N x P (set with the points)
     int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
     // 2D problems (gn_set_points_2d)
     int dim = 1, nout = 1, n_eq = 1;
@@ -319,7 +320,7 @@ gn_status jacobian_into(gn_handle h, const double *theta, double *J, int64_t ldJ
         g.B = h->Bm; g.ldb = h->ldJ; g.lb = 0;
         g.C = J; g.ldc = ldJ;
         g.alpha = 1.0; g.beta = 1.0; g.rowscale = h->cscale;
-        GN_HIP(h, launch_dgemm(st, g));
+        GN_HIP(h, launch_planned(st, g, h->cplan));
     }
     GN_TRY(deriv_jacobian(h, theta, J, ldJ));
     return GN_OK;
@@ -387,7 +388,7 @@ gn_status build_step_jacobian(gn_handle h, const double *d_theta, bool marks, bo
         GN_HIP(h, launch_mlp_rows(st, h->md, d_theta, h->thetaT, nb));
     }
     if (marks) mark(h, 2);
-    if (coupling && h->equation == GN_EQ_CCF1D) GN_HIP(h, launch_dgemm(st, coupling_desc(h)));
+    if (coupling && h->equation == GN_EQ_CCF1D) GN_HIP(h, launch_planned(st, coupling_desc(h), h->cplan));
     GN_TRY(deriv_jacobian(h, d_theta, J, ldJ));
     return GN_OK;
 }
@@ -477,21 +478,32 @@ gn_status jac_rows2d(gn_handle h, const double *theta, int64_t row0, int64_t nro
 
 // Work plan of the FP64 Gram of order P + 1 (tiles balanced over the XCDs,
 // the last round's tiles split along K), with its partial-tile workspace.
-gn_status gram_plan_alloc(gn_handle h, std::vector<void *> &A) {
-    h->gplan = GramPlan{};
-    if (h->precision != GN_FP64) return GN_OK;
+// The device copies of a work plan (table and partial-tile workspace) into
+// *out, or *out left empty when the product takes no plan.
+gn_status tile_plan_alloc(gn_handle h, std::vector<void *> &A, int64_t M, int64_t N, bool lower, TilePlan *out) {
+    *out = TilePlan{};
     int dev = 0, cus = 0;
     GN_HIP(h, hipGetDevice(&dev));
     GN_HIP(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     std::vector<int4> t;
-    GramPlan p;
-    p.M = h->md.P + 1;
-    if (!plan_gram(p.M, cus, t, p.nwork, p.nsplit, p.pieces)) return GN_OK;
+    TilePlan p;
+    p.M = M;
+    p.N = N;
+    p.lower = lower;
+    const bool ok = lower ? plan_gram(M, cus, t, p.nwork, p.nsplit, p.pieces)
+                          : plan_rect(M, N, cus, t, p.nwork, p.nsplit, p.pieces);
+    if (!ok) return GN_OK;
     GN_TRY(dev_alloc(h, A, &p.d_work, (int64_t)t.size()));
     if (p.nsplit > 0) GN_TRY(dev_alloc(h, A, &p.ws, gram_plan_ws_doubles(p.nsplit, p.pieces)));
     GN_HIP(h, hipMemcpy(p.d_work, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
-    h->gplan = p;
+    *out = p;
     return GN_OK;
+}
+
+gn_status gram_plan_alloc(gn_handle h, std::vector<void *> &A) {
+    h->gplan = TilePlan{};
+    if (h->precision != GN_FP64) return GN_OK;
+    return tile_plan_alloc(h, A, h->md.P + 1, h->md.P + 1, true, &h->gplan);
 }
 
 GemmDesc gram_desc_rows(gn_handle h, int64_t rows, double beta) {
@@ -542,7 +554,7 @@ gn_status gram2d(gn_handle h, const double *theta) {
             GN_HIP(h, launch_gemv_t(st, h->J, nr, P, h->ldJ, h->r2 + r0, Grow, h->gemv_work, c > 0));
         } else {
             GN_HIP(h, launch_copy_strided(st, h->r2 + r0, nr, 1, h->J + P, h->ldJ, 1.0));
-            GN_HIP(h, launch_gram(st, gram_desc_rows(h, nr, c > 0 ? 1.0 : 0.0), h->gplan));
+            GN_HIP(h, launch_planned(st, gram_desc_rows(h, nr, c > 0 ? 1.0 : 0.0), h->gplan));
         }
     }
     if (h->precision == GN_SPLIT32) GN_HIP(h, launch_sumsq(st, h->r2, m, 1, Grow + P, h->red_work));
@@ -794,6 +806,7 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     h->s1R = h->s1V = h->s1T = h->s1Rv = h->s1Vv = h->s1Tv = nullptr;
     h->fn_R = nullptr;
     h->cp_t = h->cp_z = h->cp_work = nullptr;
+    h->cplan = TilePlan{};
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
     const int64_t nd = n1 + n2;
@@ -826,6 +839,7 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_t, 2 * n);
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_z, 2 * m_quad);
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_work, gemv_t_work_size(m_quad, n));
+    if (s == GN_OK && m_quad > 0 && h->equation == GN_EQ_CCF1D) s = tile_plan_alloc(h, A, n, P, false, &h->cplan);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_pts, 2 * n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_nodes, 2 * m_quad);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_val, 2 * n_val);
@@ -1057,7 +1071,7 @@ gn_status gn_gram(gn_handle h, const double *d_J, int64_t m, int64_t p, int64_t 
         g.B = d_J; g.ldb = ldJ; g.lb = 0;
         g.C = d_G; g.ldc = ldG;
         g.alpha = 1.0; g.beta = 0.0; g.lower = 1;
-        GN_HIP(h, launch_gram(h->stream, g, h->gplan));
+        GN_HIP(h, launch_planned(h->stream, g, h->gplan));
     }
     if (d_r) GN_HIP(h, launch_gemv_t(h->stream, d_J, m, p, ldJ, d_r, d_g, h->gemv_work));
     return GN_OK;
@@ -1137,7 +1151,7 @@ gn_status form_system(gn_handle h, const double *d_theta) {
             GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, Grow, h->gemv_work));
             GN_HIP(h, launch_sumsq(st, h->r_tmp, m_rows, 1, Grow + P, h->red_work));
         } else {
-            GN_HIP(h, launch_gram(st, gram_desc(h), h->gplan));
+            GN_HIP(h, launch_planned(st, gram_desc(h), h->gplan));
         }
         GN_HIP(h, launch_sumsq(st, J + P, m_rows, ldJ, &h->status->half_sq_norm, h->red_work));
     }

@@ -173,28 +173,30 @@ struct GemmDesc {
     int mask_lower;            // rectangular tile set, write only n <= m + mask_shift
     int64_t mask_shift;        // with mask_lower: C's first row sits mask_shift rows below the diagonal
     const int32_t *stop_flag;  // if non-null and *stop_flag != 0 the kernel does nothing
-    // set by launch_gram for a planned launch: work entries with a piece
+    // set by launch_planned: work entries with a piece
     // index write their partial product (one of split_pieces K ranges) to
     // split_ws instead of C
     double *split_ws;
     int split_pieces;
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
-// Work plan of a large lower product with both operands contiguous along m
-// and n (the Gram [J | r]^T [J | r]; 128 x 128 tiles, four-wave workgroups,
-// two per CU).  plan_gram builds it once per order: tiles grouped in 4 x 8
-// super-tiles as in launch_dgemm, the groups dealt to the 8 XCDs so that
-// each gets the same number of tiles (entry b of the table runs on XCD
-// b % 8); on each XCD the tiles of its last, partly filled round of
-// resident workgroups are split into `pieces` K ranges that run side by
-// side, their partial products summed in a fixed order by a second launch.
-// Table entries: (unit, tile row, tile column, piece), unit -1 for a whole
-// tile, tile row -1 for padding; then one entry (first unit, tile row, tile
-// column, 0) per split tile for the summing launch.  Returns false (no plan:
-// launch_gram falls back to launch_dgemm) when the product does not take the
-// four-wave configuration or the device's CUs do not split evenly over XCDs.
-struct GramPlan {
-    int64_t M = 0;           // order of the product the plan is for (0: none)
+// Work plan of a large product with both operands contiguous along m and n
+// (128 x 128 tiles, four-wave workgroups, two per CU): the Gram
+// [J | r]^T [J | r] (lower, plan_gram) and the Hilbert coupling (M x N,
+// plan_rect), built once per shape.  Tiles are grouped in 4 x 8 super-tiles
+// as in launch_dgemm, the groups dealt to the 8 XCDs so that each gets the
+// same number of tiles (entry b of the table runs on XCD b % 8); on each XCD
+// the tiles of its last, partly filled round of resident workgroups are
+// split into `pieces` K ranges that run side by side, their partial products
+// summed in a fixed order by a second launch.  Table entries: (unit, tile
+// row, tile column, piece), unit -1 for a whole tile, tile row -1 for
+// padding; then one entry (first unit, tile row, tile column, 0) per split
+// tile for the summing launch.  Returns false (no plan: launch_planned falls
+// back to launch_dgemm) when the product does not take the four-wave
+// configuration or the device's CUs do not split evenly over XCDs.
+struct TilePlan {
+    int64_t M = 0, N = 0;    // shape of the product the plan is for (M = 0: none)
+    bool lower = false;      // lower-triangular tile set (M == N)
     int64_t nwork = 0;       // entries of the product launch
     int nsplit = 0;          // split tiles (entries of the summing launch)
     int pieces = 1;          // K ranges per split tile
@@ -202,10 +204,11 @@ struct GramPlan {
     double *ws = nullptr;    // nsplit * pieces partial 128 x 128 tiles (device)
 };
 bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces);
+bool plan_rect(int64_t M, int64_t N, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces);
 int64_t gram_plan_ws_doubles(int nsplit, int pieces);
-// The lower product g on plan p when p was built for g's order and layout,
-// else launch_dgemm(st, g).
-hipError_t launch_gram(hipStream_t st, const GemmDesc &g, const GramPlan &p);
+// The product g on plan p when p was built for g's shape and layout, else
+// launch_dgemm(st, g).
+hipError_t launch_planned(hipStream_t st, const GemmDesc &g, const TilePlan &p);
 // FP64 matrix-instruction throughput probe: cus x 8 workgroups of four waves,
 // each wave iters rounds of 8 independent v_mfma_f64_16x16x4f64 chains;
 // *flops (if not NULL) receives the flop count.

@@ -117,7 +117,7 @@ __host__ __device__ inline int64_t gram_piece_k(int64_t K, int pieces, int bk) {
     return (q + bk - 1) / bk * bk;
 }
 
-// PLAN: the planned Gram (launch_gram); a compile-time switch, so that the
+// PLAN: a planned product (launch_planned); a compile-time switch, so that the
 // other instances carry none of its code.
 template <int BM, int BN, int BK, int LA, int LB, bool BATCH, int NT, bool PLAN = false>
 __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, int tiles_m0, int tiles_n0, int sup0,
@@ -417,37 +417,41 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
     return launch_tiles<64, 64, 32, false>(st, g, b, tm, tn, nullptr, nullptr);
 }
 
-// ------------------------------------------------------------ planned Gram
+// ------------------------------------------------------ planned products
 static constexpr int GRAM_T = 128;   // tile of the planned Gram (four-wave configuration)
 static constexpr int GRAM_BK = 16;
 static constexpr int GRAM_MAX_PIECES = 4;
 
 int64_t gram_plan_ws_doubles(int nsplit, int pieces) { return (int64_t)nsplit * pieces * GRAM_T * GRAM_T; }
 
-bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces) {
+static bool plan_tiles(int64_t M, int64_t N, bool lower, int cus, std::vector<int4> &table, int64_t &nwork,
+                       int &nsplit, int &pieces) {
     table.clear();
     nwork = 0;
     nsplit = 0;
     pieces = 1;
-    const int64_t tiles = (M + GRAM_T - 1) / GRAM_T;
+    const int64_t tiles_m = (M + GRAM_T - 1) / GRAM_T, tiles_n = lower ? tiles_m : (N + GRAM_T - 1) / GRAM_T;
+    if (M <= 0 || N <= 0 || (lower && M != N) || tiles_m > (1 << 30) || tiles_n > (1 << 30)) return false;
     // the products launch_dgemm gives to the four-wave configuration
-    if (M <= 0 || tiles * (tiles + 1) / 2 < 2 * 256 || tiles > (1 << 30)) return false;
+    const int64_t ntiles = lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+    if (ntiles < 2 * 256 || (!lower && N <= 64)) return false;
     if (cus <= 0 || cus % NXCD != 0) return false;
     const int64_t slots = 2 * (int64_t)(cus / NXCD);  // resident workgroups per XCD
     // 4 x 8 super-tiles in the order of tile_of_block (rows of super-tiles,
     // tiles column by column inside one), each dealt whole to the XCD with
     // the fewest tiles so far
     std::vector<std::vector<int4>> per(NXCD);
-    const int64_t nsr = (tiles + SUP_M - 1) / SUP_M, nsc = (tiles + SUP_N - 1) / SUP_N;
+    const int64_t nsr = (tiles_m + SUP_M - 1) / SUP_M, nsc = (tiles_n + SUP_N - 1) / SUP_N;
     for (int64_t a = 0; a < nsr; ++a) {
-        const int64_t c = std::min((SUP_M * a + SUP_M - 1) / SUP_N + 1, nsc);
+        const int64_t c = lower ? std::min((SUP_M * a + SUP_M - 1) / SUP_N + 1, nsc) : nsc;
         for (int64_t b = 0; b < c; ++b) {
             int x = 0;
             for (int k = 1; k < NXCD; ++k)
                 if (per[k].size() < per[x].size()) x = k;
             for (int i = 0; i < SUP; ++i) {
                 const int64_t tm = a * SUP_M + i % SUP_M, tn = b * SUP_N + i / SUP_M;
-                if (tm < tiles && tn <= tm) per[x].push_back(make_int4(-1, (int)tm, (int)tn, 0));
+                if (tm < tiles_m && tn < tiles_n && (!lower || tn <= tm))
+                    per[x].push_back(make_int4(-1, (int)tm, (int)tn, 0));
             }
         }
     }
@@ -497,27 +501,48 @@ bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int
     return true;
 }
 
-// C = beta C + (sum of the pieces of each split tile, in piece order), lower
-// part only; one workgroup per split tile.
+bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces) {
+    return plan_tiles(M, M, true, cus, table, nwork, nsplit, pieces);
+}
+
+bool plan_rect(int64_t M, int64_t N, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces) {
+    return plan_tiles(M, N, false, cus, table, nwork, nsplit, pieces);
+}
+
+// C = beta C + (sum of the pieces of each split tile, in piece order), the
+// lower part only for a lower product.  Each split tile is summed by
+// GRAM_T / SUM_ROWS workgroups of SUM_ROWS rows, every thread issuing the
+// loads of all its entries of a piece before adding them.
+static constexpr int SUM_ROWS = 16;
 __global__ __launch_bounds__(256) void gram_sum_kernel(GemmDesc g, const int4 *__restrict__ tiles) {
     if (g.stop_flag != nullptr && *g.stop_flag != 0) return;
-    const int4 t = tiles[blockIdx.x];
-    constexpr int T = GRAM_T;
+    constexpr int T = GRAM_T, PARTS = T / SUM_ROWS, PER = SUM_ROWS * T / 256;
+    const int4 t = tiles[blockIdx.x / PARTS];
+    const int base = (blockIdx.x % PARTS) * SUM_ROWS * T + threadIdx.x;  // entry of the tile, row-major
     const double *W = g.split_ws + (int64_t)t.x * (T * T);
-    const int64_t m0 = (int64_t)t.y * T, n0 = (int64_t)t.z * T;
-    for (int e = threadIdx.x; e < T * T; e += 256) {
-        const int64_t gm = m0 + e / T, gn_ = n0 + e % T;
-        if (gm >= g.M || gn_ >= g.N || gn_ > gm + g.mask_shift) continue;
-        double v = W[e];
-        for (int q = 1; q < g.split_pieces; ++q) v += W[(int64_t)q * (T * T) + e];
+    double v[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) v[e] = W[base + e * 256];
+    for (int q = 1; q < g.split_pieces; ++q) {
+        double w[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) w[e] = W[(int64_t)q * (T * T) + base + e * 256];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) v[e] += w[e];
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int idx = base + e * 256;
+        const int64_t gm = (int64_t)t.y * T + idx / T, gn_ = (int64_t)t.z * T + idx % T;
+        if (gm >= g.M || gn_ >= g.N || (g.lower && gn_ > gm)) continue;
         double *c = g.C + gm * g.ldc + gn_;
-        *c = g.beta == 0.0 ? v : fma(g.beta, *c, v);
+        *c = g.beta == 0.0 ? v[e] : fma(g.beta, *c, v[e]);
     }
 }
 
-hipError_t launch_gram(hipStream_t st, const GemmDesc &g, const GramPlan &p) {
-    if (p.M <= 0 || p.d_work == nullptr || p.nwork <= 0 || g.M != p.M || g.N != p.M || !g.lower || g.la != 1 ||
-        g.lb != 0 || g.mask_shift != 0 || g.C == g.A || g.C == g.B)
+hipError_t launch_planned(hipStream_t st, const GemmDesc &g, const TilePlan &p) {
+    if (p.M <= 0 || p.d_work == nullptr || p.nwork <= 0 || g.M != p.M || g.N != p.N || (g.lower != 0) != p.lower ||
+        g.la != 1 || g.lb != 0 || g.mask_lower || g.mask_shift != 0 || g.C == g.A || g.C == g.B)
         return launch_dgemm(st, g);
     if (p.nsplit > 0 && (p.ws == nullptr || p.pieces < 2)) return hipErrorInvalidValue;
     GemmDesc q = g;
@@ -525,7 +550,8 @@ hipError_t launch_gram(hipStream_t st, const GemmDesc &g, const GramPlan &p) {
     q.split_pieces = p.pieces;
     hipError_t e = launch_one<GRAM_T, GRAM_T, GRAM_BK, 1, 0, false, 256, true>(st, q, 0, 0, p.nwork, nullptr, p.d_work);
     if (e != hipSuccess || p.nsplit == 0) return e;
-    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)p.nsplit), dim3(256), 0, st, q, p.d_work + p.nwork);
+    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)(p.nsplit * (GRAM_T / SUM_ROWS))), dim3(256), 0, st, q,
+                       p.d_work + p.nwork);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
-// Host check of the Gram work plan (plan_gram): for many orders and CU counts,
-// every lower 128 x 128 tile appears once, either whole or as all of its
-// pieces; piece units are distinct and in range; the summing entries name the
+// Host check of the work plans of the Gram (plan_gram, lower tiles) and of
+// the Hilbert coupling (plan_rect, all tiles of an M x N product): for many
+// shapes and CU counts, every 128 x 128 tile of the product appears once,
+// either whole or as all of its pieces; piece units are distinct and in range; the summing entries name the
 // split tiles; per-XCD counts of whole tiles differ by at most one; on every
 // XCD the pieces fit in one round of resident workgroups.  Exit status 0 when
 // all hold.  Pure host code: no device is touched.
@@ -16,16 +17,30 @@
 
 int main() {
     int bad = 0, plans = 0, split = 0;
-    const long orders[] = {1154, 3842, 3969, 4097, 4223, 4548, 4850, 5000, 8514, 9000, 12000, 12738, 16385, 20001, 50308};
-    for (long M : orders) {
+    struct Shape { long M, N; bool lower; };
+    std::vector<Shape> shapes;
+    for (long M : {1154L, 3842L, 3969L, 4097L, 4223L, 4548L, 4850L, 5000L, 8514L, 9000L, 12000L, 12738L, 16385L, 20001L,
+                   50308L})
+        shapes.push_back({M, M, true});
+    // Hilbert coupling shapes (collocation points x parameters), ragged edges
+    for (Shape r : {Shape{8192, 8513, false}, Shape{1024, 8513, false}, Shape{16384, 1153, false},
+                    Shape{6657, 1153, false}, Shape{1000, 8513, false}, Shape{4097, 4223, false}, Shape{300, 100, false},
+                    Shape{65536, 65, false}})
+        shapes.push_back(r);
+    for (const Shape &sh : shapes) {
+        const long M = sh.M;
         for (int cus : {256, 304, 240, 80, 8}) {
             std::vector<int4> t;
             int64_t nwork = 0;
             int nsplit = 0, pieces = 0;
-            const long tiles = (M + 127) / 128, lower = tiles * (tiles + 1) / 2;
-            if (!gn::plan_gram(M, cus, t, nwork, nsplit, pieces)) {
-                if (lower >= 512 && cus % 8 == 0) {
-                    printf("M %ld cus %d: no plan\n", M, cus);
+            const long tiles_m = (M + 127) / 128, tiles_n = sh.lower ? tiles_m : (sh.N + 127) / 128;
+            const long tiles = tiles_m;
+            const long lower = sh.lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+            const bool ok = sh.lower ? gn::plan_gram(M, cus, t, nwork, nsplit, pieces)
+                                     : gn::plan_rect(M, sh.N, cus, t, nwork, nsplit, pieces);
+            if (!ok) {
+                if (lower >= 512 && cus % 8 == 0 && (sh.lower || sh.N > 64)) {
+                    printf("M %ld N %ld cus %d: no plan\n", M, sh.N, cus);
                     ++bad;
                 }
                 continue;
@@ -39,7 +54,7 @@ int main() {
             for (long b = 0; b < nwork; ++b) {
                 const int4 e = t[b];
                 if (e.y < 0) continue;
-                if (e.y >= tiles || e.z < 0 || e.z > e.y) {
+                if (e.y >= tiles || e.z < 0 || e.z >= tiles_n || (sh.lower && e.z > e.y)) {
                     printf("M %ld: tile (%d, %d) outside the lower triangle\n", M, e.y, e.z);
                     ++bad;
                     continue;

@@ -1,7 +1,9 @@
-"""Invariants of the Gram work plan (plan_gram in csrc/k_dgemm.hip), checked
-on the host: tests/gram_plan_check.cpp is compiled against the built library
-and run for 15 orders and 5 CU counts.  Every lower tile appears once, whole
-or as all of its pieces; piece units are distinct and in range; the summing
+"""Invariants of the work plans of the Gram (plan_gram, lower tiles) and of
+the Hilbert coupling (plan_rect, every tile of an M x N product), both in
+csrc/k_dgemm.hip, checked on the host: tests/gram_plan_check.cpp is compiled
+against the built library and run for 15 Gram orders and 8 coupling shapes,
+each with 5 CU counts.  Every tile of the product appears once, whole or as
+all of its pieces; piece units are distinct and in range; the summing
 entries name the split tiles; the XCDs hold the same number of tiles to
 within one; the pieces of each XCD fit in one round of its resident
 workgroups.  Pure host code: no device is used."""
