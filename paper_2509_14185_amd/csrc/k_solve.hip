@@ -505,8 +505,8 @@ __global__ __launch_bounds__(256) void back_sync_kernel(const double *__restrict
 }
 
 // Forward substitution L z = b in one launch.  Workgroup w owns row block w:
-// it loads X_w into registers (in the staging order of block_lower_apply)
-// and, for I = 0 .. w-1, loads L_wI and puts it into an LDS tile before it
+// thread (row, half) keeps the entries X_w[row][half + 2j] in registers, the
+// ones its final sum needs, and, for I = 0 .. w-1, loads L_wI and puts it into an LDS tile before it
 // waits for z_I to be published, then subtracts L_wI z_I with the per-thread
 // sums of fwd_update_kernel (two threads per row, each summing every other
 // column in order) and finally forms z_w = X_w b_w in the order of
@@ -531,14 +531,9 @@ __global__ __launch_bounds__(256) void fwd_sync_kernel(const double *__restrict_
     const int64_t w0 = w * CB;
     const int kbw = (int)((n - w0) < CB ? (n - w0) : CB);
     const double *Xb = linv + w * CB * CB;
-    double xv[CB / KC][NE];
+    double xr[CB / 2];  // X_w[row][half + 2 j]
 #pragma unroll
-    for (int ch = 0; ch < CB / KC; ++ch)
-#pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC, k0 = ch * KC;
-            xv[ch][e] = (k0 < kbw && rr < kbw && k0 + kk < kbw) ? Xb[rr * CB + k0 + kk] : 0.0;
-        }
+    for (int j = 0; j < CB / 2; ++j) xr[j] = (row < kbw && half + 2 * j < kbw) ? Xb[row * CB + half + 2 * j] : 0.0;
     if (tid < kbw) bs[tid] = b[w0 + tid];
     for (int64_t I = 0; I < w; ++I) {
         const int64_t r0 = I * CB;  // block I < w is full
@@ -591,17 +586,12 @@ __global__ __launch_bounds__(256) void fwd_sync_kernel(const double *__restrict_
         __syncthreads();
         if (half == 0 && row < kbw) bs[row] = bs[row] - (part[row] + part[row + CB]);
     }
-    // z_w = X_w b_w (every read of the tile by the last block ended before its partial-sum barrier)
-#pragma unroll
-    for (int ch = 0; ch < CB / KC; ++ch)
-#pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            const int idx = tid + e * 256, rr = idx / KC, kk = idx % KC;
-            tile[rr * LD + ch * KC + kk] = xv[ch][e];
-        }
-    __syncthreads();  // the tile stored; bs final
+    // z_w = X_w b_w from the registers, the sums in the order of block_lower_apply
+    __syncthreads();  // bs final
     double acc = 0.0;
-    for (int kk = half; kk < kbw; kk += 2) acc = fma(tile[row * LD + kk], bs[kk], acc);
+#pragma unroll
+    for (int j = 0; j < CB / 2; ++j)
+        if (half + 2 * j < kbw) acc = fma(xr[j], bs[half + 2 * j], acc);
     part[tid] = acc;
     __syncthreads();
     if (half == 0 && row < kbw) {
