@@ -171,7 +171,10 @@ gn_status gn_set_stream(gn_handle h, void *stream);
  *                  GN_EQ_BURGERS1D).
  *   d_sval [n_val] validation grid in s (NULL with n_val = 0: none).
  * The library copies what it needs; caller buffers may be freed afterwards.
- * Allocates the per-step workspace (Jacobian, Gram, factor).  Synchronises.
+ * Allocates the per-step workspace (Jacobian, Gram, factor; for GN_EQ_CCF1D
+ * with at least 512 128 x 128 tiles in the n x P Hilbert coupling product,
+ * also that product's work plan: a tile table and at most 64 MB of partial
+ * tiles on 256 CUs).  Synchronises.
  * Errors: GN_EINVAL (n < 1, m_quad < 1 for CCF, null pointers), GN_ENOMEM.
  */
 gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double *d_rho,

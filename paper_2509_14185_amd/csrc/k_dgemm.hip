@@ -21,6 +21,11 @@
 // (16-byte pairs along the operand's contiguous direction, no bounds checks
 // for interior tiles) are issued before the MFMAs of chunk c.
 // Tiles are grouped in 4 x 8 super-tiles, one per XCD at a time (L2 reuse).
+// The Gram and the Hilbert coupling run on work plans built once per shape
+// (plan_gram, plan_rect): the super-tiles dealt so that every XCD holds the
+// same number of tiles, and the tiles of each XCD's last, partly filled round
+// split into K ranges whose partial products gram_sum_kernel adds in a fixed
+// order.  Workgroup b runs on XCD b % 8 and each XCD takes its share in order.
 //
 // Fragment layout of v_mfma_f64_16x16x4_f64 (wave64):
 //   A (16x4):  lane l holds A[l%16][l/16]
@@ -125,7 +130,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void dgemm_mfma_kernel(GemmDesc g0, i
                                                                  const int4 *__restrict__ work) {
     static_assert(!(BATCH && PLAN), "one table kind per instance");
     // batched launches read (problem, tile row, tile column) from a work table
-    // laid out in dispatch order (entry b runs on XCD b % 8); a planned Gram
+    // laid out in dispatch order (entry b runs on XCD b % 8); a planned product
     // reads (unit, tile row, tile column, piece)
     int4 wi = make_int4(0, 0, 0, 0);
     if (BATCH || PLAN) {
@@ -418,7 +423,7 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
 }
 
 // ------------------------------------------------------ planned products
-static constexpr int GRAM_T = 128;   // tile of the planned Gram (four-wave configuration)
+static constexpr int GRAM_T = 128;   // tile of the planned products (four-wave configuration)
 static constexpr int GRAM_BK = 16;
 static constexpr int GRAM_MAX_PIECES = 4;
 
