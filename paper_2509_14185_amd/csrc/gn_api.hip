@@ -1917,12 +1917,28 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
     }
     // batched Hilbert coupling, Gram, bordered Cholesky, back substitution and update
     bmark(GN_PHASE_JLOCAL);  // the local rows are timed with the forward phase
+    // The tail products (the coupling's last column, the bordered Gram's last
+    // rows: memory-bound, on their own tile shapes) run on a lane beside the
+    // main products; their outputs are disjoint from the main ones and both
+    // read inputs complete before the fork.
+    auto beside = [&](const BatchedGemmPlan &main, const BatchedGemmPlan &tail) -> gn_status {
+        if (tail.h_work.empty() || nl == 0) {
+            GN_HIP(h0, launch_batched_plan(st, main));
+            GN_HIP(h0, launch_batched_plan(st, tail));
+            return GN_OK;
+        }
+        GN_HIP(h0, hipEventRecord(b->fork, st));
+        GN_HIP(h0, hipStreamWaitEvent(b->lanes[0], b->fork, 0));
+        GN_HIP(h0, launch_batched_plan(b->lanes[0], tail));
+        GN_HIP(h0, launch_batched_plan(st, main));
+        GN_HIP(h0, hipEventRecord(b->join[0], b->lanes[0]));
+        GN_HIP(h0, hipStreamWaitEvent(st, b->join[0], 0));
+        return GN_OK;
+    };
     bmark(GN_PHASE_COUPLING);
-    GN_HIP(h0, launch_batched_plan(st, b->coupling));
-    GN_HIP(h0, launch_batched_plan(st, b->coupling_tail));
+    GN_TRY(beside(b->coupling, b->coupling_tail));
     bmark(GN_PHASE_GRAM);
-    GN_HIP(h0, launch_batched_plan(st, b->gram));
-    GN_HIP(h0, launch_batched_plan(st, b->gram_tail));
+    GN_TRY(beside(b->gram, b->gram_tail));
     bmark(GN_PHASE_CHOLESKY);
     GN_HIP(h0, launch_cholesky_batched(st, b->h_bc.data(), b->d_bc, b->chol, n, P + 1, mu, 1));
     bmark(GN_PHASE_SOLVE);
