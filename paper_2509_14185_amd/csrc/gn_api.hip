@@ -701,7 +701,8 @@ gn_status gn_create(const gn_problem *prob, gn_handle *out) {
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_dots, DOT_MAX);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->r1_work, dots_work_size());
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gdiag, h->cap);
-    if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->gemv_work, gemv_t_work_size(0, h->cap));
+    if (s == GN_OK)
+        s = dev_alloc(h, h->allocs, &h->gemv_work, std::max(gemv_t_work_size(0, h->cap), gemv_t2_work_size(h->cap)));
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->red_work, 1024);
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->chol_tmp, chol_tmp_size());
     if (s == GN_OK) s = dev_alloc(h, h->allocs, &h->one_x, 1);
@@ -838,7 +839,7 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->Q, m_quad * h->ldQ);
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_t, 2 * n);
     if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_z, 2 * m_quad);
-    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_work, gemv_t_work_size(m_quad, n));
+    if (s == GN_OK && m_quad > 0) s = dev_alloc(h, A, &h->cp_work, gemv_t2_work_size(n));
     if (s == GN_OK && m_quad > 0 && h->equation == GN_EQ_CCF1D) s = tile_plan_alloc(h, A, n, P, false, &h->cplan);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_pts, 2 * n);
     if (s == GN_OK) s = dev_alloc(h, A, &h->nn_nodes, 2 * m_quad);
@@ -1321,14 +1322,12 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     GN_TRY(form_jacobian(h, d_theta, !implicit));
     // g = J^T r, u = J^T v
     GN_HIP(h, launch_copy_strided(st, J + P, m_rows, ldJ, h->r_tmp, 1, 1.0));
-    GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, h->r_tmp, h->r1_g, h->gemv_work));
-    GN_HIP(h, launch_gemv_t(st, J, m_rows, P, ldJ, d_v, h->r1_u, h->gemv_work));
+    GN_HIP(h, launch_gemv_t2(st, J, m_rows, P, ldJ, h->r_tmp, d_v, h->r1_g, h->r1_u, h->gemv_work, 0));
     if (implicit) {
         double *t1 = h->cp_t, *t2 = h->cp_t + nc, *z1 = h->cp_z, *z2 = h->cp_z + mq;
         GN_HIP(h, launch_diag_scale2(st, nc, h->cscale, h->r_tmp, d_v, t1, t2, 0));
         GN_HIP(h, launch_gemv_n2(st, h->Q, mq, nc, h->ldQ, t1, t2, z1, z2));
-        GN_HIP(h, launch_gemv_t(st, h->Bm, mq, P, ldJ, z1, h->r1_g, h->gemv_work, 1));
-        GN_HIP(h, launch_gemv_t(st, h->Bm, mq, P, ldJ, z2, h->r1_u, h->gemv_work, 1));
+        GN_HIP(h, launch_gemv_t2(st, h->Bm, mq, P, ldJ, z1, z2, h->r1_g, h->r1_u, h->gemv_work, 1));
     }
     GN_HIP(h, launch_ema_rank1(st, d_G_ema, P, ldG, a->beta, h->r1_u));
     if (a->refactor) {
@@ -1344,8 +1343,7 @@ gn_status gn_step_rank1(gn_handle h, double *d_theta, double *d_G_ema, int64_t l
     if (implicit) {
         double *y1 = h->cp_z, *y2 = h->cp_z + mq, *s1 = h->cp_t, *s2 = h->cp_t + nc;
         GN_HIP(h, launch_gemv_n2(st, h->Bm, mq, P, ldJ, h->r1_D, d_prev, y1, y2));
-        GN_HIP(h, launch_gemv_t(st, h->Q, mq, nc, h->ldQ, y1, s1, h->cp_work));
-        GN_HIP(h, launch_gemv_t(st, h->Q, mq, nc, h->ldQ, y2, s2, h->cp_work));
+        GN_HIP(h, launch_gemv_t2(st, h->Q, mq, nc, h->ldQ, y1, y2, s1, s2, h->cp_work, 0));
         GN_HIP(h, launch_diag_scale2(st, nc, h->cscale, s1, s2, h->r1_w1, h->r1_w2, 1));
     }
     DotPairs dp{};

@@ -438,6 +438,11 @@ struct DotPairs {
 hipError_t launch_dots(hipStream_t st, const DotPairs &d, int64_t n, double *out, double *work);
 int64_t dots_work_size();
 // delta = alpha D + mu prev (over prev), theta += delta.
+// g1 = J^T r1, g2 = J^T r2 (accumulate: g += ...) in one pass over J, each
+// bitwise equal to launch_gemv_t's result; work holds gemv_t2_work_size(p).
+int64_t gemv_t2_work_size(int64_t p);
+hipError_t launch_gemv_t2(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, const double *r1,
+                          const double *r2, double *g1, double *g2, double *work, int accumulate);
 // y_k = cs o x_k (accumulate = 0) or y_k += cs o x_k, k = 1, 2, over n entries.
 hipError_t launch_diag_scale2(hipStream_t st, int64_t n, const double *cs, const double *x1, const double *x2,
                               double *y1, double *y2, int accumulate);

@@ -131,6 +131,54 @@ hipError_t launch_dots(hipStream_t st, const DotPairs &d, int64_t n, double *out
 
 int64_t dots_work_size() { return (int64_t)DOT_MAX * DOT_BLOCKS; }
 
+// g1 = J^T r1 and g2 = J^T r2 (accumulate: added to g1, g2) in one pass over
+// the row-major m x p matrix J: for each vector the partial sums over 64 row
+// chunks and their final sum are those of launch_gemv_t (same chunks, same
+// order), so the results are bitwise the same as two such calls.
+constexpr int GEMV2_CHUNKS = 64;
+
+int64_t gemv_t2_work_size(int64_t p) { return (int64_t)2 * GEMV2_CHUNKS * p; }
+
+__global__ void gemv_t2_partial(const double *__restrict__ J, int64_t m, int64_t p, int64_t ldj,
+                                const double *__restrict__ r1, const double *__restrict__ r2,
+                                double *__restrict__ work) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p) return;
+    const int64_t per = (m + GEMV2_CHUNKS - 1) / GEMV2_CHUNKS;
+    const int64_t i0 = blockIdx.y * per;
+    const int64_t i1 = (i0 + per < m) ? i0 + per : m;
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double v = J[i * ldj + c];
+        a1 = fma(v, r1[i], a1);
+        a2 = fma(v, r2[i], a2);
+    }
+    work[blockIdx.y * p + c] = a1;
+    work[(GEMV2_CHUNKS + blockIdx.y) * p + c] = a2;
+}
+
+__global__ void gemv_t2_final(const double *__restrict__ work, int64_t p, double *g1, double *g2, int accumulate) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < GEMV2_CHUNKS; ++k) {
+        s1 += work[k * p + c];
+        s2 += work[(GEMV2_CHUNKS + k) * p + c];
+    }
+    g1[c] = accumulate ? g1[c] + s1 : s1;
+    g2[c] = accumulate ? g2[c] + s2 : s2;
+}
+
+hipError_t launch_gemv_t2(hipStream_t st, const double *J, int64_t m, int64_t p, int64_t ldj, const double *r1,
+                          const double *r2, double *g1, double *g2, double *work, int accumulate) {
+    if (p <= 0) return hipSuccess;
+    dim3 g((unsigned)((p + 255) / 256), GEMV2_CHUNKS);
+    hipLaunchKernelGGL(gemv_t2_partial, g, dim3(256), 0, st, J, m, p, ldj, r1, r2, work);
+    hipLaunchKernelGGL(gemv_t2_final, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, work, p, g1, g2,
+                       accumulate);
+    return hipGetLastError();
+}
+
 // y_k = cs o x_k (accumulate = 0) or y_k += cs o x_k, k = 1, 2, over n
 // entries: the row scale of the Hilbert coupling applied to two vectors.
 __global__ void diag_scale2_kernel(int64_t n, const double *__restrict__ cs, const double *__restrict__ x1,
