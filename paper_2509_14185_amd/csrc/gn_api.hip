@@ -51,8 +51,8 @@ struct gn_context {
     double *vseed0 = nullptr, *vseed1 = nullptr, *useed = nullptr;
     double *J = nullptr, *Bm = nullptr, *G = nullptr, *partial = nullptr;
     // the stochastic step's Hilbert coupling applied through products (1D CCF):
-    // two n-vectors, two m-vectors, and the partial sums of a transposed
-    // product over n columns
+    // two n-vectors, two m-vectors, and the partial sums of a paired
+    // transposed product over n columns
     double *cp_t = nullptr, *cp_z = nullptr, *cp_work = nullptr;
     float *Jhi = nullptr, *Jlo = nullptr;   // split-precision parts of J (GN_SPLIT32)
     ModgramWork mg{};                        // int8 residue workspaces (GN_INT8_CRT)
@@ -476,8 +476,6 @@ gn_status jac_rows2d(gn_handle h, const double *theta, int64_t row0, int64_t nro
     return GN_OK;
 }
 
-// Work plan of the FP64 Gram of order P + 1 (tiles balanced over the XCDs,
-// the last round's tiles split along K), with its partial-tile workspace.
 // The device copies of a work plan (table and partial-tile workspace) into
 // *out, or *out left empty when the product takes no plan.
 gn_status tile_plan_alloc(gn_handle h, std::vector<void *> &A, int64_t M, int64_t N, bool lower, TilePlan *out) {
@@ -500,6 +498,8 @@ gn_status tile_plan_alloc(gn_handle h, std::vector<void *> &A, int64_t M, int64_
     return GN_OK;
 }
 
+// Work plan of the FP64 Gram of order P + 1 (tiles balanced over the XCDs,
+// the last round's tiles split along K), with its partial-tile workspace.
 gn_status gram_plan_alloc(gn_handle h, std::vector<void *> &A) {
     h->gplan = TilePlan{};
     if (h->precision != GN_FP64) return GN_OK;
@@ -1927,10 +1927,13 @@ gn_status gn_step_batched(gn_batch b, double *const *d_thetas, double mu, gn_sta
         }
         GN_HIP(h0, hipEventRecord(b->fork, st));
         GN_HIP(h0, hipStreamWaitEvent(b->lanes[0], b->fork, 0));
-        GN_HIP(h0, launch_batched_plan(b->lanes[0], tail));
-        GN_HIP(h0, launch_batched_plan(st, main));
+        // the join is recorded whatever the launches return, so st never runs ahead of the lane
+        hipError_t e = launch_batched_plan(b->lanes[0], tail);
+        const hipError_t e2 = launch_batched_plan(st, main);
+        if (e == hipSuccess) e = e2;
         GN_HIP(h0, hipEventRecord(b->join[0], b->lanes[0]));
         GN_HIP(h0, hipStreamWaitEvent(st, b->join[0], 0));
+        GN_HIP(h0, e);
         return GN_OK;
     };
     bmark(GN_PHASE_COUPLING);
