@@ -657,7 +657,8 @@ def small_bench(mu=None):
         "max_abs_R_val_initial": ev0["max_abs_R_val"],
         "max_abs_R_val_final": ev1["max_abs_R_val"],
         "phase_ms_per_step": {k: v / nrec for k, v in phases.items()},
-        "roofline": {"bound": "mfma", "kernel": "gram (dgemm_mfma_kernel<64,64,32,1,0,false,512>)",
+        "roofline": {"bound": "mfma", "kernel": ("gram (dgemm_mfma_kernel<64,64,32,1,0,false,512> on the XCD-balanced "
+                                                    "work plan, then gram_sum_kernel over the tiles split along K)"),
                      "achieved": fl["gram"] / t_gram / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": fl["gram"] / t_gram / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
         "gram_cholesky_frac": (fl["gram"] + fl["cholesky"]) / (t_gram + t_chol) / 1e12 / PEAK_FP64_TFLOPS,

@@ -488,11 +488,11 @@ gn_status tile_plan_alloc(gn_handle h, std::vector<void *> &A, int64_t M, int64_
     p.M = M;
     p.N = N;
     p.lower = lower;
-    const bool ok = lower ? plan_gram(M, cus, t, p.nwork, p.nsplit, p.pieces)
-                          : plan_rect(M, N, cus, t, p.nwork, p.nsplit, p.pieces);
+    const bool ok = lower ? plan_gram(M, cus, t, p.nwork, p.nsplit, p.pieces, p.tile)
+                          : plan_rect(M, N, cus, t, p.nwork, p.nsplit, p.pieces, p.tile);
     if (!ok) return GN_OK;
     GN_TRY(dev_alloc(h, A, &p.d_work, (int64_t)t.size()));
-    if (p.nsplit > 0) GN_TRY(dev_alloc(h, A, &p.ws, gram_plan_ws_doubles(p.nsplit, p.pieces)));
+    if (p.nsplit > 0) GN_TRY(dev_alloc(h, A, &p.ws, gram_plan_ws_doubles(p.nsplit, p.pieces, p.tile)));
     GN_HIP(h, hipMemcpy(p.d_work, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
     *out = p;
     return GN_OK;

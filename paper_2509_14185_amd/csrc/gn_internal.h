@@ -180,14 +180,16 @@ struct GemmDesc {
     int split_pieces;
 };
 hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
-// Work plan of a large product with both operands contiguous along m and n
-// (128 x 128 tiles, four-wave workgroups, two per CU): the Gram
-// [J | r]^T [J | r] (lower, plan_gram) and the Hilbert coupling (M x N,
-// plan_rect), built once per shape.  Tiles are grouped in 4 x 8 super-tiles
-// as in launch_dgemm, the groups dealt to the 8 XCDs so that each gets the
-// same number of tiles (entry b of the table runs on XCD b % 8); on each XCD
-// the tiles of its last, partly filled round of resident workgroups are
-// split into `pieces` K ranges that run side by side, their partial products
+// Work plan of a product with both operands contiguous along m and n: the
+// Gram [J | r]^T [J | r] (lower, plan_gram) and the Hilbert coupling (M x N,
+// plan_rect), built once per shape, on the tile shape launch_dgemm would use
+// (128 x 128 tiles on four-wave workgroups for large products, 64 x 64 on
+// eight-wave ones for small ones; two workgroups per CU either way).  Tiles
+// are grouped in 4 x 8 super-tiles as in launch_dgemm, the groups dealt to
+// the 8 XCDs so that each gets the same number of tiles (entry b of the table
+// runs on XCD b % 8); on each XCD the tiles of its last, partly filled round
+// of resident workgroups are split into `pieces` K ranges (the count that
+// makes the slowest XCD's last round shortest), their partial products
 // summed in a fixed order by a second launch.  Table entries: (unit, tile
 // row, tile column, piece), unit -1 for a whole tile, tile row -1 for
 // padding; then one entry (first unit, tile row, tile column, 0) per split
@@ -197,15 +199,18 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g);
 struct TilePlan {
     int64_t M = 0, N = 0;    // shape of the product the plan is for (M = 0: none)
     bool lower = false;      // lower-triangular tile set (M == N)
+    int tile = 128;          // tile edge: 128 or 64
     int64_t nwork = 0;       // entries of the product launch
     int nsplit = 0;          // split tiles (entries of the summing launch)
     int pieces = 1;          // K ranges per split tile
     int4 *d_work = nullptr;  // nwork + nsplit entries (device)
-    double *ws = nullptr;    // nsplit * pieces partial 128 x 128 tiles (device)
+    double *ws = nullptr;    // nsplit * pieces partial tile x tile tiles (device)
 };
-bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces);
-bool plan_rect(int64_t M, int64_t N, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces);
-int64_t gram_plan_ws_doubles(int nsplit, int pieces);
+int plan_tile_size(int64_t M, int64_t N, bool lower);
+bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces, int &tile);
+bool plan_rect(int64_t M, int64_t N, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces,
+               int &tile);
+int64_t gram_plan_ws_doubles(int nsplit, int pieces, int tile);
 // The product g on plan p when p was built for g's shape and layout, else
 // launch_dgemm(st, g).
 hipError_t launch_planned(hipStream_t st, const GemmDesc &g, const TilePlan &p);

@@ -423,23 +423,37 @@ hipError_t launch_dgemm(hipStream_t st, const GemmDesc &g) {
 }
 
 // ------------------------------------------------------ planned products
-static constexpr int GRAM_T = 128;   // tile of the planned products (four-wave configuration)
+// Two tile configurations take plans: 128 x 128 tiles on four-wave
+// workgroups (K chunks of 16) for the products launch_dgemm gives 128 x 128
+// tiles, and 64 x 64 tiles on eight-wave workgroups (K chunks of 32) for the
+// smaller ones it gives 64 x 64 tiles.  Both hold two workgroups per CU.
+static constexpr int GRAM_T = 128;
 static constexpr int GRAM_BK = 16;
+static constexpr int SMALL_T = 64;
+static constexpr int SMALL_BK = 32;
 static constexpr int GRAM_MAX_PIECES = 4;
 
-int64_t gram_plan_ws_doubles(int nsplit, int pieces) { return (int64_t)nsplit * pieces * GRAM_T * GRAM_T; }
+int plan_tile_size(int64_t M, int64_t N, bool lower) {
+    const int64_t a = (M + GRAM_T - 1) / GRAM_T, b = lower ? a : (N + GRAM_T - 1) / GRAM_T;
+    return (lower ? a * (a + 1) / 2 : a * b) >= 2 * 256 ? GRAM_T : SMALL_T;
+}
+
+int64_t gram_plan_ws_doubles(int nsplit, int pieces, int tile) { return (int64_t)nsplit * pieces * tile * tile; }
 
 static bool plan_tiles(int64_t M, int64_t N, bool lower, int cus, std::vector<int4> &table, int64_t &nwork,
-                       int &nsplit, int &pieces) {
+                       int &nsplit, int &pieces, int &tile) {
     table.clear();
     nwork = 0;
     nsplit = 0;
     pieces = 1;
-    const int64_t tiles_m = (M + GRAM_T - 1) / GRAM_T, tiles_n = lower ? tiles_m : (N + GRAM_T - 1) / GRAM_T;
+    tile = plan_tile_size(M, N, lower);
+    const int T = tile;
+    const int64_t tiles_m = (M + T - 1) / T, tiles_n = lower ? tiles_m : (N + T - 1) / T;
     if (M <= 0 || N <= 0 || (lower && M != N) || tiles_m > (1 << 30) || tiles_n > (1 << 30)) return false;
-    // the products launch_dgemm gives to the four-wave configuration
+    // the products launch_dgemm gives to these tile shapes: lower products, or
+    // rectangular ones wider than 64 columns; the smallest ones take no plan
     const int64_t ntiles = lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
-    if (ntiles < 2 * 256 || (!lower && N <= 64)) return false;
+    if ((!lower && N <= 64) || ntiles < 64) return false;
     if (cus <= 0 || cus % NXCD != 0) return false;
     const int64_t slots = 2 * (int64_t)(cus / NXCD);  // resident workgroups per XCD
     // 4 x 8 super-tiles in the order of tile_of_block (rows of super-tiles,
@@ -472,26 +486,37 @@ static bool plan_tiles(int64_t M, int64_t N, bool lower, int cus, std::vector<in
         per[lo].push_back(per[hi].back());
         per[hi].pop_back();
     }
-    // pieces: as many as the emptiest last round has room for (at most 4)
-    int pc = GRAM_MAX_PIECES;
+    // pieces: the count (1 to 4) that makes the slowest XCD's last round
+    // shortest, that round's r tiles becoming r * pieces units of 1 / pieces
+    // of a tile's time on the XCD's slots (the fewest pieces among equals)
+    int pc = 1;
     bool any = false;
-    for (int x = 0; x < NXCD; ++x) {
-        const int64_t r = (int64_t)per[x].size() % slots;
-        if (r == 0) continue;
-        any = true;
-        pc = (int)std::min<int64_t>(pc, slots / r);
+    double best = 0.0;
+    for (int q = 1; q <= GRAM_MAX_PIECES; ++q) {
+        double worst = 0.0;
+        for (int x = 0; x < NXCD; ++x) {
+            const int64_t r = (int64_t)per[x].size() % slots;
+            if (r == 0) continue;
+            any = true;
+            worst = std::max(worst, (double)((r * q + slots - 1) / slots) / q);
+        }
+        if (q == 1 || worst < best - 1e-9) {
+            best = worst;
+            pc = q;
+        }
     }
     std::vector<int4> fix;
     if (any && pc >= 2) {
         pieces = pc;
         for (int x = 0; x < NXCD; ++x) {
             const int64_t n = (int64_t)per[x].size(), r = n % slots;
+            per[x].reserve((size_t)(n + r * (pieces - 1)));
             for (int64_t i = n - r; i < n; ++i) {
-                int4 &e = per[x][i];
-                const int unit = nsplit * pieces;
-                e.x = unit;
-                fix.push_back(make_int4(unit, e.y, e.z, 0));
-                for (int q = 1; q < pieces; ++q) per[x].push_back(make_int4(unit + q, e.y, e.z, q));
+                // copies: the appends below may move the list
+                const int unit = nsplit * pieces, tm = per[x][i].y, tn = per[x][i].z;
+                per[x][i].x = unit;
+                fix.push_back(make_int4(unit, tm, tn, 0));
+                for (int q = 1; q < pieces; ++q) per[x].push_back(make_int4(unit + q, tm, tn, q));
                 ++nsplit;
             }
         }
@@ -506,22 +531,24 @@ static bool plan_tiles(int64_t M, int64_t N, bool lower, int cus, std::vector<in
     return true;
 }
 
-bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces) {
-    return plan_tiles(M, M, true, cus, table, nwork, nsplit, pieces);
+bool plan_gram(int64_t M, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces, int &tile) {
+    return plan_tiles(M, M, true, cus, table, nwork, nsplit, pieces, tile);
 }
 
-bool plan_rect(int64_t M, int64_t N, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces) {
-    return plan_tiles(M, N, false, cus, table, nwork, nsplit, pieces);
+bool plan_rect(int64_t M, int64_t N, int cus, std::vector<int4> &table, int64_t &nwork, int &nsplit, int &pieces,
+               int &tile) {
+    return plan_tiles(M, N, false, cus, table, nwork, nsplit, pieces, tile);
 }
 
 // C = beta C + (sum of the pieces of each split tile, in piece order), the
 // lower part only for a lower product.  Each split tile is summed by
-// GRAM_T / SUM_ROWS workgroups of SUM_ROWS rows, every thread issuing the
+// T / SUM_ROWS workgroups of SUM_ROWS rows, every thread issuing the
 // loads of all its entries of a piece before adding them.
 static constexpr int SUM_ROWS = 16;
+template <int T>
 __global__ __launch_bounds__(256) void gram_sum_kernel(GemmDesc g, const int4 *__restrict__ tiles) {
     if (g.stop_flag != nullptr && *g.stop_flag != 0) return;
-    constexpr int T = GRAM_T, PARTS = T / SUM_ROWS, PER = SUM_ROWS * T / 256;
+    constexpr int PARTS = T / SUM_ROWS, PER = SUM_ROWS * T / 256;
     const int4 t = tiles[blockIdx.x / PARTS];
     const int base = (blockIdx.x % PARTS) * SUM_ROWS * T + threadIdx.x;  // entry of the tile, row-major
     const double *W = g.split_ws + (int64_t)t.x * (T * T);
@@ -550,13 +577,22 @@ hipError_t launch_planned(hipStream_t st, const GemmDesc &g, const TilePlan &p) 
         g.la != 1 || g.lb != 0 || g.mask_lower || g.mask_shift != 0 || g.C == g.A || g.C == g.B)
         return launch_dgemm(st, g);
     if (p.nsplit > 0 && (p.ws == nullptr || p.pieces < 2)) return hipErrorInvalidValue;
+    if (p.tile != GRAM_T && p.tile != SMALL_T) return hipErrorInvalidValue;
     GemmDesc q = g;
     q.split_ws = p.ws;
     q.split_pieces = p.pieces;
-    hipError_t e = launch_one<GRAM_T, GRAM_T, GRAM_BK, 1, 0, false, 256, true>(st, q, 0, 0, p.nwork, nullptr, p.d_work);
+    const bool big = p.tile == GRAM_T;
+    hipError_t e = big ? launch_one<GRAM_T, GRAM_T, GRAM_BK, 1, 0, false, 256, true>(st, q, 0, 0, p.nwork, nullptr,
+                                                                                      p.d_work)
+                       : launch_one<SMALL_T, SMALL_T, SMALL_BK, 1, 0, false, GEMM_THREADS, true>(st, q, 0, 0, p.nwork,
+                                                                                                 nullptr, p.d_work);
     if (e != hipSuccess || p.nsplit == 0) return e;
-    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)(p.nsplit * (GRAM_T / SUM_ROWS))), dim3(256), 0, st, q,
-                       p.d_work + p.nwork);
+    if (big)
+        hipLaunchKernelGGL(gram_sum_kernel<GRAM_T>, dim3((unsigned)(p.nsplit * (GRAM_T / SUM_ROWS))), dim3(256), 0, st,
+                           q, p.d_work + p.nwork);
+    else
+        hipLaunchKernelGGL(gram_sum_kernel<SMALL_T>, dim3((unsigned)(p.nsplit * (SMALL_T / SUM_ROWS))), dim3(256), 0,
+                           st, q, p.d_work + p.nwork);
     return hipGetLastError();
 }
 

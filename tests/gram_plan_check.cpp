@@ -1,10 +1,12 @@
 // Host check of the work plans of the Gram (plan_gram, lower tiles) and of
 // the Hilbert coupling (plan_rect, all tiles of an M x N product): for many
-// shapes and CU counts, every 128 x 128 tile of the product appears once,
-// either whole or as all of its pieces; piece units are distinct and in range; the summing entries name the
-// split tiles; per-XCD counts of whole tiles differ by at most one; on every
-// XCD the pieces fit in one round of resident workgroups.  Exit status 0 when
-// all hold.  Pure host code: no device is touched.
+// shapes and CU counts, on the tile size the plan chose (128, or 64 for small
+// products), every tile of the product appears once, either whole or as all of
+// its pieces; piece units are distinct and in range; the summing entries name
+// the split tiles; per-XCD tile counts differ by at most one; the split tiles
+// are those of each XCD's last round only (fewer than its slots), and the
+// split round takes no longer than leaving it whole.  Exit status 0 when all
+// hold.  Pure host code: no device is touched.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,31 +21,36 @@ int main() {
     int bad = 0, plans = 0, split = 0;
     struct Shape { long M, N; bool lower; };
     std::vector<Shape> shapes;
-    for (long M : {1154L, 3842L, 3969L, 4097L, 4223L, 4548L, 4850L, 5000L, 8514L, 9000L, 12000L, 12738L, 16385L, 20001L,
-                   50308L})
+    for (long M : {300L, 700L, 1154L, 2100L, 3842L, 3969L, 4097L, 4223L, 4548L, 4850L, 5000L, 8514L, 9000L, 12000L,
+                   12738L, 16385L, 20001L, 50308L})
         shapes.push_back({M, M, true});
     // Hilbert coupling shapes (collocation points x parameters), ragged edges
     for (Shape r : {Shape{8192, 8513, false}, Shape{1024, 8513, false}, Shape{16384, 1153, false},
                     Shape{6657, 1153, false}, Shape{1000, 8513, false}, Shape{4097, 4223, false}, Shape{300, 100, false},
-                    Shape{65536, 65, false}})
+                    Shape{65536, 65, false}, Shape{1024, 1153, false}, Shape{777, 321, false}})
         shapes.push_back(r);
     for (const Shape &sh : shapes) {
         const long M = sh.M;
         for (int cus : {256, 304, 240, 80, 8}) {
             std::vector<int4> t;
             int64_t nwork = 0;
-            int nsplit = 0, pieces = 0;
-            const long tiles_m = (M + 127) / 128, tiles_n = sh.lower ? tiles_m : (sh.N + 127) / 128;
+            int nsplit = 0, pieces = 0, T = 0;
+            const bool ok = sh.lower ? gn::plan_gram(M, cus, t, nwork, nsplit, pieces, T)
+                                     : gn::plan_rect(M, sh.N, cus, t, nwork, nsplit, pieces, T);
+            const int Tc = gn::plan_tile_size(M, sh.N, sh.lower);
+            const long tiles_m = (M + Tc - 1) / Tc, tiles_n = sh.lower ? tiles_m : (sh.N + Tc - 1) / Tc;
             const long tiles = tiles_m;
             const long lower = sh.lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
-            const bool ok = sh.lower ? gn::plan_gram(M, cus, t, nwork, nsplit, pieces)
-                                     : gn::plan_rect(M, sh.N, cus, t, nwork, nsplit, pieces);
             if (!ok) {
-                if (lower >= 512 && cus % 8 == 0 && (sh.lower || sh.N > 64)) {
+                if (lower >= 64 && cus % 8 == 0 && (sh.lower || sh.N > 64)) {
                     printf("M %ld N %ld cus %d: no plan\n", M, sh.N, cus);
                     ++bad;
                 }
                 continue;
+            }
+            if (T != Tc || (T != 128 && T != 64) || pieces < 1 || pieces > 4) {
+                printf("M %ld: tile %d (expected %d), pieces %d\n", M, T, Tc, pieces);
+                ++bad;
             }
             ++plans;
             split += nsplit > 0;
@@ -98,8 +105,12 @@ int main() {
                 const long tiles_x = whole_x[x] + piece_x[x] / std::max(pieces, 1);
                 lo = std::min(lo, tiles_x);
                 hi = std::max(hi, tiles_x);
-                if (piece_x[x] > slots) {
-                    printf("M %ld cus %d: %ld pieces on XCD %d, %ld slots\n", M, cus, piece_x[x], x, slots);
+                // the split tiles are the last round's: fewer than the slots, and the
+                // split round (units of 1 / pieces of a tile) no longer than one whole round
+                const long split_x = piece_x[x] / std::max(pieces, 1);
+                if (split_x >= slots || (pieces > 1 && (piece_x[x] + slots - 1) / slots > pieces)) {
+                    printf("M %ld cus %d: %ld split tiles (%ld pieces) on XCD %d, %ld slots\n", M, cus, split_x,
+                           piece_x[x], x, slots);
                     ++bad;
                 }
             }

@@ -199,7 +199,16 @@ def test_batch_stale_after_set_points():
 
 def test_full_batched_workload_sampled():
     """64 instances at full size: every instance against its own single-
-    instance step; the smallest instance against the oracle."""
+    instance step; the smallest instance against the oracle.
+
+    The single-instance Gram of order 1154 runs on a work plan of 64 x 64
+    tiles whose K range is split in two pieces, while the batched Gram sums
+    each tile over the whole K range: the two steps add in different orders,
+    so they agree to what their backward errors allow, not bitwise. If both
+    have normwise backward error at most eta = 5e-14 (the level the oracle
+    check asserts), then (G + mu I)(d1 - d2) is the difference of their
+    residuals, and with |(G + mu I)^-1| <= 1/mu (G is semidefinite)
+        |d1 - d2| <= eta / mu * ((|J|_F^2 + mu sqrt(P)) (|d1| + |d2|) + 2 |J|_F |r|)."""
     inps = workloads.make_batched_inputs()
     print(f"\n[gpu batch] full batch: {len(inps)} instances, N total {sum(x['n'] for x in inps)}", flush=True)
     pgs = [make_problem(x) for x in inps]
@@ -208,10 +217,17 @@ def test_full_batched_workload_sampled():
     ts = [dev(x["theta0"]) for x in inps]
     sts = b.step(ts, mu)
     assert all(s["rc"] == gn.GN_OK and s["updated"] == 1 for s in sts)
+    eta = 5e-14
     for inp, pg, t in zip(inps, pgs, ts):
         u = dev(inp["theta0"])
+        J, r = pg.jacobian(u)
+        nJ, nr = torch.linalg.norm(J).item(), torch.linalg.norm(r).item()
+        del J, r
         pg.step(u, mu)
-        assert rel(t.cpu().numpy(), u.cpu().numpy()) < 1e-12
+        d1, d2 = t.cpu().numpy() - inp["theta0"], u.cpu().numpy() - inp["theta0"]
+        n1, n2 = np.linalg.norm(d1), np.linalg.norm(d2)
+        bound = eta / mu * ((nJ * nJ + mu * np.sqrt(pg.P)) * (n1 + n2) + 2 * nJ * nr)
+        assert np.linalg.norm(d1 - d2) <= bound
     k = int(np.argmin([x["n"] for x in inps]))
     print(f"[gpu batch] oracle check of instance {k} (n={inps[k]['n']})", flush=True)
     check_against_oracle(inps[k], inps[k]["theta0"], ts[k].cpu().numpy(), sts[k], mu)

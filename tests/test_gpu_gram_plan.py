@@ -12,6 +12,9 @@ workgroups per XCD):
     per XCD; the last 6 or 7 on each XCD are split in 4 pieces;
   - P + 1 = 4850 ([1, 48, 48, 48, 1]): 38 tile rows, 741 tiles, 92 or 93 per
     XCD; the last 28 or 29 on each XCD are split in 2;
+  - P + 1 = 1154 ([1, 32, 32, 1]): too few 128-tiles for a plan (55), so the
+    plan takes 64 x 64 tiles (K step 32): 190 lower tiles, all in the one
+    round, each split in 2 pieces;
   - P + 1 = 4548 (2D, [2, 64, 64, 3]) with the rows in three chunks of at
     most 50: G is accumulated chunk by chunk, so the summing launch adds into
     C (beta = 1). A chunk of 50 rows has pieces of 32, 18 and 0 rows (an
@@ -49,7 +52,8 @@ def gamma(m):
     return m * u / (1 - m * u)
 
 
-@pytest.mark.parametrize("widths", [[1, 63, 63, 1], [1, 48, 48, 48, 1]], ids=["order4223_4pieces", "order4850_2pieces"])
+@pytest.mark.parametrize("widths", [[1, 63, 63, 1], [1, 48, 48, 48, 1], [1, 32, 32, 1]],
+                         ids=["order4223_4pieces", "order4850_2pieces", "order1154_tile64_2pieces"])
 def test_planned_gram_every_entry(widths):
     P = workloads.num_params(widths)
     pg = gn.Problem("ccf1d", widths, 0.6057)
