@@ -146,10 +146,10 @@ const char *gn_status_string(int32_t status);
 const char *gn_last_error(gn_handle h);
 
 /* Create a handle for one problem on the current HIP device.  Copies *prob
- * (including widths).  With GN_FP64 and a Gram of order P + 1 large enough
- * for 128 x 128 tiles (P + 1 above about 4000), the handle also keeps the
- * Gram's work plan: a tile table and at most one 128 x 128 partial tile per
- * resident workgroup (64 MB on 256 CUs).  Errors: GN_EINVAL for bad widths
+ * (including widths).  With GN_FP64 and a Gram of order P + 1 of at least
+ * 64 lower tiles (128 x 128 tiles from 512 of them, P + 1 above about 4000;
+ * else 64 x 64), the handle also keeps the Gram's work plan: a tile table
+ * and at most one partial tile per resident workgroup (64 MB on 256 CUs).  Errors: GN_EINVAL for bad widths
  * (first/last != 1, hidden width > GN_MAX_WIDTH, L out of range), lam <= 0,
  * c_norm < 0; GN_ENOMEM. */
 gn_status gn_create(const gn_problem *prob, gn_handle *out);
@@ -172,9 +172,9 @@ gn_status gn_set_stream(gn_handle h, void *stream);
  *   d_sval [n_val] validation grid in s (NULL with n_val = 0: none).
  * The library copies what it needs; caller buffers may be freed afterwards.
  * Allocates the per-step workspace (Jacobian, Gram, factor; for GN_EQ_CCF1D
- * with at least 512 128 x 128 tiles in the n x P Hilbert coupling product,
- * also that product's work plan: a tile table and at most 64 MB of partial
- * tiles on 256 CUs).  Synchronises.
+ * with at least 64 tiles in the n x P Hilbert coupling product (128 x 128
+ * tiles from 512 of them, else 64 x 64), also that product's work plan: a
+ * tile table and at most 64 MB of partial tiles on 256 CUs).  Synchronises.
  * Errors: GN_EINVAL (n < 1, m_quad < 1 for CCF, null pointers), GN_ENOMEM.
  */
 gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double *d_rho,
@@ -195,6 +195,8 @@ gn_status gn_set_points(gn_handle h, int64_t n, const double *d_s, const double 
  * local variant.  The validation max-norm and max_abs_R stay on R.
  * Errors: as gn_set_points, and GN_EINVAL for n1 or n2 < 0, missing point
  * arrays, negative weights, or more than 65535 nodes with derivative rows.
+ * With GN_EQ_CCF1D the derivative rows' coupling product ((n1 + n2) x P)
+ * takes a work plan of its own, on the same terms as the n x P one.
  * Handles with derivative rows cannot join a batch. */
 gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const double *d_rho, const double *d_f,
                            int64_t m_quad, const double *d_sq, const double *d_wq, int64_t n_val,

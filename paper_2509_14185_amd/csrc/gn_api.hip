@@ -58,6 +58,7 @@ struct gn_context {
     ModgramWork mg{};                        // int8 residue workspaces (GN_INT8_CRT)
     TilePlan gplan{};                        // work plan of the FP64 Gram of order P + 1 (set at creation)
     TilePlan cplan{};                        // work plan of the Hilbert coupling, N x P (set with the points)
+    TilePlan dplan{};                        // work plan of the derivative rows' coupling, (n1 + n2) x P
     int64_t ldJ = 0, ldG = 0, n_partial_cap = 0;
     // 2D problems (gn_set_points_2d)
     int dim = 1, nout = 1, n_eq = 1;
@@ -272,7 +273,7 @@ gn_status deriv_jacobian(gn_handle h, const double *theta, double *J, int64_t ld
     g.B = h->Bm; g.ldb = h->ldJ; g.lb = 0;
     g.C = J + h->n * ldJ; g.ldc = ldJ;
     g.alpha = 1.0; g.beta = 1.0;
-    GN_HIP(h, launch_dgemm(st, g));
+    GN_HIP(h, launch_planned(st, g, h->dplan));
     return GN_OK;
 }
 
@@ -808,6 +809,7 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
     h->fn_R = nullptr;
     h->cp_t = h->cp_z = h->cp_work = nullptr;
     h->cplan = TilePlan{};
+    h->dplan = TilePlan{};
     auto &A = h->pt_allocs;
     const int64_t P = h->md.P;
     const int64_t nd = n1 + n2;
@@ -888,6 +890,7 @@ gn_status gn_set_points_ex(gn_handle h, int64_t n, const double *d_s, const doub
         if (m_quad > 0) {
             if (s == GN_OK) s = dev_alloc(h, A, &h->bseed, 8 * m_quad);
             if (s == GN_OK) s = dev_alloc(h, A, &h->dAT, 3 * m_quad * h->ldA);
+            if (s == GN_OK && h->equation == GN_EQ_CCF1D) s = tile_plan_alloc(h, A, nd, P, false, &h->dplan);
             if (s == GN_OK) s = dev_alloc(h, A, &h->nvseed, 4 * m_quad);
         }
     }

@@ -5,7 +5,9 @@ Tolerances as for the d0 rows: r, J, J^T v relative 1e-12 (normwise); the
 step by backward error <= 5e-14 and forward error <= max(1e-12, 10 kappa
 eps).  Cases: CCF with d1 and d2 rows (ragged counts, several tiles of the
 jet sweep), the local variant with d1 rows only, a deeper CCF network with
-d2 rows only; the argument checks."""
+d2 rows only, CCF with enough derivative rows for their coupling product to
+run on a work plan (K split into pieces summed in a second launch); the
+argument checks."""
 import numpy as np
 import pytest
 import torch
@@ -23,6 +25,10 @@ CASES = {
     "ccf_d1d2": (p1.CCF, dict(n=300, m_quad=64, widths=[1, 12, 10, 1]), 37, 29),
     "burgers_d1": (p1.BURGERS, dict(n=200, widths=[1, 8, 8, 1]), 50, 0),
     "ccf_deep_d2": (p1.CCF, dict(n=150, m_quad=40, widths=[1, 16, 16, 16, 1]), 0, 23),
+    # 370 derivative rows x P = 673: 66 tiles of 64 x 64 in the derivative
+    # rows' coupling product, which then runs on its work plan (every tile
+    # split in 4 K pieces of its K = 3 m_quad = 192)
+    "ccf_d1d2_planned": (p1.CCF, dict(n=300, m_quad=64, widths=[1, 24, 24, 1]), 200, 170),
 }
 
 
